@@ -1,0 +1,525 @@
+/*
+ * CPU reference ("oracle") for the ensemble integrators.
+ *
+ * TEST INFRASTRUCTURE ONLY: plain serial FP64 C, built with
+ * -O2 -ffp-contract=off and libm, one system at a time.  Only the tests, the
+ * smoke check and the benchmark's CPU-baseline leg use it.  The optional
+ * OpenMP loop over systems only runs independent systems side by side; each
+ * system is integrated by the same serial code.
+ *
+ * What it follows (arXiv:2011.01740, Nagy, Plavecz, Hegedus):
+ *   - models: the introductory example dx/dt = x^2 - p (Sec. 3); the Lorenz
+ *     system (Sec. 4.1); the dimensionless Keller--Miksis equation with its
+ *     pre-computed coefficients C0..C12 (Sec. 4.2); the pressure-relief valve
+ *     with the Newtonian impact law (Sec. 4.3);
+ *   - solvers: classic fourth-order Runge--Kutta with a fixed step (Sec. 3,
+ *     Sec. 4.1) and the Runge--Kutta--Cash--Karp 5(4) scheme with embedded
+ *     error control, rtol = atol (Sec. 4.2.1, Sec. 4.3.1);
+ *   - integration phases: the Keller--Miksis phase is one forcing period
+ *     tau in [0, 1]; the valve phase runs from one local maximum of the
+ *     displacement to the next (Sec. 4.3);
+ *   - accessories: the phase maximum of y1 taken over the natural step end
+ *     points, updated after every successful step, without dense output
+ *     (Sec. 4.2.1); for the valve the recorded maximum is y1 at the located
+ *     local maximum (the Poincare point) and the phase minimum is taken over
+ *     the step end points, impacts contributing 0 (Sec. 4.3);
+ *   - events: impact (y1 reaches 0 moving down) and local maximum (y2 goes
+ *     from positive to negative), located to an absolute tolerance on the
+ *     event function, then the impact law y1 = 0, y2 -> -r y2 (Sec. 4.3,
+ *     Sec. 4.3.1).
+ *
+ * The paper does not print the step-size controller, the error norm, the way
+ * an event is located, or what happens after a truncated last step of a
+ * phase.  The readings implemented here, binding for the GPU library too:
+ *   - error:  err_i = h * sum_j (b5_j - b4_j) k_j,i ;
+ *             E = max_i |err_i| / (atol + rtol * max(|y_i|, |y5_i|)) ;
+ *   - the fifth-order solution is propagated;
+ *   - accept iff E <= 1 or h <= dt_min (the latter sets ORC_SYS_DT_MIN);
+ *   - fac = 0.9 E^(-1/5) (5 if E == 0); accepted: h *= clamp(fac, 0.2, 5);
+ *     rejected: h *= clamp(fac, 0.2, 1); then h is clamped to [dt_min, dt_max];
+ *   - a fixed-length phase truncates the step that would pass its end; if
+ *     that step is accepted the phase ends exactly at t_phase, the clock is
+ *     reset to 0 and the next phase starts with the untruncated proposal;
+ *   - an event overshoot (g > 0 before the step, g < -tol after it) discards
+ *     the step and retries from the same point with the secant step
+ *     h * g_old / (g_old - g_new); the smallest such step wins; at most
+ *     max_event_iter retries, after which the step is taken as located;
+ *   - records are a ring: phase k (0-based, counted within one call) is
+ *     stored in slot k mod n_record.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXD 4
+
+int orc_dim(int model) {
+  switch (model) {
+    case ORC_QUAD: return 1;
+    case ORC_LORENZ: return 3;
+    case ORC_KM: return 2;
+    case ORC_PRV: return 3;
+  }
+  return -1;
+}
+
+int orc_nparam(int model) {
+  switch (model) {
+    case ORC_QUAD: return 1;
+    case ORC_LORENZ: return 1;
+    case ORC_KM: return 2;
+    case ORC_PRV: return 1;
+  }
+  return -1;
+}
+
+int orc_nshared(int model) {
+  switch (model) {
+    case ORC_QUAD: return 0;
+    case ORC_LORENZ: return 2;
+    case ORC_KM: return 11;
+    case ORC_PRV: return 4;
+  }
+  return -1;
+}
+
+int orc_nrec_fields(int model) { return model == ORC_PRV ? 2 : 1; }
+
+/* ------------------------------------------------------------------ models */
+
+/* Keller--Miksis coefficients, Sec. 4.2 (the list C0..C12 after the
+ * dimensionless numerator and denominator).  p = (P_A1, f1); shared =
+ * (rho_L, c_L, p_V, sigma, mu_L, gamma, P_inf, R_E, P_A2, f2, theta).
+ * C8 carries the second drive's angular frequency omega2: the time derivative
+ * of P_A2 sin(omega2 t + theta) brings omega2 into that term (the printed
+ * formula shows omega1; with P_A2 = 0 both readings give C8 = 0). */
+void orc_km_coeffs(const double *p, const double *sh, double *C) {
+  const double PA1 = p[0], f1 = p[1];
+  const double rhoL = sh[0], cL = sh[1], pV = sh[2], sigma = sh[3], muL = sh[4];
+  const double gam = sh[5], Pinf = sh[6], RE = sh[7], PA2 = sh[8], f2 = sh[9];
+  const double theta = sh[10];
+  const double pi = 3.14159265358979323846;
+  const double w1 = 2.0 * pi * f1;
+  const double w2 = 2.0 * pi * f2;
+  const double s = 2.0 * pi / (RE * w1); /* 2 pi / (R_E omega1) */
+  const double pg0 = Pinf - pV + 2.0 * sigma / RE;
+  C[0] = (1.0 / rhoL) * pg0 * s * s;
+  C[1] = (1.0 - 3.0 * gam) / (rhoL * cL) * pg0 * s;
+  C[2] = (Pinf - pV) / rhoL * s * s;
+  C[3] = 2.0 * sigma / (rhoL * RE) * s * s;
+  C[4] = 4.0 * muL / (rhoL * RE * RE) * (2.0 * pi / w1);
+  C[5] = PA1 / rhoL * s * s;
+  C[6] = PA2 / rhoL * s * s;
+  C[7] = RE * w1 * PA1 / (rhoL * cL) * s * s;
+  C[8] = RE * w2 * PA2 / (rhoL * cL) * s * s;
+  C[9] = RE * w1 / (2.0 * pi * cL);
+  C[10] = 3.0 * gam;
+  C[11] = w2 / w1;
+  C[12] = theta;
+}
+
+typedef struct {
+  int model;
+  int D;
+  double p[2];     /* per-system parameters                                */
+  const double *sh;/* shared parameters                                    */
+  double C[13];    /* Keller--Miksis coefficients                          */
+  int seated;      /* valve resting on its seat (sticking guard)           */
+} sysctx;
+
+/* dx/dt = x^2 - p (Sec. 3). */
+static void rhs_quad(const sysctx *s, const double *y, double *f) {
+  f[0] = y[0] * y[0] - s->p[0];
+}
+
+/* Lorenz system (Sec. 4.1): sigma (y - x), p x - y - x z, x y - beta z. */
+static void rhs_lorenz(const sysctx *s, const double *y, double *f) {
+  const double sigma = s->sh[0], beta = s->sh[1], rho = s->p[0];
+  f[0] = sigma * (y[1] - y[0]);
+  f[1] = rho * y[0] - y[1] - y[0] * y[2];
+  f[2] = y[0] * y[1] - beta * y[2];
+}
+
+/* Dimensionless Keller--Miksis equation (Sec. 4.2): dy1 = y2,
+ * dy2 = N_KM / D_KM, with tau the dimensionless time. */
+static void rhs_km(const sysctx *s, double tau, const double *y, double *f) {
+  const double *C = s->C;
+  const double pi = 3.14159265358979323846;
+  const double y1 = y[0], y2 = y[1];
+  const double rx = 1.0 / y1;
+  const double a1 = 2.0 * pi * tau;
+  const double a2 = 2.0 * pi * C[11] * tau + C[12];
+  const double N = (C[0] + C[1] * y2) * pow(rx, C[10])
+                   - C[2] * (1.0 + C[9] * y2)
+                   - C[3] * rx
+                   - C[4] * y2 * rx
+                   - (1.0 - C[9] * y2 / 3.0) * 1.5 * y2 * y2
+                   - (C[5] * sin(a1) + C[6] * sin(a2)) * (1.0 + C[9] * y2)
+                   - y1 * (C[7] * cos(a1) + C[8] * cos(a2));
+  const double Dn = y1 - C[9] * y1 * y2 + C[4] * C[9];
+  f[0] = y2;
+  f[1] = N / Dn;
+}
+
+/* Pressure-relief valve (Sec. 4.3): y1' = y2, y2' = -kappa y2 - (y1 + delta)
+ * + y3, y3' = beta (q - y1 sqrt(y3)).  While the valve rests on its seat the
+ * body does not move and the chamber fills: y1' = y2' = 0, y3' = beta q. */
+static void rhs_prv(const sysctx *s, const double *y, double *f) {
+  const double kappa = s->sh[0], delta = s->sh[1], beta = s->sh[2], q = s->p[0];
+  if (s->seated) {
+    f[0] = 0.0;
+    f[1] = 0.0;
+    f[2] = beta * q;
+    return;
+  }
+  f[0] = y[1];
+  f[1] = -kappa * y[1] - (y[0] + delta) + y[2];
+  f[2] = beta * (q - y[0] * sqrt(y[2]));
+}
+
+static void rhs(const sysctx *s, double t, const double *y, double *f) {
+  switch (s->model) {
+    case ORC_QUAD: rhs_quad(s, y, f); break;
+    case ORC_LORENZ: rhs_lorenz(s, y, f); break;
+    case ORC_KM: rhs_km(s, t, y, f); break;
+    case ORC_PRV: rhs_prv(s, y, f); break;
+  }
+}
+
+static int ctx_init(sysctx *s, int model, const double *p, const double *sh) {
+  if (orc_dim(model) < 0) return -1;
+  memset(s, 0, sizeof(*s));
+  s->model = model;
+  s->D = orc_dim(model);
+  for (int j = 0; j < orc_nparam(model); ++j) s->p[j] = p[j];
+  s->sh = sh;
+  if (model == ORC_KM) orc_km_coeffs(p, sh, s->C);
+  return 0;
+}
+
+int orc_rhs(int model, double t, const double *y, const double *p,
+            const double *shared, double *dydt) {
+  sysctx s;
+  if (ctx_init(&s, model, p, shared)) return -1;
+  rhs(&s, t, y, dydt);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ RK4 */
+
+/* Classic fourth-order Runge--Kutta step (Sec. 3):
+ * k1 = f(t, y), k2 = f(t + h/2, y + h/2 k1), k3 = f(t + h/2, y + h/2 k2),
+ * k4 = f(t + h, y + h k3), y <- y + h/6 (k1 + 2 k2 + 2 k3 + k4). */
+static void rk4_step(const sysctx *s, double t, double *y, double h) {
+  const int D = s->D;
+  double k1[MAXD], k2[MAXD], k3[MAXD], k4[MAXD], yt[MAXD];
+  rhs(s, t, y, k1);
+  for (int i = 0; i < D; ++i) yt[i] = y[i] + (h / 2.0) * k1[i];
+  rhs(s, t + h / 2.0, yt, k2);
+  for (int i = 0; i < D; ++i) yt[i] = y[i] + (h / 2.0) * k2[i];
+  rhs(s, t + h / 2.0, yt, k3);
+  for (int i = 0; i < D; ++i) yt[i] = y[i] + h * k3[i];
+  rhs(s, t + h, yt, k4);
+  for (int i = 0; i < D; ++i)
+    y[i] = y[i] + (h / 6.0) * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+int orc_rk4(int model, int64_t n, const double *params, const double *shared,
+            const double *y0, double dt, int64_t nsteps, double *y_out,
+            double *y1max, int nthreads) {
+  const int D = orc_dim(model), P = orc_nparam(model);
+  if (D < 0 || n < 0 || nsteps < 0) return -1;
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+  for (int64_t i = 0; i < n; ++i) {
+    double p[2] = {0.0, 0.0}, y[MAXD];
+    for (int j = 0; j < P; ++j) p[j] = params[j * n + i];
+    sysctx s;
+    ctx_init(&s, model, p, shared);
+    for (int c = 0; c < D; ++c) y[c] = y0[c * n + i];
+    double ymax = y[0];
+    for (int64_t j = 0; j < nsteps; ++j) {
+      rk4_step(&s, (double)j * dt, y, dt);
+      if (y[0] > ymax) ymax = y[0];
+    }
+    if (y_out)
+      for (int c = 0; c < D; ++c) y_out[c * n + i] = y[c];
+    if (y1max) y1max[i] = ymax;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ Cash--Karp */
+
+/* Runge--Kutta--Cash--Karp 5(4) coefficients (J. R. Cash and A. H. Karp,
+ * ACM TOMS 16 (1990) 201), the scheme the paper's GPU package uses. */
+static const double CK_C[6] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0};
+static const double CK_A[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0},
+    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0, 0, 0},
+    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0, 0},
+    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0,
+     253.0 / 4096.0, 0}};
+static const double CK_B5[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0,
+                                0.0, 512.0 / 1771.0};
+static const double CK_B4[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0,
+                                13525.0 / 55296.0, 277.0 / 14336.0, 1.0 / 4.0};
+
+void orc_rkck_tableau(double *a, double *b5, double *b4, double *c) {
+  for (int i = 0; i < 6; ++i) {
+    for (int j = 0; j < 6; ++j) a[i * 6 + j] = CK_A[i][j];
+    b5[i] = CK_B5[i];
+    b4[i] = CK_B4[i];
+    c[i] = CK_C[i];
+  }
+}
+
+/* One attempted step: the six stages, the fifth-order result y5 and the
+ * embedded error estimate err = h * sum_j (b5_j - b4_j) k_j. */
+static void rkck_attempt(const sysctx *s, double t, const double *y, double h,
+                         double *y5, double *err) {
+  const int D = s->D;
+  double k[6][MAXD], yt[MAXD];
+  rhs(s, t, y, k[0]);
+  for (int st = 1; st < 6; ++st) {
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      for (int l = 0; l < st; ++l) acc += CK_A[st][l] * k[l][i];
+      yt[i] = y[i] + h * acc;
+    }
+    rhs(s, t + CK_C[st] * h, yt, k[st]);
+  }
+  for (int i = 0; i < D; ++i) {
+    double a5 = 0.0, ae = 0.0;
+    for (int l = 0; l < 6; ++l) {
+      a5 += CK_B5[l] * k[l][i];
+      ae += (CK_B5[l] - CK_B4[l]) * k[l][i];
+    }
+    y5[i] = y[i] + h * a5;
+    err[i] = h * ae;
+  }
+}
+
+int orc_rkck_step(int model, double t, const double *y, const double *p,
+                  const double *shared, double h, double *y5, double *y4) {
+  sysctx s;
+  double err[MAXD];
+  if (ctx_init(&s, model, p, shared)) return -1;
+  rkck_attempt(&s, t, y, h, y5, err);
+  for (int i = 0; i < s.D; ++i) y4[i] = y5[i] - err[i];
+  return 0;
+}
+
+static double clampd(double x, double lo, double hi) {
+  return x < lo ? lo : (x > hi ? hi : x);
+}
+
+static void put_record(double *records, int64_t n, int F, int64_t R, int64_t phase,
+                       int64_t i, double ymax, double ymin) {
+  if (!records || R <= 0) return;
+  const int64_t slot = phase % R;
+  records[(slot * F + 0) * n + i] = ymax;
+  if (F > 1) records[(slot * F + 1) * n + i] = ymin;
+}
+
+/* Integrate one system through its phases.  y, t, h are updated in place. */
+static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, double *hp,
+                      double *records, int64_t n, int64_t i, int64_t st[ORC_NSTAT],
+                      int32_t *status) {
+  const int D = s->D;
+  const int F = orc_nrec_fields(s->model);
+  const int fixed_len = (s->model != ORC_PRV);
+  const double tol_ev = o->event_tol;
+  double t = *tp, h = *hp;
+  double t_ps = t;                 /* start time of the current phase */
+  double ymax = -INFINITY, ymin = INFINITY;
+  int64_t phase = 0, attempts = 0;
+  int ev_iter = 0;
+  double y5[MAXD], err[MAXD];
+
+  while (phase < o->n_phases) {
+    if (o->max_steps > 0 && attempts >= o->max_steps) {
+      *status |= ORC_SYS_MAX_STEPS;
+      break;
+    }
+    double h_try = h;
+    int trunc = 0;
+    if (fixed_len && t + h_try >= o->t_phase) {
+      h_try = o->t_phase - t;
+      trunc = 1;
+    }
+    rkck_attempt(s, t, y, h_try, y5, err);
+    attempts++;
+    st[ORC_ST_NRHS] += 6;
+
+    /* error norm */
+    double E = 0.0;
+    int finite = 1;
+    for (int c = 0; c < D; ++c) {
+      const double sc = o->atol + o->rtol * fmax(fabs(y[c]), fabs(y5[c]));
+      const double r = fabs(err[c]) / sc;
+      if (!isfinite(y5[c]) || !isfinite(r)) finite = 0;
+      if (r > E) E = r;
+    }
+    if (!finite) {
+      *status |= ORC_SYS_NONFINITE;
+      break;
+    }
+    const double fac = (E == 0.0) ? 5.0 : 0.9 * pow(E, -0.2);
+    if (E > 1.0 && h_try > o->dt_min) {
+      st[ORC_ST_REJECTED]++;
+      h = clampd(h_try * clampd(fac, 0.2, 1.0), o->dt_min, o->dt_max);
+      continue;
+    }
+    if (E > 1.0) *status |= ORC_SYS_DT_MIN;
+    const double h_next = clampd(h_try * clampd(fac, 0.2, 5.0), o->dt_min, o->dt_max);
+
+    if (s->model == ORC_PRV) {
+      /* event detection on the step (t, y) -> (t + h_try, y5) */
+      double hs = INFINITY;
+      int over = 0;
+      if (!s->seated) {
+        const double g1o = y[0], g1n = y5[0];   /* impact: y1 decreasing  */
+        const double g2o = y[1], g2n = y5[1];   /* local max: y2 decreasing */
+        if (g1o > 0.0 && g1n < -tol_ev) {
+          hs = fmin(hs, h_try * g1o / (g1o - g1n));
+          over = 1;
+        }
+        if (g1o == 0.0 && g1n < -tol_ev) {
+          /* a rebound swallowed inside one step: no secant is defined from
+           * g = 0, so the step is halved */
+          hs = fmin(hs, 0.5 * h_try);
+          over = 1;
+        }
+        if (g2o > 0.0 && g2n < -tol_ev) {
+          hs = fmin(hs, h_try * g2o / (g2o - g2n));
+          over = 1;
+        }
+      } else {
+        const double delta = s->sh[1];
+        const double g3o = y[2] - delta, g3n = y5[2] - delta; /* increasing */
+        if (g3o < 0.0 && g3n > tol_ev) {
+          hs = fmin(hs, h_try * (-g3o) / (g3n - g3o));
+          over = 1;
+        }
+      }
+      if (over && ev_iter < o->max_event_iter) {
+        ev_iter++;
+        st[ORC_ST_EVRETRY]++;
+        h = hs;
+        continue;
+      }
+      if (over) *status |= ORC_SYS_EVENT_ITER;
+      ev_iter = 0;
+
+      /* accept */
+      const double y1o = y[0], y2o = y[1];
+      (void)y1o;
+      const int was_seated = s->seated;
+      for (int c = 0; c < D; ++c) y[c] = y5[c];
+      t = t + h_try;
+      st[ORC_ST_ACCEPTED]++;
+      h = h_next;
+      int phase_end = 0, stop = 0;
+      if (was_seated) {
+        if (y[2] - s->sh[1] >= 0.0) s->seated = 0; /* lift-off */
+      } else if (y[0] <= 0.0 && y[1] < 0.0) {
+        /* located impact: Newtonian restitution, Sec. 4.3 */
+        const double v_in = y[1];
+        const double r = s->sh[3], delta = s->sh[1];
+        y[0] = 0.0;
+        y[1] = -r * v_in;
+        st[ORC_ST_IMPACTS]++;
+        if (fabs(v_in) < o->v_stick && y[2] < delta) {
+          s->seated = 1;
+          y[1] = 0.0;
+          *status |= ORC_SYS_SEATED;
+        }
+        if (o->max_impacts > 0 && st[ORC_ST_IMPACTS] >= o->max_impacts) stop = 1;
+      } else if (y2o > 0.0 && y[1] <= 0.0) {
+        phase_end = 1; /* located local maximum of y1 */
+      }
+      if (y[0] > ymax) ymax = y[0];
+      if (y[0] < ymin) ymin = y[0];
+      if (phase_end) {
+        /* the Poincare point: y1 at the located local maximum */
+        put_record(records, n, F, o->n_record, phase, i, y[0], ymin);
+        phase++;
+        st[ORC_ST_PHASES] = phase;
+        ymax = -INFINITY;
+        ymin = INFINITY;
+        t_ps = t;
+      } else if (t - t_ps >= o->t_cap) {
+        /* settled guard: no local maximum for t_cap time units */
+        put_record(records, n, F, o->n_record, phase, i, ymax, ymin);
+        phase++;
+        st[ORC_ST_PHASES] = phase;
+        *status |= ORC_SYS_SETTLED;
+        stop = 1;
+      }
+      if (stop) break;
+      continue;
+    }
+
+    /* fixed-length phases (QUAD, LORENZ, KM) */
+    for (int c = 0; c < D; ++c) y[c] = y5[c];
+    st[ORC_ST_ACCEPTED]++;
+    if (y[0] > ymax) ymax = y[0];
+    if (trunc) {
+      /* the phase ends exactly at t_phase; next phase from 0 with the
+       * untruncated proposal h */
+      put_record(records, n, F, o->n_record, phase, i, ymax, ymin);
+      phase++;
+      st[ORC_ST_PHASES] = phase;
+      ymax = -INFINITY;
+      t = 0.0;
+    } else {
+      t = t + h_try;
+      h = h_next;
+    }
+  }
+  *tp = t;
+  *hp = h;
+}
+
+int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
+               const double *y0, const double *t0, const double *h0,
+               const orc_opts *opt, double *y_out, double *t_out, double *h_out,
+               double *records, int64_t *stats, int32_t *status, int nthreads) {
+  const int D = orc_dim(model), P = orc_nparam(model);
+  if (D < 0 || n < 0 || !opt) return -1;
+  if (opt->n_record < 0 || opt->n_phases < 0) return -1;
+  if (!(opt->rtol >= 0.0) || !(opt->atol > 0.0) || !(opt->dt_min > 0.0) ||
+      !(opt->dt_max >= opt->dt_min))
+    return -1;
+  if (model != ORC_PRV && !(opt->t_phase > 0.0)) return -1;
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+  for (int64_t i = 0; i < n; ++i) {
+    double p[2] = {0.0, 0.0}, y[MAXD];
+    for (int j = 0; j < P; ++j) p[j] = params[j * n + i];
+    sysctx s;
+    ctx_init(&s, model, p, shared);
+    for (int c = 0; c < D; ++c) y[c] = y0[c * n + i];
+    double t = t0 ? t0[i] : 0.0;
+    double h = h0 ? h0[i] : opt->dt0;
+    int64_t st[ORC_NSTAT] = {0, 0, 0, 0, 0, 0};
+    int32_t stat = ORC_SYS_OK;
+    solve_one(&s, opt, y, &t, &h, records, n, i, st, &stat);
+    if (y_out)
+      for (int c = 0; c < D; ++c) y_out[c * n + i] = y[c];
+    if (t_out) t_out[i] = t;
+    if (h_out) h_out[i] = h;
+    if (stats)
+      for (int k = 0; k < ORC_NSTAT; ++k) stats[k * n + i] = st[k];
+    if (status) status[i] = stat;
+  }
+  return 0;
+}
