@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the ensemble integrator on one MI355X.
+
+Workload: the paper's Lorenz parameter sweep (Sec. 4.1) at scale --
+2^23 independent Lorenz systems, p ~ U[0, 21] and IC 10 + U[-1, 1] (seeded
+SplitMix64), classic RK4 with dt = 0.01 for 10^4 steps, FP64.  One benchmark
+step is one full pass: reset the state from the resident initial conditions
+and integrate all systems for all 10^4 steps (final state and running max of
+x written back).
+
+Output: one JSON line with system-steps/s, the FP64 roofline of the RK4
+kernel (75 algorithmic flop per system-step, peak 78.6 TFLOP/s), and the CPU
+oracle timed on a bounded sample of the same workload on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128)
+FLOP_PER_STEP = 75               # Lorenz RK4: 4 x 9 (RHS) + 3 x 6 (stage inputs) + 21 (update)
+BYTES_PER_SYSTEM = 8 * 8         # reads p, x, y, z; writes x, y, z, max x
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lorenz_rk4_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2011_01740_amd", "csrc", "rk4.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(n, nsteps):
+    """HBM bytes per launch from the committed counter run, if it was taken
+    on the current kernel source at this size; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash() or t.get("n") != n or t.get("n_steps") != nsteps:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(n_total, nsteps, dt, seed, target_s=12.0):
+    """The oracle (plain serial FP64 C, one thread per system batch) on the
+    first m systems of the same seeded ensemble, m sized for ~target_s."""
+    import oracle as O
+    from paper_2011_01740_amd import inputs as I
+
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    sh = [I.LORENZ_SIGMA, I.LORENZ_BETA]
+    probe = 64 * threads
+    P, y0 = I.lorenz_random(probe, seed=seed)
+    t0 = time.perf_counter()
+    O.rk4(O.LORENZ, P, sh, y0, dt, nsteps, nthreads=threads)
+    dt_probe = time.perf_counter() - t0
+    m = int(probe * max(1.0, target_s / max(dt_probe, 1e-3)))
+    m = max(probe, min(m, n_total))
+    P, y0 = I.lorenz_random(m, seed=seed)
+    t0 = time.perf_counter()
+    O.rk4(O.LORENZ, P, sh, y0, dt, nsteps, nthreads=threads)
+    el = time.perf_counter() - t0
+    return {"value": m * nsteps / el, "unit": "system-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {m} of the {n_total} systems, all {nsteps} steps, {el:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 23)
+    ap.add_argument("--n-steps", type=int, default=10000)
+    ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--spl", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the systems are independent; see the sharding notes in DESIGN.md).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2011_01740_amd import ens
+    from paper_2011_01740_amd import inputs as I
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n, nsteps, dt, seed = args.n, args.n_steps, args.dt, 1
+
+    P, y0 = I.lorenz_random(n, seed=seed)
+    P_d = torch.from_numpy(P).to(dev)
+    y0_d = torch.from_numpy(y0).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    e = ens.Ensemble(ens.ENS_LORENZ, ens.ENS_RK4, n, stream=stream)
+    e.set_params(P_d)
+    opts = ens.default_opts(dt=dt, n_steps=nsteps, block=args.block, spl=args.spl)
+
+    for _ in range(args.warmup):
+        e.set_state(y0_d)
+        e.solve(opts)
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        e.set_state(y0_d)
+        evs[k][0].record(stream)
+        e.solve(opts)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
+    avg_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
+    launch = e.last_launch()
+    ymax = e.read(ens.ENS_ACC, device=True)
+    finite = bool(torch.isfinite(ymax).all().item())
+    e.close()
+
+    sys_steps = n * nsteps
+    value = sys_steps * args.steps / wall
+    achieved = FLOP_PER_STEP * sys_steps / avg_kern_s / 1e12
+    line = {
+        "metric": "system-steps/s",
+        "value": value,
+        "unit": "system-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "lorenz_rk4_fixed_step", "systems": n, "rk4_steps": nsteps,
+                   "dt": dt, "p_range": [0.0, 21.0], "ic": "10 + U[-1,1]", "seed": seed,
+                   "block": launch["block"], "systems_per_lane": launch["spl"]},
+        "fp64_peak_frac": achieved / FP64_PEAK_TFLOPS,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(n, nsteps),
+                     "kernel": "k_rk4_lorenz", "kernel_ms": avg_kern_s * 1e3,
+                     "algorithmic_flop_per_launch": FLOP_PER_STEP * sys_steps,
+                     "algorithmic_bytes_per_launch": BYTES_PER_SYSTEM * n},
+        "finite": finite,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, nsteps, dt, seed)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,236 @@
+/*
+ * ens.h -- C ABI of libens, an MI355X (gfx950) library that integrates very
+ * many independent, low-dimensional, non-stiff ODE systems in FP64, one
+ * system per GPU lane with its state held in registers.
+ *
+ * The operations follow the problem statement of Nagy, Plavecz and Hegedus,
+ * "Solving large number of non-stiff, low-dimensional ordinary differential
+ * equation systems on GPUs and CPUs" (arXiv:2011.01740):
+ *   - an ensemble is N independent instances of one model, each with its own
+ *     parameters and initial conditions, solved by one thread each (Sec. 1,
+ *     Sec. 3.2.1, per-thread approach);
+ *   - models: dx/dt = x^2 - p (Sec. 3), Lorenz (Sec. 4.1), the dimensionless
+ *     Keller--Miksis bubble equation with coefficients C0..C12 computed from
+ *     the physical parameters (Sec. 4.2), the pressure-relief valve with the
+ *     Newtonian impact law (Sec. 4.3);
+ *   - solvers: classic RK4 with a fixed step (Sec. 3, Sec. 4.1) and the
+ *     Runge--Kutta--Cash--Karp 5(4) scheme with embedded error control and
+ *     equal relative and absolute tolerances (Sec. 4.2.1, Sec. 4.3.1);
+ *   - integration phases (a forcing period for Keller--Miksis; local maximum
+ *     to local maximum of the displacement for the valve), per-step
+ *     accessories (phase maximum / minimum of y1 over the step points, no
+ *     dense output), and event location with a tolerance (Sec. 4.2.1,
+ *     Sec. 4.3, Sec. 4.3.1);
+ *   - shared parameters common to an ensemble, kept in on-chip shared memory
+ *     (Sec. 3.2.1).
+ * Step-size controller, error norm, phase-end truncation and event location
+ * are not printed in the paper; the library uses fixed readings:
+ *   err_i = h sum_j (b5_j - b4_j) k_ji;  E = max_i |err_i| /
+ *   (atol + rtol max(|y_i|, |y5_i|));  accept iff E <= 1 or h <= dt_min;
+ *   fac = 0.9 E^(-1/5) (5 if E = 0); h *= clamp(fac, 0.2, 5) after an accepted
+ *   step, clamp(fac, 0.2, 1) after a rejected one, then h is clamped to
+ *   [dt_min, dt_max]; a phase's last step is truncated to land on its end and
+ *   the next phase restarts from the untruncated proposal; an event
+ *   overshoot (g > 0 before, g < -event_tol after) is retried from the same
+ *   point with the secant step h g_old / (g_old - g_new).
+ *
+ * Conventions
+ *   - Every function returns ENS_OK (0) or a negative ens_status.  Argument
+ *     errors return ENS_E_INVAL and leave the handle unchanged; the message
+ *     is available from ens_last_error.  HIP runtime failures return
+ *     ENS_E_HIP.  Problems of single systems (a step-size floor, a non-finite
+ *     state, a step cap) never fail a call: they set that system's status
+ *     word (ENS_SYS_*), read through ENS_STATUS.
+ *   - Per-system arrays are component-major ("structure of arrays"): element
+ *     (c, i) of a [C][n] array is at c * n + i.  Doubles are IEEE binary64.
+ *   - Pointers tagged with `where` are host memory (ENS_HOST) or device
+ *     memory on the handle's device (ENS_DEVICE).  The library copies inputs
+ *     and never keeps a caller pointer past the call.  It owns all its
+ *     device buffers, allocated at ens_create / the first ens_solve that
+ *     needs them and released by ens_destroy.
+ *   - Work is enqueued on the handle's HIP stream.  ens_solve returns once
+ *     the work is enqueued.  ens_read with ENS_HOST waits for the stream;
+ *     with ENS_DEVICE it is stream-ordered and does not wait.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LIBENS_ENS_H_
+#define LIBENS_ENS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ens_ctx *ens_t;
+
+enum ens_status {
+  ENS_OK = 0,
+  ENS_E_INVAL = -1,   /* bad argument (message in ens_last_error)            */
+  ENS_E_NOMEM = -2,   /* device allocation failed                            */
+  ENS_E_HIP = -3,     /* HIP runtime error                                   */
+  ENS_E_ORDER = -4,   /* call out of order (e.g. solve before set_params)    */
+  ENS_E_UNSUPPORTED = -5 /* combination the library does not implement     */
+};
+
+/* Models (dimension D / per-system parameters P / shared parameters S). */
+enum ens_model {
+  ENS_QUAD = 0,   /* dx/dt = x^2 - p.          D=1  P=1 (p)           S=0   */
+  ENS_LORENZ = 1, /* Lorenz.                   D=3  P=1 (rho)         S=2:
+                     (sigma, beta)                                           */
+  ENS_KM = 2,     /* Keller--Miksis.           D=2  P=2 (P_A1 [Pa], f1 [Hz])
+                     S=11: (rho_L, c_L, p_V, sigma, mu_L, gamma, P_inf, R_E,
+                     P_A2, f2, theta), SI units; this library requires P_A2 = 0
+                     (single-frequency drive)                               */
+  ENS_PRV = 3     /* relief valve + impacts.   D=3  P=1 (q)           S=4:
+                     (kappa, delta, beta, r)                                 */
+};
+
+enum ens_solver { ENS_RK4 = 0, ENS_RKCK45 = 1 };
+enum ens_where { ENS_HOST = 0, ENS_DEVICE = 1 };
+
+/* Per-system status bits (ENS_STATUS). */
+enum ens_sys_status {
+  ENS_SYS_OK = 0,
+  ENS_SYS_DT_MIN = 1,      /* a step was accepted only because h <= dt_min   */
+  ENS_SYS_MAX_STEPS = 2,   /* stopped at max_steps attempted steps           */
+  ENS_SYS_NONFINITE = 4,   /* stopped: state or error estimate not finite    */
+  ENS_SYS_SETTLED = 8,     /* valve: no local maximum within t_cap; stopped  */
+  ENS_SYS_EVENT_ITER = 16, /* an event was accepted after the retry cap      */
+  ENS_SYS_SEATED = 32      /* valve: an impact slower than v_stick seated it */
+};
+
+/* Rows of the ENS_STATS int64 [ENS_NSTAT][n] array. */
+enum ens_stat_row {
+  ENS_ST_ACCEPTED = 0, ENS_ST_REJECTED = 1, ENS_ST_NRHS = 2,
+  ENS_ST_IMPACTS = 3, ENS_ST_PHASES = 4, ENS_ST_EVRETRY = 5, ENS_NSTAT = 6
+};
+
+#define ENS_MAX_ENSEMBLES 16
+#define ENS_MAX_SHARED 16
+
+/* Handle description.  The n systems may be split into n_ensembles
+ * sub-ensembles (contiguous index ranges, each with its own shared
+ * parameters and budgets) that are solved together in one launch. */
+typedef struct {
+  int32_t model;          /* enum ens_model                                  */
+  int32_t solver;         /* enum ens_solver                                 */
+  int64_t n;              /* number of systems, >= 0                         */
+  int32_t n_ensembles;    /* 1..ENS_MAX_ENSEMBLES                            */
+  int32_t device;         /* HIP device ordinal                              */
+  const int64_t *ens_offsets; /* host, n_ensembles + 1 ascending offsets from
+                             0 to n; NULL means one ensemble [0, n)          */
+  void *hip_stream;       /* hipStream_t to enqueue on; NULL = null stream   */
+} ens_desc;
+
+/* Creates a handle, allocates the parameter and state buffers on `device`
+ * and sets every sub-ensemble's shared parameters to the model defaults
+ * (Lorenz sigma = 10, beta = 8/3; Keller--Miksis water at 25 C with R_E =
+ * 10 um; valve kappa = 1.25, delta = 10, beta = 20, r = 0.8).
+ * Errors: ENS_E_INVAL (bad model/solver/n/offsets, out == NULL),
+ * ENS_E_NOMEM, ENS_E_HIP.  *out is NULL on failure. */
+int ens_create(const ens_desc *desc, ens_t *out);
+
+/* Releases the handle and all its device memory after waiting for its
+ * stream.  NULL is accepted.  Returns ENS_OK or ENS_E_HIP. */
+int ens_destroy(ens_t h);
+
+/* Message of the last failed call on h (on any handle if h is NULL).  The
+ * string stays valid until the next call on that handle. */
+const char *ens_last_error(ens_t h);
+
+/* Per-system parameters p: [P][n] doubles (see ens_model), copied in.
+ * Keller--Miksis: the lane derives C0..C12 from (P_A1, f1) and the shared
+ * constants when it picks the system up.  Errors: ENS_E_INVAL, ENS_E_HIP. */
+int ens_set_params(ens_t h, const double *p, int32_t where);
+
+/* Shared parameters of sub-ensemble `ensemble` (host array of n_shared
+ * doubles, n_shared == S of the model). */
+int ens_set_shared(ens_t h, int32_t ensemble, const double *shared, int32_t n_shared);
+
+/* Budgets of sub-ensemble `ensemble` for the adaptive solver: phases to
+ * integrate (>= 0; -1 = use ens_solve_opts.n_phases) and impact budget
+ * (valve only: stop after this many impacts, 0 = none). */
+int ens_set_budget(ens_t h, int32_t ensemble, int64_t n_phases, int64_t max_impacts);
+
+/* Initial state y0: [D][n]; t0 and h0: [n] or NULL (t = 0, h = dt0).  Time
+ * is phase-local for fixed-length phases (Keller--Miksis: tau in [0, 1)) and
+ * absolute for the valve.  Passing the ENS_STATE / ENS_TIME / ENS_H outputs
+ * of a solve resumes it. */
+int ens_set_state(ens_t h, const double *y0, const double *t0, const double *h0,
+                  int32_t where);
+
+/* Solve options.  Fields not used by the chosen solver are ignored. */
+typedef struct {
+  /* RK4 */
+  double dt;          /* fixed step (> 0)                                    */
+  int64_t n_steps;    /* steps (>= 0)                                        */
+  /* RKCK45 */
+  double t_phase;     /* length of a fixed-length phase (not the valve)      */
+  double dt0, dt_min, dt_max, rtol, atol;
+  double event_tol;   /* valve event tolerance on the event function         */
+  double t_cap;       /* valve: longest phase before the system is settled   */
+  double v_stick;     /* valve: impact speed below which it seats            */
+  int64_t n_phases;   /* default phases per system                           */
+  int64_t n_record;   /* record ring length R (>= 0): phase k -> slot k % R  */
+  int64_t max_steps;  /* attempted-step cap per system, 0 = none             */
+  int32_t max_event_iter; /* secant retries per event                        */
+  /* launch (0 = tuned/default choice) */
+  int32_t block;      /* threads per block: multiple of 64, <= 1024          */
+  int32_t spl;        /* RK4: systems per lane, 1, 2 or 4                    */
+  int32_t refill;     /* RKCK45: idle lanes a wave waits for before it takes
+                         new systems from the queue (1..64)                  */
+  int32_t grid;       /* RKCK45: persistent blocks (0 = resident capacity)   */
+  int32_t use_graph;  /* RKCK45: capture the launch sequence in a hipGraph
+                         and replay it                                       */
+} ens_solve_opts;
+
+/* Fills opts with the defaults: dt 0.01, n_steps 1000, t_phase 1, dt0 1e-2,
+ * dt_min 1e-14, dt_max 0.1, rtol = atol = 1e-10, event_tol 1e-6, t_cap 50,
+ * v_stick 1e-9, n_phases 1, n_record 1, max_steps 0, max_event_iter 20, and
+ * zero (automatic) launch fields. */
+void ens_default_opts(ens_solve_opts *opts);
+
+/* Enqueues the integration of all n systems from the current state.  RK4:
+ * n_steps steps of dt; ENS_ACC receives the maximum of y1 over the initial
+ * point and every step end point.  RKCK45: each system runs its phases (or
+ * until its impact budget, step cap, or a terminating status), recording
+ * per phase y1max (valve: y1 at the located local maximum, and y1min) into
+ * the record ring, then the library-owned state holds the final y, t, h.
+ * Errors: ENS_E_INVAL (bad options), ENS_E_ORDER (no params or state yet),
+ * ENS_E_UNSUPPORTED, ENS_E_NOMEM, ENS_E_HIP. */
+int ens_solve(ens_t h, const ens_solve_opts *opts);
+
+enum ens_field {
+  ENS_STATE = 0,   /* double [D][n]                                          */
+  ENS_TIME = 1,    /* double [n]                                             */
+  ENS_H = 2,       /* double [n]: step the next solve would try              */
+  ENS_ACC = 3,     /* double [n]: RK4 running max of y1                      */
+  ENS_RECORDS = 4, /* double [R][F][n]; F = 2 for the valve (y1max, y1min),
+                      1 otherwise; slots never written hold NaN             */
+  ENS_STATS = 5,   /* int64 [ENS_NSTAT][n]                                   */
+  ENS_STATUS = 6   /* int32 [n]                                              */
+};
+
+/* Copies a result field into dst (bytes must equal the field size).
+ * ENS_HOST waits for the stream; ENS_DEVICE is stream-ordered.  Errors:
+ * ENS_E_INVAL (size, field), ENS_E_ORDER (field not produced yet), ENS_E_HIP. */
+int ens_read(ens_t h, int32_t field, void *dst, size_t bytes, int32_t where);
+
+/* Size in bytes of a field as ens_read expects it (0 if not produced yet). */
+size_t ens_field_bytes(ens_t h, int32_t field);
+
+/* Launch actually used by the last ens_solve: block size, systems per lane,
+ * grid, refill threshold.  Any pointer may be NULL. */
+int ens_last_launch(ens_t h, int32_t *block, int32_t *spl, int32_t *grid, int32_t *refill);
+
+/* Milliseconds between HIP events recorded on the handle's stream right
+ * before and after the integration kernel of the last ens_solve (waits for
+ * the stream). */
+int ens_last_kernel_ms(ens_t h, float *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBENS_ENS_H_ */

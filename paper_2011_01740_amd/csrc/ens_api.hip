@@ -1,0 +1,561 @@
+// Host implementation of the C ABI declared in include/ens.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ens_internal.h"
+
+namespace ens {
+
+ModelInfo model_info(int model) {
+  switch (model) {
+    case ENS_QUAD: return {1, 1, 0, 1};
+    case ENS_LORENZ: return {3, 1, 2, 1};
+    case ENS_KM: return {2, 2, 11, 1};
+    case ENS_PRV: return {3, 1, 4, 2};
+  }
+  return {0, 0, 0, 0};
+}
+
+}  // namespace ens
+
+using ens::EnsDesc;
+
+struct ens_ctx {
+  int model = 0, solver = 0;
+  ens::ModelInfo mi{};
+  int64_t n = 0;
+  int n_ens = 1;
+  std::vector<int64_t> off;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  int device = 0;
+  std::string err;
+  // per-sub-ensemble settings
+  double shared[ENS_MAX_ENSEMBLES][ENS_MAX_SHARED] = {};
+  int64_t ens_phases[ENS_MAX_ENSEMBLES];
+  int64_t ens_impacts[ENS_MAX_ENSEMBLES];
+  std::vector<EnsDesc> desc_dev_copy;  // what d_desc currently holds
+  // device buffers
+  double *d_p = nullptr, *d_y = nullptr, *d_t = nullptr, *d_h = nullptr;
+  double *d_acc = nullptr, *d_rec = nullptr;
+  int64_t *d_stats = nullptr;
+  int32_t *d_status = nullptr;
+  unsigned long long *d_queue = nullptr;
+  EnsDesc *d_desc = nullptr;
+  size_t rec_cap = 0;   // doubles allocated in d_rec
+  int64_t R = 0;        // record ring length of the last adaptive solve
+  bool have_p = false, have_y = false, h_init = false;
+  bool have_acc = false, have_adaptive = false, timed = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int last_block = 0, last_spl = 0, last_grid = 0, last_refill = 0;
+  // cached graph of the adaptive launch sequence
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  ens::RkckArgs g_args{};
+  int g_block = 0, g_grid = 0, g_model = -1;
+  bool g_fill_h = false;
+  double g_dt0 = 0.0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(ens_ctx *h, int code, const std::string &msg) {
+  g_err = msg;
+  if (h) h->err = msg;
+  return code;
+}
+
+int hip_fail(ens_ctx *h, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(h, e == hipErrorOutOfMemory ? ENS_E_NOMEM : ENS_E_HIP, m);
+}
+
+#define ENS_HIP(ctx, call)                                  \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
+  } while (0)
+
+// Selects the handle's device for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+void default_shared(int model, double *sh) {
+  switch (model) {
+    case ENS_LORENZ:
+      sh[0] = 10.0;
+      sh[1] = 8.0 / 3.0;
+      break;
+    case ENS_KM: {
+      const double w[11] = {997.0, 1497.0, 3166.0, 0.0728, 8.9e-4, 1.4,
+                            1.0e5, 10.0e-6, 0.0,    0.0,    0.0};
+      for (int i = 0; i < 11; ++i) sh[i] = w[i];
+      break;
+    }
+    case ENS_PRV:
+      sh[0] = 1.25;
+      sh[1] = 10.0;
+      sh[2] = 20.0;
+      sh[3] = 0.8;
+      break;
+    default: break;
+  }
+}
+
+template <class T>
+hipError_t dalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void **)p, count * sizeof(T));
+}
+
+hipMemcpyKind kind_in(int where) {
+  return where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+
+void free_graph(ens_ctx *h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ens_last_error(ens_t h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+void ens_default_opts(ens_solve_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->dt = 0.01;
+  o->n_steps = 1000;
+  o->t_phase = 1.0;
+  o->dt0 = 1e-2;
+  o->dt_min = 1e-14;
+  o->dt_max = 0.1;
+  o->rtol = 1e-10;
+  o->atol = 1e-10;
+  o->event_tol = 1e-6;
+  o->t_cap = 50.0;
+  o->v_stick = 1e-9;
+  o->n_phases = 1;
+  o->n_record = 1;
+  o->max_steps = 0;
+  o->max_event_iter = 20;
+}
+
+int ens_create(const ens_desc *d, ens_t *out) {
+  if (!out) return fail(nullptr, ENS_E_INVAL, "ens_create: out is NULL");
+  *out = nullptr;
+  if (!d) return fail(nullptr, ENS_E_INVAL, "ens_create: desc is NULL");
+  if (d->model < ENS_QUAD || d->model > ENS_PRV)
+    return fail(nullptr, ENS_E_INVAL, "ens_create: unknown model");
+  if (d->solver != ENS_RK4 && d->solver != ENS_RKCK45)
+    return fail(nullptr, ENS_E_INVAL, "ens_create: unknown solver");
+  if (d->n < 0 || d->n > (int64_t)INT32_MAX)
+    return fail(nullptr, ENS_E_INVAL, "ens_create: n must be in [0, 2^31)");
+  if (d->n_ensembles < 1 || d->n_ensembles > ENS_MAX_ENSEMBLES)
+    return fail(nullptr, ENS_E_INVAL, "ens_create: n_ensembles out of range");
+  if (d->solver == ENS_RK4 && d->model != ENS_QUAD && d->model != ENS_LORENZ)
+    return fail(nullptr, ENS_E_UNSUPPORTED, "ens_create: RK4 is built for QUAD and LORENZ");
+  std::vector<int64_t> off;
+  if (d->ens_offsets) {
+    off.assign(d->ens_offsets, d->ens_offsets + d->n_ensembles + 1);
+    if (off.front() != 0 || off.back() != d->n)
+      return fail(nullptr, ENS_E_INVAL, "ens_create: offsets must run from 0 to n");
+    for (int e = 0; e < d->n_ensembles; ++e)
+      if (off[e + 1] < off[e])
+        return fail(nullptr, ENS_E_INVAL, "ens_create: offsets must be ascending");
+  } else {
+    if (d->n_ensembles != 1)
+      return fail(nullptr, ENS_E_INVAL, "ens_create: offsets required for n_ensembles > 1");
+    off = {0, d->n};
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(nullptr, ENS_E_HIP, "ens_create: no HIP device");
+  if (d->device < 0 || d->device >= ndev)
+    return fail(nullptr, ENS_E_INVAL, "ens_create: bad device ordinal");
+
+  ens_ctx *h = new (std::nothrow) ens_ctx();
+  if (!h) return fail(nullptr, ENS_E_NOMEM, "ens_create: out of host memory");
+  h->model = d->model;
+  h->solver = d->solver;
+  h->mi = ens::model_info(d->model);
+  h->n = d->n;
+  h->n_ens = d->n_ensembles;
+  h->off = off;
+  h->stream = (hipStream_t)d->hip_stream;
+  h->device = d->device;
+  for (int e = 0; e < ENS_MAX_ENSEMBLES; ++e) {
+    default_shared(h->model, h->shared[e]);
+    h->ens_phases[e] = -1;
+    h->ens_impacts[e] = 0;
+  }
+  DeviceGuard g(h->device);
+  if (!g.ok) {
+    delete h;
+    return fail(nullptr, ENS_E_HIP, "ens_create: hipSetDevice failed");
+  }
+  const size_t n = (size_t)h->n;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = dalloc(&h->d_p, (size_t)h->mi.P * n);
+  if (e == hipSuccess) e = dalloc(&h->d_y, (size_t)h->mi.D * n);
+  if (e == hipSuccess) e = dalloc(&h->d_t, n);
+  if (e == hipSuccess) e = dalloc(&h->d_h, n);
+  if (e == hipSuccess && h->solver == ENS_RK4) e = dalloc(&h->d_acc, n);
+  if (e == hipSuccess && h->solver == ENS_RKCK45) {
+    e = dalloc(&h->d_stats, (size_t)ENS_NSTAT * n);
+    if (e == hipSuccess) e = dalloc(&h->d_status, n);
+    if (e == hipSuccess) e = dalloc(&h->d_queue, 1);
+    if (e == hipSuccess) e = dalloc(&h->d_desc, ENS_MAX_ENSEMBLES);
+  }
+  if (e == hipSuccess) e = hipEventCreate(&h->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&h->ev1);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    int code = hip_fail(nullptr, e, "ens_create: device allocation");
+    ens_destroy(h);
+    return code;
+  }
+  *out = h;
+  return ENS_OK;
+}
+
+int ens_destroy(ens_t h) {
+  if (!h) return ENS_OK;
+  DeviceGuard g(h->device);
+  hipError_t e = hipSuccess;
+  if (g.ok) e = hipStreamSynchronize(h->stream);
+  free_graph(h);
+  (void)hipFree(h->d_p);
+  (void)hipFree(h->d_y);
+  (void)hipFree(h->d_t);
+  (void)hipFree(h->d_h);
+  (void)hipFree(h->d_acc);
+  (void)hipFree(h->d_rec);
+  (void)hipFree(h->d_stats);
+  (void)hipFree(h->d_status);
+  (void)hipFree(h->d_queue);
+  (void)hipFree(h->d_desc);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  delete h;
+  return e == hipSuccess ? ENS_OK : ENS_E_HIP;
+}
+
+int ens_set_params(ens_t h, const double *p, int32_t where) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_set_params: NULL handle");
+  if (!p && h->n > 0) return fail(h, ENS_E_INVAL, "ens_set_params: p is NULL");
+  if (where != ENS_HOST && where != ENS_DEVICE)
+    return fail(h, ENS_E_INVAL, "ens_set_params: bad where");
+  DeviceGuard g(h->device);
+  const size_t bytes = (size_t)h->mi.P * h->n * sizeof(double);
+  if (bytes) ENS_HIP(h, hipMemcpyAsync(h->d_p, p, bytes, kind_in(where), h->stream));
+  if (where == ENS_HOST && bytes) ENS_HIP(h, hipStreamSynchronize(h->stream));
+  h->have_p = true;
+  return ENS_OK;
+}
+
+int ens_set_shared(ens_t h, int32_t ensemble, const double *shared, int32_t n_shared) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_set_shared: NULL handle");
+  if (ensemble < 0 || ensemble >= h->n_ens)
+    return fail(h, ENS_E_INVAL, "ens_set_shared: ensemble out of range");
+  if (n_shared != h->mi.S)
+    return fail(h, ENS_E_INVAL, "ens_set_shared: wrong number of shared parameters");
+  if (n_shared > 0 && !shared) return fail(h, ENS_E_INVAL, "ens_set_shared: NULL array");
+  for (int i = 0; i < n_shared; ++i)
+    if (!std::isfinite(shared[i]))
+      return fail(h, ENS_E_INVAL, "ens_set_shared: non-finite value");
+  if (h->model == ENS_KM && shared[8] != 0.0)
+    return fail(h, ENS_E_UNSUPPORTED, "ens_set_shared: second drive (P_A2 != 0) is not built");
+  for (int i = 0; i < n_shared; ++i) h->shared[ensemble][i] = shared[i];
+  return ENS_OK;
+}
+
+int ens_set_budget(ens_t h, int32_t ensemble, int64_t n_phases, int64_t max_impacts) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_set_budget: NULL handle");
+  if (ensemble < 0 || ensemble >= h->n_ens)
+    return fail(h, ENS_E_INVAL, "ens_set_budget: ensemble out of range");
+  if (n_phases < -1 || n_phases > (int64_t)UINT32_MAX || max_impacts < 0)
+    return fail(h, ENS_E_INVAL, "ens_set_budget: bad budget");
+  h->ens_phases[ensemble] = n_phases;
+  h->ens_impacts[ensemble] = max_impacts;
+  return ENS_OK;
+}
+
+int ens_set_state(ens_t h, const double *y0, const double *t0, const double *h0,
+                  int32_t where) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_set_state: NULL handle");
+  if (!y0 && h->n > 0) return fail(h, ENS_E_INVAL, "ens_set_state: y0 is NULL");
+  if (where != ENS_HOST && where != ENS_DEVICE)
+    return fail(h, ENS_E_INVAL, "ens_set_state: bad where");
+  DeviceGuard g(h->device);
+  const size_t n = (size_t)h->n;
+  if (n) {
+    ENS_HIP(h, hipMemcpyAsync(h->d_y, y0, (size_t)h->mi.D * n * sizeof(double), kind_in(where),
+                              h->stream));
+    if (t0)
+      ENS_HIP(h, hipMemcpyAsync(h->d_t, t0, n * sizeof(double), kind_in(where), h->stream));
+    else
+      ENS_HIP(h, ens::launch_fill_f64(h->d_t, 0.0, (int64_t)n, h->stream));
+    if (h0)
+      ENS_HIP(h, hipMemcpyAsync(h->d_h, h0, n * sizeof(double), kind_in(where), h->stream));
+    if (where == ENS_HOST) ENS_HIP(h, hipStreamSynchronize(h->stream));
+  }
+  h->h_init = h0 != nullptr;
+  h->have_y = true;
+  h->have_acc = false;
+  return ENS_OK;
+}
+
+static int solve_rk4(ens_t h, const ens_solve_opts *o) {
+  if (!(o->dt > 0.0) || !std::isfinite(o->dt) || o->n_steps < 0)
+    return fail(h, ENS_E_INVAL, "ens_solve: RK4 needs dt > 0 and n_steps >= 0");
+  int block = o->block ? o->block : 256;
+  int spl = o->spl ? o->spl : 1;
+  if (block < 64 || block > 1024 || block % 64)
+    return fail(h, ENS_E_INVAL, "ens_solve: block must be a multiple of 64 in [64, 1024]");
+  if (spl != 1 && spl != 2 && spl != 4) return fail(h, ENS_E_INVAL, "ens_solve: spl must be 1, 2 or 4");
+  ENS_HIP(h, hipEventRecord(h->ev0, h->stream));
+  ENS_HIP(h, ens::launch_rk4(h->model, block, spl, h->d_p, h->d_y, h->d_acc, h->n, o->dt,
+                             o->n_steps, h->shared[0], h->stream));
+  ENS_HIP(h, hipEventRecord(h->ev1, h->stream));
+  h->timed = true;
+  h->have_acc = true;
+  h->last_block = block;
+  h->last_spl = spl;
+  h->last_grid = (int)((h->n + (int64_t)block * spl - 1) / ((int64_t)block * spl));
+  h->last_refill = 0;
+  return ENS_OK;
+}
+
+static int solve_rkck(ens_t h, const ens_solve_opts *o) {
+  auto pos = [](double v) { return v > 0.0 && std::isfinite(v); };
+  if (!pos(o->dt0) || !pos(o->dt_min) || !pos(o->dt_max) || o->dt_max < o->dt_min)
+    return fail(h, ENS_E_INVAL, "ens_solve: need 0 < dt_min <= dt_max and dt0 > 0");
+  if (!(o->rtol >= 0.0) || !pos(o->atol))
+    return fail(h, ENS_E_INVAL, "ens_solve: need rtol >= 0 and atol > 0");
+  if (h->model != ENS_PRV && !pos(o->t_phase))
+    return fail(h, ENS_E_INVAL, "ens_solve: t_phase must be > 0");
+  if (h->model == ENS_PRV && (!pos(o->event_tol) || !pos(o->t_cap) || !(o->v_stick >= 0.0)))
+    return fail(h, ENS_E_INVAL, "ens_solve: bad event_tol, t_cap or v_stick");
+  if (o->n_phases < 0 || o->n_phases > (int64_t)UINT32_MAX || o->n_record < 0 ||
+      o->max_steps < 0 || o->max_event_iter < 0)
+    return fail(h, ENS_E_INVAL, "ens_solve: bad phase, record or step counts");
+  if (o->max_steps > (int64_t)UINT32_MAX)
+    return fail(h, ENS_E_INVAL, "ens_solve: max_steps above 2^32");
+  const int block = o->block ? o->block : 256;
+  if (block < 64 || block > 256 || block % 64)
+    return fail(h, ENS_E_INVAL, "ens_solve: adaptive block must be 64, 128, 192 or 256");
+  const int refill = o->refill ? o->refill : 1;
+  if (refill < 1 || refill > 64) return fail(h, ENS_E_INVAL, "ens_solve: refill must be in [1, 64]");
+  int grid = o->grid;
+  const int cap = ens::rkck_max_blocks(h->model, block);
+  if (cap <= 0) return fail(h, ENS_E_HIP, "ens_solve: occupancy query failed");
+  if (grid <= 0) grid = cap;
+  if (grid > cap) return fail(h, ENS_E_INVAL, "ens_solve: grid above resident capacity");
+
+  // records
+  const int64_t R = o->n_record;
+  const size_t rec_count = (size_t)R * h->mi.F * (size_t)h->n;
+  if (rec_count > h->rec_cap) {
+    free_graph(h);
+    (void)hipFree(h->d_rec);
+    h->d_rec = nullptr;
+    h->rec_cap = 0;
+    ENS_HIP(h, hipMalloc((void **)&h->d_rec, rec_count * sizeof(double)));
+    h->rec_cap = rec_count;
+  }
+  // sub-ensemble descriptors: upload only when they change
+  std::vector<EnsDesc> desc(h->n_ens);
+  for (int e = 0; e < h->n_ens; ++e) {
+    std::memset(&desc[e], 0, sizeof(EnsDesc));
+    for (int i = 0; i < ENS_MAX_SHARED; ++i) desc[e].shared[i] = h->shared[e][i];
+    desc[e].first = h->off[e];
+    desc[e].last = h->off[e + 1];
+    desc[e].n_phases = h->ens_phases[e] >= 0 ? h->ens_phases[e] : o->n_phases;
+    desc[e].max_impacts = h->model == ENS_PRV ? h->ens_impacts[e] : 0;
+  }
+  if (desc.size() != h->desc_dev_copy.size() ||
+      std::memcmp(desc.data(), h->desc_dev_copy.data(), desc.size() * sizeof(EnsDesc))) {
+    ENS_HIP(h, hipMemcpyAsync(h->d_desc, desc.data(), desc.size() * sizeof(EnsDesc),
+                              hipMemcpyHostToDevice, h->stream));
+    ENS_HIP(h, hipStreamSynchronize(h->stream));
+    h->desc_dev_copy = desc;
+  }
+
+  ens::RkckArgs a;
+  std::memset(&a, 0, sizeof(a));  // padding too: the struct is compared bytewise
+  a.p = h->d_p;
+  a.y = h->d_y;
+  a.t = h->d_t;
+  a.h = h->d_h;
+  a.rec = R > 0 ? h->d_rec : nullptr;
+  a.stats = h->d_stats;
+  a.status = h->d_status;
+  a.queue = h->d_queue;
+  a.desc = h->d_desc;
+  a.n = h->n;
+  a.R = R;
+  a.n_ens = h->n_ens;
+  a.refill = refill;
+  a.t_phase = o->t_phase;
+  a.dt_min = o->dt_min;
+  a.dt_max = o->dt_max;
+  a.rtol = o->rtol;
+  a.atol = o->atol;
+  a.event_tol = o->event_tol;
+  a.t_cap = o->t_cap;
+  a.v_stick = o->v_stick;
+  a.max_steps = o->max_steps;
+  a.max_event_iter = o->max_event_iter;
+  const bool fill_h = !h->h_init;
+
+  auto enqueue = [&](hipStream_t s) -> hipError_t {
+    hipError_t e = ens::launch_fill_u64(h->d_queue, 0ull, 1, s);
+    if (e == hipSuccess && rec_count)
+      e = ens::launch_fill_f64(h->d_rec, std::numeric_limits<double>::quiet_NaN(),
+                               (int64_t)rec_count, s);
+    if (e == hipSuccess && fill_h) e = ens::launch_fill_f64(h->d_h, o->dt0, h->n, s);
+    if (e == hipSuccess && h->n > 0) e = ens::launch_rkck(h->model, block, grid, a, s);
+    return e;
+  };
+
+  if (o->use_graph && h->n > 0) {
+    const bool same = h->gexec && h->g_block == block && h->g_grid == grid &&
+                      h->g_model == h->model && h->g_fill_h == fill_h &&
+                      (!fill_h || h->g_dt0 == o->dt0) &&
+                      std::memcmp(&h->g_args, &a, sizeof(a)) == 0;  // a is zero-filled
+    if (!same) {
+      free_graph(h);
+      ENS_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = enqueue(h->cap_stream);
+      hipGraph_t gr = nullptr;
+      hipError_t e2 = hipStreamEndCapture(h->cap_stream, &gr);
+      if (e != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return hip_fail(h, e, "ens_solve: capture");
+      }
+      if (e2 != hipSuccess) return hip_fail(h, e2, "ens_solve: hipStreamEndCapture");
+      h->graph = gr;
+      ENS_HIP(h, hipGraphInstantiate(&h->gexec, gr, nullptr, nullptr, 0));
+      std::memcpy(&h->g_args, &a, sizeof(a));
+      h->g_block = block;
+      h->g_grid = grid;
+      h->g_model = h->model;
+      h->g_fill_h = fill_h;
+      h->g_dt0 = o->dt0;
+    }
+    ENS_HIP(h, hipEventRecord(h->ev0, h->stream));
+    ENS_HIP(h, hipGraphLaunch(h->gexec, h->stream));
+    ENS_HIP(h, hipEventRecord(h->ev1, h->stream));
+  } else {
+    ENS_HIP(h, hipEventRecord(h->ev0, h->stream));
+    ENS_HIP(h, enqueue(h->stream));
+    ENS_HIP(h, hipEventRecord(h->ev1, h->stream));
+  }
+  h->timed = true;
+  h->h_init = true;
+  h->have_adaptive = true;
+  h->R = R;
+  h->last_block = block;
+  h->last_spl = 1;
+  h->last_grid = grid;
+  h->last_refill = refill;
+  return ENS_OK;
+}
+
+int ens_solve(ens_t h, const ens_solve_opts *o) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_solve: NULL handle");
+  if (!o) return fail(h, ENS_E_INVAL, "ens_solve: opts is NULL");
+  if (!h->have_p || !h->have_y)
+    return fail(h, ENS_E_ORDER, "ens_solve: set params and state first");
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(h, ENS_E_HIP, "ens_solve: hipSetDevice failed");
+  if (h->solver == ENS_RK4) return solve_rk4(h, o);
+  return solve_rkck(h, o);
+}
+
+size_t ens_field_bytes(ens_t h, int32_t field) {
+  if (!h) return 0;
+  const size_t n = (size_t)h->n;
+  switch (field) {
+    case ENS_STATE: return h->have_y ? (size_t)h->mi.D * n * sizeof(double) : 0;
+    case ENS_TIME: return h->have_y ? n * sizeof(double) : 0;
+    case ENS_H: return (h->have_y && h->h_init) ? n * sizeof(double) : 0;
+    case ENS_ACC: return h->have_acc ? n * sizeof(double) : 0;
+    case ENS_RECORDS:
+      return h->have_adaptive ? (size_t)h->R * h->mi.F * n * sizeof(double) : 0;
+    case ENS_STATS: return h->have_adaptive ? (size_t)ENS_NSTAT * n * sizeof(int64_t) : 0;
+    case ENS_STATUS: return h->have_adaptive ? n * sizeof(int32_t) : 0;
+  }
+  return 0;
+}
+
+int ens_read(ens_t h, int32_t field, void *dst, size_t bytes, int32_t where) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_read: NULL handle");
+  if (where != ENS_HOST && where != ENS_DEVICE)
+    return fail(h, ENS_E_INVAL, "ens_read: bad where");
+  if (field < ENS_STATE || field > ENS_STATUS) return fail(h, ENS_E_INVAL, "ens_read: bad field");
+  const size_t need = ens_field_bytes(h, field);
+  const bool produced = need > 0 || h->n == 0 || (field == ENS_RECORDS && h->have_adaptive);
+  if (!produced) return fail(h, ENS_E_ORDER, "ens_read: field not produced yet");
+  if (bytes != need) return fail(h, ENS_E_INVAL, "ens_read: bytes does not match the field size");
+  if (need == 0) return ENS_OK;
+  if (!dst) return fail(h, ENS_E_INVAL, "ens_read: dst is NULL");
+  const void *src = nullptr;
+  switch (field) {
+    case ENS_STATE: src = h->d_y; break;
+    case ENS_TIME: src = h->d_t; break;
+    case ENS_H: src = h->d_h; break;
+    case ENS_ACC: src = h->d_acc; break;
+    case ENS_RECORDS: src = h->d_rec; break;
+    case ENS_STATS: src = h->d_stats; break;
+    case ENS_STATUS: src = h->d_status; break;
+  }
+  DeviceGuard g(h->device);
+  const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  ENS_HIP(h, hipMemcpyAsync(dst, src, need, k, h->stream));
+  if (where == ENS_HOST) ENS_HIP(h, hipStreamSynchronize(h->stream));
+  return ENS_OK;
+}
+
+int ens_last_launch(ens_t h, int32_t *block, int32_t *spl, int32_t *grid, int32_t *refill) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_last_launch: NULL handle");
+  if (!h->timed) return fail(h, ENS_E_ORDER, "ens_last_launch: no solve yet");
+  if (block) *block = h->last_block;
+  if (spl) *spl = h->last_spl;
+  if (grid) *grid = h->last_grid;
+  if (refill) *refill = h->last_refill;
+  return ENS_OK;
+}
+
+int ens_last_kernel_ms(ens_t h, float *ms) {
+  if (!h || !ms) return fail(h, ENS_E_INVAL, "ens_last_kernel_ms: NULL argument");
+  if (!h->timed) return fail(h, ENS_E_ORDER, "ens_last_kernel_ms: no solve yet");
+  DeviceGuard g(h->device);
+  ENS_HIP(h, hipEventSynchronize(h->ev1));
+  ENS_HIP(h, hipEventElapsedTime(ms, h->ev0, h->ev1));
+  return ENS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// Internal declarations of libens (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ens.h"
+
+namespace ens {
+
+// Model sizes: state dimension, per-system parameters, shared parameters,
+// record fields.
+struct ModelInfo {
+  int D, P, S, F;
+};
+ModelInfo model_info(int model);
+
+// Per-sub-ensemble descriptor, copied into LDS by the persistent kernel.
+struct alignas(16) EnsDesc {
+  double shared[ENS_MAX_SHARED];
+  int64_t first, last;      // index range [first, last)
+  int64_t n_phases;         // phases per system
+  int64_t max_impacts;      // valve impact budget (0 = none)
+};
+
+// Everything the persistent adaptive kernel needs, passed by value.
+struct RkckArgs {
+  const double *p;          // [P][n]
+  double *y;                // [D][n] in/out
+  double *t;                // [n] in/out
+  double *h;                // [n] in/out
+  double *rec;              // [R][F][n] or null
+  int64_t *stats;           // [ENS_NSTAT][n]
+  int32_t *status;          // [n]
+  unsigned long long *queue;// next unclaimed system index
+  const EnsDesc *desc;      // [n_ens]
+  int64_t n;
+  int64_t R;
+  int32_t n_ens;
+  int32_t refill;           // idle lanes a wave waits for before refilling
+  double t_phase, dt_min, dt_max, rtol, atol, event_tol, t_cap, v_stick;
+  int64_t max_steps;
+  int32_t max_event_iter;
+};
+
+// Kernel launchers (stream-ordered; return hipSuccess or the launch error).
+hipError_t launch_rk4(int model, int block, int spl, const double *p, double *y,
+                      double *acc, int64_t n, double dt, int64_t nsteps,
+                      const double *shared, hipStream_t s);
+hipError_t launch_rkck(int model, int block, int grid, const RkckArgs &a,
+                       hipStream_t s);
+// Resident-wave capacity of the persistent kernel for this model and block.
+int rkck_max_blocks(int model, int block);
+hipError_t launch_fill_f64(double *p, double v, int64_t count, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count,
+                           hipStream_t s);
+
+}  // namespace ens

@@ -1,0 +1,498 @@
+// Persistent adaptive Runge--Kutta--Cash--Karp 5(4) integrator: one system per
+// lane, state in VGPRs, each lane on its own clock and step size (the
+// asynchronous per-system time stepping of Sec. 4.2 and Sec. 4.3 of
+// arXiv:2011.01740), with a device work queue that refills a lane as soon as
+// its system is finished.
+//
+// Work distribution.  The grid is the resident capacity of the chip.  A wave
+// keeps stepping its active lanes; when at least `refill` of its lanes are
+// idle (or all are), the lowest idle lane claims that many consecutive system
+// indices with one atomic add on the queue head, and the idle lanes take
+// base + (number of idle lanes below them).  A wave whose claim reaches n
+// stops refilling and retires when its last lane finishes.  Systems are
+// handed out in index order, so neighbouring lanes integrate neighbouring
+// parameters (the paper's advice against divergence, Sec. 3.2.1) and
+// sub-ensembles are started in the order they are given.
+//
+// Per step, per lane: six stages, the embedded error estimate, the max-norm
+// error ratio, accept/reject, step-size update, phase bookkeeping, and for
+// the relief valve event detection, secant retry and the impact law.  Only
+// the bookkeeping branches diverge; the stages are the same instruction
+// stream for every lane.  Sub-ensemble descriptors (shared parameters and
+// budgets) sit in LDS.
+#include <cmath>
+
+#include "ens_internal.h"
+
+namespace ens {
+namespace {
+
+constexpr int kMaxBlock = 256;
+
+// Cash--Karp 5(4) tableau (Cash and Karp, ACM TOMS 16, 1990).
+constexpr double A21 = 1.0 / 5.0;
+constexpr double A31 = 3.0 / 40.0, A32 = 9.0 / 40.0;
+constexpr double A41 = 3.0 / 10.0, A42 = -9.0 / 10.0, A43 = 6.0 / 5.0;
+constexpr double A51 = -11.0 / 54.0, A52 = 5.0 / 2.0, A53 = -70.0 / 27.0, A54 = 35.0 / 27.0;
+constexpr double A61 = 1631.0 / 55296.0, A62 = 175.0 / 512.0, A63 = 575.0 / 13824.0,
+                 A64 = 44275.0 / 110592.0, A65 = 253.0 / 4096.0;
+constexpr double C2 = 1.0 / 5.0, C3 = 3.0 / 10.0, C4 = 3.0 / 5.0, C5 = 1.0, C6 = 7.0 / 8.0;
+constexpr double B1 = 37.0 / 378.0, B3 = 250.0 / 621.0, B4 = 125.0 / 594.0,
+                 B6 = 512.0 / 1771.0;
+// fifth- minus fourth-order weights
+constexpr double E1 = B1 - 2825.0 / 27648.0, E3 = B3 - 18575.0 / 48384.0,
+                 E4 = B4 - 13525.0 / 55296.0, E5 = -277.0 / 14336.0, E6 = B6 - 1.0 / 4.0;
+
+// ------------------------------------------------------------------ models
+// Each model: D, lane constants set at refill, rhs(t, y, f).
+
+struct MQuad {  // dx/dt = x^2 - p (Sec. 3)
+  static constexpr int D = 1;
+  static constexpr bool kEvents = false;
+  double p;
+  __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) { p = P[i]; }
+  __device__ void rhs(double, const double *y, double *f) const { f[0] = fma(y[0], y[0], -p); }
+};
+
+struct MLorenz {  // Sec. 4.1
+  static constexpr int D = 3;
+  static constexpr bool kEvents = false;
+  double rho, sigma, beta;
+  __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
+    rho = P[i];
+    sigma = sh[0];
+    beta = sh[1];
+  }
+  __device__ void rhs(double, const double *y, double *f) const {
+    f[0] = sigma * (y[1] - y[0]);
+    f[1] = fma(-y[0], y[2], fma(rho, y[0], -y[1]));
+    f[2] = fma(y[0], y[1], -beta * y[2]);
+  }
+};
+
+// Dimensionless Keller--Miksis equation (Sec. 4.2), single-frequency drive.
+// The lane derives its coefficients from (P_A1, f1) and the shared material
+// constants when it picks the system up; only the nine that are non-zero for
+// a single-frequency drive are kept.  Terms are grouped so that each
+// coefficient multiplies once:
+//   N = (K0 + K1 y2) y1^-K10 - (K2 + K5 s)(1 + K9 y2) - (K3 + K4 y2)/y1
+//       - (1 - K9 y2 / 3) 1.5 y2^2 - K7 c y1,       s, c = sin, cos(2 pi tau)
+//   D = y1 (1 - K9 y2) + K4 K9.
+struct MKM {
+  static constexpr int D = 2;
+  static constexpr bool kEvents = false;
+  double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49;
+  __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
+    const double pa = P[i], f = P[n + i];
+    const double rhoL = sh[0], cL = sh[1], pV = sh[2], sig = sh[3], mu = sh[4];
+    const double gam = sh[5], pinf = sh[6], re = sh[7];
+    const double w = 2.0 * M_PI * f;              // omega1
+    const double q = 2.0 * M_PI / (re * w);       // 2 pi / (R_E omega1)
+    const double q2 = q * q;
+    const double g0 = pinf - pV + 2.0 * sig / re; // gas pressure at rest
+    K0 = g0 * q2 / rhoL;
+    K1 = (1.0 - 3.0 * gam) * g0 * q / (rhoL * cL);
+    K2 = (pinf - pV) * q2 / rhoL;
+    K3 = 2.0 * sig * q2 / (rhoL * re);
+    K4 = 4.0 * mu * (2.0 * M_PI / w) / (rhoL * re * re);
+    K5 = pa * q2 / rhoL;
+    K7 = re * w * pa * q2 / (rhoL * cL);
+    K9 = re * w / (2.0 * M_PI * cL);
+    K10 = 3.0 * gam;
+    K49 = K4 * K9;
+  }
+  __device__ void rhs(double tau, const double *y, double *f) const {
+    const double y1 = y[0], y2 = y[1];
+    const double r1 = 1.0 / y1;
+    const double gas = exp(-K10 * log(y1));       // (1/y1)^(3 gamma)
+    double s, c;
+    sincospi(2.0 * tau, &s, &c);
+    const double u = fma(K9, y2, 1.0);
+    double N = fma(K1, y2, K0) * gas;
+    N = fma(-fma(K5, s, K2), u, N);
+    N = fma(-fma(K4, y2, K3), r1, N);
+    N = fma(-(fma(-K9 / 3.0, y2, 1.0) * 1.5) * y2, y2, N);
+    N = fma(-K7 * c, y1, N);
+    const double Dn = fma(y1, fma(-K9, y2, 1.0), K49);
+    f[0] = y2;
+    f[1] = N / Dn;
+  }
+};
+
+// Pressure-relief valve (Sec. 4.3), shared (kappa, delta, beta, r).  While
+// seated (sticking guard) the body is held and the chamber fills.
+struct MPRV {
+  static constexpr int D = 3;
+  static constexpr bool kEvents = true;
+  double q, kappa, delta, beta, r;
+  bool seated;
+  __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
+    q = P[i];
+    kappa = sh[0];
+    delta = sh[1];
+    beta = sh[2];
+    r = sh[3];
+    seated = false;
+  }
+  __device__ void rhs(double, const double *y, double *f) const {
+    if (seated) {
+      f[0] = 0.0;
+      f[1] = 0.0;
+      f[2] = beta * q;
+    } else {
+      f[0] = y[1];
+      f[1] = fma(-kappa, y[1], y[2] - (y[0] + delta));
+      f[2] = beta * fma(-y[0], sqrt(y[2]), q);
+    }
+  }
+};
+
+// One attempted Cash--Karp step: y5 and err = h sum (b5 - b4) k.
+template <class M>
+__device__ __forceinline__ void ck_attempt(const M &m, double t, const double *y, double h,
+                                           double *y5, double *err) {
+  constexpr int D = M::D;
+  double k1[D], k2[D], k3[D], k4[D], k5[D], k6[D], yt[D];
+  m.rhs(t, y, k1);
+#pragma unroll
+  for (int c = 0; c < D; ++c) yt[c] = fma(h, A21 * k1[c], y[c]);
+  m.rhs(fma(C2, h, t), yt, k2);
+#pragma unroll
+  for (int c = 0; c < D; ++c) yt[c] = fma(h, fma(A32, k2[c], A31 * k1[c]), y[c]);
+  m.rhs(fma(C3, h, t), yt, k3);
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    yt[c] = fma(h, fma(A43, k3[c], fma(A42, k2[c], A41 * k1[c])), y[c]);
+  m.rhs(fma(C4, h, t), yt, k4);
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    yt[c] = fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], A51 * k1[c]))), y[c]);
+  m.rhs(t + C5 * h, yt, k5);
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    yt[c] = fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], A61 * k1[c])))),
+                y[c]);
+  m.rhs(fma(C6, h, t), yt, k6);
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    y5[c] = fma(h, fma(B6, k6[c], fma(B4, k4[c], fma(B3, k3[c], B1 * k1[c]))), y[c]);
+    err[c] = h * fma(E6, k6[c], fma(E5, k5[c], fma(E4, k4[c], fma(E3, k3[c], E1 * k1[c]))));
+  }
+}
+
+__device__ __forceinline__ double clampd(double x, double lo, double hi) {
+  return x < lo ? lo : (x > hi ? hi : x);
+}
+
+// Lane-private progress of one system.
+struct Lane {
+  int64_t sys;
+  double t, h, t_ps, ymax, ymin;
+  int64_t n_phases, max_impacts;
+  uint32_t phase, accepted, rejected, evretry, impacts, attempts;
+  int32_t status, ev_iter;
+};
+
+template <class M>
+__device__ __forceinline__ void store_record(const RkckArgs &a, const Lane &L, double v0,
+                                             double v1) {
+  if (a.R <= 0) return;
+  constexpr int F = M::kEvents ? 2 : 1;
+  const int64_t slot = (int64_t)(L.phase % (uint64_t)a.R);
+  a.rec[(slot * F) * a.n + L.sys] = v0;
+  if (F > 1) a.rec[(slot * F + 1) * a.n + L.sys] = v1;
+}
+
+template <class M>
+__device__ __forceinline__ void store_lane(const RkckArgs &a, const Lane &L, const double *y) {
+  constexpr int D = M::D;
+  const int64_t n = a.n, i = L.sys;
+#pragma unroll
+  for (int c = 0; c < D; ++c) a.y[c * n + i] = y[c];
+  a.t[i] = L.t;
+  a.h[i] = L.h;
+  const int64_t att = (int64_t)L.accepted + L.rejected + L.evretry;
+  a.stats[ENS_ST_ACCEPTED * n + i] = L.accepted;
+  a.stats[ENS_ST_REJECTED * n + i] = L.rejected;
+  a.stats[ENS_ST_NRHS * n + i] = 6 * att;
+  a.stats[ENS_ST_IMPACTS * n + i] = L.impacts;
+  a.stats[ENS_ST_PHASES * n + i] = L.phase;
+  a.stats[ENS_ST_EVRETRY * n + i] = L.evretry;
+  a.status[i] = L.status;
+}
+
+// One attempted step of a fixed-length-phase model; returns true when the
+// system is finished.
+template <class M>
+__device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, double *y) {
+  constexpr int D = M::D;
+  double y5[D], err[D];
+  double h_try = L.h;
+  const bool trunc = L.t + h_try >= a.t_phase;
+  if (trunc) h_try = a.t_phase - L.t;
+  ck_attempt(m, L.t, y, h_try, y5, err);
+  L.attempts++;
+  double E = 0.0;
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double sc = fma(a.rtol, fmax(fabs(y[c]), fabs(y5[c])), a.atol);
+    const double r = fabs(err[c]) / sc;
+    finite = finite && isfinite(y5[c]) && isfinite(r);
+    E = r > E ? r : E;
+  }
+  if (!finite) {
+    L.status |= ENS_SYS_NONFINITE;
+    return true;
+  }
+  const double fac = (E == 0.0) ? 5.0 : 0.9 * pow(E, -0.2);
+  if (E > 1.0 && h_try > a.dt_min) {
+    L.rejected++;
+    L.h = clampd(h_try * clampd(fac, 0.2, 1.0), a.dt_min, a.dt_max);
+  } else {
+    if (E > 1.0) L.status |= ENS_SYS_DT_MIN;
+    const double h_next = clampd(h_try * clampd(fac, 0.2, 5.0), a.dt_min, a.dt_max);
+#pragma unroll
+    for (int c = 0; c < D; ++c) y[c] = y5[c];
+    L.accepted++;
+    L.ymax = y[0] > L.ymax ? y[0] : L.ymax;
+    if (trunc) {
+      store_record<M>(a, L, L.ymax, 0.0);
+      L.phase++;
+      L.t = 0.0;
+      L.ymax = -INFINITY;
+      if (L.phase >= L.n_phases) return true;
+    } else {
+      L.t += h_try;
+      L.h = h_next;
+    }
+  }
+  if (a.max_steps > 0 && L.attempts >= a.max_steps) {
+    L.status |= ENS_SYS_MAX_STEPS;
+    return true;
+  }
+  return false;
+}
+
+// One attempted step of the relief valve with events; true when finished.
+__device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, double *y) {
+  constexpr int D = 3;
+  double y5[D], err[D];
+  const double h_try = L.h;
+  ck_attempt(m, L.t, y, h_try, y5, err);
+  L.attempts++;
+  double E = 0.0;
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double sc = fma(a.rtol, fmax(fabs(y[c]), fabs(y5[c])), a.atol);
+    const double r = fabs(err[c]) / sc;
+    finite = finite && isfinite(y5[c]) && isfinite(r);
+    E = r > E ? r : E;
+  }
+  if (!finite) {
+    L.status |= ENS_SYS_NONFINITE;
+    return true;
+  }
+  const double fac = (E == 0.0) ? 5.0 : 0.9 * pow(E, -0.2);
+  bool done = false;
+  if (E > 1.0 && h_try > a.dt_min) {
+    L.rejected++;
+    L.h = clampd(h_try * clampd(fac, 0.2, 1.0), a.dt_min, a.dt_max);
+  } else {
+    if (E > 1.0) L.status |= ENS_SYS_DT_MIN;
+    const double h_next = clampd(h_try * clampd(fac, 0.2, 5.0), a.dt_min, a.dt_max);
+    const double tol = a.event_tol;
+    // event detection: overshoot -> secant retry from the same point
+    double hs = INFINITY;
+    bool over = false;
+    if (!m.seated) {
+      if (y[0] > 0.0 && y5[0] < -tol) {  // impact, y1 decreasing through 0
+        hs = fmin(hs, h_try * y[0] / (y[0] - y5[0]));
+        over = true;
+      }
+      if (y[0] == 0.0 && y5[0] < -tol) {  // rebound swallowed by one step
+        hs = fmin(hs, 0.5 * h_try);
+        over = true;
+      }
+      if (y[1] > 0.0 && y5[1] < -tol) {  // local maximum, y2 decreasing
+        hs = fmin(hs, h_try * y[1] / (y[1] - y5[1]));
+        over = true;
+      }
+    } else {
+      const double g3o = y[2] - m.delta, g3n = y5[2] - m.delta;  // lift-off
+      if (g3o < 0.0 && g3n > tol) {
+        hs = fmin(hs, h_try * (-g3o) / (g3n - g3o));
+        over = true;
+      }
+    }
+    if (over && L.ev_iter < a.max_event_iter) {
+      L.ev_iter++;
+      L.evretry++;
+      L.h = hs;
+    } else {
+      if (over) L.status |= ENS_SYS_EVENT_ITER;
+      L.ev_iter = 0;
+      const double y2o = y[1];
+      const bool was_seated = m.seated;
+#pragma unroll
+      for (int c = 0; c < D; ++c) y[c] = y5[c];
+      L.t += h_try;
+      L.accepted++;
+      L.h = h_next;
+      bool phase_end = false;
+      if (was_seated) {
+        if (y[2] - m.delta >= 0.0) m.seated = false;
+      } else if (y[0] <= 0.0 && y[1] < 0.0) {
+        // located impact: Newtonian restitution (Sec. 4.3)
+        const double v_in = y[1];
+        y[0] = 0.0;
+        y[1] = -m.r * v_in;
+        L.impacts++;
+        if (fabs(v_in) < a.v_stick && y[2] < m.delta) {
+          m.seated = true;
+          y[1] = 0.0;
+          L.status |= ENS_SYS_SEATED;
+        }
+        if (L.max_impacts > 0 && (int64_t)L.impacts >= L.max_impacts) done = true;
+      } else if (y2o > 0.0 && y[1] <= 0.0) {
+        phase_end = true;  // located local maximum: the Poincare point
+      }
+      L.ymax = y[0] > L.ymax ? y[0] : L.ymax;
+      L.ymin = y[0] < L.ymin ? y[0] : L.ymin;
+      if (phase_end) {
+        store_record<MPRV>(a, L, y[0], L.ymin);
+        L.phase++;
+        L.ymax = -INFINITY;
+        L.ymin = INFINITY;
+        L.t_ps = L.t;
+        if (L.phase >= L.n_phases) done = true;
+      } else if (L.t - L.t_ps >= a.t_cap) {
+        store_record<MPRV>(a, L, L.ymax, L.ymin);
+        L.phase++;
+        L.status |= ENS_SYS_SETTLED;
+        done = true;
+      }
+    }
+  }
+  if (!done && a.max_steps > 0 && L.attempts >= a.max_steps) {
+    L.status |= ENS_SYS_MAX_STEPS;
+    done = true;
+  }
+  return done;
+}
+
+template <class M>
+__global__ __launch_bounds__(kMaxBlock) void k_rkck(RkckArgs a) {
+  constexpr int D = M::D;
+  __shared__ EnsDesc sdesc[ENS_MAX_ENSEMBLES];
+  for (int e = threadIdx.x; e < a.n_ens; e += blockDim.x) sdesc[e] = a.desc[e];
+  __syncthreads();
+
+  const int lane = __lane_id();
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  M m;
+  Lane L;
+  double y[D];
+  bool active = false;
+  bool drained = false;
+
+  while (true) {
+    const unsigned long long idle = __ballot(!active);
+    const int n_idle = __popcll(idle);
+    if (!drained && n_idle > 0 && (n_idle >= a.refill || idle == ~0ull)) {
+      const int leader = __ffsll((long long)idle) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)n_idle);
+      base = __shfl(base, leader);
+      if (base + (unsigned long long)n_idle >= (unsigned long long)a.n) drained = true;
+      if (!active) {
+        const unsigned long long me = base + (unsigned long long)__popcll(idle & below);
+        if (me < (unsigned long long)a.n) {
+          const int64_t i = (int64_t)me;
+          int e = 0;
+          while (e + 1 < a.n_ens && i >= sdesc[e].last) ++e;
+          m.init(a.p, a.n, i, sdesc[e].shared);
+#pragma unroll
+          for (int c = 0; c < D; ++c) y[c] = a.y[c * a.n + i];
+          L.sys = i;
+          L.t = a.t[i];
+          L.h = a.h[i];
+          L.t_ps = L.t;
+          L.ymax = -INFINITY;
+          L.ymin = INFINITY;
+          L.n_phases = sdesc[e].n_phases;
+          L.max_impacts = sdesc[e].max_impacts;
+          L.phase = L.accepted = L.rejected = L.evretry = L.impacts = L.attempts = 0;
+          L.status = 0;
+          L.ev_iter = 0;
+          active = true;
+          if (L.n_phases <= 0) {
+            store_lane<M>(a, L, y);
+            active = false;
+          }
+        }
+      }
+    }
+    if (__ballot(active) == 0ull) {
+      if (drained) break;
+      continue;
+    }
+    if (active) {
+      bool done;
+      if constexpr (M::kEvents)
+        done = step_valve(a, m, L, y);
+      else
+        done = step_fixed<M>(a, m, L, y);
+      if (done) {
+        store_lane<M>(a, L, y);
+        active = false;
+      }
+    }
+  }
+}
+
+template <class M>
+hipError_t launch_model(int block, int grid, const RkckArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rkck<M>, dim3(grid), dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class M>
+int max_blocks_model(int block) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rkck<M>, block, 0) != hipSuccess)
+    return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+}  // namespace
+
+hipError_t launch_rkck(int model, int block, int grid, const RkckArgs &a, hipStream_t s) {
+  if (block <= 0 || block > kMaxBlock || block % 64 != 0 || grid <= 0)
+    return hipErrorInvalidConfiguration;
+  switch (model) {
+    case ENS_QUAD: return launch_model<MQuad>(block, grid, a, s);
+    case ENS_LORENZ: return launch_model<MLorenz>(block, grid, a, s);
+    case ENS_KM: return launch_model<MKM>(block, grid, a, s);
+    case ENS_PRV: return launch_model<MPRV>(block, grid, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+int rkck_max_blocks(int model, int block) {
+  if (block <= 0 || block > kMaxBlock || block % 64 != 0) return 0;
+  switch (model) {
+    case ENS_QUAD: return max_blocks_model<MQuad>(block);
+    case ENS_LORENZ: return max_blocks_model<MLorenz>(block);
+    case ENS_KM: return max_blocks_model<MKM>(block);
+    case ENS_PRV: return max_blocks_model<MPRV>(block);
+  }
+  return 0;
+}
+
+}  // namespace ens

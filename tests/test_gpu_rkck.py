@@ -1,0 +1,208 @@
+"""GPU parity of the persistent adaptive Cash--Karp kernel against the oracle,
+plus the properties of the work queue (through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2011_01740_amd import inputs as I
+from tests.parity import CK_ATOL, CK_RTOL, PERTURB, close, per_system, sensitivity_mask
+
+pytestmark = pytest.mark.gpu
+
+SHARED = {0: None, 1: [I.LORENZ_SIGMA, I.LORENZ_BETA], 2: list(I.KM_WATER), 3: list(I.PRV_DEFAULT)}
+
+
+def _ens():
+    import torch
+    from paper_2011_01740_amd import ens
+    assert torch.cuda.is_available()
+    return ens
+
+
+class Res:
+    pass
+
+
+def gpu_ck(model, P, y0, opts, t0=None, h0=None, shared=None, offsets=None, budgets=None,
+           solves=1, **launch):
+    ens = _ens()
+    n = y0.shape[-1]
+    with ens.Ensemble(model, ens.ENS_RKCK45, n, offsets=offsets) as e:
+        e.set_params(P)
+        if shared is not None:
+            for k in range(e.n_ensembles):
+                e.set_shared(k, shared[k] if isinstance(shared[0], (list, tuple, np.ndarray)) else shared)
+        if budgets is not None:
+            for k, (ph, imp) in enumerate(budgets):
+                e.set_budget(k, ph, imp)
+        e.set_state(y0, t0, h0)
+        kw = dict(t_phase=opts.t_phase, dt0=opts.dt0, dt_min=opts.dt_min, dt_max=opts.dt_max,
+                  rtol=opts.rtol, atol=opts.atol, event_tol=opts.event_tol, t_cap=opts.t_cap,
+                  v_stick=opts.v_stick, n_phases=opts.n_phases, n_record=opts.n_record,
+                  max_steps=opts.max_steps, max_event_iter=opts.max_event_iter)
+        kw.update(launch)
+        for _ in range(solves):
+            e.solve(**kw)
+        r = Res()
+        r.y = e.read(ens.ENS_STATE)
+        r.t = e.read(ens.ENS_TIME)
+        r.h = e.read(ens.ENS_H)
+        r.records = e.read(ens.ENS_RECORDS)
+        r.stats = e.read(ens.ENS_STATS)
+        r.status = e.read(ens.ENS_STATUS)
+        r.launch = e.last_launch()
+        r.ms = e.last_kernel_ms()
+        return r
+
+
+def oracle_pair(model, P, sh, y0, opts, nthreads=8):
+    a = O.rkck45(model, P, sh, y0, opts, nthreads=nthreads)
+    b = O.rkck45(model, P, sh, y0 * (1 + PERTURB), opts, nthreads=nthreads)
+    keep = sensitivity_mask([a.y, a.records], [b.y, b.records], 1e-9, 1e-11)
+    return a, keep
+
+
+def check_parity(g, a, keep, min_keep=0.5, step_match=0.99):
+    ok = (per_system(close(g.y, a.y, CK_RTOL, CK_ATOL))
+          & per_system(close(g.records, a.records, CK_RTOL, CK_ATOL)))
+    bad = keep & ~ok
+    assert not bad.any(), np.nonzero(bad)[0][:10]
+    assert keep.mean() >= min_keep, keep.mean()
+    same_steps = (g.stats[O.ST_ACCEPTED] == a.stats[O.ST_ACCEPTED]) & \
+                 (g.stats[O.ST_REJECTED] == a.stats[O.ST_REJECTED])
+    assert same_steps[keep].mean() >= step_match, same_steps[keep].mean()
+    assert np.array_equal(g.stats[O.ST_PHASES], a.stats[O.ST_PHASES])
+    assert np.array_equal(g.status & ~O.SYS_DT_MIN, a.status & ~O.SYS_DT_MIN)
+
+
+def test_quad_adaptive_matches_oracle():
+    P, y0 = I.quad_linspace(1000, 0.1, 1.0)
+    o = O.Opts(t_phase=0.5, n_phases=4, n_record=4)
+    g = gpu_ck(0, P, y0, o)
+    a = O.rkck45(O.QUAD, P, None, y0, o)
+    check_parity(g, a, np.ones(1000, bool), step_match=0.999)
+
+
+def test_km_grid_matches_oracle():
+    P, y0 = I.km_grid(24, 24)
+    o = O.Opts(n_phases=6, n_record=6)
+    g = gpu_ck(2, P, y0, o)
+    a, keep = oracle_pair(O.KM, P, I.KM_WATER, y0, o)
+    check_parity(g, a, keep, min_keep=0.8)
+    assert np.all(g.stats[O.ST_NRHS] == 6 * (g.stats[O.ST_ACCEPTED] + g.stats[O.ST_REJECTED]))
+
+
+def test_prv_matches_oracle():
+    P, y0 = I.prv_linspace(256)
+    o = O.Opts(n_phases=40, n_record=8)
+    g = gpu_ck(3, P, y0, o)
+    a, keep = oracle_pair(O.PRV, P, I.PRV_DEFAULT, y0, o)
+    check_parity(g, a, keep, min_keep=0.5, step_match=0.95)
+    same_imp = g.stats[O.ST_IMPACTS] == a.stats[O.ST_IMPACTS]
+    assert same_imp[keep].all()
+
+
+def test_prv_closed_form_events_on_gpu():
+    """beta = 0 valve: GPU event location agrees with the oracle tightly."""
+    sh = [0.25, 10.0, 0.0, 0.8]
+    P = np.array([[1.0, 2.0]])
+    y0 = np.array([[10.0, 6.0], [0.0, 0.0], [10.5, 10.5]])
+    o = O.Opts(n_phases=6, n_record=6, event_tol=1e-9, t_cap=1e9)
+    g = gpu_ck(3, P, y0, o, shared=sh)
+    a = O.rkck45(O.PRV, P, sh, y0, o)
+    assert np.array_equal(g.stats[O.ST_IMPACTS], a.stats[O.ST_IMPACTS])
+    assert close(g.records, a.records, 1e-9, 1e-9).all()
+    assert close(g.t, a.t, 1e-9, 1e-9).all()
+
+
+def test_resume_is_bit_identical():
+    P, y0 = I.km_grid(8, 8)
+    full = gpu_ck(2, P, y0, O.Opts(n_phases=4, n_record=4))
+    half = gpu_ck(2, P, y0, O.Opts(n_phases=2, n_record=2))
+    rest = gpu_ck(2, P, half.y, O.Opts(n_phases=2, n_record=2), t0=half.t, h0=half.h)
+    assert np.array_equal(full.y, rest.y) and np.array_equal(full.h, rest.h)
+    assert np.array_equal(full.records[2:], rest.records)
+    # consecutive solves on one handle continue from the library-owned state
+    two = gpu_ck(2, P, y0, O.Opts(n_phases=2, n_record=2), solves=2)
+    assert np.array_equal(two.y, full.y)
+
+
+def test_permutation_invariance():
+    P, y0 = I.km_grid(16, 16)
+    o = O.Opts(n_phases=3, n_record=3)
+    g = gpu_ck(2, P, y0, o)
+    perm = np.random.default_rng(5).permutation(P.shape[1])
+    gp = gpu_ck(2, P[:, perm], y0[:, perm], o)
+    assert np.array_equal(gp.y, g.y[:, perm])
+    assert np.array_equal(gp.records, g.records[:, :, perm])
+    assert np.array_equal(gp.stats, g.stats[:, perm])
+
+
+@pytest.mark.parametrize("launch", [dict(refill=64), dict(refill=7, block=64),
+                                    dict(grid=1, block=64), dict(block=128, grid=3)])
+def test_refill_and_grid_invariance(launch):
+    P, y0 = I.prv_linspace(300)
+    o = O.Opts(n_phases=12, n_record=4)
+    ref = gpu_ck(3, P, y0, o)
+    g = gpu_ck(3, P, y0, o, **launch)
+    assert np.array_equal(g.y, ref.y) and np.array_equal(g.records, ref.records)
+    assert np.array_equal(g.stats, ref.stats)
+
+
+def test_graph_replays_match_eager():
+    ens = _ens()
+    P, y0 = I.km_grid(8, 8)
+    o = dict(n_phases=2, n_record=2)
+    eager = gpu_ck(2, P, y0, O.Opts(**o))
+    n = P.shape[1]
+    with ens.Ensemble(ens.ENS_KM, ens.ENS_RKCK45, n) as e:
+        e.set_params(P)
+        for rep in range(3):
+            e.set_state(y0)
+            e.solve(use_graph=1, **o)
+            y = e.read(ens.ENS_STATE)
+            rec = e.read(ens.ENS_RECORDS)
+            assert np.array_equal(y, eager.y), rep
+            assert np.array_equal(rec, eager.records), rep
+
+
+def test_batched_sub_ensembles_equal_separate_launches():
+    """Three valve ensembles with their own q draws and budgets in one
+    graph-captured launch give what three separate launches give."""
+    sizes, budgets = [40, 70, 100], [(30, 30), (20, 20), (10, 10)]
+    Ps, ys = [], []
+    for k, m in enumerate(sizes):
+        P, y0 = I.prv_random(m, seed=3 + k)
+        Ps.append(P)
+        ys.append(y0)
+    P = np.concatenate(Ps, axis=1)
+    y0 = np.concatenate(ys, axis=1)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    o = O.Opts(n_phases=999, n_record=8)
+    g = gpu_ck(3, P, y0, o, offsets=off, budgets=budgets, use_graph=1)
+    for k in range(3):
+        s = gpu_ck(3, Ps[k], ys[k], O.Opts(n_phases=999, n_record=8), budgets=[budgets[k]])
+        sl = slice(off[k], off[k + 1])
+        assert np.array_equal(g.y[:, sl], s.y)
+        assert np.array_equal(g.records[:, :, sl], s.records)
+        assert np.array_equal(g.stats[:, sl], s.stats)
+
+
+def test_status_words():
+    P = np.array([[1.2e5, 1.2e5, 1.2e5], [20e3, 20e3, 20e3]])
+    y0 = np.array([[1.0, np.nan, 1.0], [0.0, 0.0, 0.0]])
+    o = O.Opts(n_phases=5, n_record=1, max_steps=100)
+    g = gpu_ck(2, P, y0, o)
+    a = O.rkck45(O.KM, P, I.KM_WATER, y0, o)
+    assert g.status[0] & O.SYS_MAX_STEPS and g.status[1] & O.SYS_NONFINITE
+    assert np.array_equal(g.status, a.status)
+    o2 = O.Opts(n_phases=1, n_record=1, dt_min=1e-3, dt_max=1e-3, dt0=1e-3)
+    g2 = gpu_ck(2, P[:, :1], y0[:, :1], o2)
+    assert g2.status[0] & O.SYS_DT_MIN
+
+
+def test_zero_phases_and_empty():
+    P, y0 = I.km_grid(2, 2)
+    g = gpu_ck(2, P, y0, O.Opts(n_phases=0, n_record=0))
+    assert np.array_equal(g.y, y0)
+    assert np.all(g.stats == 0)
