@@ -368,8 +368,14 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     return fail(h, ENS_E_INVAL, "ens_solve: adaptive block must be 64, 128, 192 or 256");
   const int refill = o->refill ? o->refill : 1;
   if (refill < 1 || refill > 64) return fail(h, ENS_E_INVAL, "ens_solve: refill must be in [1, 64]");
+  // Keller--Miksis: the fifth-root kernel needs 3 gamma = 21/5 in every
+  // sub-ensemble; otherwise the general-power variant runs
+  int kmodel = h->model;
+  if (h->model == ENS_KM)
+    for (int e = 0; e < h->n_ens; ++e)
+      if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM_GENERAL;
   int grid = o->grid;
-  const int cap = ens::rkck_max_blocks(h->model, block);
+  const int cap = ens::rkck_max_blocks(kmodel, block);
   if (cap <= 0) return fail(h, ENS_E_HIP, "ens_solve: occupancy query failed");
   if (grid <= 0) grid = cap;
   if (grid > cap) return fail(h, ENS_E_INVAL, "ens_solve: grid above resident capacity");
@@ -436,13 +442,13 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
       e = ens::launch_fill_f64(h->d_rec, std::numeric_limits<double>::quiet_NaN(),
                                (int64_t)rec_count, s);
     if (e == hipSuccess && fill_h) e = ens::launch_fill_f64(h->d_h, o->dt0, h->n, s);
-    if (e == hipSuccess && h->n > 0) e = ens::launch_rkck(h->model, block, grid, a, s);
+    if (e == hipSuccess && h->n > 0) e = ens::launch_rkck(kmodel, block, grid, a, s);
     return e;
   };
 
   if (o->use_graph && h->n > 0) {
     const bool same = h->gexec && h->g_block == block && h->g_grid == grid &&
-                      h->g_model == h->model && h->g_fill_h == fill_h &&
+                      h->g_model == kmodel && h->g_fill_h == fill_h &&
                       (!fill_h || h->g_dt0 == o->dt0) &&
                       std::memcmp(&h->g_args, &a, sizeof(a)) == 0;  // a is zero-filled
     if (!same) {
@@ -461,7 +467,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
       std::memcpy(&h->g_args, &a, sizeof(a));
       h->g_block = block;
       h->g_grid = grid;
-      h->g_model = h->model;
+      h->g_model = kmodel;
       h->g_fill_h = fill_h;
       h->g_dt0 = o->dt0;
     }

@@ -46,6 +46,10 @@ struct RkckArgs {
   int32_t max_event_iter;
 };
 
+// Kernel variant of the Keller--Miksis model for a polytropic exponent with
+// 3 gamma != 21/5 (general power through exp/log).
+constexpr int ENS_KM_GENERAL = 100;
+
 // Kernel launchers (stream-ordered; return hipSuccess or the launch error).
 hipError_t launch_rk4(int model, int block, int spl, const double *p, double *y,
                       double *acc, int64_t n, double dt, int64_t nsteps,

@@ -20,6 +20,55 @@
 namespace ens {
 namespace {
 
+// One RK4 step of one Lorenz system in the accumulated, sigma-folded form.
+struct LorenzCoef {
+  double dt, h2, h3, h6, sh, sh2, sh3, sh6, beta;
+};
+
+__device__ __forceinline__ void lorenz_step(double &x, double &y, double &z, double &m,
+                                            double rho, const LorenzCoef &c) {
+  const double x0 = x, y0 = y, z0 = z;
+  double d, ky, kz, ax, ay, az, xs, ys, zs;
+  // stage 1 at (x0, y0, z0)
+  d = y0 - x0;
+  ky = fma(-x0, z0, fma(rho, x0, -y0));
+  kz = fma(x0, y0, -c.beta * z0);
+  ax = fma(c.sh6, d, x0);
+  ay = fma(c.h6, ky, y0);
+  az = fma(c.h6, kz, z0);
+  xs = fma(c.sh2, d, x0);
+  ys = fma(c.h2, ky, y0);
+  zs = fma(c.h2, kz, z0);
+  // stage 2
+  d = ys - xs;
+  ky = fma(-xs, zs, fma(rho, xs, -ys));
+  kz = fma(xs, ys, -c.beta * zs);
+  ax = fma(c.sh3, d, ax);
+  ay = fma(c.h3, ky, ay);
+  az = fma(c.h3, kz, az);
+  xs = fma(c.sh2, d, x0);
+  ys = fma(c.h2, ky, y0);
+  zs = fma(c.h2, kz, z0);
+  // stage 3
+  d = ys - xs;
+  ky = fma(-xs, zs, fma(rho, xs, -ys));
+  kz = fma(xs, ys, -c.beta * zs);
+  ax = fma(c.sh3, d, ax);
+  ay = fma(c.h3, ky, ay);
+  az = fma(c.h3, kz, az);
+  xs = fma(c.sh, d, x0);
+  ys = fma(c.dt, ky, y0);
+  zs = fma(c.dt, kz, z0);
+  // stage 4
+  d = ys - xs;
+  ky = fma(-xs, zs, fma(rho, xs, -ys));
+  kz = fma(xs, ys, -c.beta * zs);
+  x = fma(c.sh6, d, ax);
+  y = fma(c.h6, ky, ay);
+  z = fma(c.h6, kz, az);
+  m = fmax(m, x);
+}
+
 template <int SPL>
 __global__ __launch_bounds__(1024) void k_rk4_lorenz(const double *__restrict__ P,
                                                      double *__restrict__ Y,
@@ -39,52 +88,27 @@ __global__ __launch_bounds__(1024) void k_rk4_lorenz(const double *__restrict__ 
     m[k] = x[k];
   }
   // uniform stage coefficients (scalar registers)
-  const double h2 = 0.5 * dt, h3 = dt / 3.0, h6 = dt / 6.0;
-  const double sh = sigma * dt, sh2 = sigma * h2, sh3 = sigma * h3, sh6 = sigma * h6;
-  for (int64_t s = 0; s < nsteps; ++s) {
+  LorenzCoef c;
+  c.dt = dt;
+  c.h2 = 0.5 * dt;
+  c.h3 = dt / 3.0;
+  c.h6 = dt / 6.0;
+  c.sh = sigma * dt;
+  c.sh2 = sigma * c.h2;
+  c.sh3 = sigma * c.h3;
+  c.sh6 = sigma * c.h6;
+  c.beta = beta;
+  // two steps per iteration: the loop-carried state then needs no copies
+  for (int64_t s = 0; s + 1 < nsteps; s += 2) {
 #pragma unroll
     for (int k = 0; k < SPL; ++k) {
-      const double x0 = x[k], y0 = y[k], z0 = z[k], rho = r[k];
-      double d, ky, kz, ax, ay, az, xs, ys, zs;
-      // stage 1 at (x0, y0, z0)
-      d = y0 - x0;
-      ky = fma(-x0, z0, fma(rho, x0, -y0));
-      kz = fma(x0, y0, -beta * z0);
-      ax = fma(sh6, d, x0);
-      ay = fma(h6, ky, y0);
-      az = fma(h6, kz, z0);
-      xs = fma(sh2, d, x0);
-      ys = fma(h2, ky, y0);
-      zs = fma(h2, kz, z0);
-      // stage 2
-      d = ys - xs;
-      ky = fma(-xs, zs, fma(rho, xs, -ys));
-      kz = fma(xs, ys, -beta * zs);
-      ax = fma(sh3, d, ax);
-      ay = fma(h3, ky, ay);
-      az = fma(h3, kz, az);
-      xs = fma(sh2, d, x0);
-      ys = fma(h2, ky, y0);
-      zs = fma(h2, kz, z0);
-      // stage 3
-      d = ys - xs;
-      ky = fma(-xs, zs, fma(rho, xs, -ys));
-      kz = fma(xs, ys, -beta * zs);
-      ax = fma(sh3, d, ax);
-      ay = fma(h3, ky, ay);
-      az = fma(h3, kz, az);
-      xs = fma(sh, d, x0);
-      ys = fma(dt, ky, y0);
-      zs = fma(dt, kz, z0);
-      // stage 4
-      d = ys - xs;
-      ky = fma(-xs, zs, fma(rho, xs, -ys));
-      kz = fma(xs, ys, -beta * zs);
-      x[k] = fma(sh6, d, ax);
-      y[k] = fma(h6, ky, ay);
-      z[k] = fma(h6, kz, az);
-      m[k] = x[k] > m[k] ? x[k] : m[k];
+      lorenz_step(x[k], y[k], z[k], m[k], r[k], c);
+      lorenz_step(x[k], y[k], z[k], m[k], r[k], c);
     }
+  }
+  if (nsteps & 1) {
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) lorenz_step(x[k], y[k], z[k], m[k], r[k], c);
   }
 #pragma unroll
   for (int k = 0; k < SPL; ++k) {

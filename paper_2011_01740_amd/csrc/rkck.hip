@@ -43,6 +43,31 @@ constexpr double B1 = 37.0 / 378.0, B3 = 250.0 / 621.0, B4 = 125.0 / 594.0,
 constexpr double E1 = B1 - 2825.0 / 27648.0, E3 = B3 - 18575.0 / 48384.0,
                  E4 = B4 - 13525.0 / 55296.0, E5 = -277.0 / 14336.0, E6 = B6 - 1.0 / 4.0;
 
+// x^(-1/5) for x in [1e-30, 1e30]: an FP32 estimate from the hardware
+// base-2 logarithm and exponential (relative error ~1e-7), then two Newton
+// steps for r^5 x = 1 in FP64, r <- r (6 - x r^5) / 5; each step squares the
+// relative error (times 3), so two steps reach rounding level.  ~25 VALU
+// instead of the ~200 of a general pow.
+__device__ __forceinline__ double rfifth(double x) {
+  double r = (double)exp2f(-0.2f * log2f((float)x));
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double r2 = r * r;
+    const double r5 = r2 * r2 * r;
+    r = (0.2 * r) * fma(-x, r5, 6.0);
+  }
+  return r;
+}
+
+// Step-size factor 0.9 E^(-1/5), clamped to [0.2, 5] (E = 0 gives 5).  Outside
+// [1e-4, 4e3] the clamp decides, so the root is only taken where FP32 holds E.
+__device__ __forceinline__ double step_factor(double E) {
+  if (!(E >= 1e-4)) return 5.0;
+  if (E > 4e3) return 0.2;
+  const double f = 0.9 * rfifth(E);
+  return f < 0.2 ? 0.2 : (f > 5.0 ? 5.0 : f);
+}
+
 // ------------------------------------------------------------------ models
 // Each model: D, lane constants set at refill, rhs(t, y, f).
 
@@ -78,6 +103,11 @@ struct MLorenz {  // Sec. 4.1
 //   N = (K0 + K1 y2) y1^-K10 - (K2 + K5 s)(1 + K9 y2) - (K3 + K4 y2)/y1
 //       - (1 - K9 y2 / 3) 1.5 y2^2 - K7 c y1,       s, c = sin, cos(2 pi tau)
 //   D = y1 (1 - K9 y2) + K4 K9.
+// One division serves both 1/y1 and 1/D: q = 1 / (y1 D), 1/y1 = D q,
+// N / D = N y1 q.  With FIFTHS (the host checked 3 gamma = 21/5, the
+// polytropic exponent of air) the gas term is (1/y1)^4 y1^(-1/5) with the
+// Newton fifth root; otherwise exp(-K10 log y1).
+template <bool FIFTHS>
 struct MKM {
   static constexpr int D = 2;
   static constexpr bool kEvents = false;
@@ -103,8 +133,16 @@ struct MKM {
   }
   __device__ void rhs(double tau, const double *y, double *f) const {
     const double y1 = y[0], y2 = y[1];
-    const double r1 = 1.0 / y1;
-    const double gas = exp(-K10 * log(y1));       // (1/y1)^(3 gamma)
+    const double Dn = fma(y1, fma(-K9, y2, 1.0), K49);
+    const double qd = 1.0 / (y1 * Dn);
+    const double r1 = Dn * qd;                    // 1 / y1
+    double gas;                                   // (1/y1)^K10
+    if constexpr (FIFTHS) {
+      const double r2 = r1 * r1;
+      gas = (r2 * r2) * rfifth(y1);
+    } else {
+      gas = exp(-K10 * log(y1));
+    }
     double s, c;
     sincospi(2.0 * tau, &s, &c);
     const double u = fma(K9, y2, 1.0);
@@ -113,9 +151,8 @@ struct MKM {
     N = fma(-fma(K4, y2, K3), r1, N);
     N = fma(-(fma(-K9 / 3.0, y2, 1.0) * 1.5) * y2, y2, N);
     N = fma(-K7 * c, y1, N);
-    const double Dn = fma(y1, fma(-K9, y2, 1.0), K49);
     f[0] = y2;
-    f[1] = N / Dn;
+    f[1] = N * (y1 * qd);
   }
 };
 
@@ -245,13 +282,13 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
     L.status |= ENS_SYS_NONFINITE;
     return true;
   }
-  const double fac = (E == 0.0) ? 5.0 : 0.9 * pow(E, -0.2);
+  const double fac = step_factor(E);
   if (E > 1.0 && h_try > a.dt_min) {
     L.rejected++;
-    L.h = clampd(h_try * clampd(fac, 0.2, 1.0), a.dt_min, a.dt_max);
+    L.h = clampd(h_try * fmin(fac, 1.0), a.dt_min, a.dt_max);
   } else {
     if (E > 1.0) L.status |= ENS_SYS_DT_MIN;
-    const double h_next = clampd(h_try * clampd(fac, 0.2, 5.0), a.dt_min, a.dt_max);
+    const double h_next = clampd(h_try * fac, a.dt_min, a.dt_max);
 #pragma unroll
     for (int c = 0; c < D; ++c) y[c] = y5[c];
     L.accepted++;
@@ -294,14 +331,14 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
     L.status |= ENS_SYS_NONFINITE;
     return true;
   }
-  const double fac = (E == 0.0) ? 5.0 : 0.9 * pow(E, -0.2);
+  const double fac = step_factor(E);
   bool done = false;
   if (E > 1.0 && h_try > a.dt_min) {
     L.rejected++;
-    L.h = clampd(h_try * clampd(fac, 0.2, 1.0), a.dt_min, a.dt_max);
+    L.h = clampd(h_try * fmin(fac, 1.0), a.dt_min, a.dt_max);
   } else {
     if (E > 1.0) L.status |= ENS_SYS_DT_MIN;
-    const double h_next = clampd(h_try * clampd(fac, 0.2, 5.0), a.dt_min, a.dt_max);
+    const double h_next = clampd(h_try * fac, a.dt_min, a.dt_max);
     const double tol = a.event_tol;
     // event detection: overshoot -> secant retry from the same point
     double hs = INFINITY;
@@ -383,7 +420,7 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
 }
 
 template <class M>
-__global__ __launch_bounds__(kMaxBlock) void k_rkck(RkckArgs a) {
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_rkck(RkckArgs a) {
   constexpr int D = M::D;
   __shared__ EnsDesc sdesc[ENS_MAX_ENSEMBLES];
   for (int e = threadIdx.x; e < a.n_ens; e += blockDim.x) sdesc[e] = a.desc[e];
@@ -478,7 +515,8 @@ hipError_t launch_rkck(int model, int block, int grid, const RkckArgs &a, hipStr
   switch (model) {
     case ENS_QUAD: return launch_model<MQuad>(block, grid, a, s);
     case ENS_LORENZ: return launch_model<MLorenz>(block, grid, a, s);
-    case ENS_KM: return launch_model<MKM>(block, grid, a, s);
+    case ENS_KM: return launch_model<MKM<true>>(block, grid, a, s);
+    case ENS_KM_GENERAL: return launch_model<MKM<false>>(block, grid, a, s);
     case ENS_PRV: return launch_model<MPRV>(block, grid, a, s);
   }
   return hipErrorInvalidValue;
@@ -489,7 +527,8 @@ int rkck_max_blocks(int model, int block) {
   switch (model) {
     case ENS_QUAD: return max_blocks_model<MQuad>(block);
     case ENS_LORENZ: return max_blocks_model<MLorenz>(block);
-    case ENS_KM: return max_blocks_model<MKM>(block);
+    case ENS_KM: return max_blocks_model<MKM<true>>(block);
+    case ENS_KM_GENERAL: return max_blocks_model<MKM<false>>(block);
     case ENS_PRV: return max_blocks_model<MPRV>(block);
   }
   return 0;

@@ -114,7 +114,8 @@ class Ensemble:
                  offsets: Optional[Sequence[int]] = None, device: int = 0, stream=None):
         L = load()
         self.model, self.solver, self.n = int(model), int(solver), int(n)
-        self.D, self.P, self.S, self.F = MODEL_DIMS[self.model]
+        # an unknown model is passed through: ens_create rejects it
+        self.D, self.P, self.S, self.F = MODEL_DIMS.get(self.model, (0, 0, 0, 0))
         self.device = int(device)
         if stream is None:
             import torch

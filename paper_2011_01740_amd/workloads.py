@@ -1,0 +1,123 @@
+"""The paper's ensemble workloads, set up through the libens binding.
+
+Each function builds the seeded synthetic inputs (``inputs``), hands them to
+the library as device tensors, runs the solve on the current torch stream and
+returns the results with the measured kernel time.  Nothing here computes any
+part of the method.
+
+* ``lorenz``     -- Lorenz sweep with classic RK4 (Sec. 4.1)
+* ``km_sweep``   -- Keller--Miksis (p_A, f) grid, adaptive Cash--Karp, one
+                    record per acoustic cycle (Sec. 4.2)
+* ``prv_batched``-- several relief-valve ensembles with their own q draws
+                    and phase/impact budgets, solved in one graph-captured
+                    persistent launch (Sec. 4.3)
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import ens
+from . import inputs as I
+
+
+@dataclass
+class Result:
+    y: np.ndarray
+    t: Optional[np.ndarray] = None
+    h: Optional[np.ndarray] = None
+    acc: Optional[np.ndarray] = None
+    records: Optional[np.ndarray] = None
+    stats: Optional[np.ndarray] = None
+    status: Optional[np.ndarray] = None
+    kernel_ms: float = 0.0
+    wall_s: float = 0.0
+    launch: Dict[str, int] = field(default_factory=dict)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def lorenz(n: int, n_steps: int, seed: Optional[int] = 1, dt: float = 0.01, **launch) -> Result:
+    """Lorenz RK4 sweep: seeded random p and IC (seed) or the linspace sweep (seed None)."""
+    import torch
+    P, y0 = I.lorenz_random(n, seed=seed) if seed is not None else I.lorenz_linspace(n)
+    with ens.Ensemble(ens.ENS_LORENZ, ens.ENS_RK4, n) as e:
+        e.set_params(_dev(P))
+        e.set_state(_dev(y0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e.solve(dt=dt, n_steps=n_steps, **launch)
+        ms = e.last_kernel_ms()
+        wall = time.perf_counter() - t0
+        return Result(y=e.read(ens.ENS_STATE), acc=e.read(ens.ENS_ACC), kernel_ms=ms,
+                      wall_s=wall, launch=e.last_launch())
+
+
+def _adaptive(model, P, y0, opts, offsets=None, shared=None, budgets=None, read_records=True):
+    import torch
+    n = y0.shape[-1]
+    with ens.Ensemble(model, ens.ENS_RKCK45, n, offsets=offsets) as e:
+        e.set_params(_dev(P))
+        if shared is not None:
+            for k, sh in enumerate(shared):
+                e.set_shared(k, sh)
+        if budgets is not None:
+            for k, (ph, imp) in enumerate(budgets):
+                e.set_budget(k, ph, imp)
+        e.set_state(_dev(y0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e.solve(opts)
+        ms = e.last_kernel_ms()
+        wall = time.perf_counter() - t0
+        return Result(y=e.read(ens.ENS_STATE), t=e.read(ens.ENS_TIME), h=e.read(ens.ENS_H),
+                      records=e.read(ens.ENS_RECORDS) if read_records else None,
+                      stats=e.read(ens.ENS_STATS), status=e.read(ens.ENS_STATUS),
+                      kernel_ms=ms, wall_s=wall, launch=e.last_launch())
+
+
+def km_sweep(n_pa: int, n_f: int, n_phases: int = 1024, n_record: Optional[int] = None,
+             shared: Sequence[float] = I.KM_WATER, rtol: float = 1e-10, atol: float = 1e-10,
+             P: Optional[np.ndarray] = None, **launch) -> Result:
+    """Keller--Miksis sweep over an (n_pa x n_f) grid (p_A linear in [0.2, 1.2]
+    bar, f geometric in [20 kHz, 1 MHz]), IC (1, 0), one y1max record per
+    acoustic cycle (the last n_record cycles).  P overrides the grid."""
+    if P is None:
+        P, y0 = I.km_grid(n_pa, n_f)
+    else:
+        y0 = np.vstack([np.ones(P.shape[1]), np.zeros(P.shape[1])])
+    R = n_phases if n_record is None else n_record
+    o = ens.default_opts(n_phases=n_phases, n_record=R, rtol=rtol, atol=atol, **launch)
+    return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)])
+
+
+PRV_ENSEMBLES: Tuple[Tuple[int, int, int], ...] = ((1 << 15, 100000, 3), (1 << 16, 10000, 4),
+                                                   (1 << 17, 1000, 5))
+
+
+def prv_inputs(ensembles=PRV_ENSEMBLES):
+    Ps, ys = [], []
+    for m, _, seed in ensembles:
+        P, y0 = I.prv_random(m, seed=seed)
+        Ps.append(P)
+        ys.append(y0)
+    off = np.concatenate([[0], np.cumsum([m for m, _, _ in ensembles])]).astype(np.int64)
+    return np.concatenate(Ps, axis=1), np.concatenate(ys, axis=1), off
+
+
+def prv_batched(ensembles=PRV_ENSEMBLES, n_record: int = 32, use_graph: int = 1,
+                **launch) -> Result:
+    """Relief-valve ensembles (size, budget K, seed): each system runs until K
+    Poincare phases or K impacts, whichever comes first; the last n_record
+    phases (y1max, y1min) are kept.  One persistent launch for all."""
+    P, y0, off = prv_inputs(ensembles)
+    budgets = [(K, K) for _, K, _ in ensembles]
+    o = ens.default_opts(n_phases=max(K for _, K, _ in ensembles), n_record=n_record,
+                         use_graph=use_graph, **launch)
+    return _adaptive(ens.ENS_PRV, P, y0, o, offsets=off, budgets=budgets)
