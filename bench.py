@@ -74,9 +74,58 @@ def cpu_baseline(n_total, nsteps, dt, seed, target_s=12.0):
             "sample": f"first {m} of the {n_total} systems, all {nsteps} steps, {el:.1f} s"}
 
 
+def run_case(case, args):
+    """Single launches for counter runs: a 1 GiB device copy (the scale of the
+    FETCH_SIZE / WRITE_SIZE counters), a Keller--Miksis grid, or the valve
+    batch with reduced budgets.  Prints one JSON line."""
+    import torch
+
+    from paper_2011_01740_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    if case == "copy":
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.fill_(0.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"case": "copy", "bytes_read": a.numel() * 8,
+                          "bytes_written": a.numel() * 8}), flush=True)
+    elif case == "km":
+        r = W.km_sweep(args.km_grid, args.km_grid, n_phases=args.km_phases)
+        steps = int(r.stats[0].sum() + r.stats[1].sum())
+        print(json.dumps({"case": "km", "grid": args.km_grid, "phases": args.km_phases,
+                          "kernel_ms": r.kernel_ms, "attempted_steps": steps,
+                          "steps_per_s": steps / r.kernel_ms * 1e3, "launch": r.launch}),
+              flush=True)
+    elif case == "prv":
+        ensm = tuple((m, max(1, K // args.prv_div), sd) for m, K, sd in W.PRV_ENSEMBLES)
+        r = W.prv_batched(ensm)
+        steps = int(r.stats[0].sum() + r.stats[1].sum() + r.stats[5].sum())
+        print(json.dumps({"case": "prv", "budget_divisor": args.prv_div,
+                          "kernel_ms": r.kernel_ms, "attempted_steps": steps,
+                          "steps_per_s": steps / r.kernel_ms * 1e3, "launch": r.launch}),
+              flush=True)
+    else:
+        r = W.lorenz(args.n, args.n_steps, block=args.block, spl=args.spl)
+        print(json.dumps({"case": "lorenz", "n": args.n, "n_steps": args.n_steps,
+                          "kernel_ms": r.kernel_ms,
+                          "system_steps_per_s": args.n * args.n_steps / r.kernel_ms * 1e3}),
+              flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--case", choices=["bench", "lorenz", "km", "prv", "copy"], default="bench",
+                    help="bench: the benchmark line; others: one launch for counter runs")
+    ap.add_argument("--km-grid", type=int, default=512)
+    ap.add_argument("--km-phases", type=int, default=16)
+    ap.add_argument("--prv-div", type=int, default=100)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 23)
@@ -92,6 +141,8 @@ def main(argv=None):
               "(the systems are independent; see the sharding notes in DESIGN.md).",
               file=sys.stderr)
         return 2
+    if args.case != "bench":
+        return run_case(args.case, args)
 
     import torch
 

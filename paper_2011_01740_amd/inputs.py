@@ -32,6 +32,7 @@ __all__ = [
     "km_grid", "km_axes",
     "prv_random", "prv_linspace",
     "quad_linspace",
+    "mlp_init",
 ]
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
@@ -155,3 +156,16 @@ def prv_linspace(n: int, lo: float = 0.2, hi: float = 10.0):
     y0[1] = 0.0
     y0[2] = 10.2
     return q, y0
+
+
+def mlp_init(seed: int = 4, dims=(2, 256, 256, 256, 64)):
+    """Initial surrogate weights: He-uniform U[-sqrt(6/fan_in), sqrt(6/fan_in)]
+    per weight matrix (shape (out, in), row-major), zero biases, packed as
+    W1, b1, W2, b2, ...; float64 (both implementations round as they need)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(dims) - 1):
+        lim = (6.0 / dims[i]) ** 0.5
+        parts.append(rng.uniform(-lim, lim, size=(dims[i + 1], dims[i])).ravel())
+        parts.append(np.zeros(dims[i + 1]))
+    return np.concatenate(parts)
