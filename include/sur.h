@@ -1,0 +1,118 @@
+/*
+ * sur.h -- C ABI of the surrogate part of libens: a small multilayer
+ * perceptron that predicts the Keller--Miksis response from the drive
+ * parameters, trained and evaluated on the GPU with BF16 matrix-core kernels
+ * (FP32 accumulation), used to screen large (p_A, f) sweeps so that only the
+ * points it flags or is unsure about are re-solved by the FP64 integrator.
+ *
+ * The paper (Nagy, Plavecz, Hegedus, arXiv:2011.01740) has no learned
+ * component.  What the network predicts is the paper's quantity: the maximum
+ * bubble radius y1max per acoustic cycle, recorded after every successful
+ * step without dense output, over the converged cycles of a frequency sweep
+ * (Sec. 4.2).  Architecture, loss, optimiser and screening rule are this
+ * library's definitions:
+ *   - network 2 -> 256 -> 256 -> 256 -> 64, GELU (exact erf form) after each
+ *     hidden layer, linear output; parameters packed W1, b1, W2, b2, W3, b3,
+ *     W4, b4, each W row-major with shape (out, in), z = a W^T + b
+ *     (148,800 parameters);
+ *   - input: (p_A, ln f) mapped linearly to [-1, 1] with the bounds given to
+ *     sur_set_norm; output: the 64 values ln y1max of the last 64 cycles,
+ *     standardised per output with the mean / std given to sur_set_norm;
+ *   - loss: mean squared error over batch and outputs; Adam on FP32 master
+ *     weights; the layer-1 product (K = 2) runs in FP32 on the vector unit,
+ *     every other product takes BF16 operands (round to nearest even) with
+ *     FP32 accumulation;
+ *   - screening: label = [max_j y1max_j >= 2] from the de-standardised
+ *     prediction; a point is re-solved if |max_j ln y1max_j - ln 2| < margin,
+ *     or if the predicted spread max_j - min_j exceeds `spread` while
+ *     |max_j - ln 2| < flag_margin.
+ *
+ * Conventions are those of ens.h: functions return ENS_OK or a negative
+ * ens_status; arrays tagged with `where` are host (ENS_HOST) or device
+ * (ENS_DEVICE) memory on the handle's device; work is ordered on the
+ * handle's stream; host outputs are complete when the call returns.
+ */
+#ifndef LIBENS_SUR_H_
+#define LIBENS_SUR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ens.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sur_ctx *sur_t;
+
+#define SUR_N_PARAMS 148800
+#define SUR_IN 2
+#define SUR_HIDDEN 256
+#define SUR_OUT 64
+
+/* Creates a surrogate on `device`, enqueuing on `hip_stream` (NULL: null
+ * stream).  max_batch (a positive multiple of 64, <= 65536) bounds the batch
+ * of sur_train_step / sur_gradients.  Parameters start at zero; call
+ * sur_set_params.  Errors: ENS_E_INVAL, ENS_E_NOMEM, ENS_E_HIP. */
+int sur_create(int32_t device, void *hip_stream, int64_t max_batch, sur_t *out);
+int sur_destroy(sur_t s);
+const char *sur_last_error(sur_t s);
+
+/* FP32 master parameters := flat (host, SUR_N_PARAMS doubles, rounded to
+ * FP32); the BF16 copies are refreshed and the Adam state and step count are
+ * reset.  sur_get_params copies the FP32 master parameters out as doubles. */
+int sur_set_params(sur_t s, const double *flat);
+int sur_get_params(sur_t s, double *flat);
+
+/* Input bounds (in_lo, in_hi: p_A [Pa] and ln f) and output standardisation
+ * (out_mean, out_std: SUR_OUT values each, std > 0).  Host arrays. */
+int sur_set_norm(sur_t s, const double *in_lo, const double *in_hi,
+                 const double *out_mean, const double *out_std);
+
+/* Training inputs from a Keller--Miksis sweep: params [2][n] (P_A1, f1), and
+ * records: the last SUR_OUT cycle maxima y1max as a [SUR_OUT][n] double array
+ * (consecutive record slots).  Writes x [n][2] (normalised inputs) and
+ * y [n][SUR_OUT] (standardised ln y1max) as float, all device pointers.
+ * Uses the bounds and standardisation set by sur_set_norm. */
+int sur_build_dataset(sur_t s, const double *params, const double *records, int64_t n,
+                      float *x, float *y);
+
+/* Adam hyper-parameters (defaults lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8). */
+int sur_set_adam(sur_t s, double lr, double beta1, double beta2, double eps);
+
+/* One training step on a batch: forward, loss, backward, Adam.  x [m][2],
+ * target [m][SUR_OUT] float (normalised / standardised), m a positive
+ * multiple of 64 <= max_batch.  If loss is not NULL it receives the batch
+ * loss (a float; host or device per `where`, which also tags x and target). */
+int sur_train_step(sur_t s, const float *x, const float *target, int64_t m,
+                   float *loss, int32_t where);
+
+/* Loss and gradients of one batch without an update (for checking): grads
+ * receives SUR_N_PARAMS floats in the parameter packing. */
+int sur_gradients(sur_t s, const float *x, const float *target, int64_t m, float *grads,
+                  float *loss, int32_t where);
+
+/* Network output (standardised) for m inputs x [m][2] -> out [m][SUR_OUT]. */
+int sur_forward(sur_t s, const float *x, int64_t m, float *out, int32_t where);
+
+typedef struct {
+  double margin;       /* unsure band on max_j ln y1max around ln 2          */
+  double spread;       /* flag: predicted max_j - min_j above this ...       */
+  double flag_margin;  /* ... and |max_j ln y1max - ln 2| below this         */
+} sur_screen_opts;
+
+/* Screens n sweep points params [2][n] (P_A1, f1; double).  Device outputs:
+ * label [n] int8 (1: max y1max >= 2), resolve [n] uint8, pred_max [n] float
+ * (predicted max_j ln y1max), resolve_idx [n] int64 receiving the indices of
+ * the points to re-solve in ascending order; *n_resolve (host) their count.
+ * Any output pointer except n_resolve may be NULL.  All array pointers are
+ * device memory. */
+int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *opts,
+               int8_t *label, uint8_t *resolve, float *pred_max, int64_t *resolve_idx,
+               int64_t *n_resolve);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBENS_SUR_H_ */

@@ -1,0 +1,875 @@
+// Surrogate network kernels (BF16 matrix cores, FP32 accumulation) and the
+// C ABI declared in include/sur.h.
+//
+// Every product of the network has the form
+//     C[r][c] = sum_k X[r][k] * Y[c][k]
+// with X and Y row-major BF16 and the reduction index k contiguous, so one
+// wave tile (64 x 64 outputs, 4 x 4 v_mfma_f32_16x16x32_bf16 accumulators)
+// serves the three uses, given the right operands:
+//   forward      Z = A W^T       X = A  [batch][in],   Y = W   [out][in]
+//   data grad    dA = dZ W       X = dZ [batch][out],  Y = W^T [in][out]
+//   weight grad  dW = dZ^T A     X = dZ^T [out][batch], Y = A^T [in][batch]
+// The forward epilogue therefore also writes each activation transposed, the
+// backward epilogue each gradient transposed, and the optimiser refreshes
+// both W and W^T in BF16.  Operands are read as 16-byte vectors straight
+// from global memory (the weights stay in L2); weight gradients are split
+// over the batch and the partial sums reduced in a fixed order, so every
+// result is deterministic.
+//
+// MFMA 16x16x32 BF16 operand layout (lane l, 64 lanes): A fragment = row
+// (l mod 16), k = 8 (l / 16) + 0..7; B fragment = column (l mod 16), same k;
+// accumulator element q = row 4 (l / 16) + q, column (l mod 16).
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sur.h"
+#include "ens_internal.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int kIn = SUR_IN, kH = SUR_HIDDEN, kOut = SUR_OUT;
+// packed parameter offsets: W1, b1, W2, b2, W3, b3, W4, b4
+constexpr int64_t oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH,
+                  oW3 = ob2 + kH, ob3 = oW3 + kH * kH, oW4 = ob3 + kH, ob4 = oW4 + kOut * kH,
+                  kNP = ob4 + kOut;
+static_assert(kNP == SUR_N_PARAMS, "parameter count");
+
+__device__ __forceinline__ float gelu_f(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+  const float pdf = expf(-0.5f * z * z) * 0.39894228040143268f;
+  return fmaf(z, pdf, cdf);
+}
+
+// ---------------------------------------------------------------- GEMM tile
+__device__ __forceinline__ void mma_tile(const bf16 *__restrict__ X, int64_t ldx,
+                                         const bf16 *__restrict__ Y, int64_t ldy, int64_t r0,
+                                         int64_t c0, int64_t kb, int64_t ke, f32x4 acc[4][4]) {
+  const int l = threadIdx.x & 63;
+  const int64_t lr = l & 15, lk = (l >> 4) * 8;
+  const bf16 *xp = X + (r0 + lr) * ldx + lk;
+  const bf16 *yp = Y + (c0 + lr) * ldy + lk;
+  for (int64_t k = kb; k < ke; k += 32) {
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8 *)(xp + 16 * i * ldx + k);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8 *)(yp + 16 * j * ldy + k);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+enum Epi { EPI_FWD_GELU = 0, EPI_FWD_LINEAR = 1, EPI_BWD_GELU = 2, EPI_PARTIAL = 3,
+           EPI_FWD_GELU_ACT = 4 };
+
+struct GemmArgs {
+  const bf16 *X;
+  int64_t ldx;
+  const bf16 *Y;
+  int64_t ldy;
+  int64_t R, C, K;       // C[R][C], reduction length K (split over gridDim.z)
+  const float *bias;     // [C]
+  const float *zprev;    // [R][C] pre-activation for the GELU derivative
+  float *out_f32;        // [R][C], or [split][R][C] partial sums
+  bf16 *out_bf16;        // [R][C]
+  bf16 *out_bf16T;       // [C][R]
+};
+
+// One wave per 64 x 64 output tile; grid (C/64, R/64, split).
+template <int EPI>
+__global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
+  const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+  const int64_t kchunk = g.K / gridDim.z;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  mma_tile(g.X, g.ldx, g.Y, g.ldy, r0, c0, kb, kb + kchunk, acc);
+
+  const int l = threadIdx.x & 63;
+  const int64_t lc = l & 15, lrow = (l >> 4) * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t c = c0 + 16 * j + lc;
+      const int64_t rb = r0 + 16 * i + lrow;
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = acc[i][j][q];
+      if (EPI == EPI_PARTIAL) {
+        float *o = g.out_f32 + (int64_t)blockIdx.z * g.R * g.C;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[(rb + q) * g.C + c] = v[q];
+        continue;
+      }
+      if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR || EPI == EPI_FWD_GELU_ACT) {
+        const float b = g.bias[c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += b;
+      }
+      if (EPI == EPI_FWD_LINEAR) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g.out_f32[(rb + q) * g.C + c] = v[q];
+        continue;
+      }
+      float a[4];
+      if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_GELU_ACT) {
+        if (EPI == EPI_FWD_GELU) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) g.out_f32[(rb + q) * g.C + c] = v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = gelu_f(v[q]);
+      } else {  // EPI_BWD_GELU
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = v[q] * gelu_grad_f(g.zprev[(rb + q) * g.C + c]);
+        if (g.out_f32) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) g.out_f32[(rb + q) * g.C + c] = a[q];
+        }
+      }
+      if (g.out_bf16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g.out_bf16[(rb + q) * g.C + c] = (bf16)a[q];
+      }
+      if (g.out_bf16T) {
+        bf16x4 t = {(bf16)a[0], (bf16)a[1], (bf16)a[2], (bf16)a[3]};
+        *(bf16x4 *)(g.out_bf16T + c * g.R + rb) = t;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- small kernels
+// Layer 1 (K = 2) on the vector unit: z = x W1^T + b1, a = GELU(z).
+__global__ void k_layer1(const float *__restrict__ x, const float *__restrict__ P, int64_t m,
+                         float *z, bf16 *a, bf16 *aT) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * kH) return;
+  const int64_t r = idx / kH, n = idx % kH;
+  const float v = fmaf(x[2 * r + 1], P[oW1 + 2 * n + 1], fmaf(x[2 * r], P[oW1 + 2 * n], P[ob1 + n]));
+  if (z) z[idx] = v;
+  const bf16 g = (bf16)gelu_f(v);
+  a[idx] = g;
+  if (aT) aT[n * m + r] = g;
+}
+
+// dZ of the output layer: 2 (out - t) / (m * 64), with per-block partial sums
+// of (out - t)^2 for the loss.
+__global__ __launch_bounds__(256) void k_loss_grad(const float *__restrict__ out,
+                                                   const float *__restrict__ t, int64_t m,
+                                                   float *dz, bf16 *dzb, bf16 *dzbT,
+                                                   float *partial) {
+  __shared__ float red[256];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float sq = 0.f;
+  if (idx < m * kOut) {
+    const float d = out[idx] - t[idx];
+    sq = d * d;
+    const float g = 2.0f * d / (float)(m * kOut);
+    dz[idx] = g;
+    dzb[idx] = (bf16)g;
+    const int64_t r = idx / kOut, c = idx % kOut;
+    dzbT[c * m + r] = (bf16)g;
+  }
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// loss = sum(partial) / count, fixed order (one block)
+__global__ __launch_bounds__(256) void k_loss_final(const float *partial, int64_t nb,
+                                                    float count, float *loss) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int64_t i = threadIdx.x; i < nb; i += 256) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0] / count;
+}
+
+// Column sums (bias gradients): out[c] = sum_r dz[r][c], one block per column.
+__global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ dz, int64_t R,
+                                                int64_t C, float *out) {
+  __shared__ float red[256];
+  const int64_t c = blockIdx.x;
+  float s = 0.f;
+  for (int64_t r = threadIdx.x; r < R; r += 256) s += dz[r * C + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// Layer-1 weight and bias gradients on the vector unit, one block per unit n.
+__global__ __launch_bounds__(256) void k_layer1_grad(const float *__restrict__ dz1,
+                                                     const float *__restrict__ x, int64_t m,
+                                                     float *G) {
+  __shared__ float r0[256], r1[256], r2[256];
+  const int n = blockIdx.x;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  for (int64_t r = threadIdx.x; r < m; r += 256) {
+    const float d = dz1[r * kH + n];
+    s0 = fmaf(d, x[2 * r], s0);
+    s1 = fmaf(d, x[2 * r + 1], s1);
+    s2 += d;
+  }
+  r0[threadIdx.x] = s0;
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      r0[threadIdx.x] += r0[threadIdx.x + k];
+      r1[threadIdx.x] += r1[threadIdx.x + k];
+      r2[threadIdx.x] += r2[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    G[oW1 + 2 * n] = r0[0];
+    G[oW1 + 2 * n + 1] = r1[0];
+    G[ob1 + n] = r2[0];
+  }
+}
+
+// dW = sum over the split partials in order.
+__global__ void k_reduce_split(const float *__restrict__ part, int split, int64_t count,
+                               float *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float s = 0.f;
+  for (int k = 0; k < split; ++k) s += part[k * count + i];
+  out[i] = s;
+}
+
+// Adam on the FP32 master parameters (Kingma and Ba, 2015).
+__global__ void k_adam(float *__restrict__ P, const float *__restrict__ G, float *__restrict__ Mm,
+                       float *__restrict__ V, int64_t count, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float g = G[i];
+  const float m = fmaf(b1, Mm[i], (1.0f - b1) * g);
+  const float v = fmaf(b2, V[i], (1.0f - b2) * g * g);
+  Mm[i] = m;
+  V[i] = v;
+  P[i] -= lr * (m * c1) / (sqrtf(v * c2) + eps);
+}
+
+// BF16 copies of W2, W3, W4 and their transposes from the master weights.
+__global__ void k_refresh(const float *__restrict__ P, bf16 *W2, bf16 *W2T, bf16 *W3, bf16 *W3T,
+                          bf16 *W4, bf16 *W4T) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kH * kH) {
+    const int64_t o = i / kH, in = i % kH;
+    const bf16 a = (bf16)P[oW2 + i], b = (bf16)P[oW3 + i];
+    W2[i] = a;
+    W2T[in * kH + o] = a;
+    W3[i] = b;
+    W3T[in * kH + o] = b;
+  }
+  if (i < kOut * kH) {
+    const int64_t o = i / kH, in = i % kH;
+    const bf16 c = (bf16)P[oW4 + i];
+    W4[i] = c;
+    W4T[in * kOut + o] = c;
+  }
+}
+
+// Sweep inputs -> normalised network inputs: (p_A, ln f) mapped to [-1, 1].
+__global__ void k_inputs(const double *__restrict__ prm, int64_t n, int64_t first, int64_t m,
+                         double lo0, double sc0, double lo1, double sc1, float *x) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  const int64_t i = first + r;
+  if (i < n) {
+    x[2 * r] = (float)(fma(prm[i] - lo0, sc0, -1.0));
+    x[2 * r + 1] = (float)(fma(log(prm[n + i]) - lo1, sc1, -1.0));
+  } else {
+    x[2 * r] = 0.f;
+    x[2 * r + 1] = 0.f;
+  }
+}
+
+// Standardised targets: y[i][j] = (ln rec[j][i] - mean_j) / std_j.
+__global__ void k_targets(const double *__restrict__ rec, int64_t n, const double *mean,
+                          const double *stdv, float *y) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * kOut) return;
+  const int64_t i = idx / kOut, j = idx % kOut;
+  y[idx] = (float)((log(rec[j * n + i]) - mean[j]) / stdv[j]);
+}
+
+// Screening epilogue: de-standardise, label, unsure / flag, re-solve mask.
+__global__ void k_screen_epi(const float *__restrict__ out, int64_t first, int64_t m, int64_t n,
+                             const float *mean, const float *stdv, float margin, float spread,
+                             float flag_margin, int8_t *label, uint8_t *resolve, float *pmax) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m || first + r >= n) return;
+  float mx = -INFINITY, mn = INFINITY;
+  for (int j = 0; j < kOut; ++j) {
+    const float v = fmaf(out[r * kOut + j], stdv[j], mean[j]);
+    mx = fmaxf(mx, v);
+    mn = fminf(mn, v);
+  }
+  const float ln2 = 0.69314718055994531f;
+  const float d = fabsf(mx - ln2);
+  const bool unsure = d < margin;
+  const bool flag = (mx - mn > spread) && d < flag_margin;
+  const int64_t i = first + r;
+  if (label) label[i] = mx >= ln2 ? 1 : 0;
+  if (resolve) resolve[i] = (unsure || flag) ? 1 : 0;
+  if (pmax) pmax[i] = mx;
+}
+
+// Deterministic compaction of the re-solve mask: block counts, one-block
+// exclusive scan, ordered write.
+constexpr int kScanBlock = 1024;
+__global__ __launch_bounds__(kScanBlock) void k_count(const uint8_t *__restrict__ f, int64_t n,
+                                                      int64_t *counts) {
+  __shared__ int red[kScanBlock];
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  red[threadIdx.x] = (i < n && f[i]) ? 1 : 0;
+  __syncthreads();
+  for (int s = kScanBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan(int64_t *counts, int64_t nb, int64_t *total) {
+  __shared__ int64_t part[kScanBlock];
+  const int64_t per = (nb + kScanBlock - 1) / kScanBlock;
+  const int64_t b = threadIdx.x * per, e = b + per < nb ? b + per : nb;
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += counts[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int k = 0; k < kScanBlock; ++k) {
+      const int64_t v = part[k];
+      part[k] = run;
+      run += v;
+    }
+    *total = run;
+  }
+  __syncthreads();
+  int64_t run = part[threadIdx.x];
+  for (int64_t i = b; i < e; ++i) {
+    const int64_t v = counts[i];
+    counts[i] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_write_idx(const uint8_t *__restrict__ f, int64_t n,
+                                                          const int64_t *offs, int64_t *idx) {
+  __shared__ int pre[kScanBlock];
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  const int v = (i < n && f[i]) ? 1 : 0;
+  pre[threadIdx.x] = v;
+  __syncthreads();
+  // inclusive Hillis--Steele scan over the block
+  for (int s = 1; s < kScanBlock; s <<= 1) {
+    const int add = threadIdx.x >= s ? pre[threadIdx.x - s] : 0;
+    __syncthreads();
+    pre[threadIdx.x] += add;
+    __syncthreads();
+  }
+  if (v) idx[offs[blockIdx.x] + pre[threadIdx.x] - 1] = i;
+}
+
+}  // namespace
+
+// ======================================================================== API
+
+struct sur_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t max_batch = 0;
+  std::string err;
+  double lr = 1e-3, b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  int64_t t = 0;
+  double in_lo[2] = {0, 0}, in_hi[2] = {1, 1};
+  double out_mean[kOut], out_std[kOut];
+  bool have_norm = false;
+  // parameters and optimiser state
+  float *P = nullptr, *G = nullptr, *Mm = nullptr, *V = nullptr;
+  bf16 *W2 = nullptr, *W2T = nullptr, *W3 = nullptr, *W3T = nullptr, *W4 = nullptr,
+       *W4T = nullptr;
+  float *d_mean = nullptr, *d_std = nullptr;
+  double *d_dmean = nullptr, *d_dstd = nullptr;
+  // activations of one batch
+  float *x = nullptr, *tgt = nullptr, *z1 = nullptr, *z2 = nullptr, *z3 = nullptr, *out = nullptr;
+  bf16 *a1 = nullptr, *a1T = nullptr, *a2 = nullptr, *a2T = nullptr, *a3 = nullptr, *a3T = nullptr;
+  float *dz4 = nullptr, *dz3 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
+  bf16 *dz4b = nullptr, *dz4bT = nullptr, *dz3b = nullptr, *dz3bT = nullptr, *dz2b = nullptr,
+       *dz2bT = nullptr;
+  float *part = nullptr;      // split-K partial weight gradients
+  float *lpart = nullptr;     // loss partials
+  float *loss = nullptr;      // device scalar
+  int64_t *scan = nullptr;    // compaction scratch
+  int64_t scan_cap = 0;
+};
+
+namespace {
+
+constexpr int kSplit = 8;  // largest batch split of the weight-gradient products
+
+// Batch split of a weight-gradient product: every chunk must hold a multiple
+// of 32 rows (one MFMA reduction step); m is a multiple of 64.
+int wgrad_split(int64_t m) { return m % (32 * 8) == 0 ? 8 : (m % (32 * 4) == 0 ? 4 : 2); }
+
+thread_local std::string g_serr;
+
+int sfail(sur_ctx *s, int code, const std::string &m) {
+  g_serr = m;
+  if (s) s->err = m;
+  return code;
+}
+
+#define SUR_HIP(ctx, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return sfail((ctx), e_ == hipErrorOutOfMemory ? ENS_E_NOMEM : ENS_E_HIP,          \
+                   std::string(#call) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int d) {
+    if (hipGetDevice(&prev) == hipSuccess) (void)hipSetDevice(d);
+  }
+  ~DevGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <class T>
+hipError_t alloc(T **p, int64_t count) {
+  return hipMalloc((void **)p, (size_t)(count > 0 ? count : 1) * sizeof(T));
+}
+
+unsigned nblk(int64_t count, int b) { return (unsigned)((count + b - 1) / b); }
+
+template <int EPI>
+hipError_t gemm(hipStream_t st, const GemmArgs &g, int split = 1) {
+  dim3 grid((unsigned)(g.C / 64), (unsigned)(g.R / 64), (unsigned)split);
+  hipLaunchKernelGGL(k_gemm<EPI>, grid, dim3(64), 0, st, g);
+  return hipGetLastError();
+}
+
+GemmArgs gargs(const bf16 *X, int64_t ldx, const bf16 *Y, int64_t ldy, int64_t R, int64_t C,
+               int64_t K) {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.X = X;
+  g.ldx = ldx;
+  g.Y = Y;
+  g.ldy = ldy;
+  g.R = R;
+  g.C = C;
+  g.K = K;
+  return g;
+}
+
+// Forward pass of one batch of m rows (m % 64 == 0) from s->x.  train: keep
+// the pre-activations and transposed activations for the backward pass.
+hipError_t forward_batch(sur_ctx *s, int64_t m, bool train, float *out) {
+  hipStream_t st = s->stream;
+  hipLaunchKernelGGL(k_layer1, dim3(nblk(m * kH, 256)), dim3(256), 0, st, s->x, s->P, m,
+                     train ? s->z1 : nullptr, s->a1, train ? s->a1T : nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  GemmArgs g = gargs(s->a1, kH, s->W2, kH, m, kH, kH);
+  g.bias = s->P + ob2;
+  g.out_f32 = train ? s->z2 : nullptr;
+  g.out_bf16 = s->a2;
+  g.out_bf16T = train ? s->a2T : nullptr;
+  e = train ? gemm<EPI_FWD_GELU>(st, g) : gemm<EPI_FWD_GELU_ACT>(st, g);
+  if (e != hipSuccess) return e;
+  g = gargs(s->a2, kH, s->W3, kH, m, kH, kH);
+  g.bias = s->P + ob3;
+  g.out_f32 = train ? s->z3 : nullptr;
+  g.out_bf16 = s->a3;
+  g.out_bf16T = train ? s->a3T : nullptr;
+  e = train ? gemm<EPI_FWD_GELU>(st, g) : gemm<EPI_FWD_GELU_ACT>(st, g);
+  if (e != hipSuccess) return e;
+  g = gargs(s->a3, kH, s->W4, kH, m, kOut, kH);
+  g.bias = s->P + ob4;
+  g.out_f32 = out;
+  return gemm<EPI_FWD_LINEAR>(st, g);
+}
+
+// Loss, gradients of all parameters into s->G (batch already in s->x, s->tgt).
+hipError_t backward_batch(sur_ctx *s, int64_t m) {
+  hipStream_t st = s->stream;
+  hipError_t e;
+  const int split = wgrad_split(m);
+  const unsigned nb = nblk(m * kOut, 256);
+  hipLaunchKernelGGL(k_loss_grad, dim3(nb), dim3(256), 0, st, s->out, s->tgt, m, s->dz4,
+                     s->dz4b, s->dz4bT, s->lpart);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, s->lpart, (int64_t)nb,
+                     (float)(m * kOut), s->loss);
+  // output layer
+  hipLaunchKernelGGL(k_colsum, dim3(kOut), dim3(256), 0, st, s->dz4, m, (int64_t)kOut,
+                     s->G + ob4);
+  GemmArgs g = gargs(s->dz4bT, m, s->a3T, m, kOut, kH, m);
+  g.out_f32 = s->part;
+  if ((e = gemm<EPI_PARTIAL>(st, g, split)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_split, dim3(nblk(kOut * kH, 256)), dim3(256), 0, st, s->part,
+                     split, (int64_t)kOut * kH, s->G + oW4);
+  g = gargs(s->dz4b, kOut, s->W4T, kOut, m, kH, kOut);
+  g.zprev = s->z3;
+  g.out_f32 = s->dz3;
+  g.out_bf16 = s->dz3b;
+  g.out_bf16T = s->dz3bT;
+  if ((e = gemm<EPI_BWD_GELU>(st, g)) != hipSuccess) return e;
+  // layer 3
+  hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, s->dz3, m, (int64_t)kH, s->G + ob3);
+  g = gargs(s->dz3bT, m, s->a2T, m, kH, kH, m);
+  g.out_f32 = s->part;
+  if ((e = gemm<EPI_PARTIAL>(st, g, split)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_split, dim3(nblk(kH * kH, 256)), dim3(256), 0, st, s->part,
+                     split, (int64_t)kH * kH, s->G + oW3);
+  g = gargs(s->dz3b, kH, s->W3T, kH, m, kH, kH);
+  g.zprev = s->z2;
+  g.out_f32 = s->dz2;
+  g.out_bf16 = s->dz2b;
+  g.out_bf16T = s->dz2bT;
+  if ((e = gemm<EPI_BWD_GELU>(st, g)) != hipSuccess) return e;
+  // layer 2
+  hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, s->dz2, m, (int64_t)kH, s->G + ob2);
+  g = gargs(s->dz2bT, m, s->a1T, m, kH, kH, m);
+  g.out_f32 = s->part;
+  if ((e = gemm<EPI_PARTIAL>(st, g, split)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_split, dim3(nblk(kH * kH, 256)), dim3(256), 0, st, s->part,
+                     split, (int64_t)kH * kH, s->G + oW2);
+  g = gargs(s->dz2b, kH, s->W2T, kH, m, kH, kH);
+  g.zprev = s->z1;
+  g.out_f32 = s->dz1;
+  if ((e = gemm<EPI_BWD_GELU>(st, g)) != hipSuccess) return e;
+  // layer 1 (vector unit)
+  hipLaunchKernelGGL(k_layer1_grad, dim3(kH), dim3(256), 0, st, s->dz1, s->x, m, s->G);
+  return hipGetLastError();
+}
+
+hipError_t refresh(sur_ctx *s) {
+  hipLaunchKernelGGL(k_refresh, dim3(nblk(kH * kH, 256)), dim3(256), 0, s->stream, s->P, s->W2,
+                     s->W2T, s->W3, s->W3T, s->W4, s->W4T);
+  return hipGetLastError();
+}
+
+int check_batch(sur_ctx *s, int64_t m) {
+  if (m <= 0 || m % 64 || m > s->max_batch)
+    return sfail(s, ENS_E_INVAL, "batch must be a positive multiple of 64 <= max_batch");
+  return ENS_OK;
+}
+
+int load_batch(sur_ctx *s, const float *x, const float *tgt, int64_t m, int where) {
+  const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  SUR_HIP(s, hipMemcpyAsync(s->x, x, (size_t)m * kIn * sizeof(float), k, s->stream));
+  if (tgt)
+    SUR_HIP(s, hipMemcpyAsync(s->tgt, tgt, (size_t)m * kOut * sizeof(float), k, s->stream));
+  return ENS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sur_last_error(sur_t s) { return s ? s->err.c_str() : g_serr.c_str(); }
+
+int sur_create(int32_t device, void *hip_stream, int64_t max_batch, sur_t *out) {
+  if (!out) return sfail(nullptr, ENS_E_INVAL, "sur_create: out is NULL");
+  *out = nullptr;
+  if (max_batch <= 0 || max_batch % 64 || max_batch > 65536)
+    return sfail(nullptr, ENS_E_INVAL, "sur_create: max_batch must be a multiple of 64 in [64, 65536]");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return sfail(nullptr, ENS_E_HIP, "sur_create: no HIP device");
+  if (device < 0 || device >= ndev) return sfail(nullptr, ENS_E_INVAL, "sur_create: bad device");
+  sur_ctx *s = new (std::nothrow) sur_ctx();
+  if (!s) return sfail(nullptr, ENS_E_NOMEM, "sur_create: out of host memory");
+  s->device = device;
+  s->stream = (hipStream_t)hip_stream;
+  s->max_batch = max_batch;
+  for (int j = 0; j < kOut; ++j) {
+    s->out_mean[j] = 0.0;
+    s->out_std[j] = 1.0;
+  }
+  DevGuard dg(device);
+  const int64_t B = max_batch;
+  hipError_t e = hipSuccess;
+#define A(ptr, cnt) \
+  if (e == hipSuccess) e = alloc(&s->ptr, (cnt))
+  A(P, kNP); A(G, kNP); A(Mm, kNP); A(V, kNP);
+  A(W2, kH * kH); A(W2T, kH * kH); A(W3, kH * kH); A(W3T, kH * kH);
+  A(W4, kOut * kH); A(W4T, kOut * kH);
+  A(d_mean, kOut); A(d_std, kOut); A(d_dmean, kOut); A(d_dstd, kOut);
+  A(x, B * kIn); A(tgt, B * kOut); A(z1, B * kH); A(z2, B * kH); A(z3, B * kH); A(out, B * kOut);
+  A(a1, B * kH); A(a1T, B * kH); A(a2, B * kH); A(a2T, B * kH); A(a3, B * kH); A(a3T, B * kH);
+  A(dz4, B * kOut); A(dz3, B * kH); A(dz2, B * kH); A(dz1, B * kH);
+  A(dz4b, B * kOut); A(dz4bT, B * kOut); A(dz3b, B * kH); A(dz3bT, B * kH);
+  A(dz2b, B * kH); A(dz2bT, B * kH);
+  A(part, (int64_t)kSplit * kH * kH); A(lpart, nblk(B * kOut, 256)); A(loss, 1);
+#undef A
+  if (e == hipSuccess) e = hipMemsetAsync(s->P, 0, kNP * sizeof(float), s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->Mm, 0, kNP * sizeof(float), s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->V, 0, kNP * sizeof(float), s->stream);
+  if (e == hipSuccess) e = refresh(s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    int code = sfail(nullptr, e == hipErrorOutOfMemory ? ENS_E_NOMEM : ENS_E_HIP,
+                     std::string("sur_create: ") + hipGetErrorString(e));
+    sur_destroy(s);
+    return code;
+  }
+  *out = s;
+  return ENS_OK;
+}
+
+int sur_destroy(sur_t s) {
+  if (!s) return ENS_OK;
+  DevGuard dg(s->device);
+  (void)hipStreamSynchronize(s->stream);
+  void *ptrs[] = {s->P, s->G, s->Mm, s->V, s->W2, s->W2T, s->W3, s->W3T, s->W4, s->W4T,
+                  s->d_mean, s->d_std, s->d_dmean, s->d_dstd, s->x, s->tgt, s->z1, s->z2,
+                  s->z3, s->out, s->a1, s->a1T, s->a2, s->a2T, s->a3, s->a3T, s->dz4, s->dz3,
+                  s->dz2, s->dz1, s->dz4b, s->dz4bT, s->dz3b, s->dz3bT, s->dz2b, s->dz2bT,
+                  s->part, s->lpart, s->loss, s->scan};
+  for (void *p : ptrs) (void)hipFree(p);
+  delete s;
+  return ENS_OK;
+}
+
+int sur_set_params(sur_t s, const double *flat) {
+  if (!s || !flat) return sfail(s, ENS_E_INVAL, "sur_set_params: NULL argument");
+  std::vector<float> f(kNP);
+  for (int64_t i = 0; i < kNP; ++i) {
+    if (!std::isfinite(flat[i])) return sfail(s, ENS_E_INVAL, "sur_set_params: non-finite value");
+    f[i] = (float)flat[i];
+  }
+  DevGuard dg(s->device);
+  SUR_HIP(s, hipMemcpyAsync(s->P, f.data(), kNP * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  SUR_HIP(s, hipMemsetAsync(s->Mm, 0, kNP * sizeof(float), s->stream));
+  SUR_HIP(s, hipMemsetAsync(s->V, 0, kNP * sizeof(float), s->stream));
+  SUR_HIP(s, refresh(s));
+  SUR_HIP(s, hipStreamSynchronize(s->stream));
+  s->t = 0;
+  return ENS_OK;
+}
+
+int sur_get_params(sur_t s, double *flat) {
+  if (!s || !flat) return sfail(s, ENS_E_INVAL, "sur_get_params: NULL argument");
+  std::vector<float> f(kNP);
+  DevGuard dg(s->device);
+  SUR_HIP(s, hipMemcpyAsync(f.data(), s->P, kNP * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+  SUR_HIP(s, hipStreamSynchronize(s->stream));
+  for (int64_t i = 0; i < kNP; ++i) flat[i] = f[i];
+  return ENS_OK;
+}
+
+int sur_set_norm(sur_t s, const double *in_lo, const double *in_hi, const double *out_mean,
+                 const double *out_std) {
+  if (!s || !in_lo || !in_hi || !out_mean || !out_std)
+    return sfail(s, ENS_E_INVAL, "sur_set_norm: NULL argument");
+  for (int i = 0; i < 2; ++i)
+    if (!(in_hi[i] > in_lo[i]) || !std::isfinite(in_lo[i]) || !std::isfinite(in_hi[i]))
+      return sfail(s, ENS_E_INVAL, "sur_set_norm: need finite in_lo < in_hi");
+  for (int j = 0; j < kOut; ++j)
+    if (!(out_std[j] > 0.0) || !std::isfinite(out_mean[j]) || !std::isfinite(out_std[j]))
+      return sfail(s, ENS_E_INVAL, "sur_set_norm: need finite mean and std > 0");
+  std::vector<float> m(kOut), sd(kOut);
+  for (int i = 0; i < 2; ++i) {
+    s->in_lo[i] = in_lo[i];
+    s->in_hi[i] = in_hi[i];
+  }
+  for (int j = 0; j < kOut; ++j) {
+    s->out_mean[j] = out_mean[j];
+    s->out_std[j] = out_std[j];
+    m[j] = (float)out_mean[j];
+    sd[j] = (float)out_std[j];
+  }
+  DevGuard dg(s->device);
+  SUR_HIP(s, hipMemcpyAsync(s->d_mean, m.data(), kOut * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  SUR_HIP(s, hipMemcpyAsync(s->d_std, sd.data(), kOut * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  SUR_HIP(s, hipMemcpyAsync(s->d_dmean, s->out_mean, kOut * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  SUR_HIP(s, hipMemcpyAsync(s->d_dstd, s->out_std, kOut * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  SUR_HIP(s, hipStreamSynchronize(s->stream));
+  s->have_norm = true;
+  return ENS_OK;
+}
+
+int sur_build_dataset(sur_t s, const double *params, const double *records, int64_t n, float *x,
+                      float *y) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_build_dataset: NULL handle");
+  if (!s->have_norm) return sfail(s, ENS_E_ORDER, "sur_build_dataset: call sur_set_norm first");
+  if (n < 0 || (n > 0 && (!params || !records || !x || !y)))
+    return sfail(s, ENS_E_INVAL, "sur_build_dataset: bad arguments");
+  if (n == 0) return ENS_OK;
+  DevGuard dg(s->device);
+  const double sc0 = 2.0 / (s->in_hi[0] - s->in_lo[0]), sc1 = 2.0 / (s->in_hi[1] - s->in_lo[1]);
+  hipLaunchKernelGGL(k_inputs, dim3(nblk(n, 256)), dim3(256), 0, s->stream, params, n, (int64_t)0,
+                     n, s->in_lo[0], sc0, s->in_lo[1], sc1, x);
+  SUR_HIP(s, hipGetLastError());
+  hipLaunchKernelGGL(k_targets, dim3(nblk(n * kOut, 256)), dim3(256), 0, s->stream, records, n,
+                     s->d_dmean, s->d_dstd, y);
+  SUR_HIP(s, hipGetLastError());
+  SUR_HIP(s, hipStreamSynchronize(s->stream));
+  return ENS_OK;
+}
+
+int sur_set_adam(sur_t s, double lr, double beta1, double beta2, double eps) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_set_adam: NULL handle");
+  if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return sfail(s, ENS_E_INVAL, "sur_set_adam: bad hyper-parameters");
+  s->lr = lr;
+  s->b1 = beta1;
+  s->b2 = beta2;
+  s->eps = eps;
+  return ENS_OK;
+}
+
+int sur_gradients(sur_t s, const float *x, const float *target, int64_t m, float *grads,
+                  float *loss, int32_t where) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_gradients: NULL handle");
+  if (int rc = check_batch(s, m)) return rc;
+  if (!x || !target) return sfail(s, ENS_E_INVAL, "sur_gradients: NULL input");
+  DevGuard dg(s->device);
+  if (int rc = load_batch(s, x, target, m, where)) return rc;
+  SUR_HIP(s, forward_batch(s, m, true, s->out));
+  SUR_HIP(s, backward_batch(s, m));
+  const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (grads) SUR_HIP(s, hipMemcpyAsync(grads, s->G, kNP * sizeof(float), k, s->stream));
+  if (loss) SUR_HIP(s, hipMemcpyAsync(loss, s->loss, sizeof(float), k, s->stream));
+  if (where == ENS_HOST) SUR_HIP(s, hipStreamSynchronize(s->stream));
+  return ENS_OK;
+}
+
+int sur_train_step(sur_t s, const float *x, const float *target, int64_t m, float *loss,
+                   int32_t where) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_train_step: NULL handle");
+  if (int rc = check_batch(s, m)) return rc;
+  if (!x || !target) return sfail(s, ENS_E_INVAL, "sur_train_step: NULL input");
+  DevGuard dg(s->device);
+  if (int rc = load_batch(s, x, target, m, where)) return rc;
+  SUR_HIP(s, forward_batch(s, m, true, s->out));
+  SUR_HIP(s, backward_batch(s, m));
+  s->t += 1;
+  const float c1 = (float)(1.0 / (1.0 - std::pow(s->b1, (double)s->t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow(s->b2, (double)s->t)));
+  hipLaunchKernelGGL(k_adam, dim3(nblk(kNP, 256)), dim3(256), 0, s->stream, s->P, s->G, s->Mm,
+                     s->V, kNP, (float)s->lr, (float)s->b1, (float)s->b2, (float)s->eps, c1, c2);
+  SUR_HIP(s, hipGetLastError());
+  SUR_HIP(s, refresh(s));
+  if (loss) {
+    const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    SUR_HIP(s, hipMemcpyAsync(loss, s->loss, sizeof(float), k, s->stream));
+    if (where == ENS_HOST) SUR_HIP(s, hipStreamSynchronize(s->stream));
+  }
+  return ENS_OK;
+}
+
+int sur_forward(sur_t s, const float *x, int64_t m, float *out, int32_t where) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_forward: NULL handle");
+  if (m < 0 || (m > 0 && (!x || !out))) return sfail(s, ENS_E_INVAL, "sur_forward: bad arguments");
+  DevGuard dg(s->device);
+  const hipMemcpyKind kin = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const hipMemcpyKind kout = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  for (int64_t first = 0; first < m; first += s->max_batch) {
+    const int64_t rows = m - first < s->max_batch ? m - first : s->max_batch;
+    const int64_t padded = (rows + 63) / 64 * 64;
+    if (padded > rows)
+      SUR_HIP(s, hipMemsetAsync(s->x + rows * kIn, 0, (padded - rows) * kIn * sizeof(float), s->stream));
+    SUR_HIP(s, hipMemcpyAsync(s->x, x + first * kIn, rows * kIn * sizeof(float), kin, s->stream));
+    SUR_HIP(s, forward_batch(s, padded, false, s->out));
+    SUR_HIP(s, hipMemcpyAsync(out + first * kOut, s->out, rows * kOut * sizeof(float), kout, s->stream));
+  }
+  if (where == ENS_HOST) SUR_HIP(s, hipStreamSynchronize(s->stream));
+  return ENS_OK;
+}
+
+int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *o, int8_t *label,
+               uint8_t *resolve, float *pred_max, int64_t *resolve_idx, int64_t *n_resolve) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_screen: NULL handle");
+  if (!o || !n_resolve || n < 0 || (n > 0 && !params))
+    return sfail(s, ENS_E_INVAL, "sur_screen: bad arguments");
+  if (resolve_idx && !resolve)
+    return sfail(s, ENS_E_INVAL, "sur_screen: resolve_idx needs the resolve mask");
+  if (!s->have_norm) return sfail(s, ENS_E_ORDER, "sur_screen: call sur_set_norm first");
+  if (!(o->margin >= 0) || !(o->spread >= 0) || !(o->flag_margin >= 0))
+    return sfail(s, ENS_E_INVAL, "sur_screen: margins must be >= 0");
+  *n_resolve = 0;
+  if (n == 0) return ENS_OK;
+  DevGuard dg(s->device);
+  const double sc0 = 2.0 / (s->in_hi[0] - s->in_lo[0]), sc1 = 2.0 / (s->in_hi[1] - s->in_lo[1]);
+  for (int64_t first = 0; first < n; first += s->max_batch) {
+    const int64_t rows = n - first < s->max_batch ? n - first : s->max_batch;
+    const int64_t padded = (rows + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_inputs, dim3(nblk(padded, 256)), dim3(256), 0, s->stream, params, n,
+                       first, padded, s->in_lo[0], sc0, s->in_lo[1], sc1, s->x);
+    SUR_HIP(s, hipGetLastError());
+    SUR_HIP(s, forward_batch(s, padded, false, s->out));
+    hipLaunchKernelGGL(k_screen_epi, dim3(nblk(padded, 256)), dim3(256), 0, s->stream, s->out,
+                       first, padded, n, s->d_mean, s->d_std, (float)o->margin, (float)o->spread,
+                       (float)o->flag_margin, label, resolve, pred_max);
+    SUR_HIP(s, hipGetLastError());
+  }
+  if (resolve) {
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb + 1 > s->scan_cap) {
+      (void)hipFree(s->scan);
+      s->scan = nullptr;
+      s->scan_cap = 0;
+      SUR_HIP(s, hipMalloc((void **)&s->scan, (size_t)(nb + 1) * sizeof(int64_t)));
+      s->scan_cap = nb + 1;
+    }
+    hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(kScanBlock), 0, s->stream, resolve, n,
+                       s->scan);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s->stream, s->scan, nb,
+                       s->scan + nb);
+    if (resolve_idx)
+      hipLaunchKernelGGL(k_write_idx, dim3((unsigned)nb), dim3(kScanBlock), 0, s->stream,
+                         resolve, n, s->scan, resolve_idx);
+    SUR_HIP(s, hipGetLastError());
+    SUR_HIP(s, hipMemcpyAsync(n_resolve, s->scan + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
+                              s->stream));
+  }
+  SUR_HIP(s, hipStreamSynchronize(s->stream));
+  return ENS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+"""GPU surrogate kernels (BF16 MFMA, FP32 accumulation) against the NumPy
+oracle evaluated with the same BF16 rounding points.
+
+Tolerances.  Both sides round the same operands to BF16; they differ in the
+accumulation (FP32 on the GPU, FP64 in the oracle) and in the FP32 versus FP64
+GELU, which occasionally moves a value across a BF16 rounding boundary (one
+BF16 unit, 2^-8 relative).  Per tensor the relative Frobenius error is held to
+2e-3 and every element to 2e-2 of the tensor's largest magnitude.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_2011_01740_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL_NORM, TOL_ELEM = 2e-3, 2e-2
+
+
+def _sur():
+    import torch
+    from paper_2011_01740_amd import sur
+    assert torch.cuda.is_available()
+    return sur
+
+
+def _data(m, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1, 1, size=(m, 2)).astype(np.float32)
+    t = rng.normal(size=(m, 64)).astype(np.float32)
+    return x, t
+
+
+def _close(g, o, name):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    rel = np.linalg.norm(g - o) / max(np.linalg.norm(o), 1e-30)
+    el = np.abs(g - o).max() / max(np.abs(o).max(), 1e-30)
+    assert rel <= TOL_NORM and el <= TOL_ELEM, (name, rel, el)
+    return rel
+
+
+def _f32_params(seed):
+    return I.mlp_init(seed).astype(np.float32).astype(np.float64)
+
+
+def test_forward_matches_oracle():
+    sur = _sur()
+    flat = _f32_params(4)
+    x, _ = _data(320, 1)
+    with sur.Surrogate(max_batch=512) as s:
+        s.set_params(flat)
+        out = s.forward(x)
+    ref, _ = M.forward(M.unpack(flat), x.astype(np.float64), bf16=True)
+    _close(out, ref, "output")
+
+
+@pytest.mark.parametrize("m", [64, 128, 4096])
+def test_gradients_match_oracle(m):
+    sur = _sur()
+    flat = _f32_params(5)
+    x, t = _data(m, 2)
+    with sur.Surrogate(max_batch=4096) as s:
+        s.set_params(flat)
+        g, loss = s.gradients(x, t)
+        g2, loss2 = s.gradients(x, t)
+    assert np.array_equal(g, g2) and loss == loss2          # deterministic
+    ps = M.unpack(flat)
+    out, cache = M.forward(ps, x.astype(np.float64), bf16=True)
+    ref = M.backward(ps, cache, out, t.astype(np.float64), bf16=True)
+    assert loss == pytest.approx(M.mse(out, t), rel=1e-4)
+    gs = M.unpack(g.astype(np.float64))
+    names = ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"]
+    for name, gg, rr in zip(names, gs, ref):
+        _close(gg, rr, name)
+
+
+def test_adam_step_matches_formula():
+    sur = _sur()
+    flat = _f32_params(6)
+    x, t = _data(256, 3)
+    with sur.Surrogate(max_batch=256) as s:
+        s.set_params(flat)
+        s.set_adam(lr=1e-3)
+        g, _ = s.gradients(x, t)
+        s.train_step(x, t)
+        p1 = s.get_params()
+    ps = M.unpack(flat)
+    zeros = [np.zeros_like(p) for p in ps]
+    want, _, _ = M.adam_step(ps, M.unpack(g.astype(np.float64)), zeros, zeros, t=1, lr=1e-3)
+    want = M.pack(want)
+    assert np.allclose(p1, want, rtol=1e-6, atol=1e-7)
+
+
+def test_training_reduces_loss_on_a_smooth_target():
+    sur = _sur()
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-1, 1, size=(4096, 2)).astype(np.float32)
+    j = np.arange(64) / 64.0
+    t = (np.sin(2 * x[:, :1] + j) * np.cos(x[:, 1:] - j)).astype(np.float32)
+    with sur.Surrogate(max_batch=4096) as s:
+        s.set_params(I.mlp_init(4))
+        _, l0 = s.gradients(x, t)
+        for _ in range(300):
+            s.train_step(x, t)
+        _, l1 = s.gradients(x, t)
+    assert l1 < 0.05 * l0, (l0, l1)
+
+
+def test_screen_matches_forward_and_compacts_in_order():
+    import torch
+    sur = _sur()
+    P, _ = I.km_grid(40, 50)
+    n = P.shape[1]
+    lo = np.array([0.2e5, np.log(20e3)])
+    hi = np.array([1.2e5, np.log(1e6)])
+    mean = np.linspace(0.1, 0.9, 64)
+    std = np.linspace(0.5, 1.5, 64)
+    with sur.Surrogate(max_batch=1024) as s:
+        s.set_params(I.mlp_init(7))
+        s.set_norm(lo, hi, mean, std)
+        Pd = torch.from_numpy(P).cuda()
+        label, resolve, pmax, idx = s.screen(Pd, margin=0.3, spread=0.5, flag_margin=0.6)
+        label, resolve, pmax, idx = (v.cpu().numpy() for v in (label, resolve, pmax, idx))
+        x = np.stack([2 * (P[0] - lo[0]) / (hi[0] - lo[0]) - 1,
+                      2 * (np.log(P[1]) - lo[1]) / (hi[1] - lo[1]) - 1], axis=1).astype(np.float32)
+        out = s.forward(x).astype(np.float64)
+    y = out * std + mean
+    mx, mn = y.max(axis=1), y.min(axis=1)
+    ok = np.abs(mx - pmax) < 1e-4
+    assert ok.mean() > 0.999
+    d = np.abs(mx - np.log(2))
+    want_res = (d < 0.3) | ((mx - mn > 0.5) & (d < 0.6))
+    agree = (resolve.astype(bool) == want_res) | (np.abs(d - 0.3) < 1e-4) | (np.abs(d - 0.6) < 1e-4)
+    assert agree.all()
+    assert np.array_equal(idx, np.nonzero(resolve)[0])
+    assert np.array_equal(label.astype(bool)[ok], (pmax >= np.log(2))[ok])
