@@ -145,6 +145,12 @@ const char *ens_last_error(ens_t h);
  * constants when it picks the system up.  Errors: ENS_E_INVAL, ENS_E_HIP. */
 int ens_set_params(ens_t h, const double *p, int32_t where);
 
+/* Per-system parameters gathered from a larger sweep: system i takes column
+ * idx[i] of p_full [P][n_full] (device arrays; idx has the handle's n
+ * entries, each in [0, n_full)).  Used to re-solve a subset of a sweep.
+ * Errors: ENS_E_INVAL, ENS_E_HIP. */
+int ens_set_params_gather(ens_t h, const double *p_full, int64_t n_full, const int64_t *idx);
+
 /* Shared parameters of sub-ensemble `ensemble` (host array of n_shared
  * doubles, n_shared == S of the model). */
 int ens_set_shared(ens_t h, int32_t ensemble, const double *shared, int32_t n_shared);

@@ -78,6 +78,14 @@ int sur_set_norm(sur_t s, const double *in_lo, const double *in_hi,
 int sur_build_dataset(sur_t s, const double *params, const double *records, int64_t n,
                       float *x, float *y);
 
+/* Output standardisation fitted on the GPU: for each of the SUR_OUT record
+ * rows of records [SUR_OUT][n] (device, double), mean and standard deviation
+ * of ln y1max over the n points; they become the handle's output
+ * standardisation (input bounds as given here) and are copied to out_mean /
+ * out_std (host, SUR_OUT doubles each, may be NULL). */
+int sur_fit_norm(sur_t s, const double *in_lo, const double *in_hi, const double *records,
+                 int64_t n, double *out_mean, double *out_std);
+
 /* Adam hyper-parameters (defaults lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8). */
 int sur_set_adam(sur_t s, double lr, double beta1, double beta2, double eps);
 
@@ -87,6 +95,15 @@ int sur_set_adam(sur_t s, double lr, double beta1, double beta2, double eps);
  * loss (a float; host or device per `where`, which also tags x and target). */
 int sur_train_step(sur_t s, const float *x, const float *target, int64_t m,
                    float *loss, int32_t where);
+
+/* One pass over rows of a device dataset x [rows][2], y [rows][SUR_OUT]:
+ * perm (device int64 [n]) lists the rows to use in order (each a valid row
+ * index; a shuffled training subset); consecutive batches of `batch` entries
+ * (a multiple of 64 <= max_batch; the last n mod batch are skipped), one
+ * sur_train_step each.  *mean_loss (host, may be NULL) receives the mean of
+ * the batch losses. */
+int sur_train_epoch(sur_t s, const float *x, const float *y, int64_t n, const int64_t *perm,
+                    int64_t batch, float *mean_loss);
 
 /* Loss and gradients of one batch without an update (for checking): grads
  * receives SUR_N_PARAMS floats in the parameter packing. */
@@ -111,6 +128,13 @@ typedef struct {
 int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *opts,
                int8_t *label, uint8_t *resolve, float *pred_max, int64_t *resolve_idx,
                int64_t *n_resolve);
+
+/* Exact labels from re-solved points: for i < k, label[idx[i]] =
+ * [max_j records[j][i] >= 2] with records [SUR_OUT][k] the cycle maxima of
+ * the re-solved systems (device arrays; a point whose records hold a NaN is
+ * labelled -1).  With idx == NULL, label[i] is written for i < k. */
+int sur_exact_labels(sur_t s, const double *records, int64_t k, const int64_t *idx,
+                     int8_t *label);
 
 #ifdef __cplusplus
 }

@@ -135,9 +135,49 @@ void free_graph(ens_ctx *h) {
   h->graph = nullptr;
 }
 
+// p[j][i] = p_full[j][idx[i]]
+__global__ void k_gather_params(const double *__restrict__ pf, int64_t n_full,
+                                const int64_t *__restrict__ idx, int64_t n, int P, double *p,
+                                int *bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t src = idx[i];
+  if (src < 0 || src >= n_full) {
+    *bad = 1;
+    return;
+  }
+  for (int j = 0; j < P; ++j) p[j * n + i] = pf[j * n_full + src];
+}
+
 }  // namespace
 
 extern "C" {
+
+int ens_set_params_gather(ens_t h, const double *p_full, int64_t n_full, const int64_t *idx) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_set_params_gather: NULL handle");
+  if (h->n > 0 && (!p_full || !idx || n_full <= 0))
+    return fail(h, ENS_E_INVAL, "ens_set_params_gather: bad arguments");
+  DeviceGuard g(h->device);
+  if (h->n > 0) {
+    int *bad = nullptr;
+    ENS_HIP(h, hipMalloc((void **)&bad, sizeof(int)));
+    int zero = 0, hb = 0;
+    hipError_t e = hipMemcpyAsync(bad, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_gather_params, dim3((unsigned)((h->n + 255) / 256)), dim3(256), 0,
+                         h->stream, p_full, n_full, idx, h->n, h->mi.P, h->d_p, bad);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return hip_fail(h, e, "ens_set_params_gather");
+    if (hb) return fail(h, ENS_E_INVAL, "ens_set_params_gather: index out of range");
+  }
+  h->have_p = true;
+  return ENS_OK;
+}
+
 
 const char *ens_last_error(ens_t h) { return h ? h->err.c_str() : g_err.c_str(); }
 

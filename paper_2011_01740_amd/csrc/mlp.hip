@@ -410,6 +410,73 @@ __global__ __launch_bounds__(kScanBlock) void k_write_idx(const uint8_t *__restr
   if (v) idx[offs[blockIdx.x] + pre[threadIdx.x] - 1] = i;
 }
 
+// Mean of ln rec[j][i] over i (one block per output j, fixed-order tree).
+__global__ __launch_bounds__(256) void k_logmean(const double *__restrict__ rec, int64_t n,
+                                                 double *mean) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += log(rec[j * n + i]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mean[j] = red[0] / (double)n;
+}
+
+// Standard deviation of ln rec[j][i] about the mean (second pass).
+__global__ __launch_bounds__(256) void k_logstd(const double *__restrict__ rec, int64_t n,
+                                                const double *mean, double *stdv) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  const double mu = mean[j];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double d = log(rec[j * n + i]) - mu;
+    s = fma(d, d, s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) stdv[j] = sqrt(red[0] / (double)n);
+}
+
+// Rows perm[b0 .. b0 + m) of the dataset into the batch buffers.
+__global__ void k_gather_batch(const float *__restrict__ x, const float *__restrict__ y,
+                               const int64_t *__restrict__ perm, int64_t b0, int64_t m,
+                               float *bx, float *by) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * kOut) return;
+  const int64_t r = idx / kOut, j = idx % kOut;
+  const int64_t src = perm[b0 + r];
+  by[idx] = y[src * kOut + j];
+  if (j < kIn) bx[r * kIn + j] = x[src * kIn + j];
+}
+
+__global__ void k_accumulate(const float *v, float *acc, int first) {
+  if (threadIdx.x == 0) *acc = first ? *v : *acc + *v;
+}
+
+// label[idx[i]] = [max_j rec[j][i] >= 2]; -1 if any record is NaN.
+__global__ void k_exact_labels(const double *__restrict__ rec, int64_t k,
+                               const int64_t *__restrict__ idx, int8_t *label) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  double mx = -INFINITY;
+  bool bad = false;
+  for (int j = 0; j < kOut; ++j) {
+    const double v = rec[j * k + i];
+    bad = bad || isnan(v);
+    mx = v > mx ? v : mx;
+  }
+  label[idx ? idx[i] : i] = bad ? -1 : (mx >= 2.0 ? 1 : 0);
+}
+
 }  // namespace
 
 // ======================================================================== API
@@ -439,6 +506,7 @@ struct sur_ctx {
   float *part = nullptr;      // split-K partial weight gradients
   float *lpart = nullptr;     // loss partials
   float *loss = nullptr;      // device scalar
+  float *loss_acc = nullptr;  // device scalar: sum of batch losses of an epoch
   int64_t *scan = nullptr;    // compaction scratch
   int64_t scan_cap = 0;
 };
@@ -645,6 +713,7 @@ int sur_create(int32_t device, void *hip_stream, int64_t max_batch, sur_t *out) 
   A(dz4b, B * kOut); A(dz4bT, B * kOut); A(dz3b, B * kH); A(dz3bT, B * kH);
   A(dz2b, B * kH); A(dz2bT, B * kH);
   A(part, (int64_t)kSplit * kH * kH); A(lpart, nblk(B * kOut, 256)); A(loss, 1);
+  A(loss_acc, 1);
 #undef A
   if (e == hipSuccess) e = hipMemsetAsync(s->P, 0, kNP * sizeof(float), s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->Mm, 0, kNP * sizeof(float), s->stream);
@@ -669,7 +738,7 @@ int sur_destroy(sur_t s) {
                   s->d_mean, s->d_std, s->d_dmean, s->d_dstd, s->x, s->tgt, s->z1, s->z2,
                   s->z3, s->out, s->a1, s->a1T, s->a2, s->a2T, s->a3, s->a3T, s->dz4, s->dz3,
                   s->dz2, s->dz1, s->dz4b, s->dz4bT, s->dz3b, s->dz3bT, s->dz2b, s->dz2bT,
-                  s->part, s->lpart, s->loss, s->scan};
+                  s->part, s->lpart, s->loss, s->loss_acc, s->scan};
   for (void *p : ptrs) (void)hipFree(p);
   delete s;
   return ENS_OK;
@@ -868,6 +937,76 @@ int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *
     SUR_HIP(s, hipMemcpyAsync(n_resolve, s->scan + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
                               s->stream));
   }
+  SUR_HIP(s, hipStreamSynchronize(s->stream));
+  return ENS_OK;
+}
+
+int sur_fit_norm(sur_t s, const double *in_lo, const double *in_hi, const double *records,
+                 int64_t n, double *out_mean, double *out_std) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_fit_norm: NULL handle");
+  if (!in_lo || !in_hi || !records || n <= 0)
+    return sfail(s, ENS_E_INVAL, "sur_fit_norm: bad arguments");
+  DevGuard dg(s->device);
+  hipLaunchKernelGGL(k_logmean, dim3(kOut), dim3(256), 0, s->stream, records, n, s->d_dmean);
+  hipLaunchKernelGGL(k_logstd, dim3(kOut), dim3(256), 0, s->stream, records, n, s->d_dmean,
+                     s->d_dstd);
+  SUR_HIP(s, hipGetLastError());
+  double m[kOut], sd[kOut];
+  SUR_HIP(s, hipMemcpyAsync(m, s->d_dmean, sizeof(m), hipMemcpyDeviceToHost, s->stream));
+  SUR_HIP(s, hipMemcpyAsync(sd, s->d_dstd, sizeof(sd), hipMemcpyDeviceToHost, s->stream));
+  SUR_HIP(s, hipStreamSynchronize(s->stream));
+  for (int j = 0; j < kOut; ++j)
+    if (!(sd[j] > 0.0) || !std::isfinite(m[j]))
+      return sfail(s, ENS_E_INVAL, "sur_fit_norm: records give a non-positive or non-finite spread");
+  if (int rc = sur_set_norm(s, in_lo, in_hi, m, sd)) return rc;
+  if (out_mean) std::memcpy(out_mean, m, sizeof(m));
+  if (out_std) std::memcpy(out_std, sd, sizeof(sd));
+  return ENS_OK;
+}
+
+int sur_train_epoch(sur_t s, const float *x, const float *y, int64_t n, const int64_t *perm,
+                    int64_t batch, float *mean_loss) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_train_epoch: NULL handle");
+  if (int rc = check_batch(s, batch)) return rc;
+  if (!x || !y || !perm || n < batch) return sfail(s, ENS_E_INVAL, "sur_train_epoch: bad arguments");
+  DevGuard dg(s->device);
+  const int64_t nb = n / batch;
+  for (int64_t b = 0; b < nb; ++b) {
+    hipLaunchKernelGGL(k_gather_batch, dim3(nblk(batch * kOut, 256)), dim3(256), 0, s->stream,
+                       x, y, perm, b * batch, batch, s->x, s->tgt);
+    SUR_HIP(s, hipGetLastError());
+    SUR_HIP(s, forward_batch(s, batch, true, s->out));
+    SUR_HIP(s, backward_batch(s, batch));
+    s->t += 1;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(s->b1, (double)s->t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(s->b2, (double)s->t)));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(kNP, 256)), dim3(256), 0, s->stream, s->P, s->G, s->Mm,
+                       s->V, kNP, (float)s->lr, (float)s->b1, (float)s->b2, (float)s->eps, c1, c2);
+    SUR_HIP(s, hipGetLastError());
+    SUR_HIP(s, refresh(s));
+    hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(64), 0, s->stream, s->loss, s->loss_acc,
+                       b == 0 ? 1 : 0);
+    SUR_HIP(s, hipGetLastError());
+  }
+  if (mean_loss) {
+    float acc = 0.f;
+    SUR_HIP(s, hipMemcpyAsync(&acc, s->loss_acc, sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    SUR_HIP(s, hipStreamSynchronize(s->stream));
+    *mean_loss = acc / (float)nb;
+  }
+  return ENS_OK;
+}
+
+int sur_exact_labels(sur_t s, const double *records, int64_t k, const int64_t *idx,
+                     int8_t *label) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_exact_labels: NULL handle");
+  if (k < 0 || (k > 0 && (!records || !label)))
+    return sfail(s, ENS_E_INVAL, "sur_exact_labels: bad arguments");
+  if (k == 0) return ENS_OK;
+  DevGuard dg(s->device);
+  hipLaunchKernelGGL(k_exact_labels, dim3(nblk(k, 256)), dim3(256), 0, s->stream, records, k,
+                     idx, label);
+  SUR_HIP(s, hipGetLastError());
   SUR_HIP(s, hipStreamSynchronize(s->stream));
   return ENS_OK;
 }

@@ -1,0 +1,256 @@
+"""Surrogate-screened Keller--Miksis sweep.
+
+The frequency-response study of the paper (Sec. 4.2: the maximum bubble
+radius per acoustic cycle over a frequency sweep) repeated on a dense
+(p_A, f) grid.  Host logic only; every computation is a libens call:
+
+1. training data: the integrator solves a coarse grid (adaptive Cash--Karp,
+   FP64), keeping y1max of the last 64 acoustic cycles;
+2. the network (2-256-256-256-64, BF16 matrix cores) is trained on the GPU
+   to map (p_A, ln f) to those 64 values of ln y1max;
+3. the unsure band around the label threshold (max y1max = 2) is calibrated
+   on a held-out part of the coarse grid;
+4. the dense grid is screened: every point gets the network's label, and the
+   points inside the band are re-solved by the integrator, whose labels
+   replace the network's;
+5. the judge: plain FP64 solves of (a uniform sample of, or all) dense-grid
+   points, compared with the final labels.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import asdict, dataclass, field
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import ens, sur
+from . import inputs as I
+
+LN2 = math.log(2.0)
+
+
+@dataclass
+class Config:
+    train_grid: int = 512          # coarse grid side (training data)
+    screen_grid: int = 4096        # dense grid side
+    n_phases: int = 1024           # acoustic cycles integrated per point
+    n_last: int = 64               # recorded cycles (network outputs)
+    epochs: int = 100
+    batch: int = 4096
+    lr: float = 1e-3
+    init_seed: int = 4
+    split_seed: int = 11
+    shuffle_seed: int = 12
+    judge_seed: int = 13
+    holdout: float = 0.1
+    target_wrong: float = 0.005    # hold-out error allowed outside the band
+    judge_n: int = 1 << 18         # plain-solved judge points (0: whole grid)
+
+
+@dataclass
+class Report:
+    config: Dict = field(default_factory=dict)
+    times_s: Dict[str, float] = field(default_factory=dict)
+    margin: float = 0.0
+    holdout_wrong_outside: float = 0.0
+    holdout_resolve_frac: float = 0.0
+    n_screen: int = 0
+    n_resolve: int = 0
+    resolve_frac: float = 0.0
+    judge_points: int = 0
+    judge_wrong: int = 0
+    judge_wrong_frac: float = 0.0
+    network_only_wrong_frac: float = 0.0
+    positive_frac: float = 0.0
+    plain_time_s: float = 0.0
+    plain_time_measured: bool = False
+    screened_time_s: float = 0.0
+    speedup: float = 0.0
+    train_loss: float = 0.0
+    extra: Dict = field(default_factory=dict)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def km_solve_records(P_dev, n_phases, n_last, idx_dev=None, n_full=None):
+    """Solve the Keller--Miksis points (all of P_dev, or the columns idx_dev of
+    a [2][n_full] sweep) and return (records [n_last][n] device, status, kernel s)."""
+    import torch
+    n = int(idx_dev.numel()) if idx_dev is not None else int(P_dev.shape[1])
+    if n == 0:
+        return torch.empty((n_last, 0), dtype=torch.float64, device="cuda"), np.zeros(0, np.int32), 0.0
+    y0 = torch.empty((2, n), dtype=torch.float64, device="cuda")
+    y0[0].fill_(1.0)
+    y0[1].zero_()
+    with ens.Ensemble(ens.ENS_KM, ens.ENS_RKCK45, n) as e:
+        if idx_dev is not None:
+            L = ens.load()
+            rc = L.ens_set_params_gather(e.h, ens.C.c_void_p(P_dev.data_ptr()), int(n_full),
+                                         ens.C.c_void_p(idx_dev.data_ptr()))
+            ens._check(rc, e.h)
+        else:
+            e.set_params(P_dev)
+        e.set_state(y0)
+        e.solve(n_phases=n_phases, n_record=n_last)
+        ms = e.last_kernel_ms()
+        rec = e.read(ens.ENS_RECORDS, device=True)      # [n_last][1][n]
+        status = e.read(ens.ENS_STATUS)
+    # records are a ring over the last n_last phases; with n_phases a multiple
+    # of n_last the slots hold the phases in order
+    return rec.reshape(n_last, n).contiguous(), status, ms / 1e3
+
+
+def run(cfg: Config, log=print) -> Report:
+    import torch
+    rep = Report(config=asdict(cfg))
+    T = rep.times_s
+    if cfg.n_phases % cfg.n_last:
+        raise ValueError("n_phases must be a multiple of n_last")
+    pa_lo, pa_hi, f_lo, f_hi = 0.2e5, 1.2e5, 20e3, 1e6
+    in_lo = np.array([pa_lo, math.log(f_lo)])
+    in_hi = np.array([pa_hi, math.log(f_hi)])
+
+    # 1. training data
+    Pt, _ = I.km_grid(cfg.train_grid, cfg.train_grid)
+    nt = Pt.shape[1]
+    Pt_d = _dev(Pt)
+    _sync()
+    t0 = time.perf_counter()
+    rec_t, st_t, _ = km_solve_records(Pt_d, cfg.n_phases, cfg.n_last)
+    _sync()
+    T["data"] = time.perf_counter() - t0
+    ok = (st_t & ~ens.ENS_SYS_DT_MIN) == 0
+    log(f"data: {nt} points in {T['data']:.2f} s, {int((~ok).sum())} not OK")
+
+    # 2. split, normalisation, dataset, training
+    rng = np.random.default_rng(cfg.split_seed)
+    order = rng.permutation(nt)
+    n_hold = int(round(cfg.holdout * nt))
+    hold = np.sort(order[:n_hold])
+    train = order[n_hold:]
+    train = train[ok[train]]
+    s = sur.Surrogate(max_batch=cfg.batch)
+    s.set_params(I.mlp_init(cfg.init_seed))
+    s.set_adam(lr=cfg.lr)
+    _sync()
+    t0 = time.perf_counter()
+    L = sur._lib()
+    mean = np.empty(64)
+    std = np.empty(64)
+    rec_train = rec_t[:, _dev(train)].contiguous()
+    sur._check(L.sur_fit_norm(s.h, sur._dptr(in_lo), sur._dptr(in_hi),
+                              ens.C.c_void_p(rec_train.data_ptr()), int(train.size),
+                              sur._dptr(mean), sur._dptr(std)), s.h)
+    x_d, y_d = s.build_dataset(Pt_d, rec_t, nt)
+    shuf = np.random.default_rng(cfg.shuffle_seed)
+    loss = ens.C.c_float()
+    for ep in range(cfg.epochs):
+        perm = _dev(shuf.permutation(train).astype(np.int64))
+        sur._check(L.sur_train_epoch(s.h, ens.C.c_void_p(x_d.data_ptr()),
+                                     ens.C.c_void_p(y_d.data_ptr()), int(train.size),
+                                     ens.C.c_void_p(perm.data_ptr()), cfg.batch,
+                                     ens.C.byref(loss)), s.h)
+    _sync()
+    T["train"] = time.perf_counter() - t0
+    rep.train_loss = float(loss.value)
+    log(f"train: {cfg.epochs} epochs in {T['train']:.2f} s, last epoch loss {rep.train_loss:.4g}")
+
+    # 3. calibration on the hold-out part of the coarse grid
+    t0 = time.perf_counter()
+    Ph_d = Pt_d[:, _dev(hold)].contiguous()
+    _, _, pmax_h, _ = s.screen(Ph_d, 0.0, 1e30, 0.0)
+    pmax_h = pmax_h.cpu().numpy().astype(np.float64)
+    exact_h = torch.empty(n_hold, dtype=torch.int8, device="cuda")
+    rec_h = rec_t[:, _dev(hold)].contiguous()
+    sur._check(L.sur_exact_labels(s.h, ens.C.c_void_p(rec_h.data_ptr()), n_hold, None,
+                                  ens.C.c_void_p(exact_h.data_ptr())), s.h)
+    exact_h = exact_h.cpu().numpy()
+    valid = exact_h >= 0
+    d = np.abs(pmax_h - LN2)
+    wrong = ((pmax_h >= LN2).astype(np.int8) != exact_h) & valid
+    # smallest margin whose wrong-outside-band count stays within the target
+    cand = np.unique(np.concatenate([[0.0], np.sort(d[wrong]) + 1e-7]))
+    budget = cfg.target_wrong * valid.sum()
+    margin = float(cand[-1])
+    for m in cand:
+        if (wrong & (d >= m)).sum() <= budget:
+            margin = float(m)
+            break
+    rep.margin = margin
+    rep.holdout_wrong_outside = float((wrong & (d >= margin)).sum() / max(valid.sum(), 1))
+    rep.holdout_resolve_frac = float((d < margin).mean())
+    T["calibrate"] = time.perf_counter() - t0
+    log(f"calibration: margin {margin:.4f}, hold-out re-solve {rep.holdout_resolve_frac:.4f}, "
+        f"wrong outside {rep.holdout_wrong_outside:.4f}")
+
+    # 4. screening of the dense grid and re-solve
+    Ps, _ = I.km_grid(cfg.screen_grid, cfg.screen_grid)
+    ns = Ps.shape[1]
+    Ps_d = _dev(Ps)
+    _sync()
+    t0 = time.perf_counter()
+    label, resolve, pmax, idx = s.screen(Ps_d, margin, 1e30, 0.0)
+    _sync()
+    T["screen"] = time.perf_counter() - t0
+    rep.n_screen = ns
+    rep.n_resolve = int(idx.numel())
+    rep.resolve_frac = rep.n_resolve / ns
+    net_label = label.clone()
+    t0 = time.perf_counter()
+    rec_r, st_r, _ = km_solve_records(Ps_d, cfg.n_phases, cfg.n_last, idx_dev=idx, n_full=ns)
+    if rep.n_resolve:
+        sur._check(L.sur_exact_labels(s.h, ens.C.c_void_p(rec_r.data_ptr()), rep.n_resolve,
+                                      ens.C.c_void_p(idx.data_ptr()),
+                                      ens.C.c_void_p(label.data_ptr())), s.h)
+    _sync()
+    T["resolve"] = time.perf_counter() - t0
+    log(f"screen: {ns} points in {T['screen']:.3f} s; re-solve {rep.n_resolve} "
+        f"({rep.resolve_frac:.4f}) in {T['resolve']:.2f} s")
+    rep.screened_time_s = T["data"] + T["train"] + T["calibrate"] + T["screen"] + T["resolve"]
+
+    # 5. judge with plain FP64 solves
+    if cfg.judge_n and cfg.judge_n < ns:
+        jidx = np.sort(np.random.default_rng(cfg.judge_seed).choice(ns, cfg.judge_n, replace=False))
+    else:
+        jidx = np.arange(ns)
+    jidx_d = _dev(jidx.astype(np.int64))
+    _sync()
+    t0 = time.perf_counter()
+    rec_j, st_j, _ = km_solve_records(Ps_d, cfg.n_phases, cfg.n_last, idx_dev=jidx_d, n_full=ns)
+    _sync()
+    t_plain_sample = time.perf_counter() - t0
+    exact_j = torch.empty(jidx.size, dtype=torch.int8, device="cuda")
+    sur._check(L.sur_exact_labels(s.h, ens.C.c_void_p(rec_j.data_ptr()), int(jidx.size), None,
+                                  ens.C.c_void_p(exact_j.data_ptr())), s.h)
+    exact_j = exact_j.cpu().numpy()
+    final_j = label[jidx_d].cpu().numpy()
+    net_j = net_label[jidx_d].cpu().numpy()
+    vj = exact_j >= 0
+    rep.judge_points = int(vj.sum())
+    rep.judge_wrong = int(((final_j != exact_j) & vj).sum())
+    rep.judge_wrong_frac = rep.judge_wrong / max(rep.judge_points, 1)
+    rep.network_only_wrong_frac = float(((net_j != exact_j) & vj).sum() / max(rep.judge_points, 1))
+    rep.positive_frac = float((exact_j[vj] == 1).mean()) if vj.any() else 0.0
+    rep.plain_time_measured = jidx.size == ns
+    rep.plain_time_s = t_plain_sample * ns / jidx.size
+    rep.speedup = rep.plain_time_s / rep.screened_time_s
+    T["judge_plain"] = t_plain_sample
+    log(f"judge: {rep.judge_points} points, wrong {rep.judge_wrong_frac:.5f} "
+        f"(network alone {rep.network_only_wrong_frac:.5f}); plain {rep.plain_time_s:.1f} s "
+        f"({'measured' if rep.plain_time_measured else 'from a uniform sample'}), "
+        f"screened {rep.screened_time_s:.1f} s, speed-up {rep.speedup:.2f}")
+    rep.extra = {"judge_idx": jidx, "judge_exact": exact_j,
+                 "judge_pmax": pmax[jidx_d].cpu().numpy(), "judge_final": final_j,
+                 "train_lnmax": torch.log(rec_t.max(dim=0).values).cpu().numpy()}
+    s.close()
+    return rep
