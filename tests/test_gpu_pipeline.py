@@ -69,6 +69,7 @@ def test_screened_sweep_reduced_configuration():
     assert rep.resolve_frac < 0.5
     assert rep.judge_wrong_frac <= rep.network_only_wrong_frac
     assert rep.judge_wrong_frac < 0.03, rep.judge_wrong_frac
-    # the re-solved labels equal the plain solve at those points
+    # inside the band the final label is the integrator's own
     jfinal, jexact = rep.extra["judge_final"], rep.extra["judge_exact"]
-    assert np.all((jfinal == jexact) | (jexact < 0) | True)
+    band = np.abs(rep.extra["judge_pmax"] - np.log(2.0)) < rep.margin
+    assert np.array_equal(jfinal[band], jexact[band])
