@@ -101,6 +101,14 @@ def run_case(case, args):
                           "kernel_ms": r.kernel_ms, "attempted_steps": steps,
                           "steps_per_s": steps / r.kernel_ms * 1e3, "launch": r.launch}),
               flush=True)
+    elif case == "surrogate":
+        from paper_2011_01740_amd import surrogate as S
+        cfg = S.Config(train_grid=args.sur_train, screen_grid=args.sur_screen,
+                       n_phases=args.sur_phases, epochs=args.sur_epochs, judge_n=args.sur_judge)
+        rep = S.run(cfg, log=lambda *a: print(*a, file=sys.stderr, flush=True))
+        d = {k: v for k, v in rep.__dict__.items() if k != "extra"}
+        d["case"] = "surrogate"
+        print(json.dumps(d), flush=True)
     elif case == "prv":
         ensm = tuple((m, max(1, K // args.prv_div), sd) for m, K, sd in W.PRV_ENSEMBLES)
         r = W.prv_batched(ensm)
@@ -121,11 +129,17 @@ def run_case(case, args):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--case", choices=["bench", "lorenz", "km", "prv", "copy"], default="bench",
+    ap.add_argument("--case", choices=["bench", "lorenz", "km", "prv", "copy", "surrogate"],
+                    default="bench",
                     help="bench: the benchmark line; others: one launch for counter runs")
     ap.add_argument("--km-grid", type=int, default=512)
     ap.add_argument("--km-phases", type=int, default=16)
     ap.add_argument("--prv-div", type=int, default=100)
+    ap.add_argument("--sur-train", type=int, default=512)
+    ap.add_argument("--sur-screen", type=int, default=4096)
+    ap.add_argument("--sur-phases", type=int, default=1024)
+    ap.add_argument("--sur-epochs", type=int, default=100)
+    ap.add_argument("--sur-judge", type=int, default=1 << 18)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 23)

@@ -46,7 +46,7 @@ class Config:
     judge_seed: int = 13
     holdout: float = 0.1
     target_wrong: float = 0.005    # hold-out error allowed outside the band
-    judge_n: int = 1 << 18         # plain-solved judge points (0: whole grid)
+    judge_n: int = 1 << 18         # plain-solved judge points, whole grid rows (0: all)
 
 
 @dataclass
@@ -220,7 +220,16 @@ def run(cfg: Config, log=print) -> Report:
 
     # 5. judge with plain FP64 solves
     if cfg.judge_n and cfg.judge_n < ns:
-        jidx = np.sort(np.random.default_rng(cfg.judge_seed).choice(ns, cfg.judge_n, replace=False))
+        # whole rows of the grid (all frequencies) at evenly spaced p_A: the
+        # sample keeps the sweep's ordering, so neighbouring lanes get
+        # neighbouring parameters exactly as in the full plain sweep and the
+        # per-point cost extrapolates; the row offset is drawn from judge_seed
+        G = cfg.screen_grid
+        rows = max(1, cfg.judge_n // G)
+        stride = G // rows
+        off = int(np.random.default_rng(cfg.judge_seed).integers(0, stride))
+        r = off + stride * np.arange(rows)
+        jidx = (r[:, None] * G + np.arange(G)[None, :]).ravel()
     else:
         jidx = np.arange(ns)
     jidx_d = _dev(jidx.astype(np.int64))
