@@ -227,6 +227,23 @@ int ens_read(ens_t h, int32_t field, void *dst, size_t bytes, int32_t where);
 /* Size in bytes of a field as ens_read expects it (0 if not produced yet). */
 size_t ens_field_bytes(ens_t h, int32_t field);
 
+/* Autotuner.  Runs short trial solves of the handle's current problem for
+ * each launch candidate -- RK4: block {64, 128, 256, 512, 1024} x systems per
+ * lane {1, 2, 4} on min(n_steps, trial_len) steps; RKCK45: block {64, 128,
+ * 256} x refill threshold {1, 8, 32, 64} with every system capped at
+ * min(phases, trial_len) phases and impacts -- timing each with HIP events
+ * (best of two), restores the state it started from, and stores the fastest
+ * choice in a process-wide cache keyed by (model, solver, device
+ * architecture, floor(log2 n)).  Later ens_solve calls whose launch fields
+ * are 0 use the cached choice.  If the environment variable ENS_TUNE_CACHE
+ * names a file, the cache is read from it on first use and rewritten after
+ * each tuning.  best (may be NULL) receives opts with the chosen launch
+ * fields, best_ms (may be NULL) the trial time.  trial_len <= 0 means 256
+ * (RK4) or 2 (RKCK45).  Errors: ENS_E_ORDER (no params/state), ENS_E_INVAL,
+ * ENS_E_HIP. */
+int ens_tune(ens_t h, const ens_solve_opts *opts, int64_t trial_len, ens_solve_opts *best,
+             float *best_ms);
+
 /* Launch actually used by the last ens_solve: block size, systems per lane,
  * grid, refill threshold.  Any pointer may be NULL. */
 int ens_last_launch(ens_t h, int32_t *block, int32_t *spl, int32_t *grid, int32_t *refill);

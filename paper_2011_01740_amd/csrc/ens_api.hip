@@ -1,10 +1,14 @@
 // Host implementation of the C ABI declared in include/ens.h.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ens_internal.h"
@@ -60,6 +64,7 @@ struct ens_ctx {
   int g_block = 0, g_grid = 0, g_model = -1;
   bool g_fill_h = false;
   double g_dt0 = 0.0;
+  int64_t trial_cap = 0;  // > 0 while tuning: cap on phases and impacts
 };
 
 namespace {
@@ -147,6 +152,79 @@ __global__ void k_gather_params(const double *__restrict__ pf, int64_t n_full,
     return;
   }
   for (int j = 0; j < P; ++j) p[j * n + i] = pf[j * n_full + src];
+}
+
+// ---------------------------------------------------------------- tuning cache
+struct TuneVal {
+  int block = 0, spl = 0, refill = 0;
+  float ms = 0.f;
+};
+using TuneKey = std::tuple<int, int, std::string, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+bool g_tune_loaded = false;
+
+std::string arch_of(int device) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+int n_bucket(int64_t n) {
+  int b = 0;
+  while (n > 1) {
+    n >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+// File format: one "model solver arch bucket block spl refill ms" line per entry.
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = std::getenv("ENS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char arch[64];
+  int m, so, b, bl, sp, rf;
+  float ms;
+  while (std::fscanf(f, "%d %d %63s %d %d %d %d %f", &m, &so, arch, &b, &bl, &sp, &rf, &ms) == 8)
+    g_tune[TuneKey(m, so, std::string(arch), b)] = TuneVal{bl, sp, rf, ms};
+  std::fclose(f);
+}
+
+void tune_save_locked() {
+  const char *path = std::getenv("ENS_TUNE_CACHE");
+  if (!path || !*path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (const auto &kv : g_tune)
+    std::fprintf(f, "%d %d %s %d %d %d %d %.6f\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                 std::get<2>(kv.first).c_str(), std::get<3>(kv.first), kv.second.block,
+                 kv.second.spl, kv.second.refill, kv.second.ms);
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+bool tune_lookup(int model, int solver, int device, int64_t n, TuneVal *v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(TuneKey(model, solver, arch_of(device), n_bucket(n)));
+  if (it == g_tune.end()) return false;
+  *v = it->second;
+  return true;
+}
+
+void tune_store(int model, int solver, int device, int64_t n, const TuneVal &v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune[TuneKey(model, solver, arch_of(device), n_bucket(n))] = v;
+  tune_save_locked();
 }
 
 }  // namespace
@@ -370,8 +448,14 @@ int ens_set_state(ens_t h, const double *y0, const double *t0, const double *h0,
 static int solve_rk4(ens_t h, const ens_solve_opts *o) {
   if (!(o->dt > 0.0) || !std::isfinite(o->dt) || o->n_steps < 0)
     return fail(h, ENS_E_INVAL, "ens_solve: RK4 needs dt > 0 and n_steps >= 0");
-  int block = o->block ? o->block : 256;
-  int spl = o->spl ? o->spl : 1;
+  int block = o->block, spl = o->spl;
+  TuneVal tv;
+  if ((!block || !spl) && tune_lookup(h->model, h->solver, h->device, h->n, &tv)) {
+    if (!block) block = tv.block;
+    if (!spl) spl = tv.spl;
+  }
+  if (!block) block = 256;
+  if (!spl) spl = 1;
   if (block < 64 || block > 1024 || block % 64)
     return fail(h, ENS_E_INVAL, "ens_solve: block must be a multiple of 64 in [64, 1024]");
   if (spl != 1 && spl != 2 && spl != 4) return fail(h, ENS_E_INVAL, "ens_solve: spl must be 1, 2 or 4");
@@ -403,10 +487,16 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     return fail(h, ENS_E_INVAL, "ens_solve: bad phase, record or step counts");
   if (o->max_steps > (int64_t)UINT32_MAX)
     return fail(h, ENS_E_INVAL, "ens_solve: max_steps above 2^32");
-  const int block = o->block ? o->block : 256;
+  int block = o->block, refill = o->refill;
+  TuneVal tv;
+  if ((!block || !refill) && tune_lookup(h->model, h->solver, h->device, h->n, &tv)) {
+    if (!block) block = tv.block;
+    if (!refill) refill = tv.refill;
+  }
+  if (!block) block = 256;
+  if (!refill) refill = 1;
   if (block < 64 || block > 256 || block % 64)
     return fail(h, ENS_E_INVAL, "ens_solve: adaptive block must be 64, 128, 192 or 256");
-  const int refill = o->refill ? o->refill : 1;
   if (refill < 1 || refill > 64) return fail(h, ENS_E_INVAL, "ens_solve: refill must be in [1, 64]");
   // Keller--Miksis: the fifth-root kernel needs 3 gamma = 21/5 in every
   // sub-ensemble; otherwise the general-power variant runs
@@ -440,6 +530,12 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     desc[e].last = h->off[e + 1];
     desc[e].n_phases = h->ens_phases[e] >= 0 ? h->ens_phases[e] : o->n_phases;
     desc[e].max_impacts = h->model == ENS_PRV ? h->ens_impacts[e] : 0;
+    if (h->trial_cap > 0) {
+      if (desc[e].n_phases > h->trial_cap) desc[e].n_phases = h->trial_cap;
+      if (h->model == ENS_PRV &&
+          (desc[e].max_impacts == 0 || desc[e].max_impacts > h->trial_cap))
+        desc[e].max_impacts = h->trial_cap;
+    }
   }
   if (desc.size() != h->desc_dev_copy.size() ||
       std::memcmp(desc.data(), h->desc_dev_copy.data(), desc.size() * sizeof(EnsDesc))) {
@@ -582,6 +678,103 @@ int ens_read(ens_t h, int32_t field, void *dst, size_t bytes, int32_t where) {
   const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   ENS_HIP(h, hipMemcpyAsync(dst, src, need, k, h->stream));
   if (where == ENS_HOST) ENS_HIP(h, hipStreamSynchronize(h->stream));
+  return ENS_OK;
+}
+
+int ens_tune(ens_t h, const ens_solve_opts *opts, int64_t trial_len, ens_solve_opts *best,
+             float *best_ms) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_tune: NULL handle");
+  if (!opts) return fail(h, ENS_E_INVAL, "ens_tune: opts is NULL");
+  if (!h->have_p || !h->have_y) return fail(h, ENS_E_ORDER, "ens_tune: set params and state first");
+  DeviceGuard g(h->device);
+  const size_t n = (size_t)h->n;
+  const size_t ybytes = (size_t)h->mi.D * n * sizeof(double);
+  // snapshot of the state, restored before every trial and at the end
+  double *sy = nullptr, *st = nullptr, *sh = nullptr;
+  const bool had_h = h->h_init;
+  ENS_HIP(h, hipMalloc((void **)&sy, ybytes ? ybytes : 8));
+  hipError_t e = hipMalloc((void **)&st, n ? n * sizeof(double) : 8);
+  if (e == hipSuccess) e = hipMalloc((void **)&sh, n ? n * sizeof(double) : 8);
+  if (e == hipSuccess && n) e = hipMemcpyAsync(sy, h->d_y, ybytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess && n) e = hipMemcpyAsync(st, h->d_t, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess && n && had_h)
+    e = hipMemcpyAsync(sh, h->d_h, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+  auto restore = [&]() -> hipError_t {
+    hipError_t r = hipSuccess;
+    if (n) r = hipMemcpyAsync(h->d_y, sy, ybytes, hipMemcpyDeviceToDevice, h->stream);
+    if (r == hipSuccess && n)
+      r = hipMemcpyAsync(h->d_t, st, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+    if (r == hipSuccess && n && had_h)
+      r = hipMemcpyAsync(h->d_h, sh, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+    h->h_init = had_h;
+    return r;
+  };
+  ens_solve_opts trial = *opts;
+  std::vector<std::tuple<int, int, int>> cands;  // block, spl, refill
+  if (h->solver == ENS_RK4) {
+    const int64_t len = trial_len > 0 ? trial_len : 256;
+    if (trial.n_steps > len) trial.n_steps = len;
+    for (int b : {64, 128, 256, 512, 1024})
+      for (int sp : {1, 2, 4}) cands.emplace_back(b, sp, 0);
+  } else {
+    h->trial_cap = trial_len > 0 ? trial_len : 2;
+    trial.use_graph = 0;
+    for (int b : {64, 128, 256})
+      for (int rf : {1, 8, 32, 64}) cands.emplace_back(b, 1, rf);
+  }
+  int rc = e == hipSuccess ? ENS_OK : hip_fail(h, e, "ens_tune: snapshot");
+  TuneVal bestv;
+  bestv.ms = std::numeric_limits<float>::infinity();
+  for (size_t c = 0; rc == ENS_OK && c < cands.size(); ++c) {
+    trial.block = std::get<0>(cands[c]);
+    trial.spl = std::get<1>(cands[c]);
+    trial.refill = std::get<2>(cands[c]);
+    trial.grid = 0;
+    float tmin = std::numeric_limits<float>::infinity();
+    for (int rep = 0; rc == ENS_OK && rep < 2; ++rep) {
+      hipError_t r = restore();
+      if (r != hipSuccess) {
+        rc = hip_fail(h, r, "ens_tune: restore");
+        break;
+      }
+      rc = h->solver == ENS_RK4 ? solve_rk4(h, &trial) : solve_rkck(h, &trial);
+      if (rc != ENS_OK) break;
+      float ms = 0.f;
+      r = hipEventSynchronize(h->ev1);
+      if (r == hipSuccess) r = hipEventElapsedTime(&ms, h->ev0, h->ev1);
+      if (r != hipSuccess) {
+        rc = hip_fail(h, r, "ens_tune: timing");
+        break;
+      }
+      if (ms < tmin) tmin = ms;
+    }
+    if (rc == ENS_OK && tmin < bestv.ms) {
+      bestv.block = trial.block;
+      bestv.spl = trial.spl;
+      bestv.refill = trial.refill;
+      bestv.ms = tmin;
+    }
+  }
+  h->trial_cap = 0;
+  hipError_t r = restore();
+  if (rc == ENS_OK && r != hipSuccess) rc = hip_fail(h, r, "ens_tune: restore");
+  if (r == hipSuccess) r = hipStreamSynchronize(h->stream);
+  (void)hipFree(sy);
+  (void)hipFree(st);
+  (void)hipFree(sh);
+  // the trial solves produced results that belong to no real solve
+  h->have_acc = false;
+  h->have_adaptive = false;
+  h->timed = false;
+  if (rc != ENS_OK) return rc;
+  tune_store(h->model, h->solver, h->device, h->n, bestv);
+  if (best) {
+    *best = *opts;
+    best->block = bestv.block;
+    best->spl = h->solver == ENS_RK4 ? bestv.spl : 0;
+    best->refill = bestv.refill;
+  }
+  if (best_ms) *best_ms = bestv.ms;
   return ENS_OK;
 }
 

@@ -76,6 +76,9 @@ def load():
     L.ens_field_bytes.restype = C.c_size_t
     L.ens_last_launch.argtypes = [vp] + [C.POINTER(i32)] * 4
     L.ens_last_kernel_ms.argtypes = [vp, C.POINTER(C.c_float)]
+    L.ens_tune.argtypes = [vp, C.POINTER(ens_solve_opts), i64, C.POINTER(ens_solve_opts),
+                           C.POINTER(C.c_float)]
+    L.ens_set_params_gather.argtypes = [vp, vp, i64, vp]
     _lib = L
     return L
 
@@ -216,6 +219,16 @@ class Ensemble:
         out = np.empty(shape, dtype=dt)
         _check(L.ens_read(self.h, field, C.c_void_p(out.ctypes.data), nbytes, ENS_HOST), self.h)
         return out
+
+    def tune(self, opts: Optional[ens_solve_opts] = None, trial_len: int = 0, **kw):
+        """Run the library's autotuner on the current problem; returns
+        (opts with the chosen launch fields, trial milliseconds)."""
+        o = opts if opts is not None else default_opts(**kw)
+        best = ens_solve_opts()
+        ms = C.c_float()
+        _check(load().ens_tune(self.h, C.byref(o), int(trial_len), C.byref(best), C.byref(ms)),
+               self.h)
+        return best, float(ms.value)
 
     def last_kernel_ms(self) -> float:
         ms = C.c_float()
