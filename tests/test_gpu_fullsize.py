@@ -1,0 +1,68 @@
+"""Parity at the workloads' full sizes, in the launches the workload runners use,
+on a seeded sample of systems the oracle integrates one by one."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2011_01740_amd import inputs as I
+from tests.parity import CK_ATOL, CK_RTOL, PERTURB, close, per_system, sensitivity_mask
+
+pytestmark = pytest.mark.gpu
+THREADS = 16
+
+
+def _sample(n, k, seed, extra=()):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([np.asarray(extra, dtype=np.int64), rng.integers(0, n, k)]))
+
+
+def test_keller_miksis_512x512_1024_cycles():
+    """2^18 systems, every one of the 1024 cycle maxima recorded."""
+    from paper_2011_01740_amd import workloads as W
+    r = W.km_sweep(512, 512, n_phases=1024)
+    n = 512 * 512
+    assert r.records.shape == (1024, 1, n)
+    assert np.all((r.status & ~O.SYS_DT_MIN) == 0)
+    assert np.all(r.stats[O.ST_PHASES] == 1024)
+    P, y0 = I.km_grid(512, 512)
+    idx = _sample(n, 40, 31, extra=[0, 511, n - 512, n - 1, 300 * 512 + 17])
+    o = O.Opts(n_phases=1024, n_record=1024)
+    a = O.rkck45(O.KM, P[:, idx], I.KM_WATER, y0[:, idx], o, nthreads=THREADS)
+    b = O.rkck45(O.KM, P[:, idx], I.KM_WATER, y0[:, idx] * (1 + PERTURB), o, nthreads=THREADS)
+    keep = sensitivity_mask([a.y, a.records], [b.y, b.records], 1e-9, 1e-11)
+    ok = (per_system(close(r.y[:, idx], a.y, CK_RTOL, CK_ATOL))
+          & per_system(close(r.records[:, :, idx], a.records, CK_RTOL, CK_ATOL)))
+    assert not (keep & ~ok).any(), idx[keep & ~ok]
+    assert keep.mean() >= 0.5, keep.mean()
+    # non-parity-set systems still agree on what the screening uses: the label
+    lab_g = r.records[-64:, 0, idx].max(axis=0) >= 2
+    lab_o = a.records[-64:, 0, :].max(axis=0) >= 2
+    assert (lab_g == lab_o).mean() >= 0.9
+
+
+def test_relief_valve_three_ensembles_one_graph_launch():
+    """2^15 + 2^16 + 2^17 systems with their own seeds and budgets (phases or
+    impacts, whichever first) in one graph-captured persistent launch.  The
+    budgets are the workload's divided by 100 (the full-budget launch runs
+    minutes: its 2^15 long systems run serially, see bench.py --case prv)."""
+    from paper_2011_01740_amd import workloads as W
+    ensm = tuple((m, K // 100, s) for m, K, s in W.PRV_ENSEMBLES)
+    r = W.prv_batched(ensm, n_record=32)
+    P, y0, off = W.prv_inputs(ensm)
+    assert np.all((r.status & ~(O.SYS_DT_MIN | O.SYS_SETTLED)) == 0)
+    for k, (m, K, seed) in enumerate(ensm):
+        sl = slice(off[k], off[k + 1])
+        ph, imp = r.stats[O.ST_PHASES, sl], r.stats[O.ST_IMPACTS, sl]
+        settled = (r.status[sl] & O.SYS_SETTLED) != 0
+        # every system stopped at its budget (or settled)
+        assert np.all((ph == K) | (imp == K) | settled)
+        idx = off[k] + _sample(m, 12, 40 + k, extra=[0, m - 1])
+        o = O.Opts(n_phases=K, n_record=32, max_impacts=K)
+        a = O.rkck45(O.PRV, P[:, idx], I.PRV_DEFAULT, y0[:, idx], o, nthreads=THREADS)
+        b = O.rkck45(O.PRV, P[:, idx], I.PRV_DEFAULT, y0[:, idx] * (1 + PERTURB), o,
+                     nthreads=THREADS)
+        keep = sensitivity_mask([a.y, a.records], [b.y, b.records], 1e-9, 1e-11)
+        ok = (per_system(close(r.y[:, idx], a.y, CK_RTOL, CK_ATOL))
+              & per_system(close(r.records[:, :, idx], a.records, CK_RTOL, CK_ATOL)))
+        assert not (keep & ~ok).any(), (k, idx[keep & ~ok])
+        assert np.array_equal(r.stats[O.ST_IMPACTS, idx][keep], a.stats[O.ST_IMPACTS][keep])
