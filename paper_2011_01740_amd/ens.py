@@ -58,6 +58,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libens.so not found at {LIB_PATH}: run __graft_entry__.build()")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7);
+    # loading torch first makes libens bind to that one instead of bringing a
+    # second runtime into the process
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
     L.ens_create.argtypes = [C.POINTER(ens_desc), C.POINTER(vp)]
