@@ -49,7 +49,11 @@ def test_relief_valve_three_ensembles_one_graph_launch():
     ensm = tuple((m, K // 100, s) for m, K, s in W.PRV_ENSEMBLES)
     r = W.prv_batched(ensm, n_record=32)
     P, y0, off = W.prv_inputs(ensm)
-    assert np.all((r.status & ~(O.SYS_DT_MIN | O.SYS_SETTLED)) == 0)
+    # terminal / informative bits only; EVENT_ITER (secant retries capped, e.g. at
+    # near-grazing impacts) stays rare
+    allowed = O.SYS_DT_MIN | O.SYS_SETTLED | O.SYS_EVENT_ITER
+    assert np.all((r.status & ~allowed) == 0)
+    assert ((r.status & O.SYS_EVENT_ITER) != 0).mean() < 0.01
     for k, (m, K, seed) in enumerate(ensm):
         sl = slice(off[k], off[k + 1])
         ph, imp = r.stats[O.ST_PHASES, sl], r.stats[O.ST_IMPACTS, sl]
@@ -66,3 +70,4 @@ def test_relief_valve_three_ensembles_one_graph_launch():
               & per_system(close(r.records[:, :, idx], a.records, CK_RTOL, CK_ATOL)))
         assert not (keep & ~ok).any(), (k, idx[keep & ~ok])
         assert np.array_equal(r.stats[O.ST_IMPACTS, idx][keep], a.stats[O.ST_IMPACTS][keep])
+        assert np.array_equal(r.status[idx][keep] & ~O.SYS_DT_MIN, a.status[keep] & ~O.SYS_DT_MIN)
