@@ -498,12 +498,15 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   if (block < 64 || block > 256 || block % 64)
     return fail(h, ENS_E_INVAL, "ens_solve: adaptive block must be 64, 128, 192 or 256");
   if (refill < 1 || refill > 64) return fail(h, ENS_E_INVAL, "ens_solve: refill must be in [1, 64]");
-  // Keller--Miksis: the fifth-root kernel needs 3 gamma = 21/5 in every
-  // sub-ensemble; otherwise the general-power variant runs
+  // Keller--Miksis: the fast kernel (Newton fifth root, angle-addition
+  // forcing phase) needs 3 gamma = 21/5 in every sub-ensemble and
+  // dt_max <= 1/8; otherwise the general variant runs
   int kmodel = h->model;
-  if (h->model == ENS_KM)
+  if (h->model == ENS_KM) {
+    if (o->dt_max > 0.125) kmodel = ens::ENS_KM_GENERAL;
     for (int e = 0; e < h->n_ens; ++e)
       if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM_GENERAL;
+  }
   int grid = o->grid;
   const int cap = ens::rkck_max_blocks(kmodel, block);
   if (cap <= 0) return fail(h, ENS_E_HIP, "ens_solve: occupancy query failed");

@@ -47,7 +47,8 @@ struct RkckArgs {
 };
 
 // Kernel variant of the Keller--Miksis model for a polytropic exponent with
-// 3 gamma != 21/5 (general power through exp/log).
+// 3 gamma != 21/5 or dt_max > 1/8 (general power through exp/log, sincospi
+// at every stage).
 constexpr int ENS_KM_GENERAL = 100;
 
 // Kernel launchers (stream-ordered; return hipSuccess or the launch error).

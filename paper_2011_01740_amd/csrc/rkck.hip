@@ -74,26 +74,57 @@ __device__ __forceinline__ double step_factor(double E) {
 struct MQuad {  // dx/dt = x^2 - p (Sec. 3)
   static constexpr int D = 1;
   static constexpr bool kEvents = false;
+  static constexpr int kMinWaves = 5;
   double p;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) { p = P[i]; }
-  __device__ void rhs(double, const double *y, double *f) const { f[0] = fma(y[0], y[0], -p); }
+  __device__ void begin(double) {}
+  __device__ void rhs(double, double, const double *y, double *f) const {
+    f[0] = fma(y[0], y[0], -p);
+  }
 };
 
 struct MLorenz {  // Sec. 4.1
   static constexpr int D = 3;
   static constexpr bool kEvents = false;
+  static constexpr int kMinWaves = 5;
   double rho, sigma, beta;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
     rho = P[i];
     sigma = sh[0];
     beta = sh[1];
   }
-  __device__ void rhs(double, const double *y, double *f) const {
+  __device__ void begin(double) {}
+  __device__ void rhs(double, double, const double *y, double *f) const {
     f[0] = sigma * (y[1] - y[0]);
     f[1] = fma(-y[0], y[2], fma(rho, y[0], -y[1]));
     f[2] = fma(y[0], y[1], -beta * y[2]);
   }
 };
+
+// sin x and cos x for |x| <= 0.8 from their Taylor series (terms through
+// x^17 and x^18; the first omitted terms are below 1.2e-19), Horner in x^2.
+__device__ __forceinline__ void sincos_small(double x, double *s, double *c) {
+  const double x2 = x * x;
+  double ps = 1.0 / 355687428096000.0;           // 1/17!
+  ps = fma(ps, x2, -1.0 / 1307674368000.0);       // 1/15!
+  ps = fma(ps, x2, 1.0 / 6227020800.0);           // 1/13!
+  ps = fma(ps, x2, -1.0 / 39916800.0);            // 1/11!
+  ps = fma(ps, x2, 1.0 / 362880.0);               // 1/9!
+  ps = fma(ps, x2, -1.0 / 5040.0);                // 1/7!
+  ps = fma(ps, x2, 1.0 / 120.0);                  // 1/5!
+  ps = fma(ps, x2, -1.0 / 6.0);                   // 1/3!
+  *s = fma(ps * x2, x, x);
+  double pc = 1.0 / 6402373705728000.0;          // 1/18!
+  pc = fma(pc, x2, -1.0 / 20922789888000.0);      // 1/16!
+  pc = fma(pc, x2, 1.0 / 87178291200.0);          // 1/14!
+  pc = fma(pc, x2, -1.0 / 479001600.0);           // 1/12!
+  pc = fma(pc, x2, 1.0 / 3628800.0);              // 1/10!
+  pc = fma(pc, x2, -1.0 / 40320.0);               // 1/8!
+  pc = fma(pc, x2, 1.0 / 720.0);                  // 1/6!
+  pc = fma(pc, x2, -1.0 / 24.0);                  // 1/4!
+  pc = fma(pc, x2, 0.5);                          // 1/2!
+  *c = fma(-pc, x2, 1.0);
+}
 
 // Dimensionless Keller--Miksis equation (Sec. 4.2), single-frequency drive.
 // The lane derives its coefficients from (P_A1, f1) and the shared material
@@ -104,14 +135,20 @@ struct MLorenz {  // Sec. 4.1
 //       - (1 - K9 y2 / 3) 1.5 y2^2 - K7 c y1,       s, c = sin, cos(2 pi tau)
 //   D = y1 (1 - K9 y2) + K4 K9.
 // One division serves both 1/y1 and 1/D: q = 1 / (y1 D), 1/y1 = D q,
-// N / D = N y1 q.  With FIFTHS (the host checked 3 gamma = 21/5, the
-// polytropic exponent of air) the gas term is (1/y1)^4 y1^(-1/5) with the
-// Newton fifth root; otherwise exp(-K10 log y1).
-template <bool FIFTHS>
+// N / D = N y1 q.
+// FAST (chosen by the host when 3 gamma = 21/5, the polytropic exponent of
+// air, and dt_max <= 1/8): the gas term is (1/y1)^4 y1^(-1/5) with the Newton
+// fifth root, and the forcing phase of each stage, 2 pi (t + c_i h), comes
+// from sin/cos of 2 pi t (once per attempted step) by angle addition with the
+// small offset 2 pi c_i h <= pi/4.  Otherwise exp(-K10 log y1) and sincospi
+// per stage.
+template <bool FAST>
 struct MKM {
   static constexpr int D = 2;
   static constexpr bool kEvents = false;
+  static constexpr int kMinWaves = FAST ? 4 : 5;
   double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49;
+  double s0, c0;  // sin, cos (2 pi t) at the start of the attempted step
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
     const double pa = P[i], f = P[n + i];
     const double rhoL = sh[0], cL = sh[1], pV = sh[2], sig = sh[3], mu = sh[4];
@@ -131,20 +168,27 @@ struct MKM {
     K10 = 3.0 * gam;
     K49 = K4 * K9;
   }
-  __device__ void rhs(double tau, const double *y, double *f) const {
+  __device__ void begin(double t) {
+    if constexpr (FAST) sincospi(2.0 * t, &s0, &c0);
+  }
+  // tau: the stage time; off: its offset c_i h from the attempt's start.
+  __device__ void rhs(double tau, double off, const double *y, double *f) const {
     const double y1 = y[0], y2 = y[1];
     const double Dn = fma(y1, fma(-K9, y2, 1.0), K49);
     const double qd = 1.0 / (y1 * Dn);
     const double r1 = Dn * qd;                    // 1 / y1
-    double gas;                                   // (1/y1)^K10
-    if constexpr (FIFTHS) {
+    double gas, s, c;                             // (1/y1)^K10; sin, cos (2 pi tau)
+    if constexpr (FAST) {
       const double r2 = r1 * r1;
       gas = (r2 * r2) * rfifth(y1);
+      double so, co;
+      sincos_small(2.0 * M_PI * off, &so, &co);
+      s = fma(s0, co, c0 * so);
+      c = fma(c0, co, -(s0 * so));
     } else {
       gas = exp(-K10 * log(y1));
+      sincospi(2.0 * tau, &s, &c);
     }
-    double s, c;
-    sincospi(2.0 * tau, &s, &c);
     const double u = fma(K9, y2, 1.0);
     double N = fma(K1, y2, K0) * gas;
     N = fma(-fma(K5, s, K2), u, N);
@@ -161,6 +205,7 @@ struct MKM {
 struct MPRV {
   static constexpr int D = 3;
   static constexpr bool kEvents = true;
+  static constexpr int kMinWaves = 5;
   double q, kappa, delta, beta, r;
   bool seated;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
@@ -171,7 +216,8 @@ struct MPRV {
     r = sh[3];
     seated = false;
   }
-  __device__ void rhs(double, const double *y, double *f) const {
+  __device__ void begin(double) {}
+  __device__ void rhs(double, double, const double *y, double *f) const {
     if (seated) {
       f[0] = 0.0;
       f[1] = 0.0;
@@ -186,30 +232,31 @@ struct MPRV {
 
 // One attempted Cash--Karp step: y5 and err = h sum (b5 - b4) k.
 template <class M>
-__device__ __forceinline__ void ck_attempt(const M &m, double t, const double *y, double h,
+__device__ __forceinline__ void ck_attempt(M &m, double t, const double *y, double h,
                                            double *y5, double *err) {
   constexpr int D = M::D;
   double k1[D], k2[D], k3[D], k4[D], k5[D], k6[D], yt[D];
-  m.rhs(t, y, k1);
+  m.begin(t);
+  m.rhs(t, 0.0, y, k1);
 #pragma unroll
   for (int c = 0; c < D; ++c) yt[c] = fma(h, A21 * k1[c], y[c]);
-  m.rhs(fma(C2, h, t), yt, k2);
+  m.rhs(fma(C2, h, t), C2 * h, yt, k2);
 #pragma unroll
   for (int c = 0; c < D; ++c) yt[c] = fma(h, fma(A32, k2[c], A31 * k1[c]), y[c]);
-  m.rhs(fma(C3, h, t), yt, k3);
+  m.rhs(fma(C3, h, t), C3 * h, yt, k3);
 #pragma unroll
   for (int c = 0; c < D; ++c)
     yt[c] = fma(h, fma(A43, k3[c], fma(A42, k2[c], A41 * k1[c])), y[c]);
-  m.rhs(fma(C4, h, t), yt, k4);
+  m.rhs(fma(C4, h, t), C4 * h, yt, k4);
 #pragma unroll
   for (int c = 0; c < D; ++c)
     yt[c] = fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], A51 * k1[c]))), y[c]);
-  m.rhs(t + C5 * h, yt, k5);
+  m.rhs(t + C5 * h, C5 * h, yt, k5);
 #pragma unroll
   for (int c = 0; c < D; ++c)
     yt[c] = fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], A61 * k1[c])))),
                 y[c]);
-  m.rhs(fma(C6, h, t), yt, k6);
+  m.rhs(fma(C6, h, t), C6 * h, yt, k6);
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     y5[c] = fma(h, fma(B6, k6[c], fma(B4, k4[c], fma(B3, k3[c], B1 * k1[c]))), y[c]);
@@ -419,8 +466,11 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
   return done;
 }
 
+// Each model states the occupancy floor the register allocator must respect
+// (kMinWaves waves per SIMD): 5 for the light models, 4 for the fast
+// Keller--Miksis variant, whose stage trigonometry needs the extra registers.
 template <class M>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_rkck(RkckArgs a) {
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kMinWaves, 8))) void k_rkck(RkckArgs a) {
   constexpr int D = M::D;
   __shared__ EnsDesc sdesc[ENS_MAX_ENSEMBLES];
   for (int e = threadIdx.x; e < a.n_ens; e += blockDim.x) sdesc[e] = a.desc[e];
