@@ -47,6 +47,7 @@ class Config:
     holdout: float = 0.1
     target_wrong: float = 0.007    # hold-out error allowed outside the band
     judge_n: int = 1 << 18         # plain-solved judge points, whole grid rows (0: all)
+    judge_chunk: int = 1 << 22     # points per plain-sweep launch
 
 
 @dataclass
@@ -234,15 +235,23 @@ def run(cfg: Config, log=print) -> Report:
     else:
         jidx = np.arange(ns)
     jidx_d = _dev(jidx.astype(np.int64))
-    _sync()
-    t0 = time.perf_counter()
-    rec_j, st_j, _ = km_solve_records(Ps_d, cfg.n_phases, cfg.n_last, idx_dev=jidx_d, n_full=ns)
-    _sync()
-    t_plain_sample = time.perf_counter() - t0
-    exact_j = torch.empty(jidx.size, dtype=torch.int8, device="cuda")
-    sur._check(L.sur_exact_labels(s.h, ens.C.c_void_p(rec_j.data_ptr()), int(jidx.size), None,
-                                  ens.C.c_void_p(exact_j.data_ptr())), s.h)
-    exact_j = exact_j.cpu().numpy()
+    exact_d = torch.empty(jidx.size, dtype=torch.int8, device="cuda")
+    # the plain sweep runs in launches of at most judge_chunk points (each far
+    # above the resident capacity, so the queue stays full), in grid order
+    t_plain_sample = 0.0
+    for c0 in range(0, jidx.size, cfg.judge_chunk):
+        sl = jidx_d[c0:c0 + cfg.judge_chunk]
+        _sync()
+        t0 = time.perf_counter()
+        rec_j, st_j, _ = km_solve_records(Ps_d, cfg.n_phases, cfg.n_last, idx_dev=sl, n_full=ns)
+        _sync()
+        t_plain_sample += time.perf_counter() - t0
+        sur._check(L.sur_exact_labels(s.h, ens.C.c_void_p(rec_j.data_ptr()), int(sl.numel()),
+                                      None, ens.C.c_void_p(exact_d[c0:].data_ptr())), s.h)
+        del rec_j
+        log(f"plain: {min(c0 + cfg.judge_chunk, jidx.size)} of {jidx.size} points, "
+            f"{t_plain_sample:.1f} s")
+    exact_j = exact_d.cpu().numpy()
     final_j = label[jidx_d].cpu().numpy()
     net_j = net_label[jidx_d].cpu().numpy()
     vj = exact_j >= 0
