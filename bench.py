@@ -138,7 +138,7 @@ def main(argv=None):
     ap.add_argument("--sur-train", type=int, default=512)
     ap.add_argument("--sur-screen", type=int, default=4096)
     ap.add_argument("--sur-phases", type=int, default=1024)
-    ap.add_argument("--sur-epochs", type=int, default=100)
+    ap.add_argument("--sur-epochs", type=int, default=200)
     ap.add_argument("--sur-judge", type=int, default=1 << 18)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
