@@ -330,9 +330,11 @@ __global__ void k_targets(const double *__restrict__ rec, int64_t n, const doubl
 }
 
 // Screening epilogue: de-standardise, label, unsure / flag, re-solve mask.
-__global__ void k_screen_epi(const float *__restrict__ out, int64_t first, int64_t m, int64_t n,
-                             const float *mean, const float *stdv, float margin, float spread,
-                             float flag_margin, int8_t *label, uint8_t *resolve, float *pmax) {
+__global__ void k_screen_epi(const float *__restrict__ out, const float *__restrict__ x,
+                             int64_t first, int64_t m, int64_t n, const float *mean,
+                             const float *stdv, float margin, float spread, float flag_margin,
+                             const float *__restrict__ emap, int G, float rough,
+                             float rough_margin, int8_t *label, uint8_t *resolve, float *pmax) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= m || first + r >= n) return;
   float mx = -INFINITY, mn = INFINITY;
@@ -344,11 +346,51 @@ __global__ void k_screen_epi(const float *__restrict__ out, int64_t first, int64
   const float ln2 = 0.69314718055994531f;
   const float d = fabsf(mx - ln2);
   const bool unsure = d < margin;
-  const bool flag = (mx - mn > spread) && d < flag_margin;
+  bool flag = (mx - mn > spread) && d < flag_margin;
+  if (emap && d < rough_margin) {
+    // nearest training node of the (normalised) input
+    int i0 = (int)floorf((x[2 * r] + 1.0f) * 0.5f * (float)(G - 1) + 0.5f);
+    int i1 = (int)floorf((x[2 * r + 1] + 1.0f) * 0.5f * (float)(G - 1) + 0.5f);
+    i0 = i0 < 0 ? 0 : (i0 >= G ? G - 1 : i0);
+    i1 = i1 < 0 ? 0 : (i1 >= G ? G - 1 : i1);
+    flag = flag || emap[i0 * G + i1] > rough;
+  }
   const int64_t i = first + r;
   if (label) label[i] = mx >= ln2 ? 1 : 0;
   if (resolve) resolve[i] = (unsure || flag) ? 1 : 0;
   if (pmax) pmax[i] = mx;
+}
+
+// Network error at each training node: |max_j yhat_j - max_j ln rec_j|
+// (NaN where the node is unused or its records hold a NaN).
+__global__ void k_node_error(const float *__restrict__ pmax, const double *__restrict__ rec,
+                             const uint8_t *__restrict__ use, int64_t n, float *err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double mx = -INFINITY;
+  bool bad = !use[i];
+  for (int j = 0; j < kOut && !bad; ++j) {
+    const double v = rec[j * n + i];
+    bad = isnan(v);
+    mx = v > mx ? v : mx;
+  }
+  err[i] = bad ? NAN : fabsf(pmax[i] - (float)log(mx));
+}
+
+// 3 x 3 maximum over the defined node errors.
+__global__ void k_max3x3(const float *__restrict__ err, int G, float *map) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)G * G) return;
+  const int a = (int)(i / G), b = (int)(i % G);
+  float m = 0.0f;
+  for (int da = -1; da <= 1; ++da)
+    for (int db = -1; db <= 1; ++db) {
+      const int aa = a + da, bb = b + db;
+      if (aa < 0 || aa >= G || bb < 0 || bb >= G) continue;
+      const float v = err[aa * G + bb];
+      if (!isnan(v)) m = fmaxf(m, v);
+    }
+  map[i] = m;
 }
 
 // Deterministic compaction of the re-solve mask: block counts, one-block
@@ -509,6 +551,8 @@ struct sur_ctx {
   float *loss_acc = nullptr;  // device scalar: sum of batch losses of an epoch
   int64_t *scan = nullptr;    // compaction scratch
   int64_t scan_cap = 0;
+  float *emap = nullptr;      // error map of the training grid [G][G]
+  int emap_G = 0;
 };
 
 namespace {
@@ -738,7 +782,7 @@ int sur_destroy(sur_t s) {
                   s->d_mean, s->d_std, s->d_dmean, s->d_dstd, s->x, s->tgt, s->z1, s->z2,
                   s->z3, s->out, s->a1, s->a1T, s->a2, s->a2T, s->a3, s->a3T, s->dz4, s->dz3,
                   s->dz2, s->dz1, s->dz4b, s->dz4bT, s->dz3b, s->dz3bT, s->dz2b, s->dz2bT,
-                  s->part, s->lpart, s->loss, s->loss_acc, s->scan};
+                  s->part, s->lpart, s->loss, s->loss_acc, s->scan, s->emap};
   for (void *p : ptrs) (void)hipFree(p);
   delete s;
   return ENS_OK;
@@ -899,7 +943,8 @@ int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *
   if (resolve_idx && !resolve)
     return sfail(s, ENS_E_INVAL, "sur_screen: resolve_idx needs the resolve mask");
   if (!s->have_norm) return sfail(s, ENS_E_ORDER, "sur_screen: call sur_set_norm first");
-  if (!(o->margin >= 0) || !(o->spread >= 0) || !(o->flag_margin >= 0))
+  if (!(o->margin >= 0) || !(o->spread >= 0) || !(o->flag_margin >= 0) ||
+      !(o->rough_margin >= 0) || std::isnan(o->rough))
     return sfail(s, ENS_E_INVAL, "sur_screen: margins must be >= 0");
   *n_resolve = 0;
   if (n == 0) return ENS_OK;
@@ -912,9 +957,12 @@ int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *
                        first, padded, s->in_lo[0], sc0, s->in_lo[1], sc1, s->x);
     SUR_HIP(s, hipGetLastError());
     SUR_HIP(s, forward_batch(s, padded, false, s->out));
+    const bool use_map = s->emap && o->rough > 0.0;
     hipLaunchKernelGGL(k_screen_epi, dim3(nblk(padded, 256)), dim3(256), 0, s->stream, s->out,
-                       first, padded, n, s->d_mean, s->d_std, (float)o->margin, (float)o->spread,
-                       (float)o->flag_margin, label, resolve, pred_max);
+                       s->x, first, padded, n, s->d_mean, s->d_std, (float)o->margin,
+                       (float)o->spread, (float)o->flag_margin,
+                       use_map ? s->emap : (const float *)nullptr, s->emap_G, (float)o->rough,
+                       (float)o->rough_margin, label, resolve, pred_max);
     SUR_HIP(s, hipGetLastError());
   }
   if (resolve) {
@@ -1008,6 +1056,54 @@ int sur_exact_labels(sur_t s, const double *records, int64_t k, const int64_t *i
                      idx, label);
   SUR_HIP(s, hipGetLastError());
   SUR_HIP(s, hipStreamSynchronize(s->stream));
+  return ENS_OK;
+}
+
+int sur_fit_error_map(sur_t s, const double *params, const double *records, const uint8_t *use,
+                      int32_t G, float *map_out) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_fit_error_map: NULL handle");
+  if (!params || !records || !use || G < 2 || G > 65536)
+    return sfail(s, ENS_E_INVAL, "sur_fit_error_map: bad arguments");
+  const int64_t n = (int64_t)G * G;
+  DevGuard dg(s->device);
+  float *pmax = nullptr, *err = nullptr;
+  SUR_HIP(s, hipMalloc((void **)&pmax, n * sizeof(float)));
+  hipError_t e = hipMalloc((void **)&err, n * sizeof(float));
+  if (e != hipSuccess) {
+    (void)hipFree(pmax);
+    return sfail(s, ENS_E_NOMEM, "sur_fit_error_map: allocation");
+  }
+  if (s->emap_G != G) {
+    (void)hipFree(s->emap);
+    s->emap = nullptr;
+    s->emap_G = 0;
+    e = hipMalloc((void **)&s->emap, n * sizeof(float));
+    if (e == hipSuccess) s->emap_G = G;
+  }
+  int64_t cnt = 0;
+  int rc = ENS_OK;
+  if (e == hipSuccess) {
+    sur_screen_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.spread = 1e30;
+    float *keep = s->emap;  // the screen below must not use a stale map
+    s->emap = nullptr;
+    rc = sur_screen(s, params, n, &o, nullptr, nullptr, pmax, nullptr, &cnt);
+    s->emap = keep;
+  }
+  if (e == hipSuccess && rc == ENS_OK) {
+    hipLaunchKernelGGL(k_node_error, dim3(nblk(n, 256)), dim3(256), 0, s->stream, pmax, records,
+                       use, n, err);
+    hipLaunchKernelGGL(k_max3x3, dim3(nblk(n, 256)), dim3(256), 0, s->stream, err, G, s->emap);
+    e = hipGetLastError();
+    if (e == hipSuccess && map_out)
+      e = hipMemcpyAsync(map_out, s->emap, n * sizeof(float), hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  }
+  (void)hipFree(pmax);
+  (void)hipFree(err);
+  if (rc != ENS_OK) return rc;
+  if (e != hipSuccess) return sfail(s, ENS_E_HIP, std::string("sur_fit_error_map: ") + hipGetErrorString(e));
   return ENS_OK;
 }
 

@@ -50,11 +50,40 @@ class Config:
     judge_chunk: int = 1 << 22     # points per plain-sweep launch
 
 
+def calibrate(d, wrong, emap, target, n_valid):
+    """Screening thresholds from held-out points: d = |max yhat - ln 2|, wrong =
+    the network's label is wrong, emap = the error map at the point.  A point
+    is re-solved if d < m0, or if emap > e and d < m1.  Returns (m0, e, m1)
+    with the fewest re-solved points among those whose uncovered wrong points
+    stay within target * n_valid (plain band: e = inf)."""
+    budget = target * n_valid
+    dw = np.sort(d[wrong])
+    best = None
+    e_cands = [np.inf] + list(np.unique(np.quantile(emap, np.linspace(0.5, 0.995, 40))))
+    m1_cands = [0.0] + list(np.unique(np.quantile(dw, np.linspace(0.05, 1.0, 40)) + 1e-7)) if dw.size else [0.0]
+    for e in e_cands:
+        rough = emap > e
+        for m1 in m1_cands:
+            covered = rough & (d < m1)
+            rest = np.sort(d[wrong & ~covered])
+            # smallest m0 leaving at most `budget` uncovered wrong points
+            k = int(np.floor(budget))
+            m0 = 0.0 if rest.size <= k else float(rest[rest.size - k - 1]) + 1e-7
+            frac = float(((d < m0) | covered).mean())
+            if best is None or frac < best[0]:
+                best = (frac, m0, float(e), float(m1))
+            if np.isinf(e):
+                break
+    return best[1], best[2], best[3]
+
+
 @dataclass
 class Report:
     config: Dict = field(default_factory=dict)
     times_s: Dict[str, float] = field(default_factory=dict)
     margin: float = 0.0
+    rough: float = 0.0
+    rough_margin: float = 0.0
     holdout_wrong_outside: float = 0.0
     holdout_resolve_frac: float = 0.0
     n_screen: int = 0
@@ -169,6 +198,9 @@ def run(cfg: Config, log=print) -> Report:
 
     # 3. calibration on the hold-out part of the coarse grid
     t0 = time.perf_counter()
+    use = np.zeros(nt, dtype=np.uint8)
+    use[train] = 1
+    emap = s.fit_error_map(Pt_d, rec_t, _dev(use), cfg.train_grid).cpu().numpy()
     Ph_d = Pt_d[:, _dev(hold)].contiguous()
     _, _, pmax_h, _ = s.screen(Ph_d, 0.0, 1e30, 0.0)
     pmax_h = pmax_h.cpu().numpy().astype(np.float64)
@@ -180,20 +212,15 @@ def run(cfg: Config, log=print) -> Report:
     valid = exact_h >= 0
     d = np.abs(pmax_h - LN2)
     wrong = ((pmax_h >= LN2).astype(np.int8) != exact_h) & valid
-    # smallest margin whose wrong-outside-band count stays within the target
-    cand = np.unique(np.concatenate([[0.0], np.sort(d[wrong]) + 1e-7]))
-    budget = cfg.target_wrong * valid.sum()
-    margin = float(cand[-1])
-    for m in cand:
-        if (wrong & (d >= m)).sum() <= budget:
-            margin = float(m)
-            break
-    rep.margin = margin
-    rep.holdout_wrong_outside = float((wrong & (d >= margin)).sum() / max(valid.sum(), 1))
-    rep.holdout_resolve_frac = float((d < margin).mean())
+    m0, e_thr, m1 = calibrate(d, wrong, emap[hold], cfg.target_wrong, int(valid.sum()))
+    res_h = (d < m0) | ((emap[hold] > e_thr) & (d < m1))
+    rep.margin, rep.rough, rep.rough_margin = m0, e_thr, m1
+    rep.holdout_wrong_outside = float((wrong & ~res_h).sum() / max(valid.sum(), 1))
+    rep.holdout_resolve_frac = float(res_h.mean())
     T["calibrate"] = time.perf_counter() - t0
-    log(f"calibration: margin {margin:.4f}, hold-out re-solve {rep.holdout_resolve_frac:.4f}, "
-        f"wrong outside {rep.holdout_wrong_outside:.4f}")
+    log(f"calibration: margin {m0:.4f}, rough {e_thr:.4f} within {m1:.4f}; hold-out "
+        f"re-solve {rep.holdout_resolve_frac:.4f}, wrong outside {rep.holdout_wrong_outside:.4f}")
+    rough_arg = e_thr if np.isfinite(e_thr) else 0.0
 
     # 4. screening of the dense grid and re-solve
     Ps, _ = I.km_grid(cfg.screen_grid, cfg.screen_grid)
@@ -201,7 +228,7 @@ def run(cfg: Config, log=print) -> Report:
     Ps_d = _dev(Ps)
     _sync()
     t0 = time.perf_counter()
-    label, resolve, pmax, idx = s.screen(Ps_d, margin, 1e30, 0.0)
+    label, resolve, pmax, idx = s.screen(Ps_d, m0, 1e30, 0.0, rough_arg, m1)
     _sync()
     T["screen"] = time.perf_counter() - t0
     rep.n_screen = ns
