@@ -204,6 +204,11 @@ void ens_default_opts(ens_solve_opts *opts);
  * until its impact budget, step cap, or a terminating status), recording
  * per phase y1max (valve: y1 at the located local maximum, and y1min) into
  * the record ring, then the library-owned state holds the final y, t, h.
+ * RKCK45 Keller--Miksis waves raise their hardware issue priority by their
+ * estimated remaining work (last phase's attempts x phases left), so that
+ * the longest systems are not slowed by short ones sharing a SIMD; results
+ * do not depend on it, and the environment variable ENS_NO_PRIORITY (set,
+ * any value) switches it off for the solves that follow.
  * Errors: ENS_E_INVAL (bad options), ENS_E_ORDER (no params or state yet),
  * ENS_E_UNSUPPORTED, ENS_E_NOMEM, ENS_E_HIP. */
 int ens_solve(ens_t h, const ens_solve_opts *opts);

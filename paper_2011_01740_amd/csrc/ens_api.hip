@@ -573,6 +573,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   a.v_stick = o->v_stick;
   a.max_steps = o->max_steps;
   a.max_event_iter = o->max_event_iter;
+  a.prioritize = std::getenv("ENS_NO_PRIORITY") ? 0 : 1;
   const bool fill_h = !h->h_init;
 
   auto enqueue = [&](hipStream_t s) -> hipError_t {

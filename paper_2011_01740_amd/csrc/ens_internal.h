@@ -44,6 +44,7 @@ struct RkckArgs {
   double t_phase, dt_min, dt_max, rtol, atol, event_tol, t_cap, v_stick;
   int64_t max_steps;
   int32_t max_event_iter;
+  int32_t prioritize;       // waves raise their issue priority by remaining work
 };
 
 // Kernel variant of the Keller--Miksis model for a polytropic exponent with

@@ -75,6 +75,7 @@ struct MQuad {  // dx/dt = x^2 - p (Sec. 3)
   static constexpr int D = 1;
   static constexpr bool kEvents = false;
   static constexpr int kMinWaves = 5;
+  static constexpr bool kPrio = false;  // issue priority by remaining work
   double p;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) { p = P[i]; }
   __device__ void begin(double) {}
@@ -87,6 +88,7 @@ struct MLorenz {  // Sec. 4.1
   static constexpr int D = 3;
   static constexpr bool kEvents = false;
   static constexpr int kMinWaves = 5;
+  static constexpr bool kPrio = false;  // issue priority by remaining work
   double rho, sigma, beta;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
     rho = P[i];
@@ -147,6 +149,7 @@ struct MKM {
   static constexpr int D = 2;
   static constexpr bool kEvents = false;
   static constexpr int kMinWaves = FAST ? 4 : 5;
+  static constexpr bool kPrio = true;  // issue priority by remaining work
   double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49;
   double s0, c0;  // sin, cos (2 pi t) at the start of the attempted step
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
@@ -206,6 +209,7 @@ struct MPRV {
   static constexpr int D = 3;
   static constexpr bool kEvents = true;
   static constexpr int kMinWaves = 5;
+  static constexpr bool kPrio = false;  // issue priority by remaining work
   double q, kappa, delta, beta, r;
   bool seated;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
@@ -274,8 +278,17 @@ struct Lane {
   double t, h, t_ps, ymax, ymin;
   int64_t n_phases, max_impacts;
   uint32_t phase, accepted, rejected, evretry, impacts, attempts;
+  uint32_t phase_att;  // attempts when the current phase began
+  float rem;           // estimated attempts left: last phase's x phases left
   int32_t status, ev_iter;
 };
+
+// Estimated work left after a completed phase.
+__device__ __forceinline__ void note_phase_end(Lane &L) {
+  const float per = (float)(L.attempts - L.phase_att);
+  L.rem = per * (float)(L.n_phases > (int64_t)L.phase ? L.n_phases - (int64_t)L.phase : 0);
+  L.phase_att = L.attempts;
+}
 
 template <class M>
 __device__ __forceinline__ void store_record(const RkckArgs &a, const Lane &L, double v0,
@@ -343,6 +356,7 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
     if (trunc) {
       store_record<M>(a, L, L.ymax, 0.0);
       L.phase++;
+      if constexpr (M::kPrio) note_phase_end(L);
       L.t = 0.0;
       L.ymax = -INFINITY;
       if (L.phase >= L.n_phases) return true;
@@ -447,6 +461,7 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
       if (phase_end) {
         store_record<MPRV>(a, L, y[0], L.ymin);
         L.phase++;
+        if constexpr (MPRV::kPrio) note_phase_end(L);
         L.ymax = -INFINITY;
         L.ymin = INFINITY;
         L.t_ps = L.t;
@@ -478,6 +493,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kM
 
   const int lane = __lane_id();
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (M::kPrio && a.prioritize) __builtin_amdgcn_s_setprio(3);
   M m;
   Lane L;
   double y[D];
@@ -511,6 +527,10 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kM
           L.n_phases = sdesc[e].n_phases;
           L.max_impacts = sdesc[e].max_impacts;
           L.phase = L.accepted = L.rejected = L.evretry = L.impacts = L.attempts = 0;
+          if constexpr (M::kPrio) {
+            L.phase_att = 0;
+            L.rem = 3.0e38f;  // unknown until the first phase ends: treat as long
+          }
           L.status = 0;
           L.ev_iter = 0;
           active = true;
@@ -525,6 +545,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kM
       if (drained) break;
       continue;
     }
+    const uint32_t ph_before = M::kPrio ? L.phase : 0u;
     if (active) {
       bool done;
       if constexpr (M::kEvents)
@@ -535,6 +556,22 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kM
         store_lane<M>(a, L, y);
         active = false;
       }
+    }
+    // Issue priority follows the wave's longest remaining work, so that the
+    // systems that will finish last are not slowed by short ones sharing the
+    // SIMD (a wave's own priority; results do not depend on it).
+    if (M::kPrio && a.prioritize && __ballot(active && L.phase != ph_before) != 0ull) {
+      float r = active ? L.rem : 0.0f;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off));
+      if (r > 1.0e6f)
+        __builtin_amdgcn_s_setprio(3);
+      else if (r > 2.5e5f)
+        __builtin_amdgcn_s_setprio(2);
+      else if (r > 6.0e4f)
+        __builtin_amdgcn_s_setprio(1);
+      else
+        __builtin_amdgcn_s_setprio(0);
     }
   }
 }

@@ -206,3 +206,16 @@ def test_zero_phases_and_empty():
     g = gpu_ck(2, P, y0, O.Opts(n_phases=0, n_record=0))
     assert np.array_equal(g.y, y0)
     assert np.all(g.stats == 0)
+
+
+def test_issue_priority_does_not_change_results(monkeypatch):
+    """Waves raising their issue priority by remaining work (the Keller--Miksis
+    kernel does by default) reorder only the hardware's scheduling: records,
+    state and counters are bit-identical with it switched off."""
+    P, y0 = I.km_grid(48, 48)
+    o = O.Opts(n_phases=5, n_record=5)
+    ref = gpu_ck(2, P, y0, o, grid=8, block=64)
+    monkeypatch.setenv("ENS_NO_PRIORITY", "1")
+    g = gpu_ck(2, P, y0, o, grid=8, block=64)
+    assert np.array_equal(g.y, ref.y) and np.array_equal(g.records, ref.records)
+    assert np.array_equal(g.stats, ref.stats) and np.array_equal(g.status, ref.status)
