@@ -151,6 +151,26 @@ int ens_set_params(ens_t h, const double *p, int32_t where);
  * Errors: ENS_E_INVAL, ENS_E_HIP. */
 int ens_set_params_gather(ens_t h, const double *p_full, int64_t n_full, const int64_t *idx);
 
+/* Order in which the RKCK45 work queue hands systems to lanes: the k-th
+ * system taken is order[k], a permutation of 0..n-1 (n entries, host or
+ * device per `where`; copied in and checked).  Every system's arithmetic is
+ * its own, so results do not depend on the order; the launch time does: a
+ * longest-first order (for instance by the attempted steps of a previous
+ * solve, ENS_STATS) keeps the longest systems from starting last and groups
+ * systems of similar length in a wavefront (the paper's advice on limiting
+ * divergence, Sec. 3.2.1).  NULL restores the index order.  RK4 ignores it.
+ * Errors: ENS_E_INVAL (not a permutation; the previous order is dropped),
+ * ENS_E_NOMEM, ENS_E_HIP. */
+int ens_set_order(ens_t h, const int64_t *order, int32_t where);
+
+/* Longest-first queue order from the last RKCK45 solve on this handle: the
+ * systems sorted by attempted steps (accepted + rejected, ENS_STATS of that
+ * solve) in decreasing order, ties in index order, become the order of
+ * ens_set_order.  Typical use: solve a few phases, call this, solve the rest
+ * (the step counts of the first phases predict those of the later ones).
+ * Errors: ENS_E_ORDER (no previous RKCK45 solve), ENS_E_NOMEM, ENS_E_HIP. */
+int ens_order_by_work(ens_t h);
+
 /* Shared parameters of sub-ensemble `ensemble` (host array of n_shared
  * doubles, n_shared == S of the model). */
 int ens_set_shared(ens_t h, int32_t ensemble, const double *shared, int32_t n_shared);

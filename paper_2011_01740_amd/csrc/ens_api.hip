@@ -11,6 +11,8 @@
 #include <tuple>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "ens_internal.h"
 
 namespace ens {
@@ -50,6 +52,8 @@ struct ens_ctx {
   int64_t *d_stats = nullptr;
   int32_t *d_status = nullptr;
   unsigned long long *d_queue = nullptr;
+  int64_t *d_order = nullptr;  // queue order (ens_set_order), valid if use_order
+  bool use_order = false;
   EnsDesc *d_desc = nullptr;
   size_t rec_cap = 0;   // doubles allocated in d_rec
   int64_t R = 0;        // record ring length of the last adaptive solve
@@ -154,6 +158,24 @@ __global__ void k_gather_params(const double *__restrict__ pf, int64_t n_full,
   for (int j = 0; j < P; ++j) p[j * n + i] = pf[j * n_full + src];
 }
 
+// Permutation check: every entry in range and every system taken once.
+__global__ void k_check_order(const int64_t *__restrict__ order, int64_t n,
+                              unsigned *__restrict__ seen, int *bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t v = order[i];
+  if (v < 0 || v >= n || atomicAdd(&seen[v], 1u) != 0u) *bad = 1;
+}
+
+// Sort keys for a longest-first queue: attempted steps of the last solve.
+__global__ void k_work_keys(const int64_t *__restrict__ stats, int64_t n,
+                            unsigned long long *__restrict__ key, int64_t *__restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = (unsigned long long)(stats[ENS_ST_ACCEPTED * n + i] + stats[ENS_ST_REJECTED * n + i]);
+  idx[i] = i;
+}
+
 // ---------------------------------------------------------------- tuning cache
 struct TuneVal {
   int block = 0, spl = 0, refill = 0;
@@ -230,6 +252,90 @@ void tune_store(int model, int solver, int device, int64_t n, const TuneVal &v) 
 }  // namespace
 
 extern "C" {
+
+int ens_set_order(ens_t h, const int64_t *order, int32_t where) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_set_order: NULL handle");
+  if (where != ENS_HOST && where != ENS_DEVICE)
+    return fail(h, ENS_E_INVAL, "ens_set_order: bad where");
+  if (!order || h->n == 0) {
+    h->use_order = false;
+    return ENS_OK;
+  }
+  DeviceGuard g(h->device);
+  const size_t bytes = (size_t)h->n * sizeof(int64_t);
+  if (!h->d_order) {
+    hipError_t e = hipMalloc((void **)&h->d_order, bytes);
+    if (e != hipSuccess) {
+      h->d_order = nullptr;
+      return fail(h, ENS_E_NOMEM, "ens_set_order: device allocation failed");
+    }
+  }
+  h->use_order = false;
+  unsigned *seen = nullptr;
+  int *bad = nullptr;
+  int hb = 0;
+  hipError_t e = hipMemcpyAsync(h->d_order, order, bytes,
+                                where == ENS_HOST ? hipMemcpyHostToDevice
+                                                  : hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess) e = hipMalloc((void **)&seen, (size_t)h->n * sizeof(unsigned) + 64);
+  if (e == hipSuccess) {
+    bad = (int *)((char *)seen + (size_t)h->n * sizeof(unsigned));
+    e = hipMemsetAsync(seen, 0, (size_t)h->n * sizeof(unsigned) + 64, h->stream);
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_check_order, dim3((unsigned)((h->n + 255) / 256)), dim3(256), 0,
+                       h->stream, h->d_order, h->n, seen, bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (seen) (void)hipFree(seen);
+  if (e != hipSuccess) return hip_fail(h, e, "ens_set_order");
+  if (hb) return fail(h, ENS_E_INVAL, "ens_set_order: not a permutation of 0..n-1");
+  h->use_order = true;
+  return ENS_OK;
+}
+
+int ens_order_by_work(ens_t h) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_order_by_work: NULL handle");
+  if (h->solver != ENS_RKCK45 || !h->have_adaptive)
+    return fail(h, ENS_E_ORDER, "ens_order_by_work: needs a previous RKCK45 solve");
+  if (h->n == 0) return ENS_OK;
+  DeviceGuard g(h->device);
+  const int64_t n = h->n;
+  if (!h->d_order) {
+    hipError_t e = hipMalloc((void **)&h->d_order, (size_t)n * sizeof(int64_t));
+    if (e != hipSuccess) {
+      h->d_order = nullptr;
+      return fail(h, ENS_E_NOMEM, "ens_order_by_work: device allocation failed");
+    }
+  }
+  h->use_order = false;
+  size_t tmp_bytes = 0;
+  hipError_t e = rocprim::radix_sort_pairs_desc(
+      nullptr, tmp_bytes, (const unsigned long long *)nullptr, (unsigned long long *)nullptr,
+      (const int64_t *)nullptr, (int64_t *)nullptr, (size_t)n, 0u, 48u, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "ens_order_by_work");
+  const size_t kb = ((size_t)n * 8 + 255) & ~(size_t)255;
+  char *buf = nullptr;
+  e = hipMalloc((void **)&buf, 3 * kb + tmp_bytes);
+  if (e != hipSuccess) return fail(h, ENS_E_NOMEM, "ens_order_by_work: device allocation failed");
+  auto *key_in = (unsigned long long *)buf;
+  auto *key_out = (unsigned long long *)(buf + kb);
+  auto *idx_in = (int64_t *)(buf + 2 * kb);
+  hipLaunchKernelGGL(k_work_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
+                     h->d_stats, n, key_in, idx_in);
+  e = hipGetLastError();
+  // radix sort is stable: systems of equal work keep their index order
+  if (e == hipSuccess)
+    e = rocprim::radix_sort_pairs_desc(buf + 3 * kb, tmp_bytes, key_in, key_out, idx_in,
+                                       h->d_order, (size_t)n, 0u, 48u, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return hip_fail(h, e, "ens_order_by_work");
+  h->use_order = true;
+  return ENS_OK;
+}
 
 int ens_set_params_gather(ens_t h, const double *p_full, int64_t n_full, const int64_t *idx) {
   if (!h) return fail(nullptr, ENS_E_INVAL, "ens_set_params_gather: NULL handle");
@@ -372,6 +478,7 @@ int ens_destroy(ens_t h) {
   (void)hipFree(h->d_stats);
   (void)hipFree(h->d_status);
   (void)hipFree(h->d_queue);
+  (void)hipFree(h->d_order);
   (void)hipFree(h->d_desc);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
@@ -558,6 +665,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   a.stats = h->d_stats;
   a.status = h->d_status;
   a.queue = h->d_queue;
+  a.order = h->use_order ? h->d_order : nullptr;
   a.desc = h->d_desc;
   a.n = h->n;
   a.R = R;

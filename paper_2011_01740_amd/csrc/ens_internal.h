@@ -35,7 +35,8 @@ struct RkckArgs {
   double *rec;              // [R][F][n] or null
   int64_t *stats;           // [ENS_NSTAT][n]
   int32_t *status;          // [n]
-  unsigned long long *queue;// next unclaimed system index
+  unsigned long long *queue;// next unclaimed queue position
+  const int64_t *order;     // [n] system taken at each queue position, or null
   const EnsDesc *desc;      // [n_ens]
   int64_t n;
   int64_t R;

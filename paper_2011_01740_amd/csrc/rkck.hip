@@ -512,7 +512,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kM
       if (!active) {
         const unsigned long long me = base + (unsigned long long)__popcll(idle & below);
         if (me < (unsigned long long)a.n) {
-          const int64_t i = (int64_t)me;
+          const int64_t i = a.order ? a.order[me] : (int64_t)me;
           int e = 0;
           while (e + 1 < a.n_ens && i >= sdesc[e].last) ++e;
           m.init(a.p, a.n, i, sdesc[e].shared);

@@ -83,6 +83,8 @@ def load():
     L.ens_tune.argtypes = [vp, C.POINTER(ens_solve_opts), i64, C.POINTER(ens_solve_opts),
                            C.POINTER(C.c_float)]
     L.ens_set_params_gather.argtypes = [vp, vp, i64, vp]
+    L.ens_set_order.argtypes = [vp, vp, i32]
+    L.ens_order_by_work.argtypes = [vp]
     _lib = L
     return L
 
@@ -167,6 +169,29 @@ class Ensemble:
         ptr, where, keep = self._in(p, (self.P, self.n))
         _check(load().ens_set_params(self.h, ptr, where), self.h)
         self._keep_p = keep
+
+    def set_order(self, order):
+        """Queue order of the adaptive solver: the k-th system taken is
+        order[k] (a permutation of 0..n-1, int64, host or device); None
+        restores the index order."""
+        if order is None:
+            _check(load().ens_set_order(self.h, None, ENS_HOST), self.h)
+            return
+        if _is_torch(order) and order.is_cuda:
+            import torch
+            t = order.to(dtype=torch.int64).contiguous()
+            if t.numel() != self.n:
+                raise ValueError(f"expected {self.n} entries, got {t.numel()}")
+            _check(load().ens_set_order(self.h, C.c_void_p(t.data_ptr()), ENS_DEVICE), self.h)
+            return
+        a = np.ascontiguousarray(np.asarray(order, dtype=np.int64))
+        if a.size != self.n:
+            raise ValueError(f"expected {self.n} entries, got {a.size}")
+        _check(load().ens_set_order(self.h, C.c_void_p(a.ctypes.data), ENS_HOST), self.h)
+
+    def order_by_work(self):
+        """Longest-first queue order from the last adaptive solve's step counts."""
+        _check(load().ens_order_by_work(self.h), self.h)
 
     def set_shared(self, ensemble: int, shared):
         a = np.ascontiguousarray(np.asarray(shared, dtype=np.float64))

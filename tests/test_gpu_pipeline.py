@@ -61,8 +61,9 @@ def test_exact_labels_from_records():
 
 def test_screened_sweep_reduced_configuration():
     from paper_2011_01740_amd import surrogate as S
-    cfg = S.Config(train_grid=64, screen_grid=256, n_phases=64, epochs=40, batch=512,
-                   judge_n=0, target_wrong=0.005)
+    # 128 cycles: a 64-cycle pilot, then the longest-first queue order
+    cfg = S.Config(train_grid=64, screen_grid=256, n_phases=128, epochs=40, batch=512,
+                   judge_n=0, target_wrong=0.005, pilot=64)
     rep = S.run(cfg, log=lambda *a: print(*a, flush=True))
     # every re-solved point carries the exact label, so errors sit outside the band
     assert rep.judge_points == 256 * 256

@@ -219,3 +219,56 @@ def test_issue_priority_does_not_change_results(monkeypatch):
     g = gpu_ck(2, P, y0, o, grid=8, block=64)
     assert np.array_equal(g.y, ref.y) and np.array_equal(g.records, ref.records)
     assert np.array_equal(g.stats, ref.stats) and np.array_equal(g.status, ref.status)
+
+
+def test_queue_order_does_not_change_results():
+    """A permuted queue order (ens_set_order) changes which lane takes which
+    system and when, never a system's arithmetic; bad orders are refused."""
+    ens = _ens()
+    P, y0 = I.km_grid(40, 40)
+    n = P.shape[1]
+    o = O.Opts(n_phases=4, n_record=4)
+    ref = gpu_ck(2, P, y0, o, grid=4, block=64)
+    for order in (np.arange(n)[::-1], np.random.default_rng(3).permutation(n)):
+        with ens.Ensemble(ens.ENS_KM, ens.ENS_RKCK45, n) as e:
+            e.set_params(P)
+            e.set_state(y0)
+            e.set_order(order)
+            e.solve(n_phases=4, n_record=4, grid=4, block=64)
+            assert np.array_equal(e.read(ens.ENS_RECORDS), ref.records)
+            assert np.array_equal(e.read(ens.ENS_STATE), ref.y)
+            assert np.array_equal(e.read(ens.ENS_STATS), ref.stats)
+    with ens.Ensemble(ens.ENS_KM, ens.ENS_RKCK45, n) as e:
+        bad = np.arange(n)
+        bad[5] = 6
+        with pytest.raises(ens.EnsError):
+            e.set_order(bad)
+        bad[5] = n
+        with pytest.raises(ens.EnsError):
+            e.set_order(bad)
+        e.set_order(None)
+
+
+def test_longest_first_continuation_is_bit_identical():
+    """Pilot phases, ens_order_by_work, then the remaining phases: the same
+    state, step size and records as one uninterrupted solve."""
+    ens = _ens()
+    P, y0 = I.km_grid(32, 32)
+    n = P.shape[1]
+    full = gpu_ck(2, P, y0, O.Opts(n_phases=6, n_record=3), grid=4, block=64)
+    with ens.Ensemble(ens.ENS_KM, ens.ENS_RKCK45, n) as e:
+        e.set_params(P)
+        e.set_state(y0)
+        with pytest.raises(ens.EnsError):
+            e.order_by_work()           # no adaptive solve yet
+        e.solve(n_phases=3, n_record=3, grid=4, block=64)
+        pilot = e.read(ens.ENS_STATS)
+        e.order_by_work()
+        e.solve(n_phases=3, n_record=3, grid=4, block=64)
+        assert np.array_equal(e.read(ens.ENS_STATE), full.y)
+        assert np.array_equal(e.read(ens.ENS_H), full.h)
+        assert np.array_equal(e.read(ens.ENS_RECORDS), full.records)
+        rest = e.read(ens.ENS_STATS)
+    # per-solve counters add up to the uninterrupted solve's
+    for row in (O.ST_ACCEPTED, O.ST_REJECTED, O.ST_PHASES):
+        assert np.array_equal(pilot[row] + rest[row], full.stats[row])
