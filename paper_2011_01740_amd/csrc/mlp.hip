@@ -12,9 +12,11 @@
 // The forward epilogue therefore also writes each activation transposed, the
 // backward epilogue each gradient transposed, and the optimiser refreshes
 // both W and W^T in BF16.  Operands are read as 16-byte vectors straight
-// from global memory (the weights stay in L2); weight gradients are split
-// over the batch and the partial sums reduced in a fixed order, so every
-// result is deterministic.
+// from global memory (the weights stay in L2), a whole group of K steps at a
+// time.  Weight gradients are split over the batch; bias and layer-1
+// gradients are column sums that the backward epilogue forms per 32-row
+// tile; one kernel then reduces every partial sum in a fixed order, so every
+// result is deterministic.  A training step is 13 launches.
 //
 // MFMA 16x16x32 BF16 operand layout (lane l, 64 lanes): A fragment = row
 // (l mod 16), k = 8 (l / 16) + 0..7; B fragment = column (l mod 16), same k;
@@ -52,27 +54,6 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 }
 
 // ---------------------------------------------------------------- GEMM tile
-__device__ __forceinline__ void mma_tile(const bf16 *__restrict__ X, int64_t ldx,
-                                         const bf16 *__restrict__ Y, int64_t ldy, int64_t r0,
-                                         int64_t c0, int64_t kb, int64_t ke, f32x4 acc[4][4]) {
-  const int l = threadIdx.x & 63;
-  const int64_t lr = l & 15, lk = (l >> 4) * 8;
-  const bf16 *xp = X + (r0 + lr) * ldx + lk;
-  const bf16 *yp = Y + (c0 + lr) * ldy + lk;
-  for (int64_t k = kb; k < ke; k += 32) {
-    bf16x8 a[4], b[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8 *)(xp + 16 * i * ldx + k);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8 *)(yp + 16 * j * ldy + k);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-  }
-}
-
 enum Epi { EPI_FWD_GELU = 0, EPI_FWD_LINEAR = 1, EPI_BWD_GELU = 2, EPI_PARTIAL = 3,
            EPI_FWD_GELU_ACT = 4 };
 
@@ -87,27 +68,86 @@ struct GemmArgs {
   float *out_f32;        // [R][C], or [split][R][C] partial sums
   bf16 *out_bf16;        // [R][C]
   bf16 *out_bf16T;       // [C][R]
+  // backward epilogue: column sums of the result over each 32-row tile
+  float *colpart;        // [R/32][C]: sum_r dZ[r][c]              (bias gradient)
+  const float *xin;      // [R][2] layer inputs; with it also
+  float *colpart_x0;     // [R/32][C]: sum_r dZ[r][c] x[r][0]      (layer-1 weights)
+  float *colpart_x1;     // [R/32][C]: sum_r dZ[r][c] x[r][1]
 };
 
-// One wave per 64 x 64 output tile; grid (C/64, R/64, split).
-template <int EPI>
-__global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
-  const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
-  const int64_t kchunk = g.K / gridDim.z;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
-  f32x4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  mma_tile(g.X, g.ldx, g.Y, g.ldy, r0, c0, kb, kb + kchunk, acc);
+constexpr int kTile = 32;  // output tile edge per wave
 
+// One wave per 32 x 32 output tile (2 x 2 accumulators); grid (R/32, C/32,
+// split): consecutive blocks share the rows of X, and blocks are spread over
+// the XCDs by block index, so each XCD reads its own share of X.  The K range
+// is taken KG MFMA steps (32 each) at a time: all operand loads of a group are
+// issued before its products, so one memory latency covers KG steps.
+template <int EPI, int KG>
+__global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
+  const int64_t r0 = (int64_t)blockIdx.x * kTile, c0 = (int64_t)blockIdx.y * kTile;
+  const int64_t kchunk = g.K / gridDim.z;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = kb + kchunk;
   const int l = threadIdx.x & 63;
+  const int64_t lr = l & 15, lk = (l >> 4) * 8;
   const int64_t lc = l & 15, lrow = (l >> 4) * 4;
+  // epilogue operands fetched ahead of the products
+  float zp[2][2][4];
+  if (EPI == EPI_BWD_GELU) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          zp[i][j][q] = g.zprev[(r0 + 16 * i + lrow + q) * g.C + c0 + 16 * j + lc];
+  }
+  float xr[2][4][2];
+  if (EPI == EPI_BWD_GELU && g.xin) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        xr[i][q][0] = g.xin[2 * (r0 + 16 * i + lrow + q)];
+        xr[i][q][1] = g.xin[2 * (r0 + 16 * i + lrow + q) + 1];
+      }
+  }
+  float bj[2] = {0.f, 0.f};
+  if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR || EPI == EPI_FWD_GELU_ACT) {
+    bj[0] = g.bias[c0 + lc];
+    bj[1] = g.bias[c0 + 16 + lc];
+  }
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16 *xp = g.X + (r0 + lr) * g.ldx + lk;
+  const bf16 *yp = g.Y + (c0 + lr) * g.ldy + lk;
+  for (int64_t k = kb; k < ke; k += 32 * KG) {
+    bf16x8 a[KG][2], b[KG][2];
+#pragma unroll
+    for (int u = 0; u < KG; ++u) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[u][i] = *(const bf16x8 *)(xp + 16 * i * g.ldx + k + 32 * u);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[u][j] = *(const bf16x8 *)(yp + 16 * j * g.ldy + k + 32 * u);
+    }
+    // keep the whole group of loads ahead of the products
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < KG; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][i], b[u][j], acc[i][j], 0, 0, 0);
+  }
+
+  float res[2][2][4];  // backward: dZ of the tile, for the column sums
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
       const int64_t c = c0 + 16 * j + lc;
       const int64_t rb = r0 + 16 * i + lrow;
       float v[4];
@@ -120,9 +160,8 @@ __global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
         continue;
       }
       if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR || EPI == EPI_FWD_GELU_ACT) {
-        const float b = g.bias[c];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += b;
+        for (int q = 0; q < 4; ++q) v[q] += bj[j];
       }
       if (EPI == EPI_FWD_LINEAR) {
 #pragma unroll
@@ -139,7 +178,10 @@ __global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
         for (int q = 0; q < 4; ++q) a[q] = gelu_f(v[q]);
       } else {  // EPI_BWD_GELU
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = v[q] * gelu_grad_f(g.zprev[(rb + q) * g.C + c]);
+        for (int q = 0; q < 4; ++q) {
+          a[q] = v[q] * gelu_grad_f(zp[i][j][q]);
+          res[i][j][q] = a[q];
+        }
         if (g.out_f32) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) g.out_f32[(rb + q) * g.C + c] = a[q];
@@ -155,134 +197,216 @@ __global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
       }
     }
   }
+  if (EPI == EPI_BWD_GELU && g.colpart) {
+    // per column: the lane's 8 rows, then the 4 lane groups, in a fixed order
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          s0 += res[i][j][q];
+          if (g.xin) {
+            s1 = fmaf(res[i][j][q], xr[i][q][0], s1);
+            s2 = fmaf(res[i][j][q], xr[i][q][1], s2);
+          }
+        }
+      s0 += __shfl_xor(s0, 16);
+      s0 += __shfl_xor(s0, 32);
+      if (g.xin) {
+        s1 += __shfl_xor(s1, 16);
+        s1 += __shfl_xor(s1, 32);
+        s2 += __shfl_xor(s2, 16);
+        s2 += __shfl_xor(s2, 32);
+      }
+      if (l < 16) {
+        const int64_t o = (int64_t)blockIdx.x * g.C + c0 + 16 * j + lc;
+        g.colpart[o] = s0;
+        if (g.xin) {
+          g.colpart_x0[o] = s1;
+          g.colpart_x1[o] = s2;
+        }
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------- small kernels
 // Layer 1 (K = 2) on the vector unit: z = x W1^T + b1, a = GELU(z).
-__global__ void k_layer1(const float *__restrict__ x, const float *__restrict__ P, int64_t m,
-                         float *z, bf16 *a, bf16 *aT) {
+// With rows != NULL, batch row r is dataset row rows[r] of x, and the
+// gathered inputs are also written to xg (for the layer-1 gradients).  Each
+// thread computes one element in row-major order (z, a) and, when aT is
+// wanted, one in transposed order, so that both stores are coalesced.
+__global__ void k_layer1(const float *__restrict__ x, const int64_t *__restrict__ rows,
+                         float *xg, const float *__restrict__ P, int64_t m, float *z, bf16 *a,
+                         bf16 *aT) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * kH) return;
-  const int64_t r = idx / kH, n = idx % kH;
-  const float v = fmaf(x[2 * r + 1], P[oW1 + 2 * n + 1], fmaf(x[2 * r], P[oW1 + 2 * n], P[ob1 + n]));
-  if (z) z[idx] = v;
-  const bf16 g = (bf16)gelu_f(v);
-  a[idx] = g;
-  if (aT) aT[n * m + r] = g;
-}
-
-// dZ of the output layer: 2 (out - t) / (m * 64), with per-block partial sums
-// of (out - t)^2 for the loss.
-__global__ __launch_bounds__(256) void k_loss_grad(const float *__restrict__ out,
-                                                   const float *__restrict__ t, int64_t m,
-                                                   float *dz, bf16 *dzb, bf16 *dzbT,
-                                                   float *partial) {
-  __shared__ float red[256];
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float sq = 0.f;
-  if (idx < m * kOut) {
-    const float d = out[idx] - t[idx];
-    sq = d * d;
-    const float g = 2.0f * d / (float)(m * kOut);
-    dz[idx] = g;
-    dzb[idx] = (bf16)g;
-    const int64_t r = idx / kOut, c = idx % kOut;
-    dzbT[c * m + r] = (bf16)g;
-  }
-  red[threadIdx.x] = sq;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-
-// loss = sum(partial) / count, fixed order (one block)
-__global__ __launch_bounds__(256) void k_loss_final(const float *partial, int64_t nb,
-                                                    float count, float *loss) {
-  __shared__ float red[256];
-  float s = 0.f;
-  for (int64_t i = threadIdx.x; i < nb; i += 256) s += partial[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *loss = red[0] / count;
-}
-
-// Column sums (bias gradients): out[c] = sum_r dz[r][c], one block per column.
-__global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ dz, int64_t R,
-                                                int64_t C, float *out) {
-  __shared__ float red[256];
-  const int64_t c = blockIdx.x;
-  float s = 0.f;
-  for (int64_t r = threadIdx.x; r < R; r += 256) s += dz[r * C + c];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[c] = red[0];
-}
-
-// Layer-1 weight and bias gradients on the vector unit, one block per unit n.
-__global__ __launch_bounds__(256) void k_layer1_grad(const float *__restrict__ dz1,
-                                                     const float *__restrict__ x, int64_t m,
-                                                     float *G) {
-  __shared__ float r0[256], r1[256], r2[256];
-  const int n = blockIdx.x;
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-  for (int64_t r = threadIdx.x; r < m; r += 256) {
-    const float d = dz1[r * kH + n];
-    s0 = fmaf(d, x[2 * r], s0);
-    s1 = fmaf(d, x[2 * r + 1], s1);
-    s2 += d;
-  }
-  r0[threadIdx.x] = s0;
-  r1[threadIdx.x] = s1;
-  r2[threadIdx.x] = s2;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) {
-      r0[threadIdx.x] += r0[threadIdx.x + k];
-      r1[threadIdx.x] += r1[threadIdx.x + k];
-      r2[threadIdx.x] += r2[threadIdx.x + k];
+  {
+    const int64_t r = idx / kH, n = idx % kH;
+    const int64_t src = rows ? rows[r] : r;
+    const float x0 = x[2 * src], x1 = x[2 * src + 1];
+    if (rows && n == 0) {
+      xg[2 * r] = x0;
+      xg[2 * r + 1] = x1;
     }
-    __syncthreads();
+    const float v = fmaf(x1, P[oW1 + 2 * n + 1], fmaf(x0, P[oW1 + 2 * n], P[ob1 + n]));
+    if (z) z[idx] = v;
+    a[idx] = (bf16)gelu_f(v);
   }
+  if (aT) {
+    const int64_t n = idx / m, r = idx % m;
+    const int64_t src = rows ? rows[r] : r;
+    const float v = fmaf(x[2 * src + 1], P[oW1 + 2 * n + 1],
+                         fmaf(x[2 * src], P[oW1 + 2 * n], P[ob1 + n]));
+    aT[idx] = (bf16)gelu_f(v);
+  }
+}
+
+// dZ of the output layer, 2 (out - t) / (m * 64), for a block of 32 rows
+// (256 threads: column t mod 64, rows 8 (t / 64) + 0..7).  Target row r is
+// t[rows[r]] when rows is given.  Per block: column sums of dZ (bias
+// gradient) and the sum of (out - t)^2 (loss), in a fixed order.
+__global__ __launch_bounds__(256) void k_loss_grad(const float *__restrict__ out,
+                                                   const float *__restrict__ t,
+                                                   const int64_t *__restrict__ rows, int64_t m,
+                                                   bf16 *dzb, bf16 *dzbT, float *colpart,
+                                                   float *lpart) {
+  __shared__ float cs[4][kOut];
+  __shared__ float sq4[4][kOut];
+  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * 32 + rg * 8;
+  const float scale = 2.0f / (float)(m * kOut);
+  float cs_ = 0.f, sq = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int64_t r = r0 + k;
+    const int64_t src = rows ? rows[r] : r;
+    const float d = out[r * kOut + c] - t[src * kOut + c];
+    sq = fmaf(d, d, sq);
+    const float g = scale * d;
+    cs_ += g;
+    const bf16 gb = (bf16)g;
+    dzb[r * kOut + c] = gb;
+    dzbT[c * m + r] = gb;
+  }
+  cs[rg][c] = cs_;
+  sq4[rg][c] = sq;
+  __syncthreads();
+  if (rg == 0) {
+    colpart[blockIdx.x * kOut + c] = ((cs[0][c] + cs[1][c]) + cs[2][c]) + cs[3][c];
+    sq4[0][c] = ((sq4[0][c] + sq4[1][c]) + sq4[2][c]) + sq4[3][c];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    G[oW1 + 2 * n] = r0[0];
-    G[oW1 + 2 * n + 1] = r1[0];
-    G[ob1 + n] = r2[0];
+    float v = 0.f;
+    for (int k = 0; k < kOut; ++k) v += sq4[0][k];
+    lpart[blockIdx.x] = v;
   }
 }
 
-// dW = sum over the split partials in order.
-__global__ void k_reduce_split(const float *__restrict__ part, int split, int64_t count,
-                               float *out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  float s = 0.f;
-  for (int k = 0; k < split; ++k) s += part[k * count + i];
-  out[i] = s;
+// Gradients of all parameters from the partial sums of one batch of m rows
+// (T = m / 32 row tiles, S weight-gradient splits), each summed in a fixed
+// order, and the batch loss; acc (optional) accumulates the loss.
+struct GradParts {
+  const float *w1x0, *w1x1, *b1;  // [T][256]
+  const float *w2, *w3;           // [S][256][256]
+  const float *b2, *b3;           // [T][256]
+  const float *w4;                // [S][64][256]
+  const float *b4;                // [T][64]
+  const float *lpart;             // [T]
+};
+constexpr int64_t kNW = 2 * kH * kH + kOut * kH;   // weights of the MFMA layers
+constexpr int kNColSums = 5 * kH + kOut + 1;        // W1 (2 x 256), b1..b4, loss
+constexpr int kReduceWBlocks = (int)((kNW + 255) / 256);
+// Blocks [0, kReduceWBlocks): one weight per thread (S partials).  The
+// following blocks: one wave per tile-summed entry (T partials: lane l takes
+// tiles l, l + 64, ..., then a butterfly over the wave).
+__global__ __launch_bounds__(256) void k_reduce_grads(GradParts p, int64_t T, int S,
+                                                      float count, float *G, float *loss,
+                                                      float *acc, int first) {
+  if ((int)blockIdx.x < kReduceWBlocks) {
+    const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (w >= kNW) return;
+    const float *src;
+    int64_t o, stride;
+    if (w < kH * kH) {
+      src = p.w2 + w; o = oW2 + w; stride = kH * kH;
+    } else if (w < 2 * kH * kH) {
+      src = p.w3 + (w - kH * kH); o = oW3 + (w - kH * kH); stride = kH * kH;
+    } else {
+      src = p.w4 + (w - 2 * kH * kH); o = oW4 + (w - 2 * kH * kH); stride = kOut * kH;
+    }
+    float g = 0.f;
+    for (int k = 0; k < S; ++k) g += src[k * stride];
+    G[o] = g;
+    return;
+  }
+  const int e = ((int)blockIdx.x - kReduceWBlocks) * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (e >= kNColSums) return;
+  const float *src;
+  int64_t ld;
+  float *dst;
+  if (e < kH) {
+    src = p.w1x0 + e; ld = kH; dst = G + oW1 + 2 * e;
+  } else if (e < 2 * kH) {
+    src = p.w1x1 + (e - kH); ld = kH; dst = G + oW1 + 2 * (e - kH) + 1;
+  } else if (e < 3 * kH) {
+    src = p.b1 + (e - 2 * kH); ld = kH; dst = G + ob1 + (e - 2 * kH);
+  } else if (e < 4 * kH) {
+    src = p.b2 + (e - 3 * kH); ld = kH; dst = G + ob2 + (e - 3 * kH);
+  } else if (e < 5 * kH) {
+    src = p.b3 + (e - 4 * kH); ld = kH; dst = G + ob3 + (e - 4 * kH);
+  } else if (e < 5 * kH + kOut) {
+    src = p.b4 + (e - 5 * kH); ld = kOut; dst = G + ob4 + (e - 5 * kH);
+  } else {
+    src = p.lpart; ld = 1; dst = nullptr;
+  }
+  float v = 0.f;
+  for (int64_t t = l; t < T; t += 64) v += src[t * ld];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (l == 0) {
+    if (dst) {
+      *dst = v;
+    } else {
+      const float lv = v / count;
+      *loss = lv;
+      if (acc) *acc = first ? lv : *acc + lv;
+    }
+  }
 }
 
-// Adam on the FP32 master parameters (Kingma and Ba, 2015).
+// Adam on the FP32 master parameters (Kingma and Ba, 2015); the BF16 copies
+// of W2, W3, W4 and their transposes follow the updated values.
 __global__ void k_adam(float *__restrict__ P, const float *__restrict__ G, float *__restrict__ Mm,
-                       float *__restrict__ V, int64_t count, float lr, float b1, float b2,
-                       float eps, float c1, float c2) {
+                       float *__restrict__ V, float lr, float b1, float b2, float eps, float c1,
+                       float c2, bf16 *W2, bf16 *W2T, bf16 *W3, bf16 *W3T, bf16 *W4, bf16 *W4T) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
+  if (i >= kNP) return;
   const float g = G[i];
   const float m = fmaf(b1, Mm[i], (1.0f - b1) * g);
   const float v = fmaf(b2, V[i], (1.0f - b2) * g * g);
   Mm[i] = m;
   V[i] = v;
-  P[i] -= lr * (m * c1) / (sqrtf(v * c2) + eps);
+  const float w = P[i] - lr * (m * c1) / (sqrtf(v * c2) + eps);
+  P[i] = w;
+  const bf16 wb = (bf16)w;
+  if (i >= oW2 && i < ob2) {
+    const int64_t k = i - oW2, o = k / kH, in = k % kH;
+    W2[k] = wb;
+    W2T[in * kH + o] = wb;
+  } else if (i >= oW3 && i < ob3) {
+    const int64_t k = i - oW3, o = k / kH, in = k % kH;
+    W3[k] = wb;
+    W3T[in * kH + o] = wb;
+  } else if (i >= oW4 && i < ob4) {
+    const int64_t k = i - oW4, o = k / kH, in = k % kH;
+    W4[k] = wb;
+    W4T[in * kOut + o] = wb;
+  }
 }
 
 // BF16 copies of W2, W3, W4 and their transposes from the master weights.
@@ -488,22 +612,6 @@ __global__ __launch_bounds__(256) void k_logstd(const double *__restrict__ rec, 
   if (threadIdx.x == 0) stdv[j] = sqrt(red[0] / (double)n);
 }
 
-// Rows perm[b0 .. b0 + m) of the dataset into the batch buffers.
-__global__ void k_gather_batch(const float *__restrict__ x, const float *__restrict__ y,
-                               const int64_t *__restrict__ perm, int64_t b0, int64_t m,
-                               float *bx, float *by) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= m * kOut) return;
-  const int64_t r = idx / kOut, j = idx % kOut;
-  const int64_t src = perm[b0 + r];
-  by[idx] = y[src * kOut + j];
-  if (j < kIn) bx[r * kIn + j] = x[src * kIn + j];
-}
-
-__global__ void k_accumulate(const float *v, float *acc, int first) {
-  if (threadIdx.x == 0) *acc = first ? *v : *acc + *v;
-}
-
 // label[idx[i]] = [max_j rec[j][i] >= 2]; -1 if any record is NaN.
 __global__ void k_exact_labels(const double *__restrict__ rec, int64_t k,
                                const int64_t *__restrict__ idx, int8_t *label) {
@@ -542,10 +650,13 @@ struct sur_ctx {
   // activations of one batch
   float *x = nullptr, *tgt = nullptr, *z1 = nullptr, *z2 = nullptr, *z3 = nullptr, *out = nullptr;
   bf16 *a1 = nullptr, *a1T = nullptr, *a2 = nullptr, *a2T = nullptr, *a3 = nullptr, *a3T = nullptr;
-  float *dz4 = nullptr, *dz3 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
   bf16 *dz4b = nullptr, *dz4bT = nullptr, *dz3b = nullptr, *dz3bT = nullptr, *dz2b = nullptr,
        *dz2bT = nullptr;
-  float *part = nullptr;      // split-K partial weight gradients
+  // partial sums of the gradients: split-K weight products, per-32-row-tile
+  // column sums (biases, layer-1 weights), loss
+  float *part2 = nullptr, *part3 = nullptr, *part4 = nullptr;
+  float *cp1 = nullptr, *cpx0 = nullptr, *cpx1 = nullptr, *cp2 = nullptr, *cp3 = nullptr,
+        *cp4 = nullptr;
   float *lpart = nullptr;     // loss partials
   float *loss = nullptr;      // device scalar
   float *loss_acc = nullptr;  // device scalar: sum of batch losses of an epoch
@@ -553,15 +664,24 @@ struct sur_ctx {
   int64_t scan_cap = 0;
   float *emap = nullptr;      // error map of the training grid [G][G]
   int emap_G = 0;
+  // inference workspace (sur_forward, sur_screen): kInferRows rows, allocated
+  // on first use
+  float *ix = nullptr, *iout = nullptr;
+  bf16 *ia1 = nullptr, *ia2 = nullptr, *ia3 = nullptr;
 };
 
 namespace {
 
-constexpr int kSplit = 8;  // largest batch split of the weight-gradient products
+constexpr int kSplit = 16;  // largest batch split of the weight-gradient products
 
-// Batch split of a weight-gradient product: every chunk must hold a multiple
-// of 32 rows (one MFMA reduction step); m is a multiple of 64.
-int wgrad_split(int64_t m) { return m % (32 * 8) == 0 ? 8 : (m % (32 * 4) == 0 ? 4 : 2); }
+// Batch split of a weight-gradient product: chunks of 256 rows where the
+// batch allows (at most kSplit of them), else chunks of a multiple of 64 rows
+// (m is a multiple of 64).
+int wgrad_split(int64_t m) {
+  for (int s = kSplit; s > 1; s >>= 1)
+    if (m % (64 * s) == 0 && m / s >= 256) return s;
+  return 1;
+}
 
 thread_local std::string g_serr;
 
@@ -596,10 +716,14 @@ hipError_t alloc(T **p, int64_t count) {
 
 unsigned nblk(int64_t count, int b) { return (unsigned)((count + b - 1) / b); }
 
+// R, C multiples of 32; K / split a multiple of 64.
 template <int EPI>
 hipError_t gemm(hipStream_t st, const GemmArgs &g, int split = 1) {
-  dim3 grid((unsigned)(g.C / 64), (unsigned)(g.R / 64), (unsigned)split);
-  hipLaunchKernelGGL(k_gemm<EPI>, grid, dim3(64), 0, st, g);
+  dim3 grid((unsigned)(g.R / kTile), (unsigned)(g.C / kTile), (unsigned)split);
+  if ((g.K / split) % 256 == 0)
+    hipLaunchKernelGGL((k_gemm<EPI, 8>), grid, dim3(64), 0, st, g);
+  else
+    hipLaunchKernelGGL((k_gemm<EPI, 2>), grid, dim3(64), 0, st, g);
   return hipGetLastError();
 }
 
@@ -617,84 +741,133 @@ GemmArgs gargs(const bf16 *X, int64_t ldx, const bf16 *Y, int64_t ldy, int64_t R
   return g;
 }
 
-// Forward pass of one batch of m rows (m % 64 == 0) from s->x.  train: keep
-// the pre-activations and transposed activations for the backward pass.
-hipError_t forward_batch(sur_ctx *s, int64_t m, bool train, float *out) {
+// Buffers of one forward pass; z* and a*T (kept for the backward pass) are
+// NULL for inference.
+struct Fwd {
+  float *x;
+  bf16 *a1, *a2, *a3;
+  float *z1, *z2, *z3;
+  bf16 *a1T, *a2T, *a3T;
+  float *out;
+};
+
+Fwd train_bufs(sur_ctx *s) {
+  return Fwd{s->x, s->a1, s->a2, s->a3, s->z1, s->z2, s->z3, s->a1T, s->a2T, s->a3T, s->out};
+}
+
+constexpr int64_t kInferRows = 65536;
+
+Fwd infer_bufs(sur_ctx *s) {
+  return Fwd{s->ix, s->ia1, s->ia2, s->ia3, nullptr, nullptr, nullptr, nullptr, nullptr,
+             nullptr, s->iout};
+}
+
+hipError_t ensure_infer(sur_ctx *s) {
+  if (s->ix) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMalloc((void **)&s->ix, kInferRows * kIn * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void **)&s->iout, kInferRows * kOut * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void **)&s->ia1, kInferRows * kH * sizeof(bf16));
+  if (e == hipSuccess) e = hipMalloc((void **)&s->ia2, kInferRows * kH * sizeof(bf16));
+  if (e == hipSuccess) e = hipMalloc((void **)&s->ia3, kInferRows * kH * sizeof(bf16));
+  if (e != hipSuccess) {
+    (void)hipFree(s->ix); (void)hipFree(s->iout); (void)hipFree(s->ia1);
+    (void)hipFree(s->ia2); (void)hipFree(s->ia3);
+    s->ix = s->iout = nullptr;
+    s->ia1 = s->ia2 = s->ia3 = nullptr;
+  }
+  return e;
+}
+
+// Forward pass of one batch of m rows (m % 64 == 0): inputs from b.x, or
+// with rows != NULL dataset rows rows[0..m) of xsrc (gathered into b.x).
+hipError_t forward_batch(sur_ctx *s, const Fwd &b, int64_t m, const int64_t *rows = nullptr,
+                         const float *xsrc = nullptr) {
   hipStream_t st = s->stream;
-  hipLaunchKernelGGL(k_layer1, dim3(nblk(m * kH, 256)), dim3(256), 0, st, s->x, s->P, m,
-                     train ? s->z1 : nullptr, s->a1, train ? s->a1T : nullptr);
+  const bool train = b.z1 != nullptr;
+  hipLaunchKernelGGL(k_layer1, dim3(nblk(m * kH, 256)), dim3(256), 0, st, rows ? xsrc : b.x,
+                     rows, b.x, s->P, m, b.z1, b.a1, b.a1T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  GemmArgs g = gargs(s->a1, kH, s->W2, kH, m, kH, kH);
+  GemmArgs g = gargs(b.a1, kH, s->W2, kH, m, kH, kH);
   g.bias = s->P + ob2;
-  g.out_f32 = train ? s->z2 : nullptr;
-  g.out_bf16 = s->a2;
-  g.out_bf16T = train ? s->a2T : nullptr;
+  g.out_f32 = b.z2;
+  g.out_bf16 = b.a2;
+  g.out_bf16T = b.a2T;
   e = train ? gemm<EPI_FWD_GELU>(st, g) : gemm<EPI_FWD_GELU_ACT>(st, g);
   if (e != hipSuccess) return e;
-  g = gargs(s->a2, kH, s->W3, kH, m, kH, kH);
+  g = gargs(b.a2, kH, s->W3, kH, m, kH, kH);
   g.bias = s->P + ob3;
-  g.out_f32 = train ? s->z3 : nullptr;
-  g.out_bf16 = s->a3;
-  g.out_bf16T = train ? s->a3T : nullptr;
+  g.out_f32 = b.z3;
+  g.out_bf16 = b.a3;
+  g.out_bf16T = b.a3T;
   e = train ? gemm<EPI_FWD_GELU>(st, g) : gemm<EPI_FWD_GELU_ACT>(st, g);
   if (e != hipSuccess) return e;
-  g = gargs(s->a3, kH, s->W4, kH, m, kOut, kH);
+  g = gargs(b.a3, kH, s->W4, kH, m, kOut, kH);
   g.bias = s->P + ob4;
-  g.out_f32 = out;
+  g.out_f32 = b.out;
   return gemm<EPI_FWD_LINEAR>(st, g);
 }
 
-// Loss, gradients of all parameters into s->G (batch already in s->x, s->tgt).
-hipError_t backward_batch(sur_ctx *s, int64_t m) {
+// Loss and gradients of all parameters into s->G and s->loss, after
+// forward_batch(train).  Targets: row r of tgt, or row rows[r] with rows;
+// loss_acc (optional) accumulates the loss (first: starts it).
+hipError_t backward_batch(sur_ctx *s, int64_t m, const float *tgt, const int64_t *rows,
+                          float *loss_acc = nullptr, bool first = true) {
   hipStream_t st = s->stream;
   hipError_t e;
   const int split = wgrad_split(m);
-  const unsigned nb = nblk(m * kOut, 256);
-  hipLaunchKernelGGL(k_loss_grad, dim3(nb), dim3(256), 0, st, s->out, s->tgt, m, s->dz4,
-                     s->dz4b, s->dz4bT, s->lpart);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, s->lpart, (int64_t)nb,
-                     (float)(m * kOut), s->loss);
+  const int64_t T = m / 32;
+  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)T), dim3(256), 0, st, s->out, tgt, rows, m,
+                     s->dz4b, s->dz4bT, s->cp4, s->lpart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   // output layer
-  hipLaunchKernelGGL(k_colsum, dim3(kOut), dim3(256), 0, st, s->dz4, m, (int64_t)kOut,
-                     s->G + ob4);
   GemmArgs g = gargs(s->dz4bT, m, s->a3T, m, kOut, kH, m);
-  g.out_f32 = s->part;
+  g.out_f32 = s->part4;
   if ((e = gemm<EPI_PARTIAL>(st, g, split)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_split, dim3(nblk(kOut * kH, 256)), dim3(256), 0, st, s->part,
-                     split, (int64_t)kOut * kH, s->G + oW4);
   g = gargs(s->dz4b, kOut, s->W4T, kOut, m, kH, kOut);
   g.zprev = s->z3;
-  g.out_f32 = s->dz3;
   g.out_bf16 = s->dz3b;
   g.out_bf16T = s->dz3bT;
+  g.colpart = s->cp3;
   if ((e = gemm<EPI_BWD_GELU>(st, g)) != hipSuccess) return e;
   // layer 3
-  hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, s->dz3, m, (int64_t)kH, s->G + ob3);
   g = gargs(s->dz3bT, m, s->a2T, m, kH, kH, m);
-  g.out_f32 = s->part;
+  g.out_f32 = s->part3;
   if ((e = gemm<EPI_PARTIAL>(st, g, split)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_split, dim3(nblk(kH * kH, 256)), dim3(256), 0, st, s->part,
-                     split, (int64_t)kH * kH, s->G + oW3);
   g = gargs(s->dz3b, kH, s->W3T, kH, m, kH, kH);
   g.zprev = s->z2;
-  g.out_f32 = s->dz2;
   g.out_bf16 = s->dz2b;
   g.out_bf16T = s->dz2bT;
+  g.colpart = s->cp2;
   if ((e = gemm<EPI_BWD_GELU>(st, g)) != hipSuccess) return e;
   // layer 2
-  hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, s->dz2, m, (int64_t)kH, s->G + ob2);
   g = gargs(s->dz2bT, m, s->a1T, m, kH, kH, m);
-  g.out_f32 = s->part;
+  g.out_f32 = s->part2;
   if ((e = gemm<EPI_PARTIAL>(st, g, split)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_split, dim3(nblk(kH * kH, 256)), dim3(256), 0, st, s->part,
-                     split, (int64_t)kH * kH, s->G + oW2);
+  // layer 1: only the column sums of dZ1 (bias, and weights with the inputs)
   g = gargs(s->dz2b, kH, s->W2T, kH, m, kH, kH);
   g.zprev = s->z1;
-  g.out_f32 = s->dz1;
+  g.colpart = s->cp1;
+  g.xin = s->x;
+  g.colpart_x0 = s->cpx0;
+  g.colpart_x1 = s->cpx1;
   if ((e = gemm<EPI_BWD_GELU>(st, g)) != hipSuccess) return e;
-  // layer 1 (vector unit)
-  hipLaunchKernelGGL(k_layer1_grad, dim3(kH), dim3(256), 0, st, s->dz1, s->x, m, s->G);
+  GradParts p{s->cpx0, s->cpx1, s->cp1, s->part2, s->part3, s->cp2, s->cp3, s->part4, s->cp4,
+              s->lpart};
+  hipLaunchKernelGGL(k_reduce_grads, dim3(kReduceWBlocks + (kNColSums + 3) / 4), dim3(256), 0,
+                     st, p, T, split,
+                     (float)(m * kOut), s->G, s->loss, loss_acc, first ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t adam(sur_ctx *s) {
+  s->t += 1;
+  const float c1 = (float)(1.0 / (1.0 - std::pow(s->b1, (double)s->t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow(s->b2, (double)s->t)));
+  hipLaunchKernelGGL(k_adam, dim3(nblk(kNP, 256)), dim3(256), 0, s->stream, s->P, s->G, s->Mm,
+                     s->V, (float)s->lr, (float)s->b1, (float)s->b2, (float)s->eps, c1, c2,
+                     s->W2, s->W2T, s->W3, s->W3T, s->W4, s->W4T);
   return hipGetLastError();
 }
 
@@ -753,10 +926,13 @@ int sur_create(int32_t device, void *hip_stream, int64_t max_batch, sur_t *out) 
   A(d_mean, kOut); A(d_std, kOut); A(d_dmean, kOut); A(d_dstd, kOut);
   A(x, B * kIn); A(tgt, B * kOut); A(z1, B * kH); A(z2, B * kH); A(z3, B * kH); A(out, B * kOut);
   A(a1, B * kH); A(a1T, B * kH); A(a2, B * kH); A(a2T, B * kH); A(a3, B * kH); A(a3T, B * kH);
-  A(dz4, B * kOut); A(dz3, B * kH); A(dz2, B * kH); A(dz1, B * kH);
   A(dz4b, B * kOut); A(dz4bT, B * kOut); A(dz3b, B * kH); A(dz3bT, B * kH);
   A(dz2b, B * kH); A(dz2bT, B * kH);
-  A(part, (int64_t)kSplit * kH * kH); A(lpart, nblk(B * kOut, 256)); A(loss, 1);
+  A(part2, (int64_t)kSplit * kH * kH); A(part3, (int64_t)kSplit * kH * kH);
+  A(part4, (int64_t)kSplit * kOut * kH);
+  A(cp1, B / 32 * kH); A(cpx0, B / 32 * kH); A(cpx1, B / 32 * kH); A(cp2, B / 32 * kH);
+  A(cp3, B / 32 * kH); A(cp4, B / 32 * kOut);
+  A(lpart, B / 32); A(loss, 1);
   A(loss_acc, 1);
 #undef A
   if (e == hipSuccess) e = hipMemsetAsync(s->P, 0, kNP * sizeof(float), s->stream);
@@ -780,9 +956,11 @@ int sur_destroy(sur_t s) {
   (void)hipStreamSynchronize(s->stream);
   void *ptrs[] = {s->P, s->G, s->Mm, s->V, s->W2, s->W2T, s->W3, s->W3T, s->W4, s->W4T,
                   s->d_mean, s->d_std, s->d_dmean, s->d_dstd, s->x, s->tgt, s->z1, s->z2,
-                  s->z3, s->out, s->a1, s->a1T, s->a2, s->a2T, s->a3, s->a3T, s->dz4, s->dz3,
-                  s->dz2, s->dz1, s->dz4b, s->dz4bT, s->dz3b, s->dz3bT, s->dz2b, s->dz2bT,
-                  s->part, s->lpart, s->loss, s->loss_acc, s->scan, s->emap};
+                  s->z3, s->out, s->a1, s->a1T, s->a2, s->a2T, s->a3, s->a3T, s->dz4b,
+                  s->dz4bT, s->dz3b, s->dz3bT, s->dz2b, s->dz2bT, s->part2, s->part3,
+                  s->part4, s->cp1, s->cpx0, s->cpx1, s->cp2, s->cp3, s->cp4, s->lpart,
+                  s->loss, s->loss_acc, s->scan, s->emap, s->ix, s->iout, s->ia1, s->ia2,
+                  s->ia3};
   for (void *p : ptrs) (void)hipFree(p);
   delete s;
   return ENS_OK;
@@ -883,8 +1061,8 @@ int sur_gradients(sur_t s, const float *x, const float *target, int64_t m, float
   if (!x || !target) return sfail(s, ENS_E_INVAL, "sur_gradients: NULL input");
   DevGuard dg(s->device);
   if (int rc = load_batch(s, x, target, m, where)) return rc;
-  SUR_HIP(s, forward_batch(s, m, true, s->out));
-  SUR_HIP(s, backward_batch(s, m));
+  SUR_HIP(s, forward_batch(s, train_bufs(s), m));
+  SUR_HIP(s, backward_batch(s, m, s->tgt, nullptr));
   const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (grads) SUR_HIP(s, hipMemcpyAsync(grads, s->G, kNP * sizeof(float), k, s->stream));
   if (loss) SUR_HIP(s, hipMemcpyAsync(loss, s->loss, sizeof(float), k, s->stream));
@@ -899,15 +1077,9 @@ int sur_train_step(sur_t s, const float *x, const float *target, int64_t m, floa
   if (!x || !target) return sfail(s, ENS_E_INVAL, "sur_train_step: NULL input");
   DevGuard dg(s->device);
   if (int rc = load_batch(s, x, target, m, where)) return rc;
-  SUR_HIP(s, forward_batch(s, m, true, s->out));
-  SUR_HIP(s, backward_batch(s, m));
-  s->t += 1;
-  const float c1 = (float)(1.0 / (1.0 - std::pow(s->b1, (double)s->t)));
-  const float c2 = (float)(1.0 / (1.0 - std::pow(s->b2, (double)s->t)));
-  hipLaunchKernelGGL(k_adam, dim3(nblk(kNP, 256)), dim3(256), 0, s->stream, s->P, s->G, s->Mm,
-                     s->V, kNP, (float)s->lr, (float)s->b1, (float)s->b2, (float)s->eps, c1, c2);
-  SUR_HIP(s, hipGetLastError());
-  SUR_HIP(s, refresh(s));
+  SUR_HIP(s, forward_batch(s, train_bufs(s), m));
+  SUR_HIP(s, backward_batch(s, m, s->tgt, nullptr));
+  SUR_HIP(s, adam(s));
   if (loss) {
     const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     SUR_HIP(s, hipMemcpyAsync(loss, s->loss, sizeof(float), k, s->stream));
@@ -922,14 +1094,16 @@ int sur_forward(sur_t s, const float *x, int64_t m, float *out, int32_t where) {
   DevGuard dg(s->device);
   const hipMemcpyKind kin = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   const hipMemcpyKind kout = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  for (int64_t first = 0; first < m; first += s->max_batch) {
-    const int64_t rows = m - first < s->max_batch ? m - first : s->max_batch;
+  if (m > 0) SUR_HIP(s, ensure_infer(s));
+  const Fwd b = infer_bufs(s);
+  for (int64_t first = 0; first < m; first += kInferRows) {
+    const int64_t rows = m - first < kInferRows ? m - first : kInferRows;
     const int64_t padded = (rows + 63) / 64 * 64;
     if (padded > rows)
-      SUR_HIP(s, hipMemsetAsync(s->x + rows * kIn, 0, (padded - rows) * kIn * sizeof(float), s->stream));
-    SUR_HIP(s, hipMemcpyAsync(s->x, x + first * kIn, rows * kIn * sizeof(float), kin, s->stream));
-    SUR_HIP(s, forward_batch(s, padded, false, s->out));
-    SUR_HIP(s, hipMemcpyAsync(out + first * kOut, s->out, rows * kOut * sizeof(float), kout, s->stream));
+      SUR_HIP(s, hipMemsetAsync(b.x + rows * kIn, 0, (padded - rows) * kIn * sizeof(float), s->stream));
+    SUR_HIP(s, hipMemcpyAsync(b.x, x + first * kIn, rows * kIn * sizeof(float), kin, s->stream));
+    SUR_HIP(s, forward_batch(s, b, padded));
+    SUR_HIP(s, hipMemcpyAsync(out + first * kOut, b.out, rows * kOut * sizeof(float), kout, s->stream));
   }
   if (where == ENS_HOST) SUR_HIP(s, hipStreamSynchronize(s->stream));
   return ENS_OK;
@@ -950,16 +1124,18 @@ int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *
   if (n == 0) return ENS_OK;
   DevGuard dg(s->device);
   const double sc0 = 2.0 / (s->in_hi[0] - s->in_lo[0]), sc1 = 2.0 / (s->in_hi[1] - s->in_lo[1]);
-  for (int64_t first = 0; first < n; first += s->max_batch) {
-    const int64_t rows = n - first < s->max_batch ? n - first : s->max_batch;
+  SUR_HIP(s, ensure_infer(s));
+  const Fwd b = infer_bufs(s);
+  for (int64_t first = 0; first < n; first += kInferRows) {
+    const int64_t rows = n - first < kInferRows ? n - first : kInferRows;
     const int64_t padded = (rows + 63) / 64 * 64;
     hipLaunchKernelGGL(k_inputs, dim3(nblk(padded, 256)), dim3(256), 0, s->stream, params, n,
-                       first, padded, s->in_lo[0], sc0, s->in_lo[1], sc1, s->x);
+                       first, padded, s->in_lo[0], sc0, s->in_lo[1], sc1, b.x);
     SUR_HIP(s, hipGetLastError());
-    SUR_HIP(s, forward_batch(s, padded, false, s->out));
+    SUR_HIP(s, forward_batch(s, b, padded));
     const bool use_map = s->emap && o->rough > 0.0;
-    hipLaunchKernelGGL(k_screen_epi, dim3(nblk(padded, 256)), dim3(256), 0, s->stream, s->out,
-                       s->x, first, padded, n, s->d_mean, s->d_std, (float)o->margin,
+    hipLaunchKernelGGL(k_screen_epi, dim3(nblk(padded, 256)), dim3(256), 0, s->stream, b.out,
+                       b.x, first, padded, n, s->d_mean, s->d_std, (float)o->margin,
                        (float)o->spread, (float)o->flag_margin,
                        use_map ? s->emap : (const float *)nullptr, s->emap_G, (float)o->rough,
                        (float)o->rough_margin, label, resolve, pred_max);
@@ -1020,21 +1196,10 @@ int sur_train_epoch(sur_t s, const float *x, const float *y, int64_t n, const in
   DevGuard dg(s->device);
   const int64_t nb = n / batch;
   for (int64_t b = 0; b < nb; ++b) {
-    hipLaunchKernelGGL(k_gather_batch, dim3(nblk(batch * kOut, 256)), dim3(256), 0, s->stream,
-                       x, y, perm, b * batch, batch, s->x, s->tgt);
-    SUR_HIP(s, hipGetLastError());
-    SUR_HIP(s, forward_batch(s, batch, true, s->out));
-    SUR_HIP(s, backward_batch(s, batch));
-    s->t += 1;
-    const float c1 = (float)(1.0 / (1.0 - std::pow(s->b1, (double)s->t)));
-    const float c2 = (float)(1.0 / (1.0 - std::pow(s->b2, (double)s->t)));
-    hipLaunchKernelGGL(k_adam, dim3(nblk(kNP, 256)), dim3(256), 0, s->stream, s->P, s->G, s->Mm,
-                       s->V, kNP, (float)s->lr, (float)s->b1, (float)s->b2, (float)s->eps, c1, c2);
-    SUR_HIP(s, hipGetLastError());
-    SUR_HIP(s, refresh(s));
-    hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(64), 0, s->stream, s->loss, s->loss_acc,
-                       b == 0 ? 1 : 0);
-    SUR_HIP(s, hipGetLastError());
+    const int64_t *rows = perm + b * batch;
+    SUR_HIP(s, forward_batch(s, train_bufs(s), batch, rows, x));
+    SUR_HIP(s, backward_batch(s, batch, y, rows, s->loss_acc, b == 0));
+    SUR_HIP(s, adam(s));
   }
   if (mean_loss) {
     float acc = 0.f;

@@ -126,14 +126,15 @@ def _attempts(e):
     return int((st[ens.ENS_ST_ACCEPTED] + st[ens.ENS_ST_REJECTED]).sum().item())
 
 
-def km_solve_records(P_dev, n_phases, n_last, idx_dev=None, n_full=None, pilot=0):
+def km_solve_records(P_dev, n_phases, n_last, idx_dev=None, n_full=None, pilot=0, grid=0):
     """Solve the Keller--Miksis points (all of P_dev, or the columns idx_dev of
     a [2][n_full] sweep).  With 0 < pilot < n_phases (and n_phases - pilot a
     multiple of n_last) the first `pilot` phases run in index order, then the
     work queue hands out the systems longest-first by their pilot step counts
     for the remaining phases (ens_order_by_work); the results equal those of
-    one uninterrupted solve.  Returns (records [n_last][n] device, status,
-    kernel seconds, attempted steps)."""
+    one uninterrupted solve.  grid (> 0): persistent blocks of the solve after
+    the pilot (0: the resident capacity).  Returns (records [n_last][n]
+    device, status, kernel seconds, attempted steps)."""
     import torch
     n = int(idx_dev.numel()) if idx_dev is not None else int(P_dev.shape[1])
     if n == 0:
@@ -159,7 +160,7 @@ def km_solve_records(P_dev, n_phases, n_last, idx_dev=None, n_full=None, pilot=0
             att += _attempts(e)
             status = e.read(ens.ENS_STATUS)
             e.order_by_work()
-            e.solve(n_phases=n_phases - pilot, n_record=n_last)
+            e.solve(n_phases=n_phases - pilot, n_record=n_last, grid=grid)
         else:
             e.solve(n_phases=n_phases, n_record=n_last)
         ms += e.last_kernel_ms()
@@ -336,8 +337,9 @@ def run(cfg: Config, log=print) -> Report:
         f"({rep.speedup_excl_data:.2f} without the training sweep)")
     log(f"attempted steps: training sweep {rep.data_attempts:.4g}, re-solve "
         f"{rep.resolve_attempts:.4g}, plain {rep.plain_attempts:.4g}")
-    rep.extra = {"judge_idx": jidx, "judge_exact": exact_j,
+    rep.extra = {"judge_idx": jidx, "judge_exact": exact_j, "emap": emap, "use": use,
                  "judge_pmax": pmax[jidx_d].cpu().numpy(), "judge_final": final_j,
+                 "judge_resolve": resolve[jidx_d].cpu().numpy(),
                  "train_lnmax": torch.log(rec_t.max(dim=0).values).cpu().numpy()}
     s.close()
     return rep
