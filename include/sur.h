@@ -25,9 +25,9 @@
  *   - screening: label = [max_j y1max_j >= 2] from the de-standardised
  *     prediction; a point is re-solved if |max_j ln y1max_j - ln 2| < margin,
  *     or if the predicted spread max_j - min_j exceeds `spread` while
- *     |max_j - ln 2| < flag_margin, or if the network's local error on its
- *     training grid (sur_fit_error_map) exceeds `rough` while
- *     |max_j - ln 2| < rough_margin.
+ *     |max_j - ln 2| < flag_margin, or if the exact labels of the training
+ *     nodes around it (sur_fit_label_map) contradict the network's label:
+ *     all four of them, or some of them while |max_j - ln 2| < label_margin.
  *
  * Conventions are those of ens.h: functions return ENS_OK or a negative
  * ens_status; arrays tagged with `where` are host (ENS_HOST) or device
@@ -119,22 +119,20 @@ typedef struct {
   double margin;       /* unsure band on max_j ln y1max around ln 2          */
   double spread;       /* flag: predicted max_j - min_j above this ...       */
   double flag_margin;  /* ... and |max_j ln y1max - ln 2| below this         */
-  double rough;        /* flag: error map at the nearest training node above
-                          this ...  (needs sur_fit_error_map; <= 0: off)     */
-  double rough_margin; /* ... and |max_j ln y1max - ln 2| below this         */
+  double label_margin; /* flag from the training grid's exact labels (needs
+                          sur_fit_label_map; < 0: off): with k of the four
+                          training nodes around the point carrying a label
+                          other than the network's, flag if k = 4, or if
+                          k >= 1 and |max_j ln y1max - ln 2| is below this   */
 } sur_screen_opts;
 
-/* Local error map of the trained network on its training grid: G x G nodes
- * (params [2][G*G] in km-grid order, p_A linear and ln f linear between the
- * sur_set_norm bounds), records [SUR_OUT][G*G] of the integrator, use [G*G]
- * (1: a training node).  For every used node e = |max_j yhat_j - max_j ln
- * y1max_j|; the map value of a node is the maximum of e over the used nodes
- * of its 3 x 3 neighbourhood (the node itself included only if used), so a
- * held-out node sees only its neighbours.  The map stays in the handle for
- * sur_screen (the nearest node of each screened point is looked up) and is
- * copied to map_out (device float [G*G], may be NULL).  All arrays device. */
-int sur_fit_error_map(sur_t s, const double *params, const double *records,
-                      const uint8_t *use, int32_t G, float *map_out);
+/* Exact labels of a G x G training grid (km-grid order, the axes of
+ * sur_set_norm) from its records [SUR_OUT][G*G] (device, double): node label
+ * [max_j y1max_j >= 2], or -1 where a record is NaN.  The map stays in the
+ * handle for sur_screen's label flag (the four nodes of the grid cell around
+ * each screened point are looked up) and is copied to map_out (device int8
+ * [G*G], may be NULL). */
+int sur_fit_label_map(sur_t s, const double *records, int32_t G, int8_t *map_out);
 
 /* Screens n sweep points params [2][n] (P_A1, f1; double).  Device outputs:
  * label [n] int8 (1: max y1max >= 2), resolve [n] uint8, pred_max [n] float

@@ -380,12 +380,27 @@ __global__ __launch_bounds__(256) void k_reduce_grads(GradParts p, int64_t T, in
 }
 
 // Adam on the FP32 master parameters (Kingma and Ba, 2015); the BF16 copies
-// of W2, W3, W4 and their transposes follow the updated values.
+// of W2, W3, W4 and their transposes follow the updated values.  The step
+// count is t = t_base + step + 1; with hyper != NULL the learning rate,
+// betas, epsilon and t_base are read from device memory (hyper[0..4]), so a
+// captured epoch replays with new values.
 __global__ void k_adam(float *__restrict__ P, const float *__restrict__ G, float *__restrict__ Mm,
-                       float *__restrict__ V, float lr, float b1, float b2, float eps, float c1,
-                       float c2, bf16 *W2, bf16 *W2T, bf16 *W3, bf16 *W3T, bf16 *W4, bf16 *W4T) {
+                       float *__restrict__ V, const double *__restrict__ hyper, double lr_,
+                       double b1_, double b2_, double eps_, double t_base, int step, bf16 *W2,
+                       bf16 *W2T, bf16 *W3, bf16 *W3T, bf16 *W4, bf16 *W4T) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kNP) return;
+  if (hyper) {
+    lr_ = hyper[0];
+    b1_ = hyper[1];
+    b2_ = hyper[2];
+    eps_ = hyper[3];
+    t_base = hyper[4];
+  }
+  const double t = t_base + (double)step + 1.0;
+  const float c1 = (float)(1.0 / (1.0 - pow(b1_, t)));
+  const float c2 = (float)(1.0 / (1.0 - pow(b2_, t)));
+  const float lr = (float)lr_, b1 = (float)b1_, b2 = (float)b2_, eps = (float)eps_;
   const float g = G[i];
   const float m = fmaf(b1, Mm[i], (1.0f - b1) * g);
   const float v = fmaf(b2, V[i], (1.0f - b2) * g * g);
@@ -457,8 +472,8 @@ __global__ void k_targets(const double *__restrict__ rec, int64_t n, const doubl
 __global__ void k_screen_epi(const float *__restrict__ out, const float *__restrict__ x,
                              int64_t first, int64_t m, int64_t n, const float *mean,
                              const float *stdv, float margin, float spread, float flag_margin,
-                             const float *__restrict__ emap, int G, float rough,
-                             float rough_margin, int8_t *label, uint8_t *resolve, float *pmax) {
+                             const int8_t *__restrict__ nlab, int GL,
+                             float label_margin, int8_t *label, uint8_t *resolve, float *pmax) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= m || first + r >= n) return;
   float mx = -INFINITY, mn = INFINITY;
@@ -471,13 +486,19 @@ __global__ void k_screen_epi(const float *__restrict__ out, const float *__restr
   const float d = fabsf(mx - ln2);
   const bool unsure = d < margin;
   bool flag = (mx - mn > spread) && d < flag_margin;
-  if (emap && d < rough_margin) {
-    // nearest training node of the (normalised) input
-    int i0 = (int)floorf((x[2 * r] + 1.0f) * 0.5f * (float)(G - 1) + 0.5f);
-    int i1 = (int)floorf((x[2 * r + 1] + 1.0f) * 0.5f * (float)(G - 1) + 0.5f);
-    i0 = i0 < 0 ? 0 : (i0 >= G ? G - 1 : i0);
-    i1 = i1 < 0 ? 0 : (i1 >= G ? G - 1 : i1);
-    flag = flag || emap[i0 * G + i1] > rough;
+  if (nlab) {
+    // labels of the four training nodes around the point (cell corners);
+    // k = how many differ from the network's label (an unknown label counts)
+    const float u = (x[2 * r] + 1.0f) * 0.5f * (float)(GL - 1);
+    const float v = (x[2 * r + 1] + 1.0f) * 0.5f * (float)(GL - 1);
+    int u0 = (int)floorf(u), v0 = (int)floorf(v);
+    u0 = u0 < 0 ? 0 : (u0 > GL - 2 ? GL - 2 : u0);
+    v0 = v0 < 0 ? 0 : (v0 > GL - 2 ? GL - 2 : v0);
+    const int8_t lab = mx >= ln2 ? 1 : 0;
+    const int64_t b = (int64_t)u0 * GL + v0;
+    const int k = (nlab[b] != lab) + (nlab[b + 1] != lab) + (nlab[b + GL] != lab) +
+                  (nlab[b + GL + 1] != lab);
+    flag = flag || k == 4 || (k > 0 && d < label_margin);
   }
   const int64_t i = first + r;
   if (label) label[i] = mx >= ln2 ? 1 : 0;
@@ -485,36 +506,19 @@ __global__ void k_screen_epi(const float *__restrict__ out, const float *__restr
   if (pmax) pmax[i] = mx;
 }
 
-// Network error at each training node: |max_j yhat_j - max_j ln rec_j|
-// (NaN where the node is unused or its records hold a NaN).
-__global__ void k_node_error(const float *__restrict__ pmax, const double *__restrict__ rec,
-                             const uint8_t *__restrict__ use, int64_t n, float *err) {
+// Exact label of each training node: [max_j rec[j][i] >= 2], -1 if a record
+// is NaN.
+__global__ void k_node_label(const double *__restrict__ rec, int64_t n, int8_t *lab) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double mx = -INFINITY;
-  bool bad = !use[i];
-  for (int j = 0; j < kOut && !bad; ++j) {
+  bool bad = false;
+  for (int j = 0; j < kOut; ++j) {
     const double v = rec[j * n + i];
-    bad = isnan(v);
+    bad = bad || isnan(v);
     mx = v > mx ? v : mx;
   }
-  err[i] = bad ? NAN : fabsf(pmax[i] - (float)log(mx));
-}
-
-// 3 x 3 maximum over the defined node errors.
-__global__ void k_max3x3(const float *__restrict__ err, int G, float *map) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)G * G) return;
-  const int a = (int)(i / G), b = (int)(i % G);
-  float m = 0.0f;
-  for (int da = -1; da <= 1; ++da)
-    for (int db = -1; db <= 1; ++db) {
-      const int aa = a + da, bb = b + db;
-      if (aa < 0 || aa >= G || bb < 0 || bb >= G) continue;
-      const float v = err[aa * G + bb];
-      if (!isnan(v)) m = fmaxf(m, v);
-    }
-  map[i] = m;
+  lab[i] = bad ? -1 : (mx >= 2.0 ? 1 : 0);
 }
 
 // Deterministic compaction of the re-solve mask: block counts, one-block
@@ -662,8 +666,18 @@ struct sur_ctx {
   float *loss_acc = nullptr;  // device scalar: sum of batch losses of an epoch
   int64_t *scan = nullptr;    // compaction scratch
   int64_t scan_cap = 0;
-  float *emap = nullptr;      // error map of the training grid [G][G]
-  int emap_G = 0;
+  int8_t *nlab = nullptr;     // exact labels of the training grid [G][G]
+  int nlab_G = 0;
+  // captured training epoch (sur_train_epoch), replayed while the dataset,
+  // row list and batch are the same
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t ep_graph = nullptr;
+  hipGraphExec_t ep_exec = nullptr;
+  const float *ep_x = nullptr, *ep_y = nullptr;
+  const int64_t *ep_perm = nullptr;
+  int64_t ep_n = 0, ep_batch = 0;
+  double *hyper = nullptr;   // device: lr, beta1, beta2, eps, t_base
+  double hyper_host[5] = {0, 0, 0, 0, 0};
   // inference workspace (sur_forward, sur_screen): kInferRows rows, allocated
   // on first use
   float *ix = nullptr, *iout = nullptr;
@@ -862,13 +876,26 @@ hipError_t backward_batch(sur_ctx *s, int64_t m, const float *tgt, const int64_t
 }
 
 hipError_t adam(sur_ctx *s) {
-  s->t += 1;
-  const float c1 = (float)(1.0 / (1.0 - std::pow(s->b1, (double)s->t)));
-  const float c2 = (float)(1.0 / (1.0 - std::pow(s->b2, (double)s->t)));
   hipLaunchKernelGGL(k_adam, dim3(nblk(kNP, 256)), dim3(256), 0, s->stream, s->P, s->G, s->Mm,
-                     s->V, (float)s->lr, (float)s->b1, (float)s->b2, (float)s->eps, c1, c2,
-                     s->W2, s->W2T, s->W3, s->W3T, s->W4, s->W4T);
+                     s->V, (const double *)nullptr, s->lr, s->b1, s->b2, s->eps,
+                     (double)s->t, 0, s->W2, s->W2T, s->W3, s->W3T, s->W4, s->W4T);
+  s->t += 1;
   return hipGetLastError();
+}
+
+// Step `step` of a captured epoch: hyper-parameters from s->hyper.
+hipError_t adam_captured(sur_ctx *s, int step) {
+  hipLaunchKernelGGL(k_adam, dim3(nblk(kNP, 256)), dim3(256), 0, s->stream, s->P, s->G, s->Mm,
+                     s->V, (const double *)s->hyper, 0.0, 0.0, 0.0, 0.0, 0.0, step, s->W2,
+                     s->W2T, s->W3, s->W3T, s->W4, s->W4T);
+  return hipGetLastError();
+}
+
+void free_epoch_graph(sur_ctx *s) {
+  if (s->ep_exec) (void)hipGraphExecDestroy(s->ep_exec);
+  if (s->ep_graph) (void)hipGraphDestroy(s->ep_graph);
+  s->ep_exec = nullptr;
+  s->ep_graph = nullptr;
 }
 
 hipError_t refresh(sur_ctx *s) {
@@ -934,7 +961,9 @@ int sur_create(int32_t device, void *hip_stream, int64_t max_batch, sur_t *out) 
   A(cp3, B / 32 * kH); A(cp4, B / 32 * kOut);
   A(lpart, B / 32); A(loss, 1);
   A(loss_acc, 1);
+  A(hyper, 5);
 #undef A
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMemsetAsync(s->P, 0, kNP * sizeof(float), s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->Mm, 0, kNP * sizeof(float), s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->V, 0, kNP * sizeof(float), s->stream);
@@ -959,9 +988,12 @@ int sur_destroy(sur_t s) {
                   s->z3, s->out, s->a1, s->a1T, s->a2, s->a2T, s->a3, s->a3T, s->dz4b,
                   s->dz4bT, s->dz3b, s->dz3bT, s->dz2b, s->dz2bT, s->part2, s->part3,
                   s->part4, s->cp1, s->cpx0, s->cpx1, s->cp2, s->cp3, s->cp4, s->lpart,
-                  s->loss, s->loss_acc, s->scan, s->emap, s->ix, s->iout, s->ia1, s->ia2,
+                  s->loss, s->loss_acc, s->scan, s->nlab, s->ix, s->iout, s->ia1, s->ia2,
                   s->ia3};
   for (void *p : ptrs) (void)hipFree(p);
+  free_epoch_graph(s);
+  (void)hipFree(s->hyper);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
   return ENS_OK;
 }
@@ -1118,7 +1150,7 @@ int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *
     return sfail(s, ENS_E_INVAL, "sur_screen: resolve_idx needs the resolve mask");
   if (!s->have_norm) return sfail(s, ENS_E_ORDER, "sur_screen: call sur_set_norm first");
   if (!(o->margin >= 0) || !(o->spread >= 0) || !(o->flag_margin >= 0) ||
-      !(o->rough_margin >= 0) || std::isnan(o->rough))
+      std::isnan(o->label_margin))
     return sfail(s, ENS_E_INVAL, "sur_screen: margins must be >= 0");
   *n_resolve = 0;
   if (n == 0) return ENS_OK;
@@ -1133,12 +1165,12 @@ int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *
                        first, padded, s->in_lo[0], sc0, s->in_lo[1], sc1, b.x);
     SUR_HIP(s, hipGetLastError());
     SUR_HIP(s, forward_batch(s, b, padded));
-    const bool use_map = s->emap && o->rough > 0.0;
+    const bool use_labels = s->nlab && o->label_margin >= 0.0;
     hipLaunchKernelGGL(k_screen_epi, dim3(nblk(padded, 256)), dim3(256), 0, s->stream, b.out,
                        b.x, first, padded, n, s->d_mean, s->d_std, (float)o->margin,
                        (float)o->spread, (float)o->flag_margin,
-                       use_map ? s->emap : (const float *)nullptr, s->emap_G, (float)o->rough,
-                       (float)o->rough_margin, label, resolve, pred_max);
+                       use_labels ? s->nlab : (const int8_t *)nullptr, s->nlab_G,
+                       (float)o->label_margin, label, resolve, pred_max);
     SUR_HIP(s, hipGetLastError());
   }
   if (resolve) {
@@ -1195,12 +1227,46 @@ int sur_train_epoch(sur_t s, const float *x, const float *y, int64_t n, const in
   if (!x || !y || !perm || n < batch) return sfail(s, ENS_E_INVAL, "sur_train_epoch: bad arguments");
   DevGuard dg(s->device);
   const int64_t nb = n / batch;
-  for (int64_t b = 0; b < nb; ++b) {
-    const int64_t *rows = perm + b * batch;
-    SUR_HIP(s, forward_batch(s, train_bufs(s), batch, rows, x));
-    SUR_HIP(s, backward_batch(s, batch, y, rows, s->loss_acc, b == 0));
-    SUR_HIP(s, adam(s));
+  const bool same = s->ep_exec && s->ep_x == x && s->ep_y == y && s->ep_perm == perm &&
+                    s->ep_n == n && s->ep_batch == batch;
+  if (!same) {
+    // capture the epoch's launches once; replays read the hyper-parameters
+    // and the row list (its contents may change) from device memory
+    free_epoch_graph(s);
+    hipStream_t user = s->stream;
+    s->stream = s->cap_stream;
+    hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+    for (int64_t b = 0; e == hipSuccess && b < nb; ++b) {
+      const int64_t *rows = perm + b * batch;
+      e = forward_batch(s, train_bufs(s), batch, rows, x);
+      if (e == hipSuccess) e = backward_batch(s, batch, y, rows, s->loss_acc, b == 0);
+      if (e == hipSuccess) e = adam_captured(s, (int)b);
+    }
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &gr);
+    s->stream = user;
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return sfail(s, ENS_E_HIP, std::string("sur_train_epoch: capture: ") +
+                                     hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    s->ep_graph = gr;
+    SUR_HIP(s, hipGraphInstantiate(&s->ep_exec, gr, nullptr, nullptr, 0));
+    s->ep_x = x;
+    s->ep_y = y;
+    s->ep_perm = perm;
+    s->ep_n = n;
+    s->ep_batch = batch;
   }
+  s->hyper_host[0] = s->lr;
+  s->hyper_host[1] = s->b1;
+  s->hyper_host[2] = s->b2;
+  s->hyper_host[3] = s->eps;
+  s->hyper_host[4] = (double)s->t;
+  SUR_HIP(s, hipMemcpyAsync(s->hyper, s->hyper_host, sizeof(s->hyper_host),
+                            hipMemcpyHostToDevice, s->stream));
+  SUR_HIP(s, hipGraphLaunch(s->ep_exec, s->stream));
+  s->t += nb;
   if (mean_loss) {
     float acc = 0.f;
     SUR_HIP(s, hipMemcpyAsync(&acc, s->loss_acc, sizeof(float), hipMemcpyDeviceToHost, s->stream));
@@ -1224,52 +1290,24 @@ int sur_exact_labels(sur_t s, const double *records, int64_t k, const int64_t *i
   return ENS_OK;
 }
 
-int sur_fit_error_map(sur_t s, const double *params, const double *records, const uint8_t *use,
-                      int32_t G, float *map_out) {
-  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_fit_error_map: NULL handle");
-  if (!params || !records || !use || G < 2 || G > 65536)
-    return sfail(s, ENS_E_INVAL, "sur_fit_error_map: bad arguments");
+int sur_fit_label_map(sur_t s, const double *records, int32_t G, int8_t *map_out) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_fit_label_map: NULL handle");
+  if (!records || G < 2 || G > 65536) return sfail(s, ENS_E_INVAL, "sur_fit_label_map: bad arguments");
   const int64_t n = (int64_t)G * G;
   DevGuard dg(s->device);
-  float *pmax = nullptr, *err = nullptr;
-  SUR_HIP(s, hipMalloc((void **)&pmax, n * sizeof(float)));
-  hipError_t e = hipMalloc((void **)&err, n * sizeof(float));
-  if (e != hipSuccess) {
-    (void)hipFree(pmax);
-    return sfail(s, ENS_E_NOMEM, "sur_fit_error_map: allocation");
+  if (s->nlab_G != G) {
+    (void)hipFree(s->nlab);
+    s->nlab = nullptr;
+    s->nlab_G = 0;
+    SUR_HIP(s, hipMalloc((void **)&s->nlab, n));
+    s->nlab_G = G;
   }
-  if (s->emap_G != G) {
-    (void)hipFree(s->emap);
-    s->emap = nullptr;
-    s->emap_G = 0;
-    e = hipMalloc((void **)&s->emap, n * sizeof(float));
-    if (e == hipSuccess) s->emap_G = G;
-  }
-  int64_t cnt = 0;
-  int rc = ENS_OK;
-  if (e == hipSuccess) {
-    sur_screen_opts o;
-    std::memset(&o, 0, sizeof(o));
-    o.spread = 1e30;
-    float *keep = s->emap;  // the screen below must not use a stale map
-    s->emap = nullptr;
-    rc = sur_screen(s, params, n, &o, nullptr, nullptr, pmax, nullptr, &cnt);
-    s->emap = keep;
-  }
-  if (e == hipSuccess && rc == ENS_OK) {
-    hipLaunchKernelGGL(k_node_error, dim3(nblk(n, 256)), dim3(256), 0, s->stream, pmax, records,
-                       use, n, err);
-    hipLaunchKernelGGL(k_max3x3, dim3(nblk(n, 256)), dim3(256), 0, s->stream, err, G, s->emap);
-    e = hipGetLastError();
-    if (e == hipSuccess && map_out)
-      e = hipMemcpyAsync(map_out, s->emap, n * sizeof(float), hipMemcpyDeviceToDevice, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  }
-  (void)hipFree(pmax);
-  (void)hipFree(err);
-  if (rc != ENS_OK) return rc;
-  if (e != hipSuccess) return sfail(s, ENS_E_HIP, std::string("sur_fit_error_map: ") + hipGetErrorString(e));
+  hipLaunchKernelGGL(k_node_label, dim3(nblk(n, 256)), dim3(256), 0, s->stream, records, n, s->nlab);
+  SUR_HIP(s, hipGetLastError());
+  if (map_out) SUR_HIP(s, hipMemcpyAsync(map_out, s->nlab, n, hipMemcpyDeviceToDevice, s->stream));
+  SUR_HIP(s, hipStreamSynchronize(s->stream));
   return ENS_OK;
 }
+
 
 }  // extern "C"

@@ -43,20 +43,28 @@ constexpr double B1 = 37.0 / 378.0, B3 = 250.0 / 621.0, B4 = 125.0 / 594.0,
 constexpr double E1 = B1 - 2825.0 / 27648.0, E3 = B3 - 18575.0 / 48384.0,
                  E4 = B4 - 13525.0 / 55296.0, E5 = -277.0 / 14336.0, E6 = B6 - 1.0 / 4.0;
 
-// x^(-1/5) for x in [1e-30, 1e30]: an FP32 estimate from the hardware
-// base-2 logarithm and exponential (relative error ~1e-7), then two Newton
-// steps for r^5 x = 1 in FP64, r <- r (6 - x r^5) / 5; each step squares the
-// relative error (times 3), so two steps reach rounding level.  ~25 VALU
-// instead of the ~200 of a general pow.
-__device__ __forceinline__ double rfifth(double x) {
-  double r = (double)exp2f(-0.2f * log2f((float)x));
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double r2 = r * r;
-    const double r5 = r2 * r2 * r;
-    r = (0.2 * r) * fma(-x, r5, 6.0);
-  }
+// 1/d from the hardware reciprocal estimate and two Newton steps
+// r <- r + r (1 - d r), each squaring the relative error: within an ulp or
+// two of the correctly rounded quotient for the normal, finite d used here
+// (d = 0 or non-finite gives a non-finite result).
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
   return r;
+}
+
+// x^(-1/5) for x in [1e-30, 1e30]: an FP32 estimate r0 from the hardware
+// base-2 logarithm and exponential (relative error ~1e-7), then in FP64 with
+// e = 1 - x r0^5 the series r = r0 (1 - e)^(-1/5) = r0 (1 + e/5 + 3 e^2/25
+// + O(e^3)): the truncation is ~1e-20, below rounding.  ~12 VALU instead of
+// the ~200 of a general pow.
+__device__ __forceinline__ double rfifth(double x) {
+  const double r0 =
+      (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf((float)x));
+  const double r2 = r0 * r0;
+  const double e = fma(-x, r2 * r2 * r0, 1.0);
+  return fma(r0, e * fma(0.12, e, 0.2), r0);
 }
 
 // Step-size factor 0.9 E^(-1/5), clamped to [0.2, 5] (E = 0 gives 5).  Outside
@@ -79,6 +87,7 @@ struct MQuad {  // dx/dt = x^2 - p (Sec. 3)
   double p;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) { p = P[i]; }
   __device__ void begin(double) {}
+  template <int S>
   __device__ void rhs(double, double, const double *y, double *f) const {
     f[0] = fma(y[0], y[0], -p);
   }
@@ -96,6 +105,7 @@ struct MLorenz {  // Sec. 4.1
     beta = sh[1];
   }
   __device__ void begin(double) {}
+  template <int S>
   __device__ void rhs(double, double, const double *y, double *f) const {
     f[0] = sigma * (y[1] - y[0]);
     f[1] = fma(-y[0], y[2], fma(rho, y[0], -y[1]));
@@ -148,7 +158,7 @@ template <bool FAST>
 struct MKM {
   static constexpr int D = 2;
   static constexpr bool kEvents = false;
-  static constexpr int kMinWaves = FAST ? 4 : 5;
+  static constexpr int kMinWaves = 4;
   static constexpr bool kPrio = true;  // issue priority by remaining work
   double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49;
   double s0, c0;  // sin, cos (2 pi t) at the start of the attempted step
@@ -171,23 +181,56 @@ struct MKM {
     K10 = 3.0 * gam;
     K49 = K4 * K9;
   }
+  // FAST: sin/cos of the stage offsets 2 pi c_i h, c = (0, 1/5, 3/10, 3/5, 1,
+  // 7/8): stages 2, 3 and 6 from the series, stage 4 by doubling stage 3's
+  // angle and stage 5 as stage 4's plus twice stage 2's.
+  double so2, co2, so4, co4;
   __device__ void begin(double t) {
     if constexpr (FAST) sincospi(2.0 * t, &s0, &c0);
   }
-  // tau: the stage time; off: its offset c_i h from the attempt's start.
-  __device__ void rhs(double tau, double off, const double *y, double *f) const {
+  // S: the stage (1..6); tau: its time; h: the attempted step.
+  template <int S>
+  __device__ void rhs(double tau, double h, const double *y, double *f) {
     const double y1 = y[0], y2 = y[1];
     const double Dn = fma(y1, fma(-K9, y2, 1.0), K49);
-    const double qd = 1.0 / (y1 * Dn);
+    const double qd = rcp_nr(y1 * Dn);
     const double r1 = Dn * qd;                    // 1 / y1
     double gas, s, c;                             // (1/y1)^K10; sin, cos (2 pi tau)
     if constexpr (FAST) {
       const double r2 = r1 * r1;
       gas = (r2 * r2) * rfifth(y1);
       double so, co;
-      sincos_small(2.0 * M_PI * off, &so, &co);
-      s = fma(s0, co, c0 * so);
-      c = fma(c0, co, -(s0 * so));
+      if constexpr (S == 1) {
+        so = 0.0;
+        co = 1.0;
+      } else if constexpr (S == 2) {
+        sincos_small((2.0 * M_PI / 5.0) * h, &so2, &co2);
+        so = so2;
+        co = co2;
+      } else if constexpr (S == 3) {
+        double so3, co3;
+        sincos_small((2.0 * M_PI * 3.0 / 10.0) * h, &so3, &co3);
+        so4 = 2.0 * so3 * co3;             // doubled angle, for stage 4
+        co4 = fma(-2.0 * so3, so3, 1.0);
+        so = so3;
+        co = co3;
+      } else if constexpr (S == 4) {
+        so = so4;
+        co = co4;
+      } else if constexpr (S == 5) {
+        const double sd = 2.0 * so2 * co2, cd = fma(-2.0 * so2, so2, 1.0);
+        so = fma(so4, cd, co4 * sd);
+        co = fma(co4, cd, -(so4 * sd));
+      } else {
+        sincos_small((2.0 * M_PI * 7.0 / 8.0) * h, &so, &co);
+      }
+      if constexpr (S == 1) {
+        s = s0;
+        c = c0;
+      } else {
+        s = fma(s0, co, c0 * so);
+        c = fma(c0, co, -(s0 * so));
+      }
     } else {
       gas = exp(-K10 * log(y1));
       sincospi(2.0 * tau, &s, &c);
@@ -221,6 +264,7 @@ struct MPRV {
     seated = false;
   }
   __device__ void begin(double) {}
+  template <int S>
   __device__ void rhs(double, double, const double *y, double *f) const {
     if (seated) {
       f[0] = 0.0;
@@ -241,26 +285,26 @@ __device__ __forceinline__ void ck_attempt(M &m, double t, const double *y, doub
   constexpr int D = M::D;
   double k1[D], k2[D], k3[D], k4[D], k5[D], k6[D], yt[D];
   m.begin(t);
-  m.rhs(t, 0.0, y, k1);
+  m.template rhs<1>(t, h, y, k1);
 #pragma unroll
   for (int c = 0; c < D; ++c) yt[c] = fma(h, A21 * k1[c], y[c]);
-  m.rhs(fma(C2, h, t), C2 * h, yt, k2);
+  m.template rhs<2>(fma(C2, h, t), h, yt, k2);
 #pragma unroll
   for (int c = 0; c < D; ++c) yt[c] = fma(h, fma(A32, k2[c], A31 * k1[c]), y[c]);
-  m.rhs(fma(C3, h, t), C3 * h, yt, k3);
+  m.template rhs<3>(fma(C3, h, t), h, yt, k3);
 #pragma unroll
   for (int c = 0; c < D; ++c)
     yt[c] = fma(h, fma(A43, k3[c], fma(A42, k2[c], A41 * k1[c])), y[c]);
-  m.rhs(fma(C4, h, t), C4 * h, yt, k4);
+  m.template rhs<4>(fma(C4, h, t), h, yt, k4);
 #pragma unroll
   for (int c = 0; c < D; ++c)
     yt[c] = fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], A51 * k1[c]))), y[c]);
-  m.rhs(t + C5 * h, C5 * h, yt, k5);
+  m.template rhs<5>(t + C5 * h, h, yt, k5);
 #pragma unroll
   for (int c = 0; c < D; ++c)
     yt[c] = fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], A61 * k1[c])))),
                 y[c]);
-  m.rhs(fma(C6, h, t), C6 * h, yt, k6);
+  m.template rhs<6>(fma(C6, h, t), h, yt, k6);
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     y5[c] = fma(h, fma(B6, k6[c], fma(B4, k4[c], fma(B3, k3[c], B1 * k1[c]))), y[c]);
@@ -334,7 +378,7 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     const double sc = fma(a.rtol, fmax(fabs(y[c]), fabs(y5[c])), a.atol);
-    const double r = fabs(err[c]) / sc;
+    const double r = fabs(err[c]) * rcp_nr(sc);
     finite = finite && isfinite(y5[c]) && isfinite(r);
     E = r > E ? r : E;
   }
@@ -384,7 +428,7 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     const double sc = fma(a.rtol, fmax(fabs(y[c]), fabs(y5[c])), a.atol);
-    const double r = fabs(err[c]) / sc;
+    const double r = fabs(err[c]) * rcp_nr(sc);
     finite = finite && isfinite(y5[c]) && isfinite(r);
     E = r > E ? r : E;
   }

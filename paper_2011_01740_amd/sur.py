@@ -17,7 +17,7 @@ N_IN, N_HIDDEN, N_OUT = 2, 256, 64
 
 class sur_screen_opts(C.Structure):
     _fields_ = [("margin", C.c_double), ("spread", C.c_double), ("flag_margin", C.c_double),
-                ("rough", C.c_double), ("rough_margin", C.c_double)]
+                ("label_margin", C.c_double)]
 
 
 _bound = False
@@ -43,7 +43,7 @@ def _lib():
         L.sur_forward.argtypes = [vp, vp, i64, vp, i32]
         L.sur_screen.argtypes = [vp, vp, i64, C.POINTER(sur_screen_opts), vp, vp, vp, vp,
                                  C.POINTER(i64)]
-        L.sur_fit_error_map.argtypes = [vp, vp, vp, vp, i32, vp]
+        L.sur_fit_label_map.argtypes = [vp, vp, i32, vp]
         L.sur_fit_norm.argtypes = [vp, dp, dp, vp, i64, dp, dp]
         L.sur_train_epoch.argtypes = [vp, vp, vp, i64, vp, i64, C.POINTER(C.c_float)]
         L.sur_exact_labels.argtypes = [vp, vp, i64, vp, vp]
@@ -169,17 +169,15 @@ class Surrogate:
         _check(_lib().sur_forward(self.h, px, m, C.c_void_p(out.ctypes.data), w), self.h)
         return out
 
-    def fit_error_map(self, params_dev, records_dev, use_dev, G):
-        """Network error map of a G x G training grid (device float [G*G])."""
+    def fit_label_map(self, records_dev, G):
+        """Exact labels of a G x G training grid (device int8 [G*G])."""
         import torch
-        out = torch.empty(G * G, dtype=torch.float32, device=params_dev.device)
-        _check(_lib().sur_fit_error_map(self.h, C.c_void_p(params_dev.data_ptr()),
-                                        C.c_void_p(records_dev.data_ptr()),
-                                        C.c_void_p(use_dev.data_ptr()), int(G),
+        out = torch.empty(G * G, dtype=torch.int8, device=records_dev.device)
+        _check(_lib().sur_fit_label_map(self.h, C.c_void_p(records_dev.data_ptr()), int(G),
                                         C.c_void_p(out.data_ptr())), self.h)
         return out
 
-    def screen(self, params_dev, margin, spread, flag_margin, rough=0.0, rough_margin=0.0):
+    def screen(self, params_dev, margin, spread, flag_margin, label_margin=-1.0):
         """Screen device params [2][n] (float64).  Returns device tensors
         (label int8, resolve uint8, pred_max float32, resolve_idx int64[:k])."""
         import torch
@@ -190,8 +188,8 @@ class Surrogate:
         pmax = torch.empty(n, dtype=torch.float32, device=dev)
         idx = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
         k = C.c_int64()
-        o = sur_screen_opts(float(margin), float(spread), float(flag_margin), float(rough),
-                            float(rough_margin))
+        o = sur_screen_opts(float(margin), float(spread), float(flag_margin),
+                            float(label_margin))
         _check(_lib().sur_screen(self.h, C.c_void_p(params_dev.data_ptr()), n, C.byref(o),
                                  C.c_void_p(label.data_ptr()), C.c_void_p(resolve.data_ptr()),
                                  C.c_void_p(pmax.data_ptr()), C.c_void_p(idx.data_ptr()),

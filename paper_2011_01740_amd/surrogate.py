@@ -53,33 +53,49 @@ class Config:
     judge_n: int = 1 << 18         # plain-solved judge points, whole grid rows (0: all)
     judge_chunk: int = 1 << 22     # points per plain-sweep launch
     pilot: int = 64                # phases before the longest-first queue order (0: off)
+    data_grid: int = 256           # blocks of the training sweep after its pilot: one wave
+                                   # per SIMD, the fastest for its longest systems (0: all)
 
 
-def calibrate(d, wrong, emap, target, n_valid):
-    """Screening thresholds from held-out points: d = |max yhat - ln 2|, wrong =
-    the network's label is wrong, emap = the error map at the point.  A point
-    is re-solved if d < m0, or if emap > e and d < m1.  Returns (m0, e, m1)
+def loo_disagreement(nlab, node_idx, net_label):
+    """For training nodes node_idx (flat indices into the G x G label map
+    nlab), the number k of their four axis neighbours (reflected at the
+    border, the node itself never among them) whose exact label differs from
+    net_label; an unknown label (-1) counts as different.  This is the
+    screening label flag seen from a held-out node, which stands in for a
+    point between training nodes."""
+    G = int(round(np.sqrt(nlab.size)))
+    lab = nlab.reshape(G, G)
+    i, j = np.divmod(np.asarray(node_idx), G)
+    def refl(a):
+        return np.where(a < 0, -a, np.where(a >= G, 2 * (G - 1) - a, a))
+    k = np.zeros(i.shape, dtype=np.int64)
+    for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        k += lab[refl(i + di), refl(j + dj)] != net_label
+    return k
+
+
+def calibrate_labels(d, wrong, k, target, n_valid):
+    """Screening thresholds for the label rule from held-out points: d =
+    |max yhat - ln 2|, wrong = the network's label is wrong, k = training-node
+    labels around the point that differ from the network's (0..4).  A point is
+    re-solved if k = 4, or k >= 1 and d < m1, or d < m0.  Returns (m0, m1)
     with the fewest re-solved points among those whose uncovered wrong points
-    stay within target * n_valid (plain band: e = inf)."""
-    budget = target * n_valid
-    dw = np.sort(d[wrong])
+    stay within target * n_valid."""
+    budget = int(np.floor(target * n_valid))
+    part = (k >= 1) & (k < 4)
+    dw = np.sort(d[wrong & part])
+    m1_cands = [0.0] + (list(np.unique(np.quantile(dw, np.linspace(0.02, 1.0, 50)) + 1e-7))
+                        if dw.size else [])
     best = None
-    e_cands = [np.inf] + list(np.unique(np.quantile(emap, np.linspace(0.5, 0.995, 40))))
-    m1_cands = [0.0] + list(np.unique(np.quantile(dw, np.linspace(0.05, 1.0, 40)) + 1e-7)) if dw.size else [0.0]
-    for e in e_cands:
-        rough = emap > e
-        for m1 in m1_cands:
-            covered = rough & (d < m1)
-            rest = np.sort(d[wrong & ~covered])
-            # smallest m0 leaving at most `budget` uncovered wrong points
-            k = int(np.floor(budget))
-            m0 = 0.0 if rest.size <= k else float(rest[rest.size - k - 1]) + 1e-7
-            frac = float(((d < m0) | covered).mean())
-            if best is None or frac < best[0]:
-                best = (frac, m0, float(e), float(m1))
-            if np.isinf(e):
-                break
-    return best[1], best[2], best[3]
+    for m1 in m1_cands:
+        covered = (k == 4) | (part & (d < m1))
+        rest = np.sort(d[wrong & ~covered])
+        m0 = 0.0 if rest.size <= budget else float(rest[rest.size - budget - 1]) + 1e-7
+        frac = float(((d < m0) | covered).mean())
+        if best is None or frac < best[0]:
+            best = (frac, m0, float(m1))
+    return best[1], best[2]
 
 
 @dataclass
@@ -87,8 +103,7 @@ class Report:
     config: Dict = field(default_factory=dict)
     times_s: Dict[str, float] = field(default_factory=dict)
     margin: float = 0.0
-    rough: float = 0.0
-    rough_margin: float = 0.0
+    label_margin: float = 0.0
     holdout_wrong_outside: float = 0.0
     holdout_resolve_frac: float = 0.0
     n_screen: int = 0
@@ -189,7 +204,7 @@ def run(cfg: Config, log=print) -> Report:
     _sync()
     t0 = time.perf_counter()
     rec_t, st_t, _, rep.data_attempts = km_solve_records(Pt_d, cfg.n_phases, cfg.n_last,
-                                                           pilot=cfg.pilot)
+                                                           pilot=cfg.pilot, grid=cfg.data_grid)
     _sync()
     T["data"] = time.perf_counter() - t0
     ok = (st_t & ~ens.ENS_SYS_DT_MIN) == 0
@@ -217,9 +232,12 @@ def run(cfg: Config, log=print) -> Report:
     x_d, y_d = s.build_dataset(Pt_d, rec_t, nt)
     shuf = np.random.default_rng(cfg.shuffle_seed)
     loss = ens.C.c_float()
+    # one device buffer for the row order, so the library replays its
+    # captured epoch
+    perm = torch.empty(train.size, dtype=torch.int64, device="cuda")
     for ep in range(cfg.epochs):
         s.set_adam(lr=cfg.lr * 0.5 * (1.0 + math.cos(math.pi * ep / cfg.epochs)) + 1e-5)
-        perm = _dev(shuf.permutation(train).astype(np.int64))
+        perm.copy_(torch.from_numpy(shuf.permutation(train).astype(np.int64)))
         sur._check(L.sur_train_epoch(s.h, ens.C.c_void_p(x_d.data_ptr()),
                                      ens.C.c_void_p(y_d.data_ptr()), int(train.size),
                                      ens.C.c_void_p(perm.data_ptr()), cfg.batch,
@@ -229,31 +247,28 @@ def run(cfg: Config, log=print) -> Report:
     rep.train_loss = float(loss.value)
     log(f"train: {cfg.epochs} epochs in {T['train']:.2f} s, last epoch loss {rep.train_loss:.4g}")
 
-    # 3. calibration on the hold-out part of the coarse grid
+    # 3. calibration on the hold-out part of the coarse grid: the network's
+    # label is checked against the exact labels of the training grid (all
+    # nodes were solved); a held-out node sees its neighbours, not itself
     t0 = time.perf_counter()
-    use = np.zeros(nt, dtype=np.uint8)
-    use[train] = 1
-    emap = s.fit_error_map(Pt_d, rec_t, _dev(use), cfg.train_grid).cpu().numpy()
+    nlab = s.fit_label_map(rec_t, cfg.train_grid).cpu().numpy()
     Ph_d = Pt_d[:, _dev(hold)].contiguous()
     _, _, pmax_h, _ = s.screen(Ph_d, 0.0, 1e30, 0.0)
     pmax_h = pmax_h.cpu().numpy().astype(np.float64)
-    exact_h = torch.empty(n_hold, dtype=torch.int8, device="cuda")
-    rec_h = rec_t[:, _dev(hold)].contiguous()
-    sur._check(L.sur_exact_labels(s.h, ens.C.c_void_p(rec_h.data_ptr()), n_hold, None,
-                                  ens.C.c_void_p(exact_h.data_ptr())), s.h)
-    exact_h = exact_h.cpu().numpy()
+    exact_h = nlab[hold]
     valid = exact_h >= 0
     d = np.abs(pmax_h - LN2)
-    wrong = ((pmax_h >= LN2).astype(np.int8) != exact_h) & valid
-    m0, e_thr, m1 = calibrate(d, wrong, emap[hold], cfg.target_wrong, int(valid.sum()))
-    res_h = (d < m0) | ((emap[hold] > e_thr) & (d < m1))
-    rep.margin, rep.rough, rep.rough_margin = m0, e_thr, m1
+    net_h = (pmax_h >= LN2).astype(np.int8)
+    wrong = (net_h != exact_h) & valid
+    k_h = loo_disagreement(nlab, hold, net_h)
+    m0, m1 = calibrate_labels(d, wrong, k_h, cfg.target_wrong, int(valid.sum()))
+    res_h = (k_h == 4) | ((k_h >= 1) & (d < m1)) | (d < m0)
+    rep.margin, rep.label_margin = m0, m1
     rep.holdout_wrong_outside = float((wrong & ~res_h).sum() / max(valid.sum(), 1))
     rep.holdout_resolve_frac = float(res_h.mean())
     T["calibrate"] = time.perf_counter() - t0
-    log(f"calibration: margin {m0:.4f}, rough {e_thr:.4f} within {m1:.4f}; hold-out "
-        f"re-solve {rep.holdout_resolve_frac:.4f}, wrong outside {rep.holdout_wrong_outside:.4f}")
-    rough_arg = e_thr if np.isfinite(e_thr) else 0.0
+    log(f"calibration: margin {m0:.4f}, label margin {m1:.4f}; hold-out re-solve "
+        f"{rep.holdout_resolve_frac:.4f}, wrong outside {rep.holdout_wrong_outside:.4f}")
 
     # 4. screening of the dense grid and re-solve
     Ps, _ = I.km_grid(cfg.screen_grid, cfg.screen_grid)
@@ -261,7 +276,7 @@ def run(cfg: Config, log=print) -> Report:
     Ps_d = _dev(Ps)
     _sync()
     t0 = time.perf_counter()
-    label, resolve, pmax, idx = s.screen(Ps_d, m0, 1e30, 0.0, rough_arg, m1)
+    label, resolve, pmax, idx = s.screen(Ps_d, m0, 1e30, 0.0, label_margin=m1)
     _sync()
     T["screen"] = time.perf_counter() - t0
     rep.n_screen = ns
@@ -337,7 +352,7 @@ def run(cfg: Config, log=print) -> Report:
         f"({rep.speedup_excl_data:.2f} without the training sweep)")
     log(f"attempted steps: training sweep {rep.data_attempts:.4g}, re-solve "
         f"{rep.resolve_attempts:.4g}, plain {rep.plain_attempts:.4g}")
-    rep.extra = {"judge_idx": jidx, "judge_exact": exact_j, "emap": emap, "use": use,
+    rep.extra = {"judge_idx": jidx, "judge_exact": exact_j, "nlab": nlab,
                  "judge_pmax": pmax[jidx_d].cpu().numpy(), "judge_final": final_j,
                  "judge_resolve": resolve[jidx_d].cpu().numpy(),
                  "train_lnmax": torch.log(rec_t.max(dim=0).values).cpu().numpy()}

@@ -136,3 +136,89 @@ def test_screen_matches_forward_and_compacts_in_order():
     assert agree.all()
     assert np.array_equal(idx, np.nonzero(resolve)[0])
     assert np.array_equal(label.astype(bool)[ok], (pmax >= np.log(2))[ok])
+
+
+def test_epoch_graph_replays_equal_eager_steps():
+    """sur_train_epoch captures an epoch's launches once and replays them with
+    the current learning rate, step count and row order: after three epochs
+    (with different orders and learning rates, and eager work in between) the
+    parameters equal those of the same batches taken one sur_train_step at a
+    time, bit for bit."""
+    import torch
+    sur = _sur()
+    from paper_2011_01740_amd import ens
+    rows, batch = 1024, 256
+    x, t = _data(rows, 7)
+    rng = np.random.default_rng(8)
+    orders = [rng.permutation(rows)[:768].astype(np.int64) for _ in range(3)]
+    lrs = [3e-3, 2e-3, 1e-3]
+    flat = _f32_params(10)
+    with sur.Surrogate(max_batch=batch) as s:
+        s.set_params(flat)
+        xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+        perm = torch.empty(768, dtype=torch.int64, device="cuda")
+        L = sur._lib()
+        for order, lr in zip(orders, lrs):
+            s.set_adam(lr=lr)
+            perm.copy_(torch.from_numpy(order))
+            loss = ens.C.c_float()
+            sur._check(L.sur_train_epoch(s.h, ens.C.c_void_p(xd.data_ptr()),
+                                         ens.C.c_void_p(td.data_ptr()), 768,
+                                         ens.C.c_void_p(perm.data_ptr()), batch,
+                                         ens.C.byref(loss)), s.h)
+            s.forward(x[:64])                      # eager work between replays
+        graph = s.get_params()
+    with sur.Surrogate(max_batch=batch) as s:
+        s.set_params(flat)
+        for order, lr in zip(orders, lrs):
+            s.set_adam(lr=lr)
+            for b in range(3):
+                r = order[b * batch:(b + 1) * batch]
+                s.train_step(x[r], t[r])
+        eager = s.get_params()
+    assert np.array_equal(graph, eager)
+
+
+def test_label_flag_against_the_training_labels():
+    """sur_fit_label_map labels the training nodes from their records, and
+    sur_screen flags a point when the four nodes of its cell contradict the
+    network's label: all four, or some while the point is within the label
+    margin (checked at points inside the cells, away from node lines)."""
+    import torch
+    sur = _sur()
+    G = 9
+    lo = np.array([0.2e5, np.log(20e3)])
+    hi = np.array([1.2e5, np.log(1e6)])
+    rng = np.random.default_rng(12)
+    node_max = rng.choice([1.5, 3.0], size=G * G)
+    node_max[17] = np.nan                          # unknown label
+    rec = np.tile(node_max, (64, 1)) * np.linspace(0.9, 1.0, 64)[:, None]
+    want_lab = np.where(np.isnan(rec).any(axis=0), -1, (rec.max(axis=0) >= 2).astype(np.int8))
+    # screen points at fractional cell coordinates in [0.2, 0.8]
+    m = 40
+    uu = rng.integers(0, G - 1, m) + rng.uniform(0.2, 0.8, m)
+    vv = rng.integers(0, G - 1, m) + rng.uniform(0.2, 0.8, m)
+    P = np.stack([lo[0] + uu / (G - 1) * (hi[0] - lo[0]),
+                  np.exp(lo[1] + vv / (G - 1) * (hi[1] - lo[1]))])
+    mean = np.full(64, np.log(2.0))
+    std = np.full(64, 0.01)
+    with sur.Surrogate(max_batch=256) as s:
+        s.set_params(I.mlp_init(3))
+        s.set_norm(lo, hi, mean, std)
+        lab_map = s.fit_label_map(torch.from_numpy(rec).cuda(), G).cpu().numpy()
+        Pd = torch.from_numpy(P).cuda()
+        lm = 0.02
+        label, resolve, pmax, _ = s.screen(Pd, 0.0, 1e30, 0.0, label_margin=lm)
+        label, resolve, pmax = (v.cpu().numpy() for v in (label, resolve, pmax))
+        _, off, _, _ = s.screen(Pd, 0.0, 1e30, 0.0)          # flag off
+    assert np.array_equal(lab_map, want_lab)
+    assert not off.any()
+    u0, v0 = np.floor(uu).astype(int), np.floor(vv).astype(int)
+    L2 = want_lab.reshape(G, G)
+    corners = np.stack([L2[u0, v0], L2[u0, v0 + 1], L2[u0 + 1, v0], L2[u0 + 1, v0 + 1]])
+    k = (corners != label[None, :]).sum(axis=0)
+    d = np.abs(pmax - np.log(2.0))
+    want = (k == 4) | ((k >= 1) & (d < lm))
+    near = np.abs(d - lm) < 1e-5
+    assert np.array_equal(resolve.astype(bool)[~near], want[~near])
+    assert want.any() and (~want).any()
