@@ -55,6 +55,8 @@ class Config:
     pilot: int = 64                # phases before the longest-first queue order (0: off)
     data_grid: int = 256           # blocks of the training sweep after its pilot: one wave
                                    # per SIMD, the fastest for its longest systems (0: all)
+    resolve_grid: int = 512        # blocks of the re-solve after its pilot: two waves per
+                                   # SIMD (it is 1-2 resident waves of long systems; 0: all)
 
 
 def loo_disagreement(nlab, node_idx, net_label):
@@ -285,7 +287,8 @@ def run(cfg: Config, log=print) -> Report:
     net_label = label.clone()
     t0 = time.perf_counter()
     rec_r, st_r, _, rep.resolve_attempts = km_solve_records(
-        Ps_d, cfg.n_phases, cfg.n_last, idx_dev=idx, n_full=ns, pilot=cfg.pilot)
+        Ps_d, cfg.n_phases, cfg.n_last, idx_dev=idx, n_full=ns, pilot=cfg.pilot,
+        grid=cfg.resolve_grid)
     if rep.n_resolve:
         sur._check(L.sur_exact_labels(s.h, ens.C.c_void_p(rec_r.data_ptr()), rep.n_resolve,
                                       ens.C.c_void_p(idx.data_ptr()),
@@ -355,6 +358,7 @@ def run(cfg: Config, log=print) -> Report:
     rep.extra = {"judge_idx": jidx, "judge_exact": exact_j, "nlab": nlab,
                  "judge_pmax": pmax[jidx_d].cpu().numpy(), "judge_final": final_j,
                  "judge_resolve": resolve[jidx_d].cpu().numpy(),
+                 "final_all": label.cpu().numpy(),
                  "train_lnmax": torch.log(rec_t.max(dim=0).values).cpu().numpy()}
     s.close()
     return rep
