@@ -107,6 +107,20 @@ int sur_train_step(sur_t s, const float *x, const float *target, int64_t m,
 int sur_train_epoch(sur_t s, const float *x, const float *y, int64_t n, const int64_t *perm,
                     int64_t batch, float *mean_loss);
 
+/* `epochs` passes over the training rows rows[0 .. n) (device int64, row
+ * indices of the device dataset x [..][2], y [..][SUR_OUT]), batches as in
+ * sur_train_epoch; epoch e uses learning rate lr[e] (host, > 0) and a seeded
+ * random order of the rows: the rows sorted by the SplitMix64 output function
+ * of seed + 0x9E3779B97F4A7C15 (e n + i + 1) for the i-th row (ties in row
+ * order).  One epoch's launches are captured as a graph and replayed with
+ * each epoch's order, learning rate and step count from device memory, with
+ * no host synchronisation between epochs.  losses (host, `epochs` floats,
+ * may be NULL) receives each epoch's mean batch loss.  The handle's Adam
+ * betas / epsilon apply; its learning rate is not changed. */
+int sur_train_epochs(sur_t s, const float *x, const float *y, const int64_t *rows, int64_t n,
+                     int64_t batch, int64_t epochs, const double *lr, uint64_t seed,
+                     float *losses);
+
 /* Loss and gradients of one batch without an update (for checking): grads
  * receives SUR_N_PARAMS floats in the parameter packing. */
 int sur_gradients(sur_t s, const float *x, const float *target, int64_t m, float *grads,

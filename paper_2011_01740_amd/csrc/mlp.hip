@@ -27,6 +27,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "../../include/sur.h"
 #include "ens_internal.h"
 
@@ -918,6 +920,57 @@ int load_batch(sur_ctx *s, const float *x, const float *tgt, int64_t m, int wher
   return ENS_OK;
 }
 
+// Captures the launches of one epoch over perm[0 .. n) (once per dataset,
+// row-list buffer and batch); replays read the hyper-parameters and the row
+// list's contents from device memory.
+int ensure_epoch_graph(sur_ctx *s, const float *x, const float *y, int64_t n, const int64_t *perm,
+                       int64_t batch) {
+  const int64_t nb = n / batch;
+  if (s->ep_exec && s->ep_x == x && s->ep_y == y && s->ep_perm == perm && s->ep_n == n &&
+      s->ep_batch == batch)
+    return ENS_OK;
+  free_epoch_graph(s);
+  hipStream_t user = s->stream;
+  s->stream = s->cap_stream;
+  hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+  for (int64_t b = 0; e == hipSuccess && b < nb; ++b) {
+    const int64_t *rows = perm + b * batch;
+    e = forward_batch(s, train_bufs(s), batch, rows, x);
+    if (e == hipSuccess) e = backward_batch(s, batch, y, rows, s->loss_acc, b == 0);
+    if (e == hipSuccess) e = adam_captured(s, (int)b);
+  }
+  hipGraph_t gr = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &gr);
+  s->stream = user;
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return sfail(s, ENS_E_HIP, std::string("training epoch capture: ") +
+                                   hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  s->ep_graph = gr;
+  SUR_HIP(s, hipGraphInstantiate(&s->ep_exec, gr, nullptr, nullptr, 0));
+  s->ep_x = x;
+  s->ep_y = y;
+  s->ep_perm = perm;
+  s->ep_n = n;
+  s->ep_batch = batch;
+  return ENS_OK;
+}
+
+// Epoch e's row order: the training rows sorted by a hash of (seed, e, i)
+// (SplitMix64's output function of a Weyl sequence), i.e. a seeded uniformly
+// random permutation; equal keys keep index order.
+__global__ void k_epoch_keys(const int64_t *__restrict__ rows, int64_t n, uint64_t seed,
+                             int64_t epoch, unsigned long long *key, int64_t *val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(epoch * n + i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  key[i] = (unsigned long long)(z ^ (z >> 31));
+  val[i] = rows[i];
+}
+
 }  // namespace
 
 extern "C" {
@@ -1227,37 +1280,7 @@ int sur_train_epoch(sur_t s, const float *x, const float *y, int64_t n, const in
   if (!x || !y || !perm || n < batch) return sfail(s, ENS_E_INVAL, "sur_train_epoch: bad arguments");
   DevGuard dg(s->device);
   const int64_t nb = n / batch;
-  const bool same = s->ep_exec && s->ep_x == x && s->ep_y == y && s->ep_perm == perm &&
-                    s->ep_n == n && s->ep_batch == batch;
-  if (!same) {
-    // capture the epoch's launches once; replays read the hyper-parameters
-    // and the row list (its contents may change) from device memory
-    free_epoch_graph(s);
-    hipStream_t user = s->stream;
-    s->stream = s->cap_stream;
-    hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
-    for (int64_t b = 0; e == hipSuccess && b < nb; ++b) {
-      const int64_t *rows = perm + b * batch;
-      e = forward_batch(s, train_bufs(s), batch, rows, x);
-      if (e == hipSuccess) e = backward_batch(s, batch, y, rows, s->loss_acc, b == 0);
-      if (e == hipSuccess) e = adam_captured(s, (int)b);
-    }
-    hipGraph_t gr = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &gr);
-    s->stream = user;
-    if (e != hipSuccess || e2 != hipSuccess) {
-      if (gr) (void)hipGraphDestroy(gr);
-      return sfail(s, ENS_E_HIP, std::string("sur_train_epoch: capture: ") +
-                                     hipGetErrorString(e != hipSuccess ? e : e2));
-    }
-    s->ep_graph = gr;
-    SUR_HIP(s, hipGraphInstantiate(&s->ep_exec, gr, nullptr, nullptr, 0));
-    s->ep_x = x;
-    s->ep_y = y;
-    s->ep_perm = perm;
-    s->ep_n = n;
-    s->ep_batch = batch;
-  }
+  if (int rc = ensure_epoch_graph(s, x, y, n, perm, batch)) return rc;
   s->hyper_host[0] = s->lr;
   s->hyper_host[1] = s->b1;
   s->hyper_host[2] = s->b2;
@@ -1273,6 +1296,81 @@ int sur_train_epoch(sur_t s, const float *x, const float *y, int64_t n, const in
     SUR_HIP(s, hipStreamSynchronize(s->stream));
     *mean_loss = acc / (float)nb;
   }
+  return ENS_OK;
+}
+
+int sur_train_epochs(sur_t s, const float *x, const float *y, const int64_t *rows, int64_t n,
+                     int64_t batch, int64_t epochs, const double *lr, uint64_t seed,
+                     float *losses) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_train_epochs: NULL handle");
+  if (int rc = check_batch(s, batch)) return rc;
+  if (!x || !y || !rows || n < batch || epochs < 0 || (epochs > 0 && !lr))
+    return sfail(s, ENS_E_INVAL, "sur_train_epochs: bad arguments");
+  for (int64_t e = 0; e < epochs; ++e)
+    if (!(lr[e] > 0)) return sfail(s, ENS_E_INVAL, "sur_train_epochs: learning rates must be > 0");
+  if (epochs == 0) return ENS_OK;
+  DevGuard dg(s->device);
+  const int64_t nb = n / batch;
+  // device buffers of this call: sort keys and values, the epoch's order,
+  // the per-epoch hyper-parameters, the per-epoch losses, sort scratch
+  size_t tmp = 0;
+  SUR_HIP(s, rocprim::radix_sort_pairs(nullptr, tmp, (const unsigned long long *)nullptr,
+                                       (unsigned long long *)nullptr, (const int64_t *)nullptr,
+                                       (int64_t *)nullptr, (size_t)n, 0u, 64u, s->stream));
+  const size_t kb = ((size_t)n * 8 + 255) & ~(size_t)255;
+  const size_t hb = ((size_t)epochs * 5 * sizeof(double) + 255) & ~(size_t)255;
+  const size_t lb = ((size_t)epochs * sizeof(float) + 255) & ~(size_t)255;
+  char *buf = nullptr;
+  SUR_HIP(s, hipMalloc((void **)&buf, 4 * kb + hb + lb + tmp));
+  auto *key_in = (unsigned long long *)buf;
+  auto *key_out = (unsigned long long *)(buf + kb);
+  auto *val_in = (int64_t *)(buf + 2 * kb);
+  auto *order = (int64_t *)(buf + 3 * kb);
+  auto *hyp = (double *)(buf + 4 * kb);
+  auto *loss_d = (float *)(buf + 4 * kb + hb);
+  void *sort_tmp = buf + 4 * kb + hb + lb;
+  std::vector<double> h((size_t)epochs * 5);
+  for (int64_t e = 0; e < epochs; ++e) {
+    h[5 * e + 0] = lr[e];
+    h[5 * e + 1] = s->b1;
+    h[5 * e + 2] = s->b2;
+    h[5 * e + 3] = s->eps;
+    h[5 * e + 4] = (double)(s->t + e * nb);
+  }
+  hipError_t err = hipMemcpyAsync(hyp, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
+                                  s->stream);
+  int rc = ENS_OK;
+  if (err == hipSuccess) rc = ensure_epoch_graph(s, x, y, n, order, batch);
+  for (int64_t e = 0; err == hipSuccess && rc == ENS_OK && e < epochs; ++e) {
+    hipLaunchKernelGGL(k_epoch_keys, dim3(nblk(n, 256)), dim3(256), 0, s->stream, rows, n,
+                       (uint64_t)seed, e, key_in, val_in);
+    err = hipGetLastError();
+    if (err == hipSuccess)
+      err = rocprim::radix_sort_pairs(sort_tmp, tmp, key_in, key_out, val_in, order, (size_t)n,
+                                      0u, 64u, s->stream);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(s->hyper, hyp + 5 * e, 5 * sizeof(double), hipMemcpyDeviceToDevice,
+                           s->stream);
+    if (err == hipSuccess) err = hipGraphLaunch(s->ep_exec, s->stream);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(loss_d + e, s->loss_acc, sizeof(float), hipMemcpyDeviceToDevice,
+                           s->stream);
+  }
+  std::vector<float> lh((size_t)epochs);
+  if (err == hipSuccess && rc == ENS_OK)
+    err = hipMemcpyAsync(lh.data(), loss_d, epochs * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(s->stream);
+  // the epoch graph reads `order`, which is freed here: drop it
+  free_epoch_graph(s);
+  s->ep_perm = nullptr;
+  (void)hipFree(buf);
+  if (rc != ENS_OK) return rc;
+  if (err != hipSuccess)
+    return sfail(s, err == hipErrorOutOfMemory ? ENS_E_NOMEM : ENS_E_HIP,
+                 std::string("sur_train_epochs: ") + hipGetErrorString(err));
+  s->t += epochs * nb;
+  if (losses)
+    for (int64_t e = 0; e < epochs; ++e) losses[e] = lh[e] / (float)nb;
   return ENS_OK;
 }
 

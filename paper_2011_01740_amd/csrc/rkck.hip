@@ -113,28 +113,28 @@ struct MLorenz {  // Sec. 4.1
   }
 };
 
-// sin x and cos x for |x| <= 0.8 from their Taylor series (terms through
-// x^17 and x^18; the first omitted terms are below 1.2e-19), Horner in x^2.
-__device__ __forceinline__ void sincos_small(double x, double *s, double *c) {
+// sin x and cos x from their Taylor series, sin through x^(2 NS - 1) and cos
+// through x^(2 NC - 2), Horner in x^2.  The callers size NS, NC for the
+// largest |x| they pass so that the first omitted term is below 1e-18.
+constexpr double kInvFact[20] = {
+    1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040, 1.0 / 40320,
+    1.0 / 362880, 1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600, 1.0 / 6227020800.0,
+    1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0,
+    1.0 / 355687428096000.0, 1.0 / 6402373705728000.0, 1.0 / 121645100408832000.0};
+
+template <int NS, int NC>
+__device__ __forceinline__ void sincos_taylor(double x, double *s, double *c) {
+  static_assert(NS >= 2 && NC >= 2 && 2 * NS - 1 < 20 && 2 * NC - 2 < 20, "series length");
   const double x2 = x * x;
-  double ps = 1.0 / 355687428096000.0;           // 1/17!
-  ps = fma(ps, x2, -1.0 / 1307674368000.0);       // 1/15!
-  ps = fma(ps, x2, 1.0 / 6227020800.0);           // 1/13!
-  ps = fma(ps, x2, -1.0 / 39916800.0);            // 1/11!
-  ps = fma(ps, x2, 1.0 / 362880.0);               // 1/9!
-  ps = fma(ps, x2, -1.0 / 5040.0);                // 1/7!
-  ps = fma(ps, x2, 1.0 / 120.0);                  // 1/5!
-  ps = fma(ps, x2, -1.0 / 6.0);                   // 1/3!
+  // sin x = x (1 - x^2/3! + ...): coefficients of x^(2k+1), k = 0 .. NS-1
+  double ps = ((NS - 1) % 2 ? -1.0 : 1.0) * kInvFact[2 * NS - 1];
+#pragma unroll
+  for (int k = NS - 2; k >= 1; --k) ps = fma(ps, x2, (k % 2 ? -1.0 : 1.0) * kInvFact[2 * k + 1]);
   *s = fma(ps * x2, x, x);
-  double pc = 1.0 / 6402373705728000.0;          // 1/18!
-  pc = fma(pc, x2, -1.0 / 20922789888000.0);      // 1/16!
-  pc = fma(pc, x2, 1.0 / 87178291200.0);          // 1/14!
-  pc = fma(pc, x2, -1.0 / 479001600.0);           // 1/12!
-  pc = fma(pc, x2, 1.0 / 3628800.0);              // 1/10!
-  pc = fma(pc, x2, -1.0 / 40320.0);               // 1/8!
-  pc = fma(pc, x2, 1.0 / 720.0);                  // 1/6!
-  pc = fma(pc, x2, -1.0 / 24.0);                  // 1/4!
-  pc = fma(pc, x2, 0.5);                          // 1/2!
+  // cos x = 1 - x^2 (1/2! - x^2/4! + ...): coefficients of x^(2k), k = 1 .. NC-1
+  double pc = ((NC - 1) % 2 ? 1.0 : -1.0) * kInvFact[2 * NC - 2];
+#pragma unroll
+  for (int k = NC - 2; k >= 1; --k) pc = fma(pc, x2, (k % 2 ? 1.0 : -1.0) * kInvFact[2 * k]);
   *c = fma(-pc, x2, 1.0);
 }
 
@@ -204,12 +204,12 @@ struct MKM {
         so = 0.0;
         co = 1.0;
       } else if constexpr (S == 2) {
-        sincos_small((2.0 * M_PI / 5.0) * h, &so2, &co2);
+        sincos_taylor<6, 6>((2.0 * M_PI / 5.0) * h, &so2, &co2);        // |x| <= 0.16
         so = so2;
         co = co2;
       } else if constexpr (S == 3) {
         double so3, co3;
-        sincos_small((2.0 * M_PI * 3.0 / 10.0) * h, &so3, &co3);
+        sincos_taylor<8, 8>((2.0 * M_PI * 3.0 / 10.0) * h, &so3, &co3);  // |x| <= 0.24
         so4 = 2.0 * so3 * co3;             // doubled angle, for stage 4
         co4 = fma(-2.0 * so3, so3, 1.0);
         so = so3;
@@ -222,7 +222,7 @@ struct MKM {
         so = fma(so4, cd, co4 * sd);
         co = fma(co4, cd, -(so4 * sd));
       } else {
-        sincos_small((2.0 * M_PI * 7.0 / 8.0) * h, &so, &co);
+        sincos_taylor<9, 10>((2.0 * M_PI * 7.0 / 8.0) * h, &so, &co);     // |x| <= 0.69
       }
       if constexpr (S == 1) {
         s = s0;

@@ -46,6 +46,8 @@ def _lib():
         L.sur_fit_label_map.argtypes = [vp, vp, i32, vp]
         L.sur_fit_norm.argtypes = [vp, dp, dp, vp, i64, dp, dp]
         L.sur_train_epoch.argtypes = [vp, vp, vp, i64, vp, i64, C.POINTER(C.c_float)]
+        L.sur_train_epochs.argtypes = [vp, vp, vp, vp, i64, i64, i64, dp, C.c_uint64,
+                                       C.POINTER(C.c_float)]
         L.sur_exact_labels.argtypes = [vp, vp, i64, vp, vp]
         _bound = True
     return L
@@ -156,6 +158,18 @@ class Surrogate:
         _check(_lib().sur_gradients(self.h, px, pt, m, C.c_void_p(g.ctypes.data),
                                     C.c_void_p(loss.ctypes.data), w), self.h)
         return g, float(loss[0])
+
+    def train_epochs(self, x_dev, y_dev, rows_dev, batch, lrs, seed):
+        """Epochs over device dataset rows (see sur_train_epochs); returns the
+        per-epoch mean losses."""
+        lr = np.ascontiguousarray(lrs, dtype=np.float64)
+        out = np.empty(lr.size, dtype=np.float32)
+        _check(_lib().sur_train_epochs(self.h, C.c_void_p(x_dev.data_ptr()),
+                                       C.c_void_p(y_dev.data_ptr()),
+                                       C.c_void_p(rows_dev.data_ptr()), int(rows_dev.numel()),
+                                       int(batch), int(lr.size), _dptr(lr), int(seed),
+                                       out.ctypes.data_as(C.POINTER(C.c_float))), self.h)
+        return out
 
     def forward(self, x):
         px, w, kx = _ptr(x)

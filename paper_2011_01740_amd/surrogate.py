@@ -232,21 +232,15 @@ def run(cfg: Config, log=print) -> Report:
                               ens.C.c_void_p(rec_train.data_ptr()), int(train.size),
                               sur._dptr(mean), sur._dptr(std)), s.h)
     x_d, y_d = s.build_dataset(Pt_d, rec_t, nt)
-    shuf = np.random.default_rng(cfg.shuffle_seed)
-    loss = ens.C.c_float()
-    # one device buffer for the row order, so the library replays its
-    # captured epoch
-    perm = torch.empty(train.size, dtype=torch.int64, device="cuda")
-    for ep in range(cfg.epochs):
-        s.set_adam(lr=cfg.lr * 0.5 * (1.0 + math.cos(math.pi * ep / cfg.epochs)) + 1e-5)
-        perm.copy_(torch.from_numpy(shuf.permutation(train).astype(np.int64)))
-        sur._check(L.sur_train_epoch(s.h, ens.C.c_void_p(x_d.data_ptr()),
-                                     ens.C.c_void_p(y_d.data_ptr()), int(train.size),
-                                     ens.C.c_void_p(perm.data_ptr()), cfg.batch,
-                                     ens.C.byref(loss)), s.h)
+    # cosine-decayed learning rate; the row order of each epoch is drawn on
+    # the device from shuffle_seed
+    lrs = [cfg.lr * 0.5 * (1.0 + math.cos(math.pi * ep / cfg.epochs)) + 1e-5
+           for ep in range(cfg.epochs)]
+    losses = s.train_epochs(x_d, y_d, _dev(train.astype(np.int64)), cfg.batch, lrs,
+                            cfg.shuffle_seed)
     _sync()
     T["train"] = time.perf_counter() - t0
-    rep.train_loss = float(loss.value)
+    rep.train_loss = float(losses[-1]) if len(losses) else 0.0
     log(f"train: {cfg.epochs} epochs in {T['train']:.2f} s, last epoch loss {rep.train_loss:.4g}")
 
     # 3. calibration on the hold-out part of the coarse grid: the network's

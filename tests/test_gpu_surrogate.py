@@ -222,3 +222,51 @@ def test_label_flag_against_the_training_labels():
     near = np.abs(d - lm) < 1e-5
     assert np.array_equal(resolve.astype(bool)[~near], want[~near])
     assert want.any() and (~want).any()
+
+
+def _epoch_order(rows, seed, epoch):
+    """The documented order of sur_train_epochs: rows sorted (stably) by the
+    SplitMix64 output function of seed + golden * (epoch * n + i + 1)."""
+    n = rows.size
+    with np.errstate(over="ignore"):
+        z = (np.uint64(seed) + np.uint64(0x9E3779B97F4A7C15)
+             * (np.uint64(epoch * n) + np.arange(n, dtype=np.uint64) + np.uint64(1)))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return rows[np.argsort(z, kind="stable")]
+
+
+def test_train_epochs_equals_single_epochs_with_its_orders():
+    import torch
+    sur = _sur()
+    from paper_2011_01740_amd import ens
+    rows_total, batch = 1024, 256
+    x, t = _data(rows_total, 11)
+    rows = np.sort(np.random.default_rng(2).permutation(rows_total)[:800]).astype(np.int64)
+    lrs = [3e-3, 1e-3, 2e-3]
+    flat = _f32_params(12)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    with sur.Surrogate(max_batch=batch) as s:
+        s.set_params(flat)
+        losses = s.train_epochs(xd, td, torch.from_numpy(rows).cuda(), batch, lrs, 77)
+        multi = s.get_params()
+        with pytest.raises(ens.EnsError):
+            s.train_epochs(xd, td, torch.from_numpy(rows).cuda(), batch, [1e-3, 0.0], 77)
+    single_losses = []
+    with sur.Surrogate(max_batch=batch) as s:
+        s.set_params(flat)
+        perm = torch.empty(rows.size, dtype=torch.int64, device="cuda")
+        L = sur._lib()
+        for e, lr in enumerate(lrs):
+            s.set_adam(lr=lr)
+            perm.copy_(torch.from_numpy(_epoch_order(rows, 77, e)))
+            loss = ens.C.c_float()
+            sur._check(L.sur_train_epoch(s.h, ens.C.c_void_p(xd.data_ptr()),
+                                         ens.C.c_void_p(td.data_ptr()), rows.size,
+                                         ens.C.c_void_p(perm.data_ptr()), batch,
+                                         ens.C.byref(loss)), s.h)
+            single_losses.append(loss.value)
+        single = s.get_params()
+    assert np.array_equal(multi, single)
+    assert np.allclose(losses, single_losses, rtol=0, atol=0)
