@@ -95,9 +95,12 @@ def run_case(case, args):
         print(json.dumps({"case": "copy", "bytes_read": a.numel() * 8,
                           "bytes_written": a.numel() * 8}), flush=True)
     elif case == "km":
-        r = W.km_sweep(args.km_grid, args.km_grid, n_phases=args.km_phases)
+        r = W.km_sweep(args.km_grid, args.km_grid, n_phases=args.km_phases,
+                       n_record=args.km_record or None, pilot=args.km_pilot,
+                       pilot_grid=args.km_blocks)
         steps = int(r.stats[0].sum() + r.stats[1].sum())
         print(json.dumps({"case": "km", "grid": args.km_grid, "phases": args.km_phases,
+                          "pilot": args.km_pilot, "blocks_after_pilot": args.km_blocks,
                           "kernel_ms": r.kernel_ms, "attempted_steps": steps,
                           "steps_per_s": steps / r.kernel_ms * 1e3, "launch": r.launch}),
               flush=True)
@@ -134,6 +137,11 @@ def main(argv=None):
                     help="bench: the benchmark line; others: one launch for counter runs")
     ap.add_argument("--km-grid", type=int, default=512)
     ap.add_argument("--km-phases", type=int, default=16)
+    ap.add_argument("--km-pilot", type=int, default=0,
+                    help="cycles before the longest-first queue order (0: one solve)")
+    ap.add_argument("--km-blocks", type=int, default=0,
+                    help="persistent blocks after the pilot (0: resident capacity)")
+    ap.add_argument("--km-record", type=int, default=0, help="record ring (0: all cycles)")
     ap.add_argument("--prv-div", type=int, default=100)
     ap.add_argument("--sur-train", type=int, default=512)
     ap.add_argument("--sur-screen", type=int, default=4096)

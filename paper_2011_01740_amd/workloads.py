@@ -59,7 +59,12 @@ def lorenz(n: int, n_steps: int, seed: Optional[int] = 1, dt: float = 0.01, **la
                       wall_s=wall, launch=e.last_launch())
 
 
-def _adaptive(model, P, y0, opts, offsets=None, shared=None, budgets=None, read_records=True):
+def _adaptive(model, P, y0, opts, offsets=None, shared=None, budgets=None, read_records=True,
+              rest_opts=None):
+    """One solve with opts; or, with rest_opts, a pilot solve with opts, the
+    queue ordered longest-first by its step counts (ens_order_by_work) and a
+    second solve with rest_opts (stats summed, status bits or-ed, kernel
+    times added)."""
     import torch
     n = y0.shape[-1]
     with ens.Ensemble(model, ens.ENS_RKCK45, n, offsets=offsets) as e:
@@ -75,24 +80,42 @@ def _adaptive(model, P, y0, opts, offsets=None, shared=None, budgets=None, read_
         t0 = time.perf_counter()
         e.solve(opts)
         ms = e.last_kernel_ms()
+        stats0, status0 = 0, 0
+        if rest_opts is not None:
+            stats0, status0 = e.read(ens.ENS_STATS), e.read(ens.ENS_STATUS)
+            e.order_by_work()
+            e.solve(rest_opts)
+            ms += e.last_kernel_ms()
         wall = time.perf_counter() - t0
         return Result(y=e.read(ens.ENS_STATE), t=e.read(ens.ENS_TIME), h=e.read(ens.ENS_H),
                       records=e.read(ens.ENS_RECORDS) if read_records else None,
-                      stats=e.read(ens.ENS_STATS), status=e.read(ens.ENS_STATUS),
+                      stats=stats0 + e.read(ens.ENS_STATS),
+                      status=status0 | e.read(ens.ENS_STATUS),
                       kernel_ms=ms, wall_s=wall, launch=e.last_launch())
 
 
 def km_sweep(n_pa: int, n_f: int, n_phases: int = 1024, n_record: Optional[int] = None,
              shared: Sequence[float] = I.KM_WATER, rtol: float = 1e-10, atol: float = 1e-10,
-             P: Optional[np.ndarray] = None, **launch) -> Result:
+             P: Optional[np.ndarray] = None, pilot: int = 0, pilot_grid: int = 0,
+             **launch) -> Result:
     """Keller--Miksis sweep over an (n_pa x n_f) grid (p_A linear in [0.2, 1.2]
     bar, f geometric in [20 kHz, 1 MHz]), IC (1, 0), one y1max record per
-    acoustic cycle (the last n_record cycles).  P overrides the grid."""
+    acoustic cycle (the last n_record cycles).  P overrides the grid.  With
+    pilot > 0 the first `pilot` cycles run in index order and the rest
+    longest-first (on pilot_grid blocks; 0: all); the record ring then holds
+    the phases in order only if n_phases - pilot is a multiple of n_record."""
     if P is None:
         P, y0 = I.km_grid(n_pa, n_f)
     else:
         y0 = np.vstack([np.ones(P.shape[1]), np.zeros(P.shape[1])])
     R = n_phases if n_record is None else n_record
+    if 0 < pilot < n_phases:
+        if (n_phases - pilot) % R:
+            raise ValueError("n_phases - pilot must be a multiple of n_record")
+        o = ens.default_opts(n_phases=pilot, n_record=R, rtol=rtol, atol=atol, **launch)
+        rest = dict(launch, grid=pilot_grid or launch.get("grid", 0))
+        o2 = ens.default_opts(n_phases=n_phases - pilot, n_record=R, rtol=rtol, atol=atol, **rest)
+        return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], rest_opts=o2)
     o = ens.default_opts(n_phases=n_phases, n_record=R, rtol=rtol, atol=atol, **launch)
     return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)])
 
