@@ -74,6 +74,54 @@ def cpu_baseline(n_total, nsteps, dt, seed, target_s=12.0):
             "sample": f"first {m} of the {n_total} systems, all {nsteps} steps, {el:.1f} s"}
 
 
+def _threads():
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+def km_cpu_baseline(G, n_phases, side):
+    """The oracle on a side x side sub-grid (evenly spaced rows and columns)
+    of the G x G Keller--Miksis grid, all n_phases cycles."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2011_01740_amd import inputs as I
+    P, y0 = I.km_grid(G, G)
+    rows = np.linspace(0, G - 1, side).round().astype(np.int64)
+    idx = (rows[:, None] * G + rows[None, :]).ravel()
+    th = _threads()
+    t0 = time.perf_counter()
+    a = O.rkck45(O.KM, P[:, idx], I.KM_WATER, y0[:, idx],
+                 O.Opts(n_phases=n_phases, n_record=1), nthreads=th)
+    el = time.perf_counter() - t0
+    steps = float(a.stats[O.ST_ACCEPTED].sum() + a.stats[O.ST_REJECTED].sum())
+    return {"value": steps / el, "unit": "attempted steps/s", "cores": th, "kind": "oracle",
+            "sample": f"{side} x {side} evenly spaced points of the {G} x {G} grid, all "
+                      f"{n_phases} cycles, {el:.1f} s"}
+
+
+def prv_cpu_baseline(ensembles, m_each):
+    """The oracle on the first m_each systems of each valve ensemble, with the
+    ensemble's budget."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2011_01740_amd import inputs as I
+    from paper_2011_01740_amd import workloads as W
+    P, y0, off = W.prv_inputs(ensembles)
+    th = _threads()
+    steps, el = 0.0, 0.0
+    for k, (m, K, _) in enumerate(ensembles):
+        sl = slice(off[k], off[k] + min(m, m_each))
+        t0 = time.perf_counter()
+        a = O.rkck45(O.PRV, P[:, sl], I.PRV_DEFAULT, y0[:, sl],
+                     O.Opts(n_phases=K, n_record=1, max_impacts=K), nthreads=th)
+        el += time.perf_counter() - t0
+        steps += float(a.stats[O.ST_ACCEPTED].sum() + a.stats[O.ST_REJECTED].sum()
+                       + a.stats[O.ST_EVRETRY].sum())
+    return {"value": steps / el, "unit": "attempted steps/s", "cores": th, "kind": "oracle",
+            "sample": f"first {m_each} systems of each ensemble with its budget, {el:.1f} s"}
+
+
 def run_case(case, args):
     """Single launches for counter runs: a 1 GiB device copy (the scale of the
     FETCH_SIZE / WRITE_SIZE counters), a Keller--Miksis grid, or the valve
@@ -98,12 +146,19 @@ def run_case(case, args):
         r = W.km_sweep(args.km_grid, args.km_grid, n_phases=args.km_phases,
                        n_record=args.km_record or None, pilot=args.km_pilot,
                        pilot_grid=args.km_blocks)
-        steps = int(r.stats[0].sum() + r.stats[1].sum())
-        print(json.dumps({"case": "km", "grid": args.km_grid, "phases": args.km_phases,
-                          "pilot": args.km_pilot, "blocks_after_pilot": args.km_blocks,
-                          "kernel_ms": r.kernel_ms, "attempted_steps": steps,
-                          "steps_per_s": steps / r.kernel_ms * 1e3, "launch": r.launch}),
-              flush=True)
+        att = r.stats[0] + r.stats[1]
+        steps = int(att.sum())
+        line = {"case": "km", "grid": args.km_grid, "phases": args.km_phases,
+                "pilot": args.km_pilot, "blocks_after_pilot": args.km_blocks,
+                "kernel_ms": r.kernel_ms, "attempted_steps": steps,
+                "steps_per_s": steps / r.kernel_ms * 1e3,
+                "accepted_per_s": float(r.stats[0].sum()) / r.kernel_ms * 1e3,
+                "rhs_per_s": float(r.stats[2].sum()) / r.kernel_ms * 1e3,
+                "attempts_max_over_mean": float(att.max() / max(att.mean(), 1e-30)),
+                "launch": r.launch}
+        if args.cpu_sample:
+            line["cpu_baseline"] = km_cpu_baseline(args.km_grid, args.km_phases, args.cpu_sample)
+        print(json.dumps(line), flush=True)
     elif case == "surrogate":
         from paper_2011_01740_amd import surrogate as S
         cfg = S.Config(train_grid=args.sur_train, screen_grid=args.sur_screen,
@@ -116,10 +171,15 @@ def run_case(case, args):
         ensm = tuple((m, max(1, K // args.prv_div), sd) for m, K, sd in W.PRV_ENSEMBLES)
         r = W.prv_batched(ensm)
         steps = int(r.stats[0].sum() + r.stats[1].sum() + r.stats[5].sum())
-        print(json.dumps({"case": "prv", "budget_divisor": args.prv_div,
-                          "kernel_ms": r.kernel_ms, "attempted_steps": steps,
-                          "steps_per_s": steps / r.kernel_ms * 1e3, "launch": r.launch}),
-              flush=True)
+        line = {"case": "prv", "budget_divisor": args.prv_div,
+                "kernel_ms": r.kernel_ms, "attempted_steps": steps,
+                "steps_per_s": steps / r.kernel_ms * 1e3,
+                "impacts_per_s": float(r.stats[3].sum()) / r.kernel_ms * 1e3,
+                "phases_per_s": float(r.stats[4].sum()) / r.kernel_ms * 1e3,
+                "launch": r.launch}
+        if args.cpu_sample:
+            line["cpu_baseline"] = prv_cpu_baseline(ensm, args.cpu_sample)
+        print(json.dumps(line), flush=True)
     else:
         r = W.lorenz(args.n, args.n_steps, block=args.block, spl=args.spl)
         print(json.dumps({"case": "lorenz", "n": args.n, "n_steps": args.n_steps,
@@ -142,6 +202,9 @@ def main(argv=None):
     ap.add_argument("--km-blocks", type=int, default=0,
                     help="persistent blocks after the pilot (0: resident capacity)")
     ap.add_argument("--km-record", type=int, default=0, help="record ring (0: all cycles)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="km/prv cases: time the oracle on a sample (km: side of a sub-grid, "
+                         "prv: systems per ensemble; 0: off)")
     ap.add_argument("--prv-div", type=int, default=100)
     ap.add_argument("--sur-train", type=int, default=512)
     ap.add_argument("--sur-screen", type=int, default=4096)
@@ -212,6 +275,9 @@ def main(argv=None):
     ymax = e.read(ens.ENS_ACC, device=True)
     finite = bool(torch.isfinite(ymax).all().item())
     e.close()
+    # the FP64 FMA rate the chip sustains (independent FMA chains): the peak
+    # the clock under dense FP64 load allows, beside the published one
+    fma_tflops, _ = ens.micro_fma(0, 1 << 16)
 
     sys_steps = n * nsteps
     value = sys_steps * args.steps / wall
@@ -237,6 +303,8 @@ def main(argv=None):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(n, nsteps),
+                     "fma_chain_tflops": fma_tflops,
+                     "frac_of_fma_chain": achieved / fma_tflops,
                      "kernel": "k_rk4_lorenz", "kernel_ms": avg_kern_s * 1e3,
                      "algorithmic_flop_per_launch": FLOP_PER_STEP * sys_steps,
                      "algorithmic_bytes_per_launch": BYTES_PER_SYSTEM * n},

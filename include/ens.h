@@ -278,6 +278,16 @@ int ens_last_launch(ens_t h, int32_t *block, int32_t *spl, int32_t *grid, int32_
  * the stream). */
 int ens_last_kernel_ms(ens_t h, float *ms);
 
+/* Measurement helper (not part of the method): the FP64 FMA rate the device
+ * sustains, from 8 independent FMA chains per lane, 8 waves per SIMD on every
+ * compute unit, `iters` rounds per chain (one untimed warm-up launch, then one
+ * launch timed with HIP events on the null stream).  *tflops receives
+ * 2 x chains x iters x lanes / time in TFLOP/s, *ms (may be NULL) the time.
+ * This is the peak the clock under dense FP64 load allows, beside the
+ * published one that assumes the 2.4 GHz peak engine clock.
+ * Errors: ENS_E_INVAL (iters <= 0, tflops NULL, bad device), ENS_E_HIP. */
+int ens_micro_fma(int32_t device, int64_t iters, double *tflops, float *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libens.so")
-SOURCES = ["ens_api.hip", "rk4.hip", "rkck.hip", "mlp.hip"]
+SOURCES = ["ens_api.hip", "rk4.hip", "rkck.hip", "mlp.hip", "micro.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

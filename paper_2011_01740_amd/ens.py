@@ -85,8 +85,17 @@ def load():
     L.ens_set_params_gather.argtypes = [vp, vp, i64, vp]
     L.ens_set_order.argtypes = [vp, vp, i32]
     L.ens_order_by_work.argtypes = [vp]
+    L.ens_micro_fma.argtypes = [i32, i64, C.POINTER(C.c_double), C.POINTER(C.c_float)]
     _lib = L
     return L
+
+
+def micro_fma(device: int = 0, iters: int = 1 << 16):
+    """Sustained FP64 FMA rate of the device (TFLOP/s, ms); see ens_micro_fma."""
+    tf = C.c_double()
+    ms = C.c_float()
+    _check(load().ens_micro_fma(int(device), int(iters), C.byref(tf), C.byref(ms)))
+    return tf.value, ms.value
 
 
 class EnsError(RuntimeError):
