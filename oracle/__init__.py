@@ -20,6 +20,7 @@ SYS_OK, SYS_DT_MIN, SYS_MAX_STEPS, SYS_NONFINITE = 0, 1, 2, 4
 SYS_SETTLED, SYS_EVENT_ITER, SYS_SEATED = 8, 16, 32
 ST_ACCEPTED, ST_REJECTED, ST_NRHS, ST_IMPACTS, ST_PHASES, ST_EVRETRY = range(6)
 NSTAT = 6
+CASH_KARP, DORMAND_PRINCE = 0, 1
 
 _lib = None
 _dp = C.POINTER(C.c_double)
@@ -33,7 +34,7 @@ class _Opts(C.Structure):
                 ("event_tol", C.c_double), ("t_cap", C.c_double), ("v_stick", C.c_double),
                 ("n_phases", C.c_int64), ("n_record", C.c_int64),
                 ("max_impacts", C.c_int64), ("max_steps", C.c_int64),
-                ("max_event_iter", C.c_int32), ("pad_", C.c_int32)]
+                ("max_event_iter", C.c_int32), ("scheme", C.c_int32)]
 
 
 @dataclass
@@ -53,6 +54,7 @@ class Opts:
     max_impacts: int = 0
     max_steps: int = 0
     max_event_iter: int = 20
+    scheme: int = 0                 # CASH_KARP or DORMAND_PRINCE
 
     def _c(self) -> _Opts:
         o = _Opts()
@@ -76,6 +78,8 @@ def lib():
                                  C.POINTER(_Opts), _dp, _dp, _dp, _dp, _i64p, _i32p, C.c_int]
         L.orc_rkck_step.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, C.c_double, _dp, _dp]
         L.orc_rkck_tableau.argtypes = [_dp, _dp, _dp, _dp]
+        L.orc_rkdp_step.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, C.c_double, _dp, _dp]
+        L.orc_rkdp_tableau.argtypes = [_dp, _dp, _dp, _dp]
         for f in ("orc_dim", "orc_nparam", "orc_nshared", "orc_nrec_fields"):
             getattr(L, f).argtypes = [C.c_int]
         _lib = L
@@ -161,7 +165,8 @@ class AdaptiveResult:
 
 
 def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1):
-    """Adaptive Cash--Karp solve of an ensemble through its phases."""
+    """Adaptive solve of an ensemble through its phases with the scheme of
+    opts.scheme (Cash--Karp by default)."""
     D = dim(model)
     y0 = _f64(y0)
     n = y0.shape[-1]
@@ -206,4 +211,31 @@ def rkck_tableau():
     b4 = np.zeros(6)
     c = np.zeros(6)
     lib().orc_rkck_tableau(_ptr(a), _ptr(b5), _ptr(b4), _ptr(c))
+    return a, b5, b4, c
+
+
+def rkdp45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1):
+    """Adaptive Dormand--Prince solve (first same as last) of an ensemble."""
+    o = Opts(**{f.name: getattr(opts, f.name) for f in fields(opts)})
+    o.scheme = DORMAND_PRINCE
+    return rkck45(model, params, shared, y0, o, t0, h0, nthreads)
+
+
+def rkdp_step(model, t, y, p, shared, h):
+    """One Dormand--Prince step without error control: (y5, y4)."""
+    y = _f64(y)
+    p = _f64(p)
+    sh = _shared(model, shared)
+    y5 = np.zeros(dim(model))
+    y4 = np.zeros(dim(model))
+    lib().orc_rkdp_step(model, float(t), _ptr(y), _ptr(p), _ptr(sh), float(h), _ptr(y5), _ptr(y4))
+    return y5, y4
+
+
+def rkdp_tableau():
+    a = np.zeros((7, 7))
+    b5 = np.zeros(7)
+    b4 = np.zeros(7)
+    c = np.zeros(7)
+    lib().orc_rkdp_tableau(_ptr(a), _ptr(b5), _ptr(b4), _ptr(c))
     return a, b5, b4, c

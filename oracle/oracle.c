@@ -317,6 +317,78 @@ int orc_rkck_step(int model, double t, const double *y, const double *p,
   return 0;
 }
 
+/* ------------------------------------------------------------------ Dormand--Prince */
+
+/* Runge--Kutta--Dormand--Prince 5(4) coefficients (J. R. Dormand and P. J.
+ * Prince, J. Comput. Appl. Math. 6 (1980) 19), the scheme of the paper's
+ * Julia runs (Sec. 4.2.1).  The last row of A equals the fifth-order weights:
+ * the seventh stage is the derivative at the new point, so an accepted step's
+ * k7 is the next step's k1 (first same as last). */
+static const double DP_C[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
+static const double DP_A[7][7] = {
+    {0, 0, 0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0, 0},
+    {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0, 0},
+    {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0, 0},
+    {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0, 0},
+    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0}};
+static const double DP_B5[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
+                                -2187.0 / 6784.0, 11.0 / 84.0, 0.0};
+static const double DP_B4[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
+                                -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
+
+void orc_rkdp_tableau(double *a, double *b5, double *b4, double *c) {
+  for (int i = 0; i < 7; ++i) {
+    for (int j = 0; j < 7; ++j) a[i * 7 + j] = DP_A[i][j];
+    b5[i] = DP_B5[i];
+    b4[i] = DP_B4[i];
+    c[i] = DP_C[i];
+  }
+}
+
+/* One attempted step.  k1 holds f(t, y) on entry if have_k1, else it is
+ * evaluated (and returned in k1); k7 receives f(t + h, y5).  Returns the
+ * number of RHS evaluations (6 or 7). */
+static int rkdp_attempt(const sysctx *s, double t, const double *y, double h, double *k1,
+                        int have_k1, double *y5, double *err, double *k7) {
+  const int D = s->D;
+  double k[7][MAXD], yt[MAXD];
+  int nf = 6;
+  if (!have_k1) {
+    rhs(s, t, y, k1);
+    nf = 7;
+  }
+  for (int i = 0; i < D; ++i) k[0][i] = k1[i];
+  for (int st = 1; st < 7; ++st) {
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      for (int l = 0; l < st; ++l) acc += DP_A[st][l] * k[l][i];
+      yt[i] = y[i] + h * acc;
+    }
+    if (st == 6)
+      for (int i = 0; i < D; ++i) y5[i] = yt[i];     /* row 7 of A = b5 */
+    rhs(s, t + DP_C[st] * h, yt, k[st]);
+  }
+  for (int i = 0; i < D; ++i) {
+    double ae = 0.0;
+    for (int l = 0; l < 7; ++l) ae += (DP_B5[l] - DP_B4[l]) * k[l][i];
+    err[i] = h * ae;
+    k7[i] = k[6][i];
+  }
+  return nf;
+}
+
+int orc_rkdp_step(int model, double t, const double *y, const double *p,
+                  const double *shared, double h, double *y5, double *y4) {
+  sysctx s;
+  double err[MAXD], k1[MAXD], k7[MAXD];
+  if (ctx_init(&s, model, p, shared)) return -1;
+  rkdp_attempt(&s, t, y, h, k1, 0, y5, err, k7);
+  for (int i = 0; i < s.D; ++i) y4[i] = y5[i] - err[i];
+  return 0;
+}
+
 static double clampd(double x, double lo, double hi) {
   return x < lo ? lo : (x > hi ? hi : x);
 }
@@ -343,6 +415,10 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
   int64_t phase = 0, attempts = 0;
   int ev_iter = 0;
   double y5[MAXD], err[MAXD];
+  /* Dormand--Prince: k1 = f(t, y) of the next attempt when have_k1 */
+  const int dp = o->scheme == ORC_DORMAND_PRINCE;
+  double k1[MAXD], k7[MAXD];
+  int have_k1 = 0;
 
   while (phase < o->n_phases) {
     if (o->max_steps > 0 && attempts >= o->max_steps) {
@@ -355,9 +431,14 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
       h_try = o->t_phase - t;
       trunc = 1;
     }
-    rkck_attempt(s, t, y, h_try, y5, err);
+    if (dp) {
+      st[ORC_ST_NRHS] += rkdp_attempt(s, t, y, h_try, k1, have_k1, y5, err, k7);
+      have_k1 = 1;  /* k1 = f(t, y) stays valid while the step is retried */
+    } else {
+      rkck_attempt(s, t, y, h_try, y5, err);
+      st[ORC_ST_NRHS] += 6;
+    }
     attempts++;
-    st[ORC_ST_NRHS] += 6;
 
     /* error norm */
     double E = 0.0;
@@ -427,10 +508,15 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
       t = t + h_try;
       st[ORC_ST_ACCEPTED]++;
       h = h_next;
+      for (int c = 0; c < D; ++c) k1[c] = k7[c];   /* first same as last */
       int phase_end = 0, stop = 0;
       if (was_seated) {
-        if (y[2] - s->sh[1] >= 0.0) s->seated = 0; /* lift-off */
+        if (y[2] - s->sh[1] >= 0.0) {
+          s->seated = 0; /* lift-off */
+          have_k1 = 0;
+        }
       } else if (y[0] <= 0.0 && y[1] < 0.0) {
+        have_k1 = 0;   /* the impact law changes the state */
         /* located impact: Newtonian restitution, Sec. 4.3 */
         const double v_in = y[1];
         const double r = s->sh[3], delta = s->sh[1];
@@ -450,6 +536,7 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
       if (y[0] < ymin) ymin = y[0];
       if (phase_end) {
         /* the Poincare point: y1 at the located local maximum */
+        have_k1 = 0;   /* every phase starts with k1 evaluated */
         put_record(records, n, F, o->n_record, phase, i, y[0], ymin);
         phase++;
         st[ORC_ST_PHASES] = phase;
@@ -470,9 +557,11 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
 
     /* fixed-length phases (QUAD, LORENZ, KM) */
     for (int c = 0; c < D; ++c) y[c] = y5[c];
+    for (int c = 0; c < D; ++c) k1[c] = k7[c];   /* first same as last */
     st[ORC_ST_ACCEPTED]++;
     if (y[0] > ymax) ymax = y[0];
     if (trunc) {
+      have_k1 = 0;   /* every phase starts with k1 evaluated (the clock resets) */
       /* the phase ends exactly at t_phase; next phase from 0 with the
        * untruncated proposal h */
       put_record(records, n, F, o->n_record, phase, i, ymax, ymin);

@@ -82,8 +82,12 @@ typedef struct {
   int64_t max_impacts; /* PRV: stop after this many impacts (0: no limit)  */
   int64_t max_steps;   /* cap on attempted steps per system                */
   int32_t max_event_iter; /* secant retries per event                      */
-  int32_t pad_;
+  int32_t scheme;    /* ORC_CASH_KARP or ORC_DORMAND_PRINCE                  */
 } orc_opts;
+
+/* Adaptive schemes: Cash--Karp 5(4) (six stages) and Dormand--Prince 5(4)
+ * (seven stages, first-same-as-last). */
+enum { ORC_CASH_KARP = 0, ORC_DORMAND_PRINCE = 1 };
 
 /* Number of record fields per phase: PRV records (y1max, y1min), other models
  * record y1max. */
@@ -111,6 +115,14 @@ int orc_rkck_step(int model, double t, const double *y, const double *p,
 /* The Cash--Karp coefficients the oracle uses: a[6][6] (row-major, lower
  * triangle), b5[6], b4[6], c[6]. */
 void orc_rkck_tableau(double *a, double *b5, double *b4, double *c);
+
+/* The Dormand--Prince 5(4) tableau: a [7][7] row-major, b5, b4, c [7]. */
+void orc_rkdp_tableau(double *a, double *b5, double *b4, double *c);
+
+/* One Dormand--Prince attempt from (t, y) with step h (k1 evaluated): the
+ * fifth-order y5 and the embedded fourth-order y4. */
+int orc_rkdp_step(int model, double t, const double *y, const double *p,
+                  const double *shared, double h, double *y5, double *y4);
 
 #ifdef __cplusplus
 }

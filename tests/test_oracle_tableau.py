@@ -191,3 +191,74 @@ def test_quad_sweep_matches_closed_form():
 def test_quad_quarter_is_an_exact_equilibrium():
     y, ymax = O.rk4(O.QUAD, np.array([[0.25]]), None, np.array([[-0.5]]), 0.01, 1000)
     assert y[0, 0] == -0.5 and ymax[0] == -0.5
+
+
+# --------------------------------------------------------- Dormand--Prince 5(4)
+def _dp_tab():
+    a, b5, b4, c = O.rkdp_tableau()
+    A = [[_rat(v) for v in row] for row in a]
+    return A, [_rat(v) for v in b5], [_rat(v) for v in b4], [_rat(v) for v in c]
+
+
+def test_dormand_prince_rows_and_first_same_as_last():
+    A, b5, _, c = _dp_tab()
+    for i in range(7):
+        assert sum(A[i]) == c[i]
+        assert all(A[i][j] == 0 for j in range(i, 7))
+    # the seventh stage evaluates f at the fifth-order result (FSAL)
+    assert A[6][:6] == b5[:6] and b5[6] == 0 and c[6] == 1
+
+
+def test_dormand_prince_fifth_order_weights_satisfy_all_17_conditions():
+    A, b5, _, c = _dp_tab()
+    conds = _order_conditions(A, b5, c)
+    assert sum(len(v) for v in conds.values()) == 17
+    for order, lst in conds.items():
+        for got, want in lst:
+            assert got == want, (order, got, want)
+
+
+def test_dormand_prince_embedded_weights_are_order_four_exactly():
+    A, _, b4, c = _dp_tab()
+    conds = _order_conditions(A, b4, c)
+    for order in (1, 2, 3, 4):
+        for got, want in conds[order]:
+            assert got == want, (order, got, want)
+    assert any(got != want for got, want in conds[5])
+
+
+@pytest.mark.parametrize("h", [0.01, 0.1, 0.3, 0.7])
+def test_dormand_prince_step_is_stability_polynomial(h):
+    # the propagated fifth-order solution of DOPRI5 has R(w) = sum_k<=5 w^k/k!
+    # + w^6/600 (Hairer, Norsett, Wanner, Solving ODEs I, Sec. II.5)
+    sh = np.array([I.LORENZ_SIGMA, I.LORENZ_BETA])
+    z0 = 1.3
+    y5, y4 = O.rkdp_step(O.LORENZ, 0.0, np.array([0.0, 0.0, z0]), np.array([0.0]), sh, h)
+    w = -I.LORENZ_BETA * h
+    R5 = 1 + w + w**2 / 2 + w**3 / 6 + w**4 / 24 + w**5 / 120 + w**6 / 600
+    assert y5[2] == pytest.approx(z0 * R5, rel=4e-15)
+    # the embedded solution agrees with exp(w) through w^4 only
+    base = 1 + w + w**2 / 2 + w**3 / 6 + w**4 / 24
+    assert abs(y4[2] / z0 - base) < 0.02 * abs(w) ** 5 + 1e-15
+
+
+def test_dormand_prince_fixed_step_orders_five_and_four():
+    p = np.array([0.7])
+    T = 2.0
+    e5, e4 = [], []
+    for k in range(4):
+        n = 40 * 2**k
+        h = T / n
+        x5 = np.array([-0.5])
+        x4 = np.array([-0.5])
+        for j in range(n):
+            x5, _ = O.rkdp_step(O.QUAD, j * h, x5, p, None, h)
+            _, x4 = O.rkdp_step(O.QUAD, j * h, x4, p, None, h)
+        e5.append(abs(x5[0] - _quad_exact(0.7, T)))
+        e4.append(abs(x4[0] - _quad_exact(0.7, T)))
+    r5 = [e5[i] / e5[i + 1] for i in range(2)]
+    r4 = [e4[i] / e4[i + 1] for i in range(3)]
+    for r in r5:
+        assert 28.0 < r < 36.0, r5
+    for r in r4:
+        assert 14.0 < r < 18.0, r4
