@@ -78,7 +78,7 @@ def _threads():
     return max(1, min(os.cpu_count() or 1, 16))
 
 
-def km_cpu_baseline(G, n_phases, side):
+def km_cpu_baseline(G, n_phases, side, solver="ck"):
     """The oracle on a side x side sub-grid (evenly spaced rows and columns)
     of the G x G Keller--Miksis grid, all n_phases cycles."""
     import numpy as np
@@ -90,8 +90,9 @@ def km_cpu_baseline(G, n_phases, side):
     idx = (rows[:, None] * G + rows[None, :]).ravel()
     th = _threads()
     t0 = time.perf_counter()
+    scheme = O.DORMAND_PRINCE if solver == "dp" else O.CASH_KARP
     a = O.rkck45(O.KM, P[:, idx], I.KM_WATER, y0[:, idx],
-                 O.Opts(n_phases=n_phases, n_record=1), nthreads=th)
+                 O.Opts(n_phases=n_phases, n_record=1, scheme=scheme), nthreads=th)
     el = time.perf_counter() - t0
     steps = float(a.stats[O.ST_ACCEPTED].sum() + a.stats[O.ST_REJECTED].sum())
     return {"value": steps / el, "unit": "attempted steps/s", "cores": th, "kind": "oracle",
@@ -99,7 +100,7 @@ def km_cpu_baseline(G, n_phases, side):
                       f"{n_phases} cycles, {el:.1f} s"}
 
 
-def prv_cpu_baseline(ensembles, m_each):
+def prv_cpu_baseline(ensembles, m_each, solver="ck"):
     """The oracle on the first m_each systems of each valve ensemble, with the
     ensemble's budget."""
     import numpy as np
@@ -114,7 +115,9 @@ def prv_cpu_baseline(ensembles, m_each):
         sl = slice(off[k], off[k] + min(m, m_each))
         t0 = time.perf_counter()
         a = O.rkck45(O.PRV, P[:, sl], I.PRV_DEFAULT, y0[:, sl],
-                     O.Opts(n_phases=K, n_record=1, max_impacts=K), nthreads=th)
+                     O.Opts(n_phases=K, n_record=1, max_impacts=K,
+                            scheme=O.DORMAND_PRINCE if solver == "dp" else O.CASH_KARP),
+                     nthreads=th)
         el += time.perf_counter() - t0
         steps += float(a.stats[O.ST_ACCEPTED].sum() + a.stats[O.ST_REJECTED].sum()
                        + a.stats[O.ST_EVRETRY].sum())
@@ -143,12 +146,15 @@ def run_case(case, args):
         print(json.dumps({"case": "copy", "bytes_read": a.numel() * 8,
                           "bytes_written": a.numel() * 8}), flush=True)
     elif case == "km":
+        from paper_2011_01740_amd import ens
+        solver = ens.ENS_RKDP45 if args.solver == "dp" else ens.ENS_RKCK45
         r = W.km_sweep(args.km_grid, args.km_grid, n_phases=args.km_phases,
                        n_record=args.km_record or None, pilot=args.km_pilot,
-                       pilot_grid=args.km_blocks)
+                       pilot_grid=args.km_blocks, solver=solver)
         att = r.stats[0] + r.stats[1]
         steps = int(att.sum())
-        line = {"case": "km", "grid": args.km_grid, "phases": args.km_phases,
+        line = {"case": "km", "solver": args.solver, "grid": args.km_grid,
+                "phases": args.km_phases,
                 "pilot": args.km_pilot, "blocks_after_pilot": args.km_blocks,
                 "kernel_ms": r.kernel_ms, "attempted_steps": steps,
                 "steps_per_s": steps / r.kernel_ms * 1e3,
@@ -157,7 +163,8 @@ def run_case(case, args):
                 "attempts_max_over_mean": float(att.max() / max(att.mean(), 1e-30)),
                 "launch": r.launch}
         if args.cpu_sample:
-            line["cpu_baseline"] = km_cpu_baseline(args.km_grid, args.km_phases, args.cpu_sample)
+            line["cpu_baseline"] = km_cpu_baseline(args.km_grid, args.km_phases, args.cpu_sample,
+                                                   args.solver)
         print(json.dumps(line), flush=True)
     elif case == "surrogate":
         from paper_2011_01740_amd import surrogate as S
@@ -168,17 +175,18 @@ def run_case(case, args):
         d["case"] = "surrogate"
         print(json.dumps(d), flush=True)
     elif case == "prv":
+        from paper_2011_01740_amd import ens
         ensm = tuple((m, max(1, K // args.prv_div), sd) for m, K, sd in W.PRV_ENSEMBLES)
-        r = W.prv_batched(ensm)
+        r = W.prv_batched(ensm, solver=ens.ENS_RKDP45 if args.solver == "dp" else None)
         steps = int(r.stats[0].sum() + r.stats[1].sum() + r.stats[5].sum())
-        line = {"case": "prv", "budget_divisor": args.prv_div,
+        line = {"case": "prv", "solver": args.solver, "budget_divisor": args.prv_div,
                 "kernel_ms": r.kernel_ms, "attempted_steps": steps,
                 "steps_per_s": steps / r.kernel_ms * 1e3,
                 "impacts_per_s": float(r.stats[3].sum()) / r.kernel_ms * 1e3,
                 "phases_per_s": float(r.stats[4].sum()) / r.kernel_ms * 1e3,
                 "launch": r.launch}
         if args.cpu_sample:
-            line["cpu_baseline"] = prv_cpu_baseline(ensm, args.cpu_sample)
+            line["cpu_baseline"] = prv_cpu_baseline(ensm, args.cpu_sample, args.solver)
         print(json.dumps(line), flush=True)
     else:
         r = W.lorenz(args.n, args.n_steps, block=args.block, spl=args.spl)
@@ -202,6 +210,8 @@ def main(argv=None):
     ap.add_argument("--km-blocks", type=int, default=0,
                     help="persistent blocks after the pilot (0: resident capacity)")
     ap.add_argument("--km-record", type=int, default=0, help="record ring (0: all cycles)")
+    ap.add_argument("--solver", choices=["ck", "dp"], default="ck",
+                    help="km/prv cases: Cash--Karp or Dormand--Prince 5(4)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="km/prv cases: time the oracle on a sample (km: side of a sub-grid, "
                          "prv: systems per ensemble; 0: off)")

@@ -87,7 +87,14 @@ enum ens_model {
                      (kappa, delta, beta, r)                                 */
 };
 
-enum ens_solver { ENS_RK4 = 0, ENS_RKCK45 = 1 };
+/* Solvers: classic RK4 with a fixed step; Runge--Kutta--Cash--Karp 5(4)
+ * (six stages per attempt, the paper's GPU and ODEINT scheme); Runge--Kutta--
+ * Dormand--Prince 5(4) (the paper's Julia scheme, Sec. 4.2.1: seven stages,
+ * the last being f at the new point, so an accepted step's last stage is the
+ * next step's first -- 6 evaluations per attempt, plus one where a phase
+ * starts or after an impact or lift-off).  Both adaptive schemes use the same
+ * controller, phases, accessories and events. */
+enum ens_solver { ENS_RK4 = 0, ENS_RKCK45 = 1, ENS_RKDP45 = 2 };
 enum ens_where { ENS_HOST = 0, ENS_DEVICE = 1 };
 
 /* Per-system status bits (ENS_STATUS). */

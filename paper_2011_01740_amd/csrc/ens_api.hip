@@ -298,8 +298,8 @@ int ens_set_order(ens_t h, const int64_t *order, int32_t where) {
 
 int ens_order_by_work(ens_t h) {
   if (!h) return fail(nullptr, ENS_E_INVAL, "ens_order_by_work: NULL handle");
-  if (h->solver != ENS_RKCK45 || !h->have_adaptive)
-    return fail(h, ENS_E_ORDER, "ens_order_by_work: needs a previous RKCK45 solve");
+  if (h->solver == ENS_RK4 || !h->have_adaptive)
+    return fail(h, ENS_E_ORDER, "ens_order_by_work: needs a previous adaptive solve");
   if (h->n == 0) return ENS_OK;
   DeviceGuard g(h->device);
   const int64_t n = h->n;
@@ -391,7 +391,7 @@ int ens_create(const ens_desc *d, ens_t *out) {
   if (!d) return fail(nullptr, ENS_E_INVAL, "ens_create: desc is NULL");
   if (d->model < ENS_QUAD || d->model > ENS_PRV)
     return fail(nullptr, ENS_E_INVAL, "ens_create: unknown model");
-  if (d->solver != ENS_RK4 && d->solver != ENS_RKCK45)
+  if (d->solver != ENS_RK4 && d->solver != ENS_RKCK45 && d->solver != ENS_RKDP45)
     return fail(nullptr, ENS_E_INVAL, "ens_create: unknown solver");
   if (d->n < 0 || d->n > (int64_t)INT32_MAX)
     return fail(nullptr, ENS_E_INVAL, "ens_create: n must be in [0, 2^31)");
@@ -445,7 +445,7 @@ int ens_create(const ens_desc *d, ens_t *out) {
   if (e == hipSuccess) e = dalloc(&h->d_t, n);
   if (e == hipSuccess) e = dalloc(&h->d_h, n);
   if (e == hipSuccess && h->solver == ENS_RK4) e = dalloc(&h->d_acc, n);
-  if (e == hipSuccess && h->solver == ENS_RKCK45) {
+  if (e == hipSuccess && h->solver != ENS_RK4) {
     e = dalloc(&h->d_stats, (size_t)ENS_NSTAT * n);
     if (e == hipSuccess) e = dalloc(&h->d_status, n);
     if (e == hipSuccess) e = dalloc(&h->d_queue, 1);
@@ -615,7 +615,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
       if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM_GENERAL;
   }
   int grid = o->grid;
-  const int cap = ens::rkck_max_blocks(kmodel, block);
+  const int cap = ens::rkck_max_blocks(kmodel, h->solver, block);
   if (cap <= 0) return fail(h, ENS_E_HIP, "ens_solve: occupancy query failed");
   if (grid <= 0) grid = cap;
   if (grid > cap) return fail(h, ENS_E_INVAL, "ens_solve: grid above resident capacity");
@@ -690,7 +690,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
       e = ens::launch_fill_f64(h->d_rec, std::numeric_limits<double>::quiet_NaN(),
                                (int64_t)rec_count, s);
     if (e == hipSuccess && fill_h) e = ens::launch_fill_f64(h->d_h, o->dt0, h->n, s);
-    if (e == hipSuccess && h->n > 0) e = ens::launch_rkck(kmodel, block, grid, a, s);
+    if (e == hipSuccess && h->n > 0) e = ens::launch_rkck(kmodel, h->solver, block, grid, a, s);
     return e;
   };
 

@@ -57,10 +57,11 @@ constexpr int ENS_KM_GENERAL = 100;
 hipError_t launch_rk4(int model, int block, int spl, const double *p, double *y,
                       double *acc, int64_t n, double dt, int64_t nsteps,
                       const double *shared, hipStream_t s);
-hipError_t launch_rkck(int model, int block, int grid, const RkckArgs &a,
+// solver: ENS_RKCK45 or ENS_RKDP45.
+hipError_t launch_rkck(int model, int solver, int block, int grid, const RkckArgs &a,
                        hipStream_t s);
-// Resident-wave capacity of the persistent kernel for this model and block.
-int rkck_max_blocks(int model, int block);
+// Resident-wave capacity of the persistent kernel for this model, solver and block.
+int rkck_max_blocks(int model, int solver, int block);
 hipError_t launch_fill_f64(double *p, double v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count,
                            hipStream_t s);

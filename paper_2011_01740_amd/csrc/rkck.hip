@@ -43,6 +43,32 @@ constexpr double B1 = 37.0 / 378.0, B3 = 250.0 / 621.0, B4 = 125.0 / 594.0,
 constexpr double E1 = B1 - 2825.0 / 27648.0, E3 = B3 - 18575.0 / 48384.0,
                  E4 = B4 - 13525.0 / 55296.0, E5 = -277.0 / 14336.0, E6 = B6 - 1.0 / 4.0;
 
+// Schemes of the persistent kernel.
+constexpr int kCK = 0;  // Cash--Karp 5(4), six stages
+constexpr int kDP = 1;  // Dormand--Prince 5(4), seven stages, first same as last
+
+// Dormand--Prince 5(4) tableau (Dormand and Prince, J. Comput. Appl. Math. 6,
+// 1980).  Its last row is the fifth-order weights: stage 7 is f at y5.
+constexpr double D21 = 1.0 / 5.0;
+constexpr double D31 = 3.0 / 40.0, D32 = 9.0 / 40.0;
+constexpr double D41 = 44.0 / 45.0, D42 = -56.0 / 15.0, D43 = 32.0 / 9.0;
+constexpr double D51 = 19372.0 / 6561.0, D52 = -25360.0 / 2187.0, D53 = 64448.0 / 6561.0,
+                 D54 = -212.0 / 729.0;
+constexpr double D61 = 9017.0 / 3168.0, D62 = -355.0 / 33.0, D63 = 46732.0 / 5247.0,
+                 D64 = 49.0 / 176.0, D65 = -5103.0 / 18656.0;
+constexpr double D71 = 35.0 / 384.0, D73 = 500.0 / 1113.0, D74 = 125.0 / 192.0,
+                 D75 = -2187.0 / 6784.0, D76 = 11.0 / 84.0;
+constexpr double DC2 = 1.0 / 5.0, DC3 = 3.0 / 10.0, DC4 = 4.0 / 5.0, DC5 = 8.0 / 9.0;
+// fifth- minus fourth-order weights (the fourth-order ones: 5179/57600, 0,
+// 7571/16695, 393/640, -92097/339200, 187/2100, 1/40)
+constexpr double DE1 = D71 - 5179.0 / 57600.0, DE3 = D73 - 7571.0 / 16695.0,
+                 DE4 = D74 - 393.0 / 640.0, DE5 = D75 + 92097.0 / 339200.0,
+                 DE6 = D76 - 187.0 / 2100.0, DE7 = -1.0 / 40.0;
+
+// Occupancy floor per (model, scheme): the seventh stage and the carried k1
+// of Dormand--Prince cost one wave per SIMD.
+constexpr int min_waves(int base, int sc) { return sc == kDP ? base - 1 : base; }
+
 // 1/d from the hardware reciprocal estimate and two Newton steps
 // r <- r + r (1 - d r), each squaring the relative error: within an ulp or
 // two of the correctly rounded quotient for the normal, finite d used here
@@ -87,7 +113,7 @@ struct MQuad {  // dx/dt = x^2 - p (Sec. 3)
   double p;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) { p = P[i]; }
   __device__ void begin(double) {}
-  template <int S>
+  template <int SC, int S>
   __device__ void rhs(double, double, const double *y, double *f) const {
     f[0] = fma(y[0], y[0], -p);
   }
@@ -105,7 +131,7 @@ struct MLorenz {  // Sec. 4.1
     beta = sh[1];
   }
   __device__ void begin(double) {}
-  template <int S>
+  template <int SC, int S>
   __device__ void rhs(double, double, const double *y, double *f) const {
     f[0] = sigma * (y[1] - y[0]);
     f[1] = fma(-y[0], y[2], fma(rho, y[0], -y[1]));
@@ -181,15 +207,18 @@ struct MKM {
     K10 = 3.0 * gam;
     K49 = K4 * K9;
   }
-  // FAST: sin/cos of the stage offsets 2 pi c_i h, c = (0, 1/5, 3/10, 3/5, 1,
-  // 7/8): stages 2, 3 and 6 from the series, stage 4 by doubling stage 3's
-  // angle and stage 5 as stage 4's plus twice stage 2's.
-  double so2, co2, so4, co4;
+  // FAST: sin/cos of the stage offsets 2 pi c_i h.  Cash--Karp, c = (0, 1/5,
+  // 3/10, 3/5, 1, 7/8): stages 2, 3 and 6 from the series, stage 4 by
+  // doubling stage 3's angle and stage 5 as stage 4's plus twice stage 2's.
+  // Dormand--Prince, c = (0, 1/5, 3/10, 4/5, 8/9, 1, 1): stages 2, 3 and 5
+  // from the series, stage 4 by doubling stage 2's angle twice, stage 6 as
+  // stage 4's plus stage 2's, stage 7 the same angle as stage 6.
+  double so2, co2, so4, co4, so1, co1;
   __device__ void begin(double t) {
     if constexpr (FAST) sincospi(2.0 * t, &s0, &c0);
   }
-  // S: the stage (1..6); tau: its time; h: the attempted step.
-  template <int S>
+  // SC: the scheme; S: the stage (1..7); tau: its time; h: the attempted step.
+  template <int SC, int S>
   __device__ void rhs(double tau, double h, const double *y, double *f) {
     const double y1 = y[0], y2 = y[1];
     const double Dn = fma(y1, fma(-K9, y2, 1.0), K49);
@@ -203,6 +232,30 @@ struct MKM {
       if constexpr (S == 1) {
         so = 0.0;
         co = 1.0;
+      } else if constexpr (SC == kDP) {
+        if constexpr (S == 2) {
+          sincos_taylor<6, 6>((2.0 * M_PI / 5.0) * h, &so2, &co2);      // |x| <= 0.16
+          so = so2;
+          co = co2;
+        } else if constexpr (S == 3) {
+          sincos_taylor<8, 8>((2.0 * M_PI * 3.0 / 10.0) * h, &so, &co);  // |x| <= 0.24
+        } else if constexpr (S == 4) {
+          const double sd = 2.0 * so2 * co2, cd = fma(-2.0 * so2, so2, 1.0);  // 2/5
+          so4 = 2.0 * sd * cd;                                                // 4/5
+          co4 = fma(-2.0 * sd, sd, 1.0);
+          so = so4;
+          co = co4;
+        } else if constexpr (S == 5) {
+          sincos_taylor<9, 10>((2.0 * M_PI * 8.0 / 9.0) * h, &so, &co);  // |x| <= 0.70
+        } else if constexpr (S == 6) {
+          so1 = fma(so4, co2, co4 * so2);                                 // 4/5 + 1/5
+          co1 = fma(co4, co2, -(so4 * so2));
+          so = so1;
+          co = co1;
+        } else {
+          so = so1;
+          co = co1;
+        }
       } else if constexpr (S == 2) {
         sincos_taylor<6, 6>((2.0 * M_PI / 5.0) * h, &so2, &co2);        // |x| <= 0.16
         so = so2;
@@ -264,7 +317,7 @@ struct MPRV {
     seated = false;
   }
   __device__ void begin(double) {}
-  template <int S>
+  template <int SC, int S>
   __device__ void rhs(double, double, const double *y, double *f) const {
     if (seated) {
       f[0] = 0.0;
@@ -285,31 +338,74 @@ __device__ __forceinline__ void ck_attempt(M &m, double t, const double *y, doub
   constexpr int D = M::D;
   double k1[D], k2[D], k3[D], k4[D], k5[D], k6[D], yt[D];
   m.begin(t);
-  m.template rhs<1>(t, h, y, k1);
+  m.template rhs<kCK, 1>(t, h, y, k1);
 #pragma unroll
   for (int c = 0; c < D; ++c) yt[c] = fma(h, A21 * k1[c], y[c]);
-  m.template rhs<2>(fma(C2, h, t), h, yt, k2);
+  m.template rhs<kCK, 2>(fma(C2, h, t), h, yt, k2);
 #pragma unroll
   for (int c = 0; c < D; ++c) yt[c] = fma(h, fma(A32, k2[c], A31 * k1[c]), y[c]);
-  m.template rhs<3>(fma(C3, h, t), h, yt, k3);
+  m.template rhs<kCK, 3>(fma(C3, h, t), h, yt, k3);
 #pragma unroll
   for (int c = 0; c < D; ++c)
     yt[c] = fma(h, fma(A43, k3[c], fma(A42, k2[c], A41 * k1[c])), y[c]);
-  m.template rhs<4>(fma(C4, h, t), h, yt, k4);
+  m.template rhs<kCK, 4>(fma(C4, h, t), h, yt, k4);
 #pragma unroll
   for (int c = 0; c < D; ++c)
     yt[c] = fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], A51 * k1[c]))), y[c]);
-  m.template rhs<5>(t + C5 * h, h, yt, k5);
+  m.template rhs<kCK, 5>(t + C5 * h, h, yt, k5);
 #pragma unroll
   for (int c = 0; c < D; ++c)
     yt[c] = fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], A61 * k1[c])))),
                 y[c]);
-  m.template rhs<6>(fma(C6, h, t), h, yt, k6);
+  m.template rhs<kCK, 6>(fma(C6, h, t), h, yt, k6);
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     y5[c] = fma(h, fma(B6, k6[c], fma(B4, k4[c], fma(B3, k3[c], B1 * k1[c]))), y[c]);
     err[c] = h * fma(E6, k6[c], fma(E5, k5[c], fma(E4, k4[c], fma(E3, k3[c], E1 * k1[c]))));
   }
+}
+
+// One attempted Dormand--Prince step from (t, y): k1 = f(t, y) is taken from
+// kf when have_k1 (first same as last), else evaluated and left in kf; k7
+// receives f(t + h, y5).  Returns the number of RHS evaluations.
+template <class M>
+__device__ __forceinline__ int dp_attempt(M &m, double t, const double *y, double h,
+                                          double *kf, bool have_k1, double *y5, double *err,
+                                          double *k7) {
+  constexpr int D = M::D;
+  double k2[D], k3[D], k4[D], k5[D], k6[D], yt[D];
+  m.begin(t);
+  if (!have_k1) m.template rhs<kDP, 1>(t, h, y, kf);
+  const double *k1 = kf;
+#pragma unroll
+  for (int c = 0; c < D; ++c) yt[c] = fma(h, D21 * k1[c], y[c]);
+  m.template rhs<kDP, 2>(fma(DC2, h, t), h, yt, k2);
+#pragma unroll
+  for (int c = 0; c < D; ++c) yt[c] = fma(h, fma(D32, k2[c], D31 * k1[c]), y[c]);
+  m.template rhs<kDP, 3>(fma(DC3, h, t), h, yt, k3);
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    yt[c] = fma(h, fma(D43, k3[c], fma(D42, k2[c], D41 * k1[c])), y[c]);
+  m.template rhs<kDP, 4>(fma(DC4, h, t), h, yt, k4);
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    yt[c] = fma(h, fma(D54, k4[c], fma(D53, k3[c], fma(D52, k2[c], D51 * k1[c]))), y[c]);
+  m.template rhs<kDP, 5>(fma(DC5, h, t), h, yt, k5);
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    yt[c] = fma(h, fma(D65, k5[c], fma(D64, k4[c], fma(D63, k3[c], fma(D62, k2[c], D61 * k1[c])))),
+                y[c]);
+  m.template rhs<kDP, 6>(t + h, h, yt, k6);
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    y5[c] = fma(h, fma(D76, k6[c], fma(D75, k5[c], fma(D74, k4[c], fma(D73, k3[c], D71 * k1[c])))),
+                y[c]);
+  m.template rhs<kDP, 7>(t + h, h, y5, k7);
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    err[c] = h * fma(DE7, k7[c], fma(DE6, k6[c], fma(DE5, k5[c], fma(DE4, k4[c],
+                                                      fma(DE3, k3[c], DE1 * k1[c])))));
+  return have_k1 ? 6 : 7;
 }
 
 __device__ __forceinline__ double clampd(double x, double lo, double hi) {
@@ -324,7 +420,18 @@ struct Lane {
   uint32_t phase, accepted, rejected, evretry, impacts, attempts;
   uint32_t phase_att;  // attempts when the current phase began
   float rem;           // estimated attempts left: last phase's x phases left
+  uint32_t nrhs;       // Dormand--Prince: RHS evaluations (6 or 7 per attempt)
   int32_t status, ev_iter;
+};
+
+// Dormand--Prince: k1 = f(t, y) of the next attempt, valid when `have`.  An
+// attempt leaves its k1 here (a rejected step retries from the same point);
+// an accepted one replaces it by its k7 (first same as last); a phase end, an
+// impact or a lift-off clears it, so that every phase starts by evaluating k1.
+template <int D>
+struct Fsal {
+  double k[D];
+  bool have;
 };
 
 // Estimated work left after a completed phase.
@@ -344,7 +451,7 @@ __device__ __forceinline__ void store_record(const RkckArgs &a, const Lane &L, d
   if (F > 1) a.rec[(slot * F + 1) * a.n + L.sys] = v1;
 }
 
-template <class M>
+template <class M, int SC>
 __device__ __forceinline__ void store_lane(const RkckArgs &a, const Lane &L, const double *y) {
   constexpr int D = M::D;
   const int64_t n = a.n, i = L.sys;
@@ -355,7 +462,7 @@ __device__ __forceinline__ void store_lane(const RkckArgs &a, const Lane &L, con
   const int64_t att = (int64_t)L.accepted + L.rejected + L.evretry;
   a.stats[ENS_ST_ACCEPTED * n + i] = L.accepted;
   a.stats[ENS_ST_REJECTED * n + i] = L.rejected;
-  a.stats[ENS_ST_NRHS * n + i] = 6 * att;
+  a.stats[ENS_ST_NRHS * n + i] = SC == kDP ? (int64_t)L.nrhs : 6 * att;
   a.stats[ENS_ST_IMPACTS * n + i] = L.impacts;
   a.stats[ENS_ST_PHASES * n + i] = L.phase;
   a.stats[ENS_ST_EVRETRY * n + i] = L.evretry;
@@ -364,14 +471,20 @@ __device__ __forceinline__ void store_lane(const RkckArgs &a, const Lane &L, con
 
 // One attempted step of a fixed-length-phase model; returns true when the
 // system is finished.
-template <class M>
-__device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, double *y) {
+template <class M, int SC>
+__device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, double *y,
+                                           Fsal<M::D> &fs) {
   constexpr int D = M::D;
-  double y5[D], err[D];
+  double y5[D], err[D], k7[D];
   double h_try = L.h;
   const bool trunc = L.t + h_try >= a.t_phase;
   if (trunc) h_try = a.t_phase - L.t;
-  ck_attempt(m, L.t, y, h_try, y5, err);
+  if constexpr (SC == kDP) {
+    L.nrhs += dp_attempt(m, L.t, y, h_try, fs.k, fs.have, y5, err, k7);
+    fs.have = true;
+  } else {
+    ck_attempt(m, L.t, y, h_try, y5, err);
+  }
   L.attempts++;
   double E = 0.0;
   bool finite = true;
@@ -395,9 +508,14 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
     const double h_next = clampd(h_try * fac, a.dt_min, a.dt_max);
 #pragma unroll
     for (int c = 0; c < D; ++c) y[c] = y5[c];
+    if constexpr (SC == kDP) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) fs.k[c] = k7[c];
+    }
     L.accepted++;
     L.ymax = y[0] > L.ymax ? y[0] : L.ymax;
     if (trunc) {
+      fs.have = false;
       store_record<M>(a, L, L.ymax, 0.0);
       L.phase++;
       if constexpr (M::kPrio) note_phase_end(L);
@@ -417,11 +535,18 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
 }
 
 // One attempted step of the relief valve with events; true when finished.
-__device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, double *y) {
+template <int SC>
+__device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, double *y,
+                                           Fsal<3> &fs) {
   constexpr int D = 3;
-  double y5[D], err[D];
+  double y5[D], err[D], k7[D];
   const double h_try = L.h;
-  ck_attempt(m, L.t, y, h_try, y5, err);
+  if constexpr (SC == kDP) {
+    L.nrhs += dp_attempt(m, L.t, y, h_try, fs.k, fs.have, y5, err, k7);
+    fs.have = true;
+  } else {
+    ck_attempt(m, L.t, y, h_try, y5, err);
+  }
   L.attempts++;
   double E = 0.0;
   bool finite = true;
@@ -479,14 +604,22 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
       const bool was_seated = m.seated;
 #pragma unroll
       for (int c = 0; c < D; ++c) y[c] = y5[c];
+      if constexpr (SC == kDP) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) fs.k[c] = k7[c];
+      }
       L.t += h_try;
       L.accepted++;
       L.h = h_next;
       bool phase_end = false;
       if (was_seated) {
-        if (y[2] - m.delta >= 0.0) m.seated = false;
+        if (y[2] - m.delta >= 0.0) {
+          m.seated = false;
+          fs.have = false;
+        }
       } else if (y[0] <= 0.0 && y[1] < 0.0) {
         // located impact: Newtonian restitution (Sec. 4.3)
+        fs.have = false;
         const double v_in = y[1];
         y[0] = 0.0;
         y[1] = -m.r * v_in;
@@ -503,6 +636,7 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
       L.ymax = y[0] > L.ymax ? y[0] : L.ymax;
       L.ymin = y[0] < L.ymin ? y[0] : L.ymin;
       if (phase_end) {
+        fs.have = false;
         store_record<MPRV>(a, L, y[0], L.ymin);
         L.phase++;
         if constexpr (MPRV::kPrio) note_phase_end(L);
@@ -528,8 +662,9 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
 // Each model states the occupancy floor the register allocator must respect
 // (kMinWaves waves per SIMD): 5 for the light models, 4 for the fast
 // Keller--Miksis variant, whose stage trigonometry needs the extra registers.
-template <class M>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kMinWaves, 8))) void k_rkck(RkckArgs a) {
+template <class M, int SC>
+__global__ __launch_bounds__(kMaxBlock)
+__attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC), 8))) void k_rkck(RkckArgs a) {
   constexpr int D = M::D;
   __shared__ EnsDesc sdesc[ENS_MAX_ENSEMBLES];
   for (int e = threadIdx.x; e < a.n_ens; e += blockDim.x) sdesc[e] = a.desc[e];
@@ -540,6 +675,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kM
   if (M::kPrio && a.prioritize) __builtin_amdgcn_s_setprio(3);
   M m;
   Lane L;
+  Fsal<D> fs;
   double y[D];
   bool active = false;
   bool drained = false;
@@ -577,9 +713,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kM
           }
           L.status = 0;
           L.ev_iter = 0;
+          L.nrhs = 0;
+          fs.have = false;
           active = true;
           if (L.n_phases <= 0) {
-            store_lane<M>(a, L, y);
+            store_lane<M, SC>(a, L, y);
             active = false;
           }
         }
@@ -593,11 +731,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kM
     if (active) {
       bool done;
       if constexpr (M::kEvents)
-        done = step_valve(a, m, L, y);
+        done = step_valve<SC>(a, m, L, y, fs);
       else
-        done = step_fixed<M>(a, m, L, y);
+        done = step_fixed<M, SC>(a, m, L, y, fs);
       if (done) {
-        store_lane<M>(a, L, y);
+        store_lane<M, SC>(a, L, y);
         active = false;
       }
     }
@@ -620,16 +758,16 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(M::kM
   }
 }
 
-template <class M>
+template <class M, int SC>
 hipError_t launch_model(int block, int grid, const RkckArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_rkck<M>, dim3(grid), dim3(block), 0, s, a);
+  hipLaunchKernelGGL((k_rkck<M, SC>), dim3(grid), dim3(block), 0, s, a);
   return hipGetLastError();
 }
 
-template <class M>
+template <class M, int SC>
 int max_blocks_model(int block) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rkck<M>, block, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rkck<M, SC>, block, 0) != hipSuccess)
     return 0;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -638,30 +776,45 @@ int max_blocks_model(int block) {
   return per_cu * cus;
 }
 
-}  // namespace
-
-hipError_t launch_rkck(int model, int block, int grid, const RkckArgs &a, hipStream_t s) {
-  if (block <= 0 || block > kMaxBlock || block % 64 != 0 || grid <= 0)
-    return hipErrorInvalidConfiguration;
+template <int SC>
+hipError_t launch_scheme(int model, int block, int grid, const RkckArgs &a, hipStream_t s) {
   switch (model) {
-    case ENS_QUAD: return launch_model<MQuad>(block, grid, a, s);
-    case ENS_LORENZ: return launch_model<MLorenz>(block, grid, a, s);
-    case ENS_KM: return launch_model<MKM<true>>(block, grid, a, s);
-    case ENS_KM_GENERAL: return launch_model<MKM<false>>(block, grid, a, s);
-    case ENS_PRV: return launch_model<MPRV>(block, grid, a, s);
+    case ENS_QUAD: return launch_model<MQuad, SC>(block, grid, a, s);
+    case ENS_LORENZ: return launch_model<MLorenz, SC>(block, grid, a, s);
+    case ENS_KM: return launch_model<MKM<true>, SC>(block, grid, a, s);
+    case ENS_KM_GENERAL: return launch_model<MKM<false>, SC>(block, grid, a, s);
+    case ENS_PRV: return launch_model<MPRV, SC>(block, grid, a, s);
   }
   return hipErrorInvalidValue;
 }
 
-int rkck_max_blocks(int model, int block) {
-  if (block <= 0 || block > kMaxBlock || block % 64 != 0) return 0;
+template <int SC>
+int max_blocks_scheme(int model, int block) {
   switch (model) {
-    case ENS_QUAD: return max_blocks_model<MQuad>(block);
-    case ENS_LORENZ: return max_blocks_model<MLorenz>(block);
-    case ENS_KM: return max_blocks_model<MKM<true>>(block);
-    case ENS_KM_GENERAL: return max_blocks_model<MKM<false>>(block);
-    case ENS_PRV: return max_blocks_model<MPRV>(block);
+    case ENS_QUAD: return max_blocks_model<MQuad, SC>(block);
+    case ENS_LORENZ: return max_blocks_model<MLorenz, SC>(block);
+    case ENS_KM: return max_blocks_model<MKM<true>, SC>(block);
+    case ENS_KM_GENERAL: return max_blocks_model<MKM<false>, SC>(block);
+    case ENS_PRV: return max_blocks_model<MPRV, SC>(block);
   }
+  return 0;
+}
+
+}  // namespace
+
+hipError_t launch_rkck(int model, int solver, int block, int grid, const RkckArgs &a,
+                       hipStream_t s) {
+  if (block <= 0 || block > kMaxBlock || block % 64 != 0 || grid <= 0)
+    return hipErrorInvalidConfiguration;
+  if (solver == ENS_RKDP45) return launch_scheme<kDP>(model, block, grid, a, s);
+  if (solver == ENS_RKCK45) return launch_scheme<kCK>(model, block, grid, a, s);
+  return hipErrorInvalidValue;
+}
+
+int rkck_max_blocks(int model, int solver, int block) {
+  if (block <= 0 || block > kMaxBlock || block % 64 != 0) return 0;
+  if (solver == ENS_RKDP45) return max_blocks_scheme<kDP>(model, block);
+  if (solver == ENS_RKCK45) return max_blocks_scheme<kCK>(model, block);
   return 0;
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libens.so")
 # enums (include/ens.h)
 ENS_OK, ENS_E_INVAL, ENS_E_NOMEM, ENS_E_HIP, ENS_E_ORDER, ENS_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 ENS_QUAD, ENS_LORENZ, ENS_KM, ENS_PRV = 0, 1, 2, 3
-ENS_RK4, ENS_RKCK45 = 0, 1
+ENS_RK4, ENS_RKCK45, ENS_RKDP45 = 0, 1, 2
 ENS_HOST, ENS_DEVICE = 0, 1
 ENS_STATE, ENS_TIME, ENS_H, ENS_ACC, ENS_RECORDS, ENS_STATS, ENS_STATUS = range(7)
 ENS_SYS_OK, ENS_SYS_DT_MIN, ENS_SYS_MAX_STEPS, ENS_SYS_NONFINITE = 0, 1, 2, 4

@@ -60,14 +60,15 @@ def lorenz(n: int, n_steps: int, seed: Optional[int] = 1, dt: float = 0.01, **la
 
 
 def _adaptive(model, P, y0, opts, offsets=None, shared=None, budgets=None, read_records=True,
-              rest_opts=None):
+              rest_opts=None, solver=None):
     """One solve with opts; or, with rest_opts, a pilot solve with opts, the
     queue ordered longest-first by its step counts (ens_order_by_work) and a
     second solve with rest_opts (stats summed, status bits or-ed, kernel
     times added)."""
     import torch
     n = y0.shape[-1]
-    with ens.Ensemble(model, ens.ENS_RKCK45, n, offsets=offsets) as e:
+    solver = ens.ENS_RKCK45 if solver is None else solver
+    with ens.Ensemble(model, solver, n, offsets=offsets) as e:
         e.set_params(_dev(P))
         if shared is not None:
             for k, sh in enumerate(shared):
@@ -97,13 +98,14 @@ def _adaptive(model, P, y0, opts, offsets=None, shared=None, budgets=None, read_
 def km_sweep(n_pa: int, n_f: int, n_phases: int = 1024, n_record: Optional[int] = None,
              shared: Sequence[float] = I.KM_WATER, rtol: float = 1e-10, atol: float = 1e-10,
              P: Optional[np.ndarray] = None, pilot: int = 0, pilot_grid: int = 0,
-             **launch) -> Result:
+             solver: Optional[int] = None, **launch) -> Result:
     """Keller--Miksis sweep over an (n_pa x n_f) grid (p_A linear in [0.2, 1.2]
     bar, f geometric in [20 kHz, 1 MHz]), IC (1, 0), one y1max record per
     acoustic cycle (the last n_record cycles).  P overrides the grid.  With
     pilot > 0 the first `pilot` cycles run in index order and the rest
     longest-first (on pilot_grid blocks; 0: all); the record ring then holds
-    the phases in order only if n_phases - pilot is a multiple of n_record."""
+    the phases in order only if n_phases - pilot is a multiple of n_record.
+    solver: ENS_RKCK45 (default) or ENS_RKDP45."""
     if P is None:
         P, y0 = I.km_grid(n_pa, n_f)
     else:
@@ -115,9 +117,10 @@ def km_sweep(n_pa: int, n_f: int, n_phases: int = 1024, n_record: Optional[int] 
         o = ens.default_opts(n_phases=pilot, n_record=R, rtol=rtol, atol=atol, **launch)
         rest = dict(launch, grid=pilot_grid or launch.get("grid", 0))
         o2 = ens.default_opts(n_phases=n_phases - pilot, n_record=R, rtol=rtol, atol=atol, **rest)
-        return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], rest_opts=o2)
+        return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], rest_opts=o2,
+                         solver=solver)
     o = ens.default_opts(n_phases=n_phases, n_record=R, rtol=rtol, atol=atol, **launch)
-    return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)])
+    return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], solver=solver)
 
 
 PRV_ENSEMBLES: Tuple[Tuple[int, int, int], ...] = ((1 << 15, 100000, 3), (1 << 16, 10000, 4),
@@ -135,7 +138,7 @@ def prv_inputs(ensembles=PRV_ENSEMBLES):
 
 
 def prv_batched(ensembles=PRV_ENSEMBLES, n_record: int = 32, use_graph: int = 1,
-                **launch) -> Result:
+                solver: Optional[int] = None, **launch) -> Result:
     """Relief-valve ensembles (size, budget K, seed): each system runs until K
     Poincare phases or K impacts, whichever comes first; the last n_record
     phases (y1max, y1min) are kept.  One persistent launch for all."""
@@ -143,4 +146,4 @@ def prv_batched(ensembles=PRV_ENSEMBLES, n_record: int = 32, use_graph: int = 1,
     budgets = [(K, K) for _, K, _ in ensembles]
     o = ens.default_opts(n_phases=max(K for _, K, _ in ensembles), n_record=n_record,
                          use_graph=use_graph, **launch)
-    return _adaptive(ens.ENS_PRV, P, y0, o, offsets=off, budgets=budgets)
+    return _adaptive(ens.ENS_PRV, P, y0, o, offsets=off, budgets=budgets, solver=solver)

@@ -16,17 +16,21 @@ def _sample(n, k, seed, extra=()):
     return np.unique(np.concatenate([np.asarray(extra, dtype=np.int64), rng.integers(0, n, k)]))
 
 
-def test_keller_miksis_512x512_1024_cycles():
-    """2^18 systems, every one of the 1024 cycle maxima recorded."""
+@pytest.mark.parametrize("scheme", [O.CASH_KARP, O.DORMAND_PRINCE])
+def test_keller_miksis_512x512_1024_cycles(scheme):
+    """2^18 systems, every one of the 1024 cycle maxima recorded (both
+    adaptive schemes)."""
+    from paper_2011_01740_amd import ens
     from paper_2011_01740_amd import workloads as W
-    r = W.km_sweep(512, 512, n_phases=1024)
+    solver = ens.ENS_RKDP45 if scheme == O.DORMAND_PRINCE else ens.ENS_RKCK45
+    r = W.km_sweep(512, 512, n_phases=1024, solver=solver)
     n = 512 * 512
     assert r.records.shape == (1024, 1, n)
     assert np.all((r.status & ~O.SYS_DT_MIN) == 0)
     assert np.all(r.stats[O.ST_PHASES] == 1024)
     P, y0 = I.km_grid(512, 512)
     idx = _sample(n, 40, 31, extra=[0, 511, n - 512, n - 1, 300 * 512 + 17])
-    o = O.Opts(n_phases=1024, n_record=1024)
+    o = O.Opts(n_phases=1024, n_record=1024, scheme=scheme)
     a = O.rkck45(O.KM, P[:, idx], I.KM_WATER, y0[:, idx], o, nthreads=THREADS)
     b = O.rkck45(O.KM, P[:, idx], I.KM_WATER, y0[:, idx] * (1 + PERTURB), o, nthreads=THREADS)
     keep = sensitivity_mask([a.y, a.records], [b.y, b.records], 1e-9, 1e-11)

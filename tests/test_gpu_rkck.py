@@ -24,10 +24,11 @@ class Res:
 
 
 def gpu_ck(model, P, y0, opts, t0=None, h0=None, shared=None, offsets=None, budgets=None,
-           solves=1, **launch):
+           solves=1, solver=None, **launch):
     ens = _ens()
     n = y0.shape[-1]
-    with ens.Ensemble(model, ens.ENS_RKCK45, n, offsets=offsets) as e:
+    solver = ens.ENS_RKCK45 if solver is None else solver
+    with ens.Ensemble(model, solver, n, offsets=offsets) as e:
         e.set_params(P)
         if shared is not None:
             for k in range(e.n_ensembles):
@@ -272,3 +273,65 @@ def test_longest_first_continuation_is_bit_identical():
     # per-solve counters add up to the uninterrupted solve's
     for row in (O.ST_ACCEPTED, O.ST_REJECTED, O.ST_PHASES):
         assert np.array_equal(pilot[row] + rest[row], full.stats[row])
+
+
+
+# ------------------------------------------------------------ Dormand--Prince
+def _dp():
+    return _ens().ENS_RKDP45
+
+
+def test_dp_quad_matches_oracle():
+    P, y0 = I.quad_linspace(1000, 0.1, 1.0)
+    o = O.Opts(t_phase=0.5, n_phases=4, n_record=4, scheme=O.DORMAND_PRINCE)
+    g = gpu_ck(0, P, y0, o, solver=_dp())
+    a = O.rkck45(O.QUAD, P, None, y0, o)
+    check_parity(g, a, np.ones(1000, bool), step_match=0.999)
+    assert np.array_equal(g.stats[O.ST_NRHS], a.stats[O.ST_NRHS])
+
+
+def test_dp_km_grid_matches_oracle():
+    P, y0 = I.km_grid(24, 24)
+    o = O.Opts(n_phases=6, n_record=6, scheme=O.DORMAND_PRINCE)
+    g = gpu_ck(2, P, y0, o, solver=_dp())
+    a, keep = oracle_pair(O.KM, P, I.KM_WATER, y0, o)
+    check_parity(g, a, keep, min_keep=0.8)
+    # first same as last: 6 per attempt plus one per phase start
+    assert np.all(g.stats[O.ST_NRHS] == 6 * (g.stats[O.ST_ACCEPTED] + g.stats[O.ST_REJECTED])
+                  + g.stats[O.ST_PHASES])
+    same = g.stats[O.ST_NRHS] == a.stats[O.ST_NRHS]
+    assert same[keep].mean() >= 0.99
+
+
+def test_dp_prv_matches_oracle():
+    P, y0 = I.prv_linspace(256)
+    o = O.Opts(n_phases=40, n_record=8, scheme=O.DORMAND_PRINCE)
+    g = gpu_ck(3, P, y0, o, solver=_dp())
+    a, keep = oracle_pair(O.PRV, P, I.PRV_DEFAULT, y0, o)
+    check_parity(g, a, keep, min_keep=0.5, step_match=0.95)
+    assert (g.stats[O.ST_IMPACTS] == a.stats[O.ST_IMPACTS])[keep].all()
+    assert (g.stats[O.ST_NRHS] == a.stats[O.ST_NRHS])[keep].mean() >= 0.95
+
+
+def test_dp_prv_closed_form_events_on_gpu():
+    sh = [0.25, 10.0, 0.0, 0.8]
+    P = np.array([[1.0, 2.0]])
+    y0 = np.array([[10.0, 6.0], [0.0, 0.0], [10.5, 10.5]])
+    o = O.Opts(n_phases=6, n_record=6, event_tol=1e-9, t_cap=1e9, scheme=O.DORMAND_PRINCE)
+    g = gpu_ck(3, P, y0, o, shared=sh, solver=_dp())
+    a = O.rkck45(O.PRV, P, sh, y0, o)
+    assert np.array_equal(g.stats[O.ST_IMPACTS], a.stats[O.ST_IMPACTS])
+    assert close(g.records, a.records, 1e-9, 1e-9).all()
+    assert close(g.t, a.t, 1e-9, 1e-9).all()
+
+
+def test_dp_resume_and_refill_invariance():
+    P, y0 = I.km_grid(8, 8)
+    dp = _dp()
+    full = gpu_ck(2, P, y0, O.Opts(n_phases=4, n_record=4), solver=dp)
+    half = gpu_ck(2, P, y0, O.Opts(n_phases=2, n_record=2), solver=dp)
+    rest = gpu_ck(2, P, half.y, O.Opts(n_phases=2, n_record=2), t0=half.t, h0=half.h, solver=dp)
+    assert np.array_equal(full.y, rest.y) and np.array_equal(full.h, rest.h)
+    assert np.array_equal(full.records[2:], rest.records)
+    alt = gpu_ck(2, P, y0, O.Opts(n_phases=4, n_record=4), solver=dp, refill=7, block=64)
+    assert np.array_equal(alt.y, full.y) and np.array_equal(alt.stats, full.stats)
