@@ -34,7 +34,8 @@ class _Opts(C.Structure):
                 ("event_tol", C.c_double), ("t_cap", C.c_double), ("v_stick", C.c_double),
                 ("n_phases", C.c_int64), ("n_record", C.c_int64),
                 ("max_impacts", C.c_int64), ("max_steps", C.c_int64),
-                ("max_event_iter", C.c_int32), ("scheme", C.c_int32)]
+                ("max_event_iter", C.c_int32), ("scheme", C.c_int32),
+                ("locate_max", C.c_int32), ("pad_", C.c_int32)]
 
 
 @dataclass
@@ -55,6 +56,8 @@ class Opts:
     max_steps: int = 0
     max_event_iter: int = 20
     scheme: int = 0                 # CASH_KARP or DORMAND_PRINCE
+    locate_max: int = 0             # KM: maxima located on the step interpolant
+    pad_: int = 0
 
     def _c(self) -> _Opts:
         o = _Opts()

@@ -401,6 +401,32 @@ static void put_record(double *records, int64_t n, int F, int64_t R, int64_t pha
   if (F > 1) records[(slot * F + 1) * n + i] = ymin;
 }
 
+/* Dense output of a step from (t, y0) to (t + h, y1) with derivatives f0,
+ * f1 at its ends: the cubic Hermite interpolant, component c at theta in
+ * [0, 1]. */
+static double hermite(const double *y0, const double *y1, const double *f0, const double *f1,
+                      double h, int c, double th) {
+  const double t2 = th * th, t3 = t2 * th;
+  return (2.0 * t3 - 3.0 * t2 + 1.0) * y0[c] + (t3 - 2.0 * t2 + th) * h * f0[c] +
+         (-2.0 * t3 + 3.0 * t2) * y1[c] + (t3 - t2) * h * f1[c];
+}
+
+/* A local maximum of y1 inside a step in which y2 = y1' falls from > 0 to
+ * <= 0: the zero of the interpolant's y2 by bisection on theta (60 halvings
+ * reach adjacent doubles), and the interpolant's y1 there. */
+static double located_max(const double *y0, const double *y1, const double *f0,
+                          const double *f1, double h) {
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (hermite(y0, y1, f0, f1, h, 1, mid) > 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return hermite(y0, y1, f0, f1, h, 0, 0.5 * (lo + hi));
+}
+
 /* Integrate one system through its phases.  y, t, h are updated in place. */
 static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, double *hp,
                       double *records, int64_t n, int64_t i, int64_t st[ORC_NSTAT],
@@ -556,6 +582,23 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
     }
 
     /* fixed-length phases (QUAD, LORENZ, KM) */
+    if (o->locate_max && s->model == ORC_KM && y[1] > 0.0 && y5[1] <= 0.0) {
+      /* the maximum of y1 between the step points: Dormand--Prince has f at
+       * both ends (k1, k7); Cash--Karp evaluates them */
+      double f0[MAXD], f1[MAXD];
+      if (dp) {
+        for (int c = 0; c < D; ++c) {
+          f0[c] = k1[c];
+          f1[c] = k7[c];
+        }
+      } else {
+        rhs(s, t, y, f0);
+        rhs(s, t + h_try, y5, f1);
+        st[ORC_ST_NRHS] += 2;
+      }
+      const double ym = located_max(y, y5, f0, f1, h_try);
+      if (ym > ymax) ymax = ym;
+    }
     for (int c = 0; c < D; ++c) y[c] = y5[c];
     for (int c = 0; c < D; ++c) k1[c] = k7[c];   /* first same as last */
     st[ORC_ST_ACCEPTED]++;
@@ -589,6 +632,7 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
       !(opt->dt_max >= opt->dt_min))
     return -1;
   if (model != ORC_PRV && !(opt->t_phase > 0.0)) return -1;
+  if (opt->locate_max && model != ORC_KM) return -1;
   if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
   for (int64_t i = 0; i < n; ++i) {

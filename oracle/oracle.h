@@ -83,6 +83,9 @@ typedef struct {
   int64_t max_steps;   /* cap on attempted steps per system                */
   int32_t max_event_iter; /* secant retries per event                      */
   int32_t scheme;    /* ORC_CASH_KARP or ORC_DORMAND_PRINCE                  */
+  int32_t locate_max; /* KM: also take y1 where y2 falls through 0 inside a
+                         step, on the step's cubic Hermite interpolant       */
+  int32_t pad_;
 } orc_opts;
 
 /* Adaptive schemes: Cash--Karp 5(4) (six stages) and Dormand--Prince 5(4)

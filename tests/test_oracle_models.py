@@ -138,6 +138,38 @@ def test_km_small_amplitude_linear_resonance():
     assert r.records[0, 0, 0] - 1 == pytest.approx(abs(X), rel=1e-3)
 
 
+@pytest.mark.parametrize("scheme", [O.CASH_KARP, O.DORMAND_PRINCE])
+def test_km_located_maximum_on_the_step_interpolant(scheme):
+    """Located maxima (y1 where y2 = y1' falls through 0 inside a step, on the
+    step's cubic Hermite interpolant): at a loose tolerance the maximum over
+    the step points misses the steady amplitude of a small drive by ~5e-4 of
+    it, the located maximum agrees with a fine-step reference (dt_max 1e-3,
+    tolerance 1e-12) to ~1e-7 of it.  Cash--Karp pays two RHS evaluations per
+    located maximum, Dormand--Prince none (first same as last)."""
+    sh = np.array(I.KM_WATER)
+    P = np.array([[10.0], [100e3]])
+    y0 = np.array([[1.0], [0.0]])
+    ref = O.rkck45(O.KM, P, sh, y0, O.Opts(n_phases=100, n_record=1, rtol=1e-12,
+                                           atol=1e-14, dt_max=1e-3))
+    amp = ref.records[0, 0, 0] - 1.0
+    o = dict(n_phases=100, n_record=1, rtol=1e-8, atol=1e-10, dt_max=0.1, scheme=scheme)
+    plain = O.rkck45(O.KM, P, sh, y0, O.Opts(**o))
+    loc = O.rkck45(O.KM, P, sh, y0, O.Opts(locate_max=1, **o))
+    assert abs(plain.records[0, 0, 0] - ref.records[0, 0, 0]) > 1e-4 * amp
+    assert abs(loc.records[0, 0, 0] - ref.records[0, 0, 0]) < 1e-6 * amp
+    # the same steps; only the records and (Cash--Karp) the RHS count change
+    assert np.array_equal(plain.stats[O.ST_ACCEPTED], loc.stats[O.ST_ACCEPTED])
+    assert np.array_equal(plain.y, loc.y)
+    extra = loc.stats[O.ST_NRHS, 0] - plain.stats[O.ST_NRHS, 0]
+    if scheme == O.DORMAND_PRINCE:
+        assert extra == 0
+    else:
+        assert 2 * 99 <= extra <= 2 * 110 and extra % 2 == 0   # ~one maximum per cycle
+    with pytest.raises(ValueError):
+        O.rkck45(O.LORENZ, np.array([[1.0]]), LOR_SH, np.ones((3, 1)),
+                 O.Opts(locate_max=1))
+
+
 def test_km_work_counts_match_paper_table4():
     """Tab. 4: RHS evaluations over tau in [0, 2] at tolerance 1e-10 (the
     paper's material constants, 1.5 bar).  The controller is not printed in
