@@ -217,6 +217,13 @@ typedef struct {
   int32_t grid;       /* RKCK45: persistent blocks (0 = resident capacity)   */
   int32_t use_graph;  /* RKCK45: capture the launch sequence in a hipGraph
                          and replay it                                       */
+  /* accessory */
+  int32_t locate_max; /* Keller--Miksis, adaptive solvers: besides the step
+                         points, a phase's y1max also takes y1 where y2 = y1'
+                         falls through 0 inside a step, located on the
+                         step's cubic Hermite interpolant (f at both ends:
+                         free with RKDP45, two evaluations with RKCK45) by
+                         bisection; other models: ENS_E_UNSUPPORTED        */
 } ens_solve_opts;
 
 /* Fills opts with the defaults: dt 0.01, n_steps 1000, t_phase 1, dt0 1e-2,

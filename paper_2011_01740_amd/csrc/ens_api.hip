@@ -594,6 +594,8 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     return fail(h, ENS_E_INVAL, "ens_solve: bad phase, record or step counts");
   if (o->max_steps > (int64_t)UINT32_MAX)
     return fail(h, ENS_E_INVAL, "ens_solve: max_steps above 2^32");
+  if (o->locate_max && h->model != ENS_KM)
+    return fail(h, ENS_E_UNSUPPORTED, "ens_solve: locate_max is built for Keller--Miksis");
   int block = o->block, refill = o->refill;
   TuneVal tv;
   if ((!block || !refill) && tune_lookup(h->model, h->solver, h->device, h->n, &tv)) {
@@ -615,7 +617,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
       if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM_GENERAL;
   }
   int grid = o->grid;
-  const int cap = ens::rkck_max_blocks(kmodel, h->solver, block);
+  const int cap = ens::rkck_max_blocks(kmodel, h->solver, o->locate_max != 0, block);
   if (cap <= 0) return fail(h, ENS_E_HIP, "ens_solve: occupancy query failed");
   if (grid <= 0) grid = cap;
   if (grid > cap) return fail(h, ENS_E_INVAL, "ens_solve: grid above resident capacity");
@@ -682,6 +684,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   a.max_steps = o->max_steps;
   a.max_event_iter = o->max_event_iter;
   a.prioritize = std::getenv("ENS_NO_PRIORITY") ? 0 : 1;
+  a.locate_max = o->locate_max ? 1 : 0;
   const bool fill_h = !h->h_init;
 
   auto enqueue = [&](hipStream_t s) -> hipError_t {

@@ -46,6 +46,7 @@ struct RkckArgs {
   int64_t max_steps;
   int32_t max_event_iter;
   int32_t prioritize;       // waves raise their issue priority by remaining work
+  int32_t locate_max;       // Keller--Miksis: maxima located on the step interpolant
 };
 
 // Kernel variant of the Keller--Miksis model for a polytropic exponent with
@@ -61,7 +62,7 @@ hipError_t launch_rk4(int model, int block, int spl, const double *p, double *y,
 hipError_t launch_rkck(int model, int solver, int block, int grid, const RkckArgs &a,
                        hipStream_t s);
 // Resident-wave capacity of the persistent kernel for this model, solver and block.
-int rkck_max_blocks(int model, int solver, int block);
+int rkck_max_blocks(int model, int solver, bool locate_max, int block);
 hipError_t launch_fill_f64(double *p, double v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count,
                            hipStream_t s);

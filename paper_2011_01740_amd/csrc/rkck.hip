@@ -65,9 +65,12 @@ constexpr double DE1 = D71 - 5179.0 / 57600.0, DE3 = D73 - 7571.0 / 16695.0,
                  DE4 = D74 - 393.0 / 640.0, DE5 = D75 + 92097.0 / 339200.0,
                  DE6 = D76 - 187.0 / 2100.0, DE7 = -1.0 / 40.0;
 
-// Occupancy floor per (model, scheme): the seventh stage and the carried k1
-// of Dormand--Prince cost one wave per SIMD.
-constexpr int min_waves(int base, int sc) { return sc == kDP ? base - 1 : base; }
+// Occupancy floor per (model, scheme, located maxima): the seventh stage and
+// the carried k1 of Dormand--Prince, or Cash--Karp's end-point evaluations
+// for located maxima, cost one wave per SIMD.
+constexpr int min_waves(int base, int sc, bool loc) {
+  return (sc == kDP || loc) ? base - 1 : base;
+}
 
 // 1/d from the hardware reciprocal estimate and two Newton steps
 // r <- r + r (1 - d r), each squaring the relative error: within an ulp or
@@ -110,6 +113,7 @@ struct MQuad {  // dx/dt = x^2 - p (Sec. 3)
   static constexpr bool kEvents = false;
   static constexpr int kMinWaves = 5;
   static constexpr bool kPrio = false;  // issue priority by remaining work
+  static constexpr bool kLocate = false;
   double p;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) { p = P[i]; }
   __device__ void begin(double) {}
@@ -124,6 +128,7 @@ struct MLorenz {  // Sec. 4.1
   static constexpr bool kEvents = false;
   static constexpr int kMinWaves = 5;
   static constexpr bool kPrio = false;  // issue priority by remaining work
+  static constexpr bool kLocate = false;
   double rho, sigma, beta;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
     rho = P[i];
@@ -186,6 +191,7 @@ struct MKM {
   static constexpr bool kEvents = false;
   static constexpr int kMinWaves = 4;
   static constexpr bool kPrio = true;  // issue priority by remaining work
+  static constexpr bool kLocate = true;  // y2 = y1': maxima can be located
   double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49;
   double s0, c0;  // sin, cos (2 pi t) at the start of the attempted step
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
@@ -306,6 +312,7 @@ struct MPRV {
   static constexpr bool kEvents = true;
   static constexpr int kMinWaves = 5;
   static constexpr bool kPrio = false;  // issue priority by remaining work
+  static constexpr bool kLocate = false;
   double q, kappa, delta, beta, r;
   bool seated;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
@@ -462,16 +469,43 @@ __device__ __forceinline__ void store_lane(const RkckArgs &a, const Lane &L, con
   const int64_t att = (int64_t)L.accepted + L.rejected + L.evretry;
   a.stats[ENS_ST_ACCEPTED * n + i] = L.accepted;
   a.stats[ENS_ST_REJECTED * n + i] = L.rejected;
-  a.stats[ENS_ST_NRHS * n + i] = SC == kDP ? (int64_t)L.nrhs : 6 * att;
+  // Cash--Karp: 6 per attempt plus the evaluations of located maxima
+  a.stats[ENS_ST_NRHS * n + i] = SC == kDP ? (int64_t)L.nrhs : 6 * att + (int64_t)L.nrhs;
   a.stats[ENS_ST_IMPACTS * n + i] = L.impacts;
   a.stats[ENS_ST_PHASES * n + i] = L.phase;
   a.stats[ENS_ST_EVRETRY * n + i] = L.evretry;
   a.status[i] = L.status;
 }
 
+// Dense output of a step from y0 to y1 with end derivatives f0, f1 and step
+// h: the cubic Hermite interpolant, component c at theta in [0, 1].
+template <int D>
+__device__ __forceinline__ double hermite(const double *y0, const double *y1, const double *f0,
+                                          const double *f1, double h, int c, double th) {
+  const double t2 = th * th, t3 = t2 * th;
+  return (2.0 * t3 - 3.0 * t2 + 1.0) * y0[c] + (t3 - 2.0 * t2 + th) * h * f0[c] +
+         (-2.0 * t3 + 3.0 * t2) * y1[c] + (t3 - t2) * h * f1[c];
+}
+
+// y1 at the zero of the interpolant's y2 = y1' inside the step (y2 > 0 at
+// its start, <= 0 at its end), by 60 bisections of theta.
+template <int D>
+__device__ __noinline__ double located_max(const double *y0, const double *y1, const double *f0,
+                                           const double *f1, double h) {
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (hermite<D>(y0, y1, f0, f1, h, 1, mid) > 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return hermite<D>(y0, y1, f0, f1, h, 0, 0.5 * (lo + hi));
+}
+
 // One attempted step of a fixed-length-phase model; returns true when the
 // system is finished.
-template <class M, int SC>
+template <class M, int SC, bool LOC>
 __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, double *y,
                                            Fsal<M::D> &fs) {
   constexpr int D = M::D;
@@ -506,6 +540,28 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
   } else {
     if (E > 1.0) L.status |= ENS_SYS_DT_MIN;
     const double h_next = clampd(h_try * fac, a.dt_min, a.dt_max);
+    if constexpr (LOC) {
+      if (y[1] > 0.0 && y5[1] <= 0.0) {
+        // the maximum of y1 between the step points, on the interpolant
+        // (Dormand--Prince has f at both ends; Cash--Karp evaluates them)
+        double f0[D], f1[D];
+        if constexpr (SC == kDP) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            f0[c] = fs.k[c];
+            f1[c] = k7[c];
+          }
+        } else {
+          m.begin(L.t);
+          m.template rhs<SC, 1>(L.t, h_try, y, f0);
+          m.begin(L.t + h_try);
+          m.template rhs<SC, 1>(L.t + h_try, h_try, y5, f1);
+          L.nrhs += 2;
+        }
+        const double ym = located_max<D>(y, y5, f0, f1, h_try);
+        L.ymax = ym > L.ymax ? ym : L.ymax;
+      }
+    }
 #pragma unroll
     for (int c = 0; c < D; ++c) y[c] = y5[c];
     if constexpr (SC == kDP) {
@@ -662,9 +718,11 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
 // Each model states the occupancy floor the register allocator must respect
 // (kMinWaves waves per SIMD): 5 for the light models, 4 for the fast
 // Keller--Miksis variant, whose stage trigonometry needs the extra registers.
-template <class M, int SC>
+// LOC: Keller--Miksis maxima located on the step interpolant (an instantiation
+// of its own, so that the plain kernels carry none of its registers).
+template <class M, int SC, bool LOC>
 __global__ __launch_bounds__(kMaxBlock)
-__attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC), 8))) void k_rkck(RkckArgs a) {
+__attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k_rkck(RkckArgs a) {
   constexpr int D = M::D;
   __shared__ EnsDesc sdesc[ENS_MAX_ENSEMBLES];
   for (int e = threadIdx.x; e < a.n_ens; e += blockDim.x) sdesc[e] = a.desc[e];
@@ -733,7 +791,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC), 8))) void k_rkck
       if constexpr (M::kEvents)
         done = step_valve<SC>(a, m, L, y, fs);
       else
-        done = step_fixed<M, SC>(a, m, L, y, fs);
+        done = step_fixed<M, SC, LOC>(a, m, L, y, fs);
       if (done) {
         store_lane<M, SC>(a, L, y);
         active = false;
@@ -758,16 +816,17 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC), 8))) void k_rkck
   }
 }
 
-template <class M, int SC>
+template <class M, int SC, bool LOC>
 hipError_t launch_model(int block, int grid, const RkckArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_rkck<M, SC>), dim3(grid), dim3(block), 0, s, a);
+  hipLaunchKernelGGL((k_rkck<M, SC, LOC>), dim3(grid), dim3(block), 0, s, a);
   return hipGetLastError();
 }
 
-template <class M, int SC>
+template <class M, int SC, bool LOC>
 int max_blocks_model(int block) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rkck<M, SC>, block, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rkck<M, SC, LOC>, block, 0) !=
+      hipSuccess)
     return 0;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -777,25 +836,34 @@ int max_blocks_model(int block) {
 }
 
 template <int SC>
-hipError_t launch_scheme(int model, int block, int grid, const RkckArgs &a, hipStream_t s) {
+hipError_t launch_scheme(int model, bool loc, int block, int grid, const RkckArgs &a,
+                         hipStream_t s) {
   switch (model) {
-    case ENS_QUAD: return launch_model<MQuad, SC>(block, grid, a, s);
-    case ENS_LORENZ: return launch_model<MLorenz, SC>(block, grid, a, s);
-    case ENS_KM: return launch_model<MKM<true>, SC>(block, grid, a, s);
-    case ENS_KM_GENERAL: return launch_model<MKM<false>, SC>(block, grid, a, s);
-    case ENS_PRV: return launch_model<MPRV, SC>(block, grid, a, s);
+    case ENS_QUAD: return launch_model<MQuad, SC, false>(block, grid, a, s);
+    case ENS_LORENZ: return launch_model<MLorenz, SC, false>(block, grid, a, s);
+    case ENS_KM:
+      return loc ? launch_model<MKM<true>, SC, true>(block, grid, a, s)
+                 : launch_model<MKM<true>, SC, false>(block, grid, a, s);
+    case ENS_KM_GENERAL:
+      return loc ? launch_model<MKM<false>, SC, true>(block, grid, a, s)
+                 : launch_model<MKM<false>, SC, false>(block, grid, a, s);
+    case ENS_PRV: return launch_model<MPRV, SC, false>(block, grid, a, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int SC>
-int max_blocks_scheme(int model, int block) {
+int max_blocks_scheme(int model, bool loc, int block) {
   switch (model) {
-    case ENS_QUAD: return max_blocks_model<MQuad, SC>(block);
-    case ENS_LORENZ: return max_blocks_model<MLorenz, SC>(block);
-    case ENS_KM: return max_blocks_model<MKM<true>, SC>(block);
-    case ENS_KM_GENERAL: return max_blocks_model<MKM<false>, SC>(block);
-    case ENS_PRV: return max_blocks_model<MPRV, SC>(block);
+    case ENS_QUAD: return max_blocks_model<MQuad, SC, false>(block);
+    case ENS_LORENZ: return max_blocks_model<MLorenz, SC, false>(block);
+    case ENS_KM:
+      return loc ? max_blocks_model<MKM<true>, SC, true>(block)
+                 : max_blocks_model<MKM<true>, SC, false>(block);
+    case ENS_KM_GENERAL:
+      return loc ? max_blocks_model<MKM<false>, SC, true>(block)
+                 : max_blocks_model<MKM<false>, SC, false>(block);
+    case ENS_PRV: return max_blocks_model<MPRV, SC, false>(block);
   }
   return 0;
 }
@@ -806,15 +874,16 @@ hipError_t launch_rkck(int model, int solver, int block, int grid, const RkckArg
                        hipStream_t s) {
   if (block <= 0 || block > kMaxBlock || block % 64 != 0 || grid <= 0)
     return hipErrorInvalidConfiguration;
-  if (solver == ENS_RKDP45) return launch_scheme<kDP>(model, block, grid, a, s);
-  if (solver == ENS_RKCK45) return launch_scheme<kCK>(model, block, grid, a, s);
+  const bool loc = a.locate_max != 0;
+  if (solver == ENS_RKDP45) return launch_scheme<kDP>(model, loc, block, grid, a, s);
+  if (solver == ENS_RKCK45) return launch_scheme<kCK>(model, loc, block, grid, a, s);
   return hipErrorInvalidValue;
 }
 
-int rkck_max_blocks(int model, int solver, int block) {
+int rkck_max_blocks(int model, int solver, bool locate_max, int block) {
   if (block <= 0 || block > kMaxBlock || block % 64 != 0) return 0;
-  if (solver == ENS_RKDP45) return max_blocks_scheme<kDP>(model, block);
-  if (solver == ENS_RKCK45) return max_blocks_scheme<kCK>(model, block);
+  if (solver == ENS_RKDP45) return max_blocks_scheme<kDP>(model, locate_max, block);
+  if (solver == ENS_RKCK45) return max_blocks_scheme<kCK>(model, locate_max, block);
   return 0;
 }
 

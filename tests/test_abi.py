@@ -46,7 +46,7 @@ def test_default_opts_are_the_documented_readings():
 
 def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(ens.ens_desc) == 40
-    assert ctypes.sizeof(ens.ens_solve_opts) == 136
+    assert ctypes.sizeof(ens.ens_solve_opts) == 144
 
 
 def test_create_validates_before_touching_the_device():

@@ -335,3 +335,24 @@ def test_dp_resume_and_refill_invariance():
     assert np.array_equal(full.records[2:], rest.records)
     alt = gpu_ck(2, P, y0, O.Opts(n_phases=4, n_record=4), solver=dp, refill=7, block=64)
     assert np.array_equal(alt.y, full.y) and np.array_equal(alt.stats, full.stats)
+
+
+@pytest.mark.parametrize("scheme", [O.CASH_KARP, O.DORMAND_PRINCE])
+def test_located_maxima_match_oracle(scheme):
+    """locate_max: Keller--Miksis y1max also takes the maxima located on the
+    step interpolant; the steps themselves do not change."""
+    ens = _ens()
+    solver = ens.ENS_RKDP45 if scheme == O.DORMAND_PRINCE else ens.ENS_RKCK45
+    P, y0 = I.km_grid(24, 24)
+    o = O.Opts(n_phases=6, n_record=6, scheme=scheme, locate_max=1)
+    g = gpu_ck(2, P, y0, o, solver=solver, locate_max=1)
+    plain = gpu_ck(2, P, y0, o, solver=solver)
+    a, keep = oracle_pair(O.KM, P, I.KM_WATER, y0, o)
+    check_parity(g, a, keep, min_keep=0.8)
+    assert (g.stats[O.ST_NRHS] == a.stats[O.ST_NRHS])[keep].mean() >= 0.99
+    assert np.array_equal(g.y, plain.y) and np.array_equal(g.h, plain.h)
+    assert np.array_equal(g.stats[O.ST_ACCEPTED], plain.stats[O.ST_ACCEPTED])
+    assert np.all(g.records >= plain.records)      # the step points are still included
+    assert (g.records > plain.records).mean() > 0.5
+    with pytest.raises(ens.EnsError):
+        gpu_ck(3, *I.prv_linspace(4), O.Opts(n_phases=2), solver=solver, locate_max=1)
