@@ -77,8 +77,9 @@ def lib():
         L.orc_km_coeffs.argtypes = [_dp, _dp, _dp]
         L.orc_rk4.argtypes = [C.c_int, C.c_int64, _dp, _dp, _dp, C.c_double, C.c_int64,
                               _dp, _dp, C.c_int]
-        L.orc_rkck45.argtypes = [C.c_int, C.c_int64, _dp, _dp, _dp, _dp, _dp,
-                                 C.POINTER(_Opts), _dp, _dp, _dp, _dp, _i64p, _i32p, C.c_int]
+        L.orc_rkck45.argtypes = [C.c_int, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp,
+                                 C.POINTER(_Opts), _dp, _dp, _dp, _dp, _dp, _i64p, _i32p,
+                                 C.c_int]
         L.orc_rkck_step.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, C.c_double, _dp, _dp]
         L.orc_rkck_tableau.argtypes = [_dp, _dp, _dp, _dp]
         L.orc_rkdp_step.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, C.c_double, _dp, _dp]
@@ -165,11 +166,13 @@ class AdaptiveResult:
     records: np.ndarray  # [R][F][n], ring: phase k in slot k % R
     stats: np.ndarray    # [NSTAT][n] int64
     status: np.ndarray   # [n] int32
+    phi: np.ndarray      # [n] Keller--Miksis: second drive's phase at the phase start
 
 
-def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1):
+def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, phi0=None):
     """Adaptive solve of an ensemble through its phases with the scheme of
-    opts.scheme (Cash--Karp by default)."""
+    opts.scheme (Cash--Karp by default).  phi0 (Keller--Miksis): the second
+    drive's phase in cycles at the start of the current phase (0 if None)."""
     D = dim(model)
     y0 = _f64(y0)
     n = y0.shape[-1]
@@ -178,23 +181,25 @@ def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1):
     sh = _shared(model, shared)
     t0 = None if t0 is None else _f64(t0).reshape(n)
     h0 = None if h0 is None else _f64(h0).reshape(n)
+    phi0 = None if phi0 is None else _f64(phi0).reshape(n)
     R = int(opts.n_record)
     F = nrec_fields(model)
     y = np.empty((D, n))
     t = np.empty(n)
     h = np.empty(n)
+    phi = np.empty(n)
     rec = np.full((max(R, 0), F, n), np.nan)
     stats = np.zeros((NSTAT, n), dtype=np.int64)
     status = np.zeros(n, dtype=np.int32)
     o = opts._c()
     rc = lib().orc_rkck45(model, n, _ptr(params), _ptr(sh), _ptr(y0), _ptr(t0), _ptr(h0),
-                          C.byref(o), _ptr(y), _ptr(t), _ptr(h),
+                          _ptr(phi0), C.byref(o), _ptr(y), _ptr(t), _ptr(h), _ptr(phi),
                           _ptr(rec) if R > 0 else None,
                           stats.ctypes.data_as(_i64p), status.ctypes.data_as(_i32p),
                           int(nthreads))
     if rc:
         raise ValueError("orc_rkck45 rejected its arguments")
-    return AdaptiveResult(y, t, h, rec, stats, status)
+    return AdaptiveResult(y, t, h, rec, stats, status, phi)
 
 
 def rkck_step(model, t, y, p, shared, h):
@@ -217,11 +222,11 @@ def rkck_tableau():
     return a, b5, b4, c
 
 
-def rkdp45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1):
+def rkdp45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, phi0=None):
     """Adaptive Dormand--Prince solve (first same as last) of an ensemble."""
     o = Opts(**{f.name: getattr(opts, f.name) for f in fields(opts)})
     o.scheme = DORMAND_PRINCE
-    return rkck45(model, params, shared, y0, o, t0, h0, nthreads)
+    return rkck45(model, params, shared, y0, o, t0, h0, nthreads, phi0)
 
 
 def rkdp_step(model, t, y, p, shared, h):

@@ -16,8 +16,13 @@
  *     Sec. 4.1) and the Runge--Kutta--Cash--Karp 5(4) scheme with embedded
  *     error control, rtol = atol (Sec. 4.2.1, Sec. 4.3.1);
  *   - integration phases: the Keller--Miksis phase is one forcing period
- *     tau in [0, 1]; the valve phase runs from one local maximum of the
- *     displacement to the next (Sec. 4.3);
+ *     tau in [0, 1] of the first drive; the valve phase runs from one local
+ *     maximum of the displacement to the next (Sec. 4.3);
+ *   - the second drive of the Keller--Miksis forcing is a function of the
+ *     absolute time (Sec. 4.2, the far-field pressure), so it does not
+ *     restart with the phase: its angle is 2 pi (phi2 + C11 tau) + C12, with
+ *     phi2 the drive's phase in cycles at the start of the phase, advanced by
+ *     C11 t_phase (modulo 1) at every phase end;
  *   - accessories: the phase maximum of y1 taken over the natural step end
  *     points, updated after every successful step, without dense output
  *     (Sec. 4.2.1); for the valve the recorded maximum is y1 at the located
@@ -129,6 +134,8 @@ typedef struct {
   double p[2];     /* per-system parameters                                */
   const double *sh;/* shared parameters                                    */
   double C[13];    /* Keller--Miksis coefficients                          */
+  double phi2;     /* Keller--Miksis: phase of the second drive (cycles of
+                      omega2) when the current phase began                 */
   int seated;      /* valve resting on its seat (sticking guard)           */
 } sysctx;
 
@@ -153,7 +160,12 @@ static void rhs_km(const sysctx *s, double tau, const double *y, double *f) {
   const double y1 = y[0], y2 = y[1];
   const double rx = 1.0 / y1;
   const double a1 = 2.0 * pi * tau;
-  const double a2 = 2.0 * pi * C[11] * tau + C[12];
+  /* tau is local to the phase (it restarts at 0 every forcing period of the
+   * first drive); the second drive keeps running across phases, so its angle
+   * is 2 pi C11 tau_abs + C12 with tau_abs = (phase start) + tau, written as
+   * 2 pi (phi2 + C11 tau) + C12, phi2 being C11 x (phase start) reduced
+   * modulo 1 */
+  const double a2 = 2.0 * pi * (s->phi2 + C[11] * tau) + C[12];
   const double N = (C[0] + C[1] * y2) * pow(rx, C[10])
                    - C[2] * (1.0 + C[9] * y2)
                    - C[3] * rx
@@ -612,6 +624,11 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
       st[ORC_ST_PHASES] = phase;
       ymax = -INFINITY;
       t = 0.0;
+      if (s->model == ORC_KM) {
+        /* the second drive went through C11 x t_phase cycles in the phase */
+        const double v = s->phi2 + s->C[11] * o->t_phase;
+        s->phi2 = v - floor(v);
+      }
     } else {
       t = t + h_try;
       h = h_next;
@@ -622,9 +639,10 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
 }
 
 int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
-               const double *y0, const double *t0, const double *h0,
+               const double *y0, const double *t0, const double *h0, const double *phi0,
                const orc_opts *opt, double *y_out, double *t_out, double *h_out,
-               double *records, int64_t *stats, int32_t *status, int nthreads) {
+               double *phi_out, double *records, int64_t *stats, int32_t *status,
+               int nthreads) {
   const int D = orc_dim(model), P = orc_nparam(model);
   if (D < 0 || n < 0 || !opt) return -1;
   if (opt->n_record < 0 || opt->n_phases < 0) return -1;
@@ -640,6 +658,7 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
     for (int j = 0; j < P; ++j) p[j] = params[j * n + i];
     sysctx s;
     ctx_init(&s, model, p, shared);
+    s.phi2 = phi0 ? phi0[i] : 0.0;
     for (int c = 0; c < D; ++c) y[c] = y0[c * n + i];
     double t = t0 ? t0[i] : 0.0;
     double h = h0 ? h0[i] : opt->dt0;
@@ -650,6 +669,7 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
       for (int c = 0; c < D; ++c) y_out[c * n + i] = y[c];
     if (t_out) t_out[i] = t;
     if (h_out) h_out[i] = h;
+    if (phi_out) phi_out[i] = s.phi2;
     if (stats)
       for (int k = 0; k < ORC_NSTAT; ++k) stats[k * n + i] = st[k];
     if (status) status[i] = stat;

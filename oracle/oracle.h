@@ -96,19 +96,27 @@ enum { ORC_CASH_KARP = 0, ORC_DORMAND_PRINCE = 1 };
  * record y1max. */
 int orc_nrec_fields(int model);
 
-/* Adaptive Runge--Kutta--Cash--Karp 5(4) with error control, integration
- * phases, per-step accessories, and (PRV) event location with the impact law.
+/* Adaptive Runge--Kutta 5(4) (Cash--Karp or Dormand--Prince, opt->scheme)
+ * with error control, integration phases, per-step accessories, and (PRV)
+ * event location with the impact law.
  *
  *  params [P][n], shared [S], y0 [D][n];  t0, h0: [n] or NULL (0 and dt0).
- *  y_out [D][n], t_out [n], h_out [n]: state, phase-local (QUAD/LORENZ/KM)
- *    or absolute (PRV) time, and the step size the next call would try.
- *  records [n_record][F][n]: record r holds phase n_phases - n_record + r.
- *  stats [ORC_NSTAT][n], status [n].  Any output pointer may be NULL.
+ *  phi0 [n] or NULL (0): Keller--Miksis, the second drive's phase in cycles
+ *    of omega2 at the start of the current phase (its forcing angle is
+ *    2 pi (phi0 + C11 tau) + C12 within the phase); ignored otherwise.
+ *  y_out [D][n], t_out [n], h_out [n], phi_out [n]: state, phase-local
+ *    (QUAD/LORENZ/KM) or absolute (PRV) time, the step size the next call
+ *    would try, and the second drive's phase (KM; passing all four back
+ *    resumes the solve).
+ *  records [n_record][F][n]: a ring, phase k of this call in slot
+ *    k % n_record.  stats [ORC_NSTAT][n], status [n].  Any output pointer may
+ *    be NULL.
  */
 int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
-               const double *y0, const double *t0, const double *h0,
+               const double *y0, const double *t0, const double *h0, const double *phi0,
                const orc_opts *opt, double *y_out, double *t_out, double *h_out,
-               double *records, int64_t *stats, int32_t *status, int nthreads);
+               double *phi_out, double *records, int64_t *stats, int32_t *status,
+               int nthreads);
 
 /* One Cash--Karp step without error control, for order and stability tests:
  * y5 = fifth-order result, y4 = embedded fourth-order result. */

@@ -251,6 +251,44 @@ def test_km_resume_is_bit_identical():
     assert np.array_equal(full.records[:2], a.records)
 
 
+def _dual_drive():
+    sh = np.array(I.KM_WATER)
+    sh[8], sh[9], sh[10] = 0.4e5, 1.37 * 200e3, 0.7   # P_A2, f2 = 1.37 f1, theta
+    P = np.array([[0.5e5, 0.9e5], [200e3, 200e3]])
+    return sh, P, np.array([[1.0, 1.0], [0.0, 0.0]])
+
+
+@pytest.mark.parametrize("scheme", [O.CASH_KARP, O.DORMAND_PRINCE])
+def test_km_dual_drive_runs_on_across_phases(scheme):
+    # Sec. 4.2: p_inf(t) carries P_A2 sin(omega2 t + theta) on the absolute
+    # time, while a phase restarts tau at 0.  Three phases of length 1 must
+    # follow the same trajectory as one phase of length 3, in which tau is
+    # the absolute time and the angle is 2 pi C11 tau + C12 as printed; a
+    # second drive restarted with every phase misses it by O(1).
+    sh, P, y0 = _dual_drive()
+    o = dict(rtol=1e-12, atol=1e-12, n_record=1, scheme=scheme)
+    split = O.rkck45(O.KM, P, sh, y0, O.Opts(n_phases=3, **o))
+    whole = O.rkck45(O.KM, P, sh, y0, O.Opts(n_phases=1, t_phase=3.0, **o))
+    np.testing.assert_allclose(split.y, whole.y, rtol=1e-10, atol=1e-12)
+    # phi = frac(3 C11) with C11 = f2 / f1 = 1.37
+    np.testing.assert_allclose(split.phi, 0.11, rtol=0, atol=1e-12)
+    y, t, h = y0, None, None
+    for _ in range(3):   # the wrong reading: phi left at 0
+        r = O.rkck45(O.KM, P, sh, y, O.Opts(n_phases=1, **o), t0=t, h0=h)
+        y, t, h = r.y, r.t, r.h
+    assert np.max(np.abs(y - whole.y) / np.abs(whole.y)) > 0.1
+
+
+def test_km_dual_drive_resume_is_bit_identical():
+    sh, P, y0 = _dual_drive()
+    full = O.rkck45(O.KM, P, sh, y0, O.Opts(n_phases=4, n_record=4))
+    a = O.rkck45(O.KM, P, sh, y0, O.Opts(n_phases=2, n_record=2))
+    b = O.rkck45(O.KM, P, sh, a.y, O.Opts(n_phases=2, n_record=2), t0=a.t, h0=a.h, phi0=a.phi)
+    assert np.array_equal(full.y, b.y)
+    assert np.array_equal(full.phi, b.phi)
+    assert np.array_equal(full.records[2:], b.records)
+
+
 def test_km_ring_records_keep_last_phases():
     P, y0 = I.km_grid(1, 2)
     full = O.rkck45(O.KM, P, I.KM_WATER, y0, O.Opts(n_phases=6, n_record=6))
