@@ -78,7 +78,7 @@ def _threads():
     return max(1, min(os.cpu_count() or 1, 16))
 
 
-def km_cpu_baseline(G, n_phases, side, solver="ck"):
+def km_cpu_baseline(G, n_phases, side, solver="ck", shared=None):
     """The oracle on a side x side sub-grid (evenly spaced rows and columns)
     of the G x G Keller--Miksis grid, all n_phases cycles."""
     import numpy as np
@@ -91,7 +91,8 @@ def km_cpu_baseline(G, n_phases, side, solver="ck"):
     th = _threads()
     t0 = time.perf_counter()
     scheme = O.DORMAND_PRINCE if solver == "dp" else O.CASH_KARP
-    a = O.rkck45(O.KM, P[:, idx], I.KM_WATER, y0[:, idx],
+    sh = I.KM_WATER if shared is None else shared
+    a = O.rkck45(O.KM, P[:, idx], sh, y0[:, idx],
                  O.Opts(n_phases=n_phases, n_record=1, scheme=scheme), nthreads=th)
     el = time.perf_counter() - t0
     steps = float(a.stats[O.ST_ACCEPTED].sum() + a.stats[O.ST_REJECTED].sum())
@@ -147,14 +148,18 @@ def run_case(case, args):
                           "bytes_written": a.numel() * 8}), flush=True)
     elif case == "km":
         from paper_2011_01740_amd import ens
+        from paper_2011_01740_amd import inputs as I
         solver = ens.ENS_RKDP45 if args.solver == "dp" else ens.ENS_RKCK45
+        sh = list(I.KM_WATER)
+        sh[8], sh[9], sh[10] = args.km_pa2, args.km_f2, args.km_theta
         r = W.km_sweep(args.km_grid, args.km_grid, n_phases=args.km_phases,
                        n_record=args.km_record or None, pilot=args.km_pilot,
-                       pilot_grid=args.km_blocks, solver=solver)
+                       pilot_grid=args.km_blocks, solver=solver, shared=sh)
         att = r.stats[0] + r.stats[1]
         steps = int(att.sum())
         line = {"case": "km", "solver": args.solver, "grid": args.km_grid,
                 "phases": args.km_phases,
+                "second_drive": {"P_A2": args.km_pa2, "f2": args.km_f2, "theta": args.km_theta},
                 "pilot": args.km_pilot, "blocks_after_pilot": args.km_blocks,
                 "kernel_ms": r.kernel_ms, "attempted_steps": steps,
                 "steps_per_s": steps / r.kernel_ms * 1e3,
@@ -164,7 +169,7 @@ def run_case(case, args):
                 "launch": r.launch}
         if args.cpu_sample:
             line["cpu_baseline"] = km_cpu_baseline(args.km_grid, args.km_phases, args.cpu_sample,
-                                                   args.solver)
+                                                   args.solver, sh)
         print(json.dumps(line), flush=True)
     elif case == "surrogate":
         from paper_2011_01740_amd import surrogate as S
@@ -210,6 +215,10 @@ def main(argv=None):
     ap.add_argument("--km-blocks", type=int, default=0,
                     help="persistent blocks after the pilot (0: resident capacity)")
     ap.add_argument("--km-record", type=int, default=0, help="record ring (0: all cycles)")
+    ap.add_argument("--km-pa2", type=float, default=0.0,
+                    help="second drive amplitude P_A2 [Pa] (0: single frequency)")
+    ap.add_argument("--km-f2", type=float, default=0.0, help="second drive frequency f2 [Hz]")
+    ap.add_argument("--km-theta", type=float, default=0.0, help="second drive phase shift [rad]")
     ap.add_argument("--solver", choices=["ck", "dp"], default="ck",
                     help="km/prv cases: Cash--Karp or Dormand--Prince 5(4)")
     ap.add_argument("--cpu-sample", type=int, default=0,

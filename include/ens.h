@@ -81,8 +81,10 @@ enum ens_model {
                      (sigma, beta)                                           */
   ENS_KM = 2,     /* Keller--Miksis.           D=2  P=2 (P_A1 [Pa], f1 [Hz])
                      S=11: (rho_L, c_L, p_V, sigma, mu_L, gamma, P_inf, R_E,
-                     P_A2, f2, theta), SI units; this library requires P_A2 = 0
-                     (single-frequency drive)                               */
+                     P_A2, f2, theta), SI units.  With P_A2 != 0 (dual-
+                     frequency drive, Sec. 4.2) the second drive runs on
+                     the absolute time: its phase is carried across the
+                     integration phases (ENS_DRIVE_PHASE)                  */
   ENS_PRV = 3     /* relief valve + impacts.   D=3  P=1 (q)           S=4:
                      (kappa, delta, beta, r)                                 */
 };
@@ -189,10 +191,19 @@ int ens_set_budget(ens_t h, int32_t ensemble, int64_t n_phases, int64_t max_impa
 
 /* Initial state y0: [D][n]; t0 and h0: [n] or NULL (t = 0, h = dt0).  Time
  * is phase-local for fixed-length phases (Keller--Miksis: tau in [0, 1)) and
- * absolute for the valve.  Passing the ENS_STATE / ENS_TIME / ENS_H outputs
- * of a solve resumes it. */
+ * absolute for the valve.  Keller--Miksis adaptive handles: the second
+ * drive's phase (ENS_DRIVE_PHASE) is set to 0.  Passing the ENS_STATE /
+ * ENS_TIME / ENS_H outputs of a solve (and, for a dual-frequency Keller--
+ * Miksis drive, ENS_DRIVE_PHASE through ens_set_drive_phase) resumes it. */
 int ens_set_state(ens_t h, const double *y0, const double *t0, const double *h0,
                   int32_t where);
+
+/* Keller--Miksis, adaptive solvers (Sec. 4.2, dual-frequency forcing): sets
+ * the second drive's phase per system, [n] doubles in cycles (the
+ * ENS_DRIVE_PHASE layout), after ens_set_state.  ENS_HOST copies and waits;
+ * ENS_DEVICE is stream-ordered.  Errors: ENS_E_UNSUPPORTED (other models or
+ * RK4), ENS_E_ORDER (no state yet), ENS_E_INVAL, ENS_E_HIP. */
+int ens_set_drive_phase(ens_t h, const double *phi, int32_t where);
 
 /* Solve options.  Fields not used by the chosen solver are ignored. */
 typedef struct {
@@ -255,7 +266,13 @@ enum ens_field {
   ENS_RECORDS = 4, /* double [R][F][n]; F = 2 for the valve (y1max, y1min),
                       1 otherwise; slots never written hold NaN             */
   ENS_STATS = 5,   /* int64 [ENS_NSTAT][n]                                   */
-  ENS_STATUS = 6   /* int32 [n]                                              */
+  ENS_STATUS = 6,  /* int32 [n]                                              */
+  ENS_DRIVE_PHASE = 7 /* double [n], Keller--Miksis adaptive handles: phase of
+                      the second drive in cycles of omega2, in [0, 1), at
+                      the start of the system's current integration phase;
+                      its forcing angle is 2 pi (phase + C11 tau) + theta,
+                      C11 = f2 / f1 (Sec. 4.2).  Zeroed by ens_set_state,
+                      advanced by C11 t_phase (modulo 1) at every phase end */
 };
 
 /* Copies a result field into dst (bytes must equal the field size).

@@ -49,6 +49,7 @@ struct ens_ctx {
   // device buffers
   double *d_p = nullptr, *d_y = nullptr, *d_t = nullptr, *d_h = nullptr;
   double *d_acc = nullptr, *d_rec = nullptr;
+  double *d_phi = nullptr;  // Keller--Miksis adaptive: second drive's phase [n]
   int64_t *d_stats = nullptr;
   int32_t *d_status = nullptr;
   unsigned long long *d_queue = nullptr;
@@ -450,6 +451,7 @@ int ens_create(const ens_desc *d, ens_t *out) {
     if (e == hipSuccess) e = dalloc(&h->d_status, n);
     if (e == hipSuccess) e = dalloc(&h->d_queue, 1);
     if (e == hipSuccess) e = dalloc(&h->d_desc, ENS_MAX_ENSEMBLES);
+    if (e == hipSuccess && h->model == ENS_KM) e = dalloc(&h->d_phi, n);
   }
   if (e == hipSuccess) e = hipEventCreate(&h->ev0);
   if (e == hipSuccess) e = hipEventCreate(&h->ev1);
@@ -475,6 +477,7 @@ int ens_destroy(ens_t h) {
   (void)hipFree(h->d_h);
   (void)hipFree(h->d_acc);
   (void)hipFree(h->d_rec);
+  (void)hipFree(h->d_phi);
   (void)hipFree(h->d_stats);
   (void)hipFree(h->d_status);
   (void)hipFree(h->d_queue);
@@ -510,8 +513,6 @@ int ens_set_shared(ens_t h, int32_t ensemble, const double *shared, int32_t n_sh
   for (int i = 0; i < n_shared; ++i)
     if (!std::isfinite(shared[i]))
       return fail(h, ENS_E_INVAL, "ens_set_shared: non-finite value");
-  if (h->model == ENS_KM && shared[8] != 0.0)
-    return fail(h, ENS_E_UNSUPPORTED, "ens_set_shared: second drive (P_A2 != 0) is not built");
   for (int i = 0; i < n_shared; ++i) h->shared[ensemble][i] = shared[i];
   return ENS_OK;
 }
@@ -544,11 +545,29 @@ int ens_set_state(ens_t h, const double *y0, const double *t0, const double *h0,
       ENS_HIP(h, ens::launch_fill_f64(h->d_t, 0.0, (int64_t)n, h->stream));
     if (h0)
       ENS_HIP(h, hipMemcpyAsync(h->d_h, h0, n * sizeof(double), kind_in(where), h->stream));
+    if (h->d_phi) ENS_HIP(h, ens::launch_fill_f64(h->d_phi, 0.0, (int64_t)n, h->stream));
     if (where == ENS_HOST) ENS_HIP(h, hipStreamSynchronize(h->stream));
   }
   h->h_init = h0 != nullptr;
   h->have_y = true;
   h->have_acc = false;
+  return ENS_OK;
+}
+
+int ens_set_drive_phase(ens_t h, const double *phi, int32_t where) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_set_drive_phase: NULL handle");
+  if (!h->d_phi)
+    return fail(h, ENS_E_UNSUPPORTED, "ens_set_drive_phase: Keller--Miksis adaptive handles only");
+  if (!h->have_y) return fail(h, ENS_E_ORDER, "ens_set_drive_phase: set the state first");
+  if (!phi && h->n > 0) return fail(h, ENS_E_INVAL, "ens_set_drive_phase: phi is NULL");
+  if (where != ENS_HOST && where != ENS_DEVICE)
+    return fail(h, ENS_E_INVAL, "ens_set_drive_phase: bad where");
+  DeviceGuard g(h->device);
+  const size_t bytes = (size_t)h->n * sizeof(double);
+  if (bytes) {
+    ENS_HIP(h, hipMemcpyAsync(h->d_phi, phi, bytes, kind_in(where), h->stream));
+    if (where == ENS_HOST) ENS_HIP(h, hipStreamSynchronize(h->stream));
+  }
   return ENS_OK;
 }
 
@@ -608,13 +627,18 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     return fail(h, ENS_E_INVAL, "ens_solve: adaptive block must be 64, 128, 192 or 256");
   if (refill < 1 || refill > 64) return fail(h, ENS_E_INVAL, "ens_solve: refill must be in [1, 64]");
   // Keller--Miksis: the fast kernel (Newton fifth root, angle-addition
-  // forcing phase) needs 3 gamma = 21/5 in every sub-ensemble and
-  // dt_max <= 1/8; otherwise the general variant runs
+  // forcing phase) needs 3 gamma = 21/5 in every sub-ensemble and dt_max <=
+  // 1/8; otherwise the general variant runs, and a second drive (P_A2 != 0)
+  // in any sub-ensemble selects the general variant that carries it
   int kmodel = h->model;
   if (h->model == ENS_KM) {
+    bool dual = false;
     if (o->dt_max > 0.125) kmodel = ens::ENS_KM_GENERAL;
-    for (int e = 0; e < h->n_ens; ++e)
+    for (int e = 0; e < h->n_ens; ++e) {
       if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM_GENERAL;
+      if (h->shared[e][8] != 0.0) dual = true;
+    }
+    if (dual) kmodel = ens::ENS_KM_DUAL;
   }
   int grid = o->grid;
   const int cap = ens::rkck_max_blocks(kmodel, h->solver, o->locate_max != 0, block);
@@ -661,6 +685,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   std::memset(&a, 0, sizeof(a));  // padding too: the struct is compared bytewise
   a.p = h->d_p;
   a.y = h->d_y;
+  a.phi2 = h->d_phi;
   a.t = h->d_t;
   a.h = h->d_h;
   a.rec = R > 0 ? h->d_rec : nullptr;
@@ -764,6 +789,7 @@ size_t ens_field_bytes(ens_t h, int32_t field) {
       return h->have_adaptive ? (size_t)h->R * h->mi.F * n * sizeof(double) : 0;
     case ENS_STATS: return h->have_adaptive ? (size_t)ENS_NSTAT * n * sizeof(int64_t) : 0;
     case ENS_STATUS: return h->have_adaptive ? n * sizeof(int32_t) : 0;
+    case ENS_DRIVE_PHASE: return (h->have_y && h->d_phi) ? n * sizeof(double) : 0;
   }
   return 0;
 }
@@ -772,7 +798,10 @@ int ens_read(ens_t h, int32_t field, void *dst, size_t bytes, int32_t where) {
   if (!h) return fail(nullptr, ENS_E_INVAL, "ens_read: NULL handle");
   if (where != ENS_HOST && where != ENS_DEVICE)
     return fail(h, ENS_E_INVAL, "ens_read: bad where");
-  if (field < ENS_STATE || field > ENS_STATUS) return fail(h, ENS_E_INVAL, "ens_read: bad field");
+  if (field < ENS_STATE || field > ENS_DRIVE_PHASE)
+    return fail(h, ENS_E_INVAL, "ens_read: bad field");
+  if (field == ENS_DRIVE_PHASE && !h->d_phi)
+    return fail(h, ENS_E_UNSUPPORTED, "ens_read: ENS_DRIVE_PHASE is Keller--Miksis adaptive only");
   const size_t need = ens_field_bytes(h, field);
   const bool produced = need > 0 || h->n == 0 || (field == ENS_RECORDS && h->have_adaptive);
   if (!produced) return fail(h, ENS_E_ORDER, "ens_read: field not produced yet");
@@ -788,6 +817,7 @@ int ens_read(ens_t h, int32_t field, void *dst, size_t bytes, int32_t where) {
     case ENS_RECORDS: src = h->d_rec; break;
     case ENS_STATS: src = h->d_stats; break;
     case ENS_STATUS: src = h->d_status; break;
+    case ENS_DRIVE_PHASE: src = h->d_phi; break;
   }
   DeviceGuard g(h->device);
   const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -805,11 +835,14 @@ int ens_tune(ens_t h, const ens_solve_opts *opts, int64_t trial_len, ens_solve_o
   const size_t n = (size_t)h->n;
   const size_t ybytes = (size_t)h->mi.D * n * sizeof(double);
   // snapshot of the state, restored before every trial and at the end
-  double *sy = nullptr, *st = nullptr, *sh = nullptr;
+  double *sy = nullptr, *st = nullptr, *sh = nullptr, *sp = nullptr;
   const bool had_h = h->h_init;
   ENS_HIP(h, hipMalloc((void **)&sy, ybytes ? ybytes : 8));
   hipError_t e = hipMalloc((void **)&st, n ? n * sizeof(double) : 8);
   if (e == hipSuccess) e = hipMalloc((void **)&sh, n ? n * sizeof(double) : 8);
+  if (e == hipSuccess && h->d_phi) e = hipMalloc((void **)&sp, n ? n * sizeof(double) : 8);
+  if (e == hipSuccess && n && sp)
+    e = hipMemcpyAsync(sp, h->d_phi, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess && n) e = hipMemcpyAsync(sy, h->d_y, ybytes, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess && n) e = hipMemcpyAsync(st, h->d_t, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess && n && had_h)
@@ -821,6 +854,8 @@ int ens_tune(ens_t h, const ens_solve_opts *opts, int64_t trial_len, ens_solve_o
       r = hipMemcpyAsync(h->d_t, st, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
     if (r == hipSuccess && n && had_h)
       r = hipMemcpyAsync(h->d_h, sh, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+    if (r == hipSuccess && n && sp)
+      r = hipMemcpyAsync(h->d_phi, sp, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
     h->h_init = had_h;
     return r;
   };
@@ -877,6 +912,7 @@ int ens_tune(ens_t h, const ens_solve_opts *opts, int64_t trial_len, ens_solve_o
   (void)hipFree(sy);
   (void)hipFree(st);
   (void)hipFree(sh);
+  (void)hipFree(sp);
   // the trial solves produced results that belong to no real solve
   h->have_acc = false;
   h->have_adaptive = false;

@@ -30,6 +30,7 @@ struct alignas(16) EnsDesc {
 struct RkckArgs {
   const double *p;          // [P][n]
   double *y;                // [D][n] in/out
+  double *phi2;             // [n] in/out: Keller--Miksis second drive's phase, or null
   double *t;                // [n] in/out
   double *h;                // [n] in/out
   double *rec;              // [R][F][n] or null
@@ -49,10 +50,12 @@ struct RkckArgs {
   int32_t locate_max;       // Keller--Miksis: maxima located on the step interpolant
 };
 
-// Kernel variant of the Keller--Miksis model for a polytropic exponent with
-// 3 gamma != 21/5 or dt_max > 1/8 (general power through exp/log, sincospi
-// at every stage).
+// Kernel variants of the Keller--Miksis model: for a polytropic exponent
+// with 3 gamma != 21/5 or dt_max > 1/8 (general power through exp/log,
+// sincospi at every stage), and the same with the second drive (its phase
+// carried across phases).
 constexpr int ENS_KM_GENERAL = 100;
+constexpr int ENS_KM_DUAL = 101;
 
 // Kernel launchers (stream-ordered; return hipSuccess or the launch error).
 hipError_t launch_rk4(int model, int block, int spl, const double *p, double *y,

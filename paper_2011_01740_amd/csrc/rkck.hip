@@ -114,6 +114,7 @@ struct MQuad {  // dx/dt = x^2 - p (Sec. 3)
   static constexpr int kMinWaves = 5;
   static constexpr bool kPrio = false;  // issue priority by remaining work
   static constexpr bool kLocate = false;
+  static constexpr bool kDrive2 = false;
   double p;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) { p = P[i]; }
   __device__ void begin(double) {}
@@ -129,6 +130,7 @@ struct MLorenz {  // Sec. 4.1
   static constexpr int kMinWaves = 5;
   static constexpr bool kPrio = false;  // issue priority by remaining work
   static constexpr bool kLocate = false;
+  static constexpr bool kDrive2 = false;
   double rho, sigma, beta;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
     rho = P[i];
@@ -185,13 +187,21 @@ __device__ __forceinline__ void sincos_taylor(double x, double *s, double *c) {
 // from sin/cos of 2 pi t (once per attempted step) by angle addition with the
 // small offset 2 pi c_i h <= pi/4.  Otherwise exp(-K10 log y1) and sincospi
 // per stage.
-template <bool FAST>
+// DUAL (general arithmetic only; chosen when a sub-ensemble has P_A2 != 0):
+// the second drive -(K6 sin a2 (1 + K9 y2) + K8 y1 cos a2), a2 = 2 pi (phi +
+// K11 tau) + theta, with phi the drive's phase when the integration phase
+// began, carried across phases and stored per system (Sec. 4.2: the drive is
+// a function of the absolute time, while tau restarts with each phase).
+template <bool FAST, bool DUAL = false>
 struct MKM {
+  static_assert(!(FAST && DUAL), "the second drive runs on the general variant");
   static constexpr int D = 2;
   static constexpr bool kEvents = false;
-  static constexpr int kMinWaves = 4;
+  // the second drive's sin/cos needs registers beyond the 4-wave budget
+  static constexpr int kMinWaves = DUAL ? 3 : 4;
   static constexpr bool kPrio = true;  // issue priority by remaining work
   static constexpr bool kLocate = true;  // y2 = y1': maxima can be located
+  static constexpr bool kDrive2 = DUAL;
   double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49;
   double s0, c0;  // sin, cos (2 pi t) at the start of the attempted step
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
@@ -212,6 +222,24 @@ struct MKM {
     K9 = re * w / (2.0 * M_PI * cL);
     K10 = 3.0 * gam;
     K49 = K4 * K9;
+    if constexpr (DUAL) {
+      const double pa2 = sh[8], w2 = 2.0 * M_PI * sh[9];
+      dual = pa2 != 0.0;
+      K6 = pa2 * q2 / rhoL;
+      K8 = re * w2 * pa2 * q2 / (rhoL * cL);
+      K11 = w2 / w;                 // omega2 / omega1, correctly rounded
+      thpi = sh[10] * M_1_PI;       // theta / pi
+    }
+  }
+  // Second drive: phi = its phase in cycles when the current phase began;
+  // within the phase its angle is 2 pi (phi + K11 tau) + theta.
+  double K6, K8, K11, thpi, phi;
+  bool dual;
+  // A phase of length tp ended: the drive went through K11 tp cycles
+  // (multiply and add rounded separately, then reduced modulo 1).
+  __device__ void next_phase(double tp) {
+    const double v = __dadd_rn(phi, __dmul_rn(K11, tp));
+    phi = v - floor(v);
   }
   // FAST: sin/cos of the stage offsets 2 pi c_i h.  Cash--Karp, c = (0, 1/5,
   // 3/10, 3/5, 1, 7/8): stages 2, 3 and 6 from the series, stage 4 by
@@ -294,12 +322,21 @@ struct MKM {
       gas = exp(-K10 * log(y1));
       sincospi(2.0 * tau, &s, &c);
     }
+    double fs = fma(K5, s, K2), fc = K7 * c;  // forcing terms of N
+    if constexpr (DUAL) {
+      if (dual) {
+        double s2, c2;
+        sincospi(fma(2.0, fma(K11, tau, phi), thpi), &s2, &c2);
+        fs = fma(K6, s2, fs);
+        fc = fma(K8, c2, fc);
+      }
+    }
     const double u = fma(K9, y2, 1.0);
     double N = fma(K1, y2, K0) * gas;
-    N = fma(-fma(K5, s, K2), u, N);
+    N = fma(-fs, u, N);
     N = fma(-fma(K4, y2, K3), r1, N);
     N = fma(-(fma(-K9 / 3.0, y2, 1.0) * 1.5) * y2, y2, N);
-    N = fma(-K7 * c, y1, N);
+    N = fma(-fc, y1, N);
     f[0] = y2;
     f[1] = N * (y1 * qd);
   }
@@ -313,6 +350,7 @@ struct MPRV {
   static constexpr int kMinWaves = 5;
   static constexpr bool kPrio = false;  // issue priority by remaining work
   static constexpr bool kLocate = false;
+  static constexpr bool kDrive2 = false;
   double q, kappa, delta, beta, r;
   bool seated;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
@@ -575,6 +613,7 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
       store_record<M>(a, L, L.ymax, 0.0);
       L.phase++;
       if constexpr (M::kPrio) note_phase_end(L);
+      if constexpr (M::kDrive2) m.next_phase(a.t_phase);
       L.t = 0.0;
       L.ymax = -INFINITY;
       if (L.phase >= L.n_phases) return true;
@@ -754,6 +793,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
           int e = 0;
           while (e + 1 < a.n_ens && i >= sdesc[e].last) ++e;
           m.init(a.p, a.n, i, sdesc[e].shared);
+          if constexpr (M::kDrive2) m.phi = a.phi2[i];
 #pragma unroll
           for (int c = 0; c < D; ++c) y[c] = a.y[c * a.n + i];
           L.sys = i;
@@ -776,6 +816,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
           active = true;
           if (L.n_phases <= 0) {
             store_lane<M, SC>(a, L, y);
+            if constexpr (M::kDrive2) a.phi2[i] = m.phi;
             active = false;
           }
         }
@@ -794,6 +835,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
         done = step_fixed<M, SC, LOC>(a, m, L, y, fs);
       if (done) {
         store_lane<M, SC>(a, L, y);
+        if constexpr (M::kDrive2) a.phi2[L.sys] = m.phi;
         active = false;
       }
     }
@@ -847,6 +889,9 @@ hipError_t launch_scheme(int model, bool loc, int block, int grid, const RkckArg
     case ENS_KM_GENERAL:
       return loc ? launch_model<MKM<false>, SC, true>(block, grid, a, s)
                  : launch_model<MKM<false>, SC, false>(block, grid, a, s);
+    case ENS_KM_DUAL:
+      return loc ? launch_model<MKM<false, true>, SC, true>(block, grid, a, s)
+                 : launch_model<MKM<false, true>, SC, false>(block, grid, a, s);
     case ENS_PRV: return launch_model<MPRV, SC, false>(block, grid, a, s);
   }
   return hipErrorInvalidValue;
@@ -863,6 +908,9 @@ int max_blocks_scheme(int model, bool loc, int block) {
     case ENS_KM_GENERAL:
       return loc ? max_blocks_model<MKM<false>, SC, true>(block)
                  : max_blocks_model<MKM<false>, SC, false>(block);
+    case ENS_KM_DUAL:
+      return loc ? max_blocks_model<MKM<false, true>, SC, true>(block)
+                 : max_blocks_model<MKM<false, true>, SC, false>(block);
     case ENS_PRV: return max_blocks_model<MPRV, SC, false>(block);
   }
   return 0;

@@ -21,7 +21,7 @@ ENS_OK, ENS_E_INVAL, ENS_E_NOMEM, ENS_E_HIP, ENS_E_ORDER, ENS_E_UNSUPPORTED = 0,
 ENS_QUAD, ENS_LORENZ, ENS_KM, ENS_PRV = 0, 1, 2, 3
 ENS_RK4, ENS_RKCK45, ENS_RKDP45 = 0, 1, 2
 ENS_HOST, ENS_DEVICE = 0, 1
-ENS_STATE, ENS_TIME, ENS_H, ENS_ACC, ENS_RECORDS, ENS_STATS, ENS_STATUS = range(7)
+ENS_STATE, ENS_TIME, ENS_H, ENS_ACC, ENS_RECORDS, ENS_STATS, ENS_STATUS, ENS_DRIVE_PHASE = range(8)
 ENS_SYS_OK, ENS_SYS_DT_MIN, ENS_SYS_MAX_STEPS, ENS_SYS_NONFINITE = 0, 1, 2, 4
 ENS_SYS_SETTLED, ENS_SYS_EVENT_ITER, ENS_SYS_SEATED = 8, 16, 32
 ENS_ST_ACCEPTED, ENS_ST_REJECTED, ENS_ST_NRHS, ENS_ST_IMPACTS, ENS_ST_PHASES, ENS_ST_EVRETRY = range(6)
@@ -73,6 +73,7 @@ def load():
     L.ens_set_shared.argtypes = [vp, i32, dp, i32]
     L.ens_set_budget.argtypes = [vp, i32, i64, i64]
     L.ens_set_state.argtypes = [vp, vp, vp, vp, i32]
+    L.ens_set_drive_phase.argtypes = [vp, vp, i32]
     L.ens_default_opts.argtypes = [C.POINTER(ens_solve_opts)]
     L.ens_default_opts.restype = None
     L.ens_solve.argtypes = [vp, C.POINTER(ens_solve_opts)]
@@ -220,6 +221,13 @@ class Ensemble:
             raise ValueError("y0, t0 and h0 must all be host or all device arrays")
         _check(load().ens_set_state(self.h, py, pt, ph, wy), self.h)
         self._keep_state = (ky, kt, kh)
+
+    def set_drive_phase(self, phi):
+        """Keller--Miksis: the second drive's phase per system (cycles), e.g.
+        the ENS_DRIVE_PHASE output of an earlier solve, to resume it."""
+        p, w, k = self._in(phi, (self.n,))
+        _check(load().ens_set_drive_phase(self.h, p, w), self.h)
+        self._keep_phi = k
 
     def solve(self, opts: Optional[ens_solve_opts] = None, **kw):
         o = opts if opts is not None else default_opts(**kw)

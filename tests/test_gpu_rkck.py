@@ -24,7 +24,7 @@ class Res:
 
 
 def gpu_ck(model, P, y0, opts, t0=None, h0=None, shared=None, offsets=None, budgets=None,
-           solves=1, solver=None, **launch):
+           solves=1, solver=None, phi0=None, **launch):
     ens = _ens()
     n = y0.shape[-1]
     solver = ens.ENS_RKCK45 if solver is None else solver
@@ -37,6 +37,8 @@ def gpu_ck(model, P, y0, opts, t0=None, h0=None, shared=None, offsets=None, budg
             for k, (ph, imp) in enumerate(budgets):
                 e.set_budget(k, ph, imp)
         e.set_state(y0, t0, h0)
+        if phi0 is not None:
+            e.set_drive_phase(phi0)
         kw = dict(t_phase=opts.t_phase, dt0=opts.dt0, dt_min=opts.dt_min, dt_max=opts.dt_max,
                   rtol=opts.rtol, atol=opts.atol, event_tol=opts.event_tol, t_cap=opts.t_cap,
                   v_stick=opts.v_stick, n_phases=opts.n_phases, n_record=opts.n_record,
@@ -51,6 +53,7 @@ def gpu_ck(model, P, y0, opts, t0=None, h0=None, shared=None, offsets=None, budg
         r.records = e.read(ens.ENS_RECORDS)
         r.stats = e.read(ens.ENS_STATS)
         r.status = e.read(ens.ENS_STATUS)
+        r.phi = e.read(ens.ENS_DRIVE_PHASE) if model == 2 else None
         r.launch = e.last_launch()
         r.ms = e.last_kernel_ms()
         return r
