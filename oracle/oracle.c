@@ -69,6 +69,8 @@ int orc_dim(int model) {
     case ORC_LORENZ: return 3;
     case ORC_KM: return 2;
     case ORC_PRV: return 3;
+    case ORC_DIV: return 1;
+    case ORC_SIN: return 1;
   }
   return -1;
 }
@@ -79,6 +81,8 @@ int orc_nparam(int model) {
     case ORC_LORENZ: return 1;
     case ORC_KM: return 2;
     case ORC_PRV: return 1;
+    case ORC_DIV: return 1;
+    case ORC_SIN: return 1;
   }
   return -1;
 }
@@ -89,6 +93,8 @@ int orc_nshared(int model) {
     case ORC_LORENZ: return 2;
     case ORC_KM: return 11;
     case ORC_PRV: return 4;
+    case ORC_DIV: return 0;
+    case ORC_SIN: return 0;
   }
   return -1;
 }
@@ -142,6 +148,17 @@ typedef struct {
 /* dx/dt = x^2 - p (Sec. 3). */
 static void rhs_quad(const sysctx *s, const double *y, double *f) {
   f[0] = y[0] * y[0] - s->p[0];
+}
+
+/* dx/dt = 1/x - p x: the introductory example with a division (Sec. 3.3). */
+static void rhs_div(const sysctx *s, const double *y, double *f) {
+  f[0] = 1.0 / y[0] - s->p[0] * y[0];
+}
+
+/* dx/dt = p sin(x): the introductory example with a transcendental function
+ * (Sec. 3.3). */
+static void rhs_sin(const sysctx *s, const double *y, double *f) {
+  f[0] = s->p[0] * sin(y[0]);
 }
 
 /* Lorenz system (Sec. 4.1): sigma (y - x), p x - y - x z, x y - beta z. */
@@ -200,6 +217,8 @@ static void rhs(const sysctx *s, double t, const double *y, double *f) {
     case ORC_LORENZ: rhs_lorenz(s, y, f); break;
     case ORC_KM: rhs_km(s, t, y, f); break;
     case ORC_PRV: rhs_prv(s, y, f); break;
+    case ORC_DIV: rhs_div(s, y, f); break;
+    case ORC_SIN: rhs_sin(s, y, f); break;
   }
 }
 

@@ -24,6 +24,10 @@
  *                         P_A2, f2, theta)
  *   ORC_PRV     pressure-relief valve + impacts  (Sec. 4.3)
  *               D = 3, per-system p = (q), shared = (kappa, delta, beta, r)
+ *   ORC_DIV     dx/dt = 1/x - p x                (Sec. 3.3, the division
+ *               variant of the introductory example) D = 1, p = (p)
+ *   ORC_SIN     dx/dt = p sin(x)                 (Sec. 3.3, the
+ *               transcendental variant)          D = 1, p = (p)
  */
 #ifndef ENS_ORACLE_H
 #define ENS_ORACLE_H
@@ -33,7 +37,7 @@
 extern "C" {
 #endif
 
-enum { ORC_QUAD = 0, ORC_LORENZ = 1, ORC_KM = 2, ORC_PRV = 3 };
+enum { ORC_QUAD = 0, ORC_LORENZ = 1, ORC_KM = 2, ORC_PRV = 3, ORC_DIV = 4, ORC_SIN = 5 };
 
 /* Per-system status bits. */
 enum {
