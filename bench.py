@@ -179,6 +179,26 @@ def run_case(case, args):
         d = {k: v for k, v in rep.__dict__.items() if k != "extra"}
         d["case"] = "surrogate"
         print(json.dumps(d), flush=True)
+    elif case == "micro":
+        # the (B, N) table of the introductory example and its division and
+        # sine variants: one JSON line per configuration
+        from paper_2011_01740_amd import ens
+        models = {"quad": ens.ENS_QUAD, "div": ens.ENS_DIV, "sin": ens.ENS_SIN}
+        for name in args.micro_models.split(","):
+            for n in (int(v) for v in args.micro_n.split(",")):
+                for block in (int(v) for v in args.micro_blocks.split(",")):
+                    for spl in (int(v) for v in args.micro_spl.split(",")):
+                        W.scalar_rk4(models[name], min(n, 4096), 10, block=block, spl=spl)
+                        r = W.scalar_rk4(models[name], n, args.micro_steps, block=block, spl=spl)
+                        rate = n * args.micro_steps / r.kernel_ms * 1e3
+                        line = {"case": "micro", "model": name, "n": n, "block": block,
+                                "spl": spl, "n_steps": args.micro_steps,
+                                "kernel_ms": r.kernel_ms, "system_steps_per_s": rate}
+                        if name == "quad":
+                            # 11 FMA per step in the accumulated stage form
+                            line["tflops"] = 22.0 * rate / 1e12
+                            line["frac_of_spec_fp64"] = 22.0 * rate / 78.6e12
+                        print(json.dumps(line), flush=True)
     elif case == "prv":
         from paper_2011_01740_amd import ens
         ensm = tuple((m, max(1, K // args.prv_div), sd) for m, K, sd in W.PRV_ENSEMBLES)
@@ -205,7 +225,7 @@ def run_case(case, args):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--case", choices=["bench", "lorenz", "km", "prv", "copy", "surrogate"],
+    ap.add_argument("--case", choices=["bench", "lorenz", "km", "prv", "copy", "surrogate", "micro"],
                     default="bench",
                     help="bench: the benchmark line; others: one launch for counter runs")
     ap.add_argument("--km-grid", type=int, default=512)
@@ -215,6 +235,12 @@ def main(argv=None):
     ap.add_argument("--km-blocks", type=int, default=0,
                     help="persistent blocks after the pilot (0: resident capacity)")
     ap.add_argument("--km-record", type=int, default=0, help="record ring (0: all cycles)")
+    ap.add_argument("--micro-models", default="quad,div,sin")
+    ap.add_argument("--micro-n", default="65536",
+                    help="comma-separated ensemble sizes for --case micro")
+    ap.add_argument("--micro-blocks", default="256", help="comma-separated block sizes")
+    ap.add_argument("--micro-spl", default="1", help="comma-separated systems per lane")
+    ap.add_argument("--micro-steps", type=int, default=1000)
     ap.add_argument("--km-pa2", type=float, default=0.0,
                     help="second drive amplitude P_A2 [Pa] (0: single frequency)")
     ap.add_argument("--km-f2", type=float, default=0.0, help="second drive frequency f2 [Hz]")

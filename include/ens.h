@@ -85,8 +85,13 @@ enum ens_model {
                      frequency drive, Sec. 4.2) the second drive runs on
                      the absolute time: its phase is carried across the
                      integration phases (ENS_DRIVE_PHASE)                  */
-  ENS_PRV = 3     /* relief valve + impacts.   D=3  P=1 (q)           S=4:
+  ENS_PRV = 3,    /* relief valve + impacts.   D=3  P=1 (q)           S=4:
                      (kappa, delta, beta, r)                                 */
+  /* The division and transcendental variants of the introductory example
+   * (Sec. 3.3), built for RK4 only (measurement of what a division or a
+   * sine costs per step against the FMA-only dx/dt = x^2 - p): */
+  ENS_DIV = 4,    /* dx/dt = 1/x - p x.        D=1  P=1 (p)           S=0   */
+  ENS_SIN = 5     /* dx/dt = p sin(x).         D=1  P=1 (p)           S=0   */
 };
 
 /* Solvers: classic RK4 with a fixed step; Runge--Kutta--Cash--Karp 5(4)

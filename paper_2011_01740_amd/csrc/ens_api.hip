@@ -23,6 +23,8 @@ ModelInfo model_info(int model) {
     case ENS_LORENZ: return {3, 1, 2, 1};
     case ENS_KM: return {2, 2, 11, 1};
     case ENS_PRV: return {3, 1, 4, 2};
+    case ENS_DIV: return {1, 1, 0, 1};
+    case ENS_SIN: return {1, 1, 0, 1};
   }
   return {0, 0, 0, 0};
 }
@@ -390,7 +392,7 @@ int ens_create(const ens_desc *d, ens_t *out) {
   if (!out) return fail(nullptr, ENS_E_INVAL, "ens_create: out is NULL");
   *out = nullptr;
   if (!d) return fail(nullptr, ENS_E_INVAL, "ens_create: desc is NULL");
-  if (d->model < ENS_QUAD || d->model > ENS_PRV)
+  if (d->model < ENS_QUAD || d->model > ENS_SIN)
     return fail(nullptr, ENS_E_INVAL, "ens_create: unknown model");
   if (d->solver != ENS_RK4 && d->solver != ENS_RKCK45 && d->solver != ENS_RKDP45)
     return fail(nullptr, ENS_E_INVAL, "ens_create: unknown solver");
@@ -398,8 +400,10 @@ int ens_create(const ens_desc *d, ens_t *out) {
     return fail(nullptr, ENS_E_INVAL, "ens_create: n must be in [0, 2^31)");
   if (d->n_ensembles < 1 || d->n_ensembles > ENS_MAX_ENSEMBLES)
     return fail(nullptr, ENS_E_INVAL, "ens_create: n_ensembles out of range");
-  if (d->solver == ENS_RK4 && d->model != ENS_QUAD && d->model != ENS_LORENZ)
-    return fail(nullptr, ENS_E_UNSUPPORTED, "ens_create: RK4 is built for QUAD and LORENZ");
+  if (d->solver == ENS_RK4 && (d->model == ENS_KM || d->model == ENS_PRV))
+    return fail(nullptr, ENS_E_UNSUPPORTED, "ens_create: RK4 is built for QUAD, LORENZ, DIV, SIN");
+  if (d->solver != ENS_RK4 && (d->model == ENS_DIV || d->model == ENS_SIN))
+    return fail(nullptr, ENS_E_UNSUPPORTED, "ens_create: DIV and SIN are built for RK4");
   std::vector<int64_t> off;
   if (d->ens_offsets) {
     off.assign(d->ens_offsets, d->ens_offsets + d->n_ensembles + 1);
@@ -638,7 +642,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
       if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM_GENERAL;
       if (h->shared[e][8] != 0.0) dual = true;
     }
-    if (dual) kmodel = ens::ENS_KM_DUAL;
+    if (dual) kmodel = kmodel == ENS_KM ? ens::ENS_KM_DUAL_FAST : ens::ENS_KM_DUAL;
   }
   int grid = o->grid;
   const int cap = ens::rkck_max_blocks(kmodel, h->solver, o->locate_max != 0, block);

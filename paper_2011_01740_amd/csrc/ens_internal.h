@@ -50,12 +50,13 @@ struct RkckArgs {
   int32_t locate_max;       // Keller--Miksis: maxima located on the step interpolant
 };
 
-// Kernel variants of the Keller--Miksis model: for a polytropic exponent
-// with 3 gamma != 21/5 or dt_max > 1/8 (general power through exp/log,
-// sincospi at every stage), and the same with the second drive (its phase
-// carried across phases).
+// Kernel variants of the Keller--Miksis model (ENS_KM itself is the fast
+// single-drive kernel): for a polytropic exponent with 3 gamma != 21/5 or
+// dt_max > 1/8 (general power through exp/log, sincospi at every stage); and
+// both with the second drive (its phase carried across phases).
 constexpr int ENS_KM_GENERAL = 100;
-constexpr int ENS_KM_DUAL = 101;
+constexpr int ENS_KM_DUAL = 101;       // general arithmetic + second drive
+constexpr int ENS_KM_DUAL_FAST = 102;  // fast arithmetic + second drive
 
 // Kernel launchers (stream-ordered; return hipSuccess or the launch error).
 hipError_t launch_rk4(int model, int block, int spl, const double *p, double *y,

@@ -122,41 +122,82 @@ __global__ __launch_bounds__(1024) void k_rk4_lorenz(const double *__restrict__ 
   }
 }
 
-// dx/dt = x^2 - p (Sec. 3): the same accumulated stage form.
-template <int SPL>
-__global__ __launch_bounds__(1024) void k_rk4_quad(const double *__restrict__ P,
-                                                   double *__restrict__ Y,
-                                                   double *__restrict__ ACC, int64_t n,
-                                                   double dt, int64_t nsteps) {
+// The one-dimensional introductory example (Sec. 3) and its division and
+// transcendental variants (Sec. 3.3).  The quadratic right-hand side is one
+// FMA; the others are written as a user would: an IEEE division, and the
+// device library's sine.
+struct FQuad {
+  __device__ static double f(double x, double p) { return fma(x, x, -p); }
+};
+struct FDiv {
+  __device__ static double f(double x, double p) { return fma(-p, x, 1.0 / x); }
+};
+struct FSin {
+  __device__ static double f(double x, double p) { return p * sin(x); }
+};
+
+// Running maximum with one v_max_f64.  The same as a compare-and-select here
+// (a NaN state stays NaN, and both keep the last number).  Written out
+// because the compiler, unable to prove the loop-carried maximum canonical,
+// adds a second v_max (x, x) per iteration to quiet it: one VALU slot in 23
+// of the two-step loop of the one-dimensional models.
+__device__ __forceinline__ double vmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// One RK4 step of a one-dimensional model in the accumulated stage form; m
+// is the running maximum.
+template <class F>
+__device__ __forceinline__ void scalar_step(double &x, double &m, double p, double dt,
+                                            double h2, double h3, double h6) {
+  const double x0 = x;
+  double f, a, xs;
+  f = F::f(x0, p);
+  a = fma(h6, f, x0);
+  xs = fma(h2, f, x0);
+  f = F::f(xs, p);
+  a = fma(h3, f, a);
+  xs = fma(h2, f, x0);
+  f = F::f(xs, p);
+  a = fma(h3, f, a);
+  xs = fma(dt, f, x0);
+  f = F::f(xs, p);
+  x = fma(h6, f, a);
+  m = vmax(m, x);
+}
+
+// One-dimensional models, SPL systems per lane.
+template <class F, int SPL>
+__global__ __launch_bounds__(1024) void k_rk4_scalar(const double *__restrict__ P,
+                                                     double *__restrict__ Y,
+                                                     double *__restrict__ ACC, int64_t n,
+                                                     double dt, int64_t nsteps) {
   const int64_t base = (int64_t)blockIdx.x * ((int64_t)blockDim.x * SPL) + threadIdx.x;
   double x[SPL], p[SPL], m[SPL];
 #pragma unroll
   for (int k = 0; k < SPL; ++k) {
     const int64_t i = base + (int64_t)k * blockDim.x;
     const bool ok = i < n;
-    p[k] = ok ? P[i] : 0.0;
-    x[k] = ok ? Y[i] : 0.0;
+    // idle lanes (past n) sit at x = p = 1, where every variant is finite
+    p[k] = ok ? P[i] : 1.0;
+    x[k] = ok ? Y[i] : 1.0;
     m[k] = x[k];
   }
   const double h2 = 0.5 * dt, h3 = dt / 3.0, h6 = dt / 6.0;
-  for (int64_t s = 0; s < nsteps; ++s) {
+  // 11 FMAs and one v_max per step; two steps per iteration, so that the
+  // loop-carried state needs no register copy
+  for (int64_t s = nsteps >> 1; s != 0; --s) {
 #pragma unroll
     for (int k = 0; k < SPL; ++k) {
-      const double x0 = x[k], pk = p[k];
-      double f, a, xs;
-      f = fma(x0, x0, -pk);
-      a = fma(h6, f, x0);
-      xs = fma(h2, f, x0);
-      f = fma(xs, xs, -pk);
-      a = fma(h3, f, a);
-      xs = fma(h2, f, x0);
-      f = fma(xs, xs, -pk);
-      a = fma(h3, f, a);
-      xs = fma(dt, f, x0);
-      f = fma(xs, xs, -pk);
-      x[k] = fma(h6, f, a);
-      m[k] = x[k] > m[k] ? x[k] : m[k];
+      scalar_step<F>(x[k], m[k], p[k], dt, h2, h3, h6);
+      scalar_step<F>(x[k], m[k], p[k], dt, h2, h3, h6);
     }
+  }
+  if (nsteps & 1) {
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) scalar_step<F>(x[k], m[k], p[k], dt, h2, h3, h6);
   }
 #pragma unroll
   for (int k = 0; k < SPL; ++k) {
@@ -188,12 +229,22 @@ hipError_t rk4_spl(int model, int block, const double *p, double *y, double *acc
   const int64_t blocks = (n + per_block - 1) / per_block;
   if (blocks == 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  if (model == ENS_LORENZ) {
-    hipLaunchKernelGGL(k_rk4_lorenz<SPL>, dim3((unsigned)blocks), dim3(block), 0, s, p, y,
-                       acc, n, dt, nsteps, shared[0], shared[1]);
-  } else {
-    hipLaunchKernelGGL(k_rk4_quad<SPL>, dim3((unsigned)blocks), dim3(block), 0, s, p, y,
-                       acc, n, dt, nsteps);
+  const dim3 g((unsigned)blocks), b(block);
+  switch (model) {
+    case ENS_LORENZ:
+      hipLaunchKernelGGL(k_rk4_lorenz<SPL>, g, b, 0, s, p, y, acc, n, dt, nsteps, shared[0],
+                         shared[1]);
+      break;
+    case ENS_QUAD:
+      hipLaunchKernelGGL((k_rk4_scalar<FQuad, SPL>), g, b, 0, s, p, y, acc, n, dt, nsteps);
+      break;
+    case ENS_DIV:
+      hipLaunchKernelGGL((k_rk4_scalar<FDiv, SPL>), g, b, 0, s, p, y, acc, n, dt, nsteps);
+      break;
+    case ENS_SIN:
+      hipLaunchKernelGGL((k_rk4_scalar<FSin, SPL>), g, b, 0, s, p, y, acc, n, dt, nsteps);
+      break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

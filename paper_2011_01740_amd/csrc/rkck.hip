@@ -187,14 +187,14 @@ __device__ __forceinline__ void sincos_taylor(double x, double *s, double *c) {
 // from sin/cos of 2 pi t (once per attempted step) by angle addition with the
 // small offset 2 pi c_i h <= pi/4.  Otherwise exp(-K10 log y1) and sincospi
 // per stage.
-// DUAL (general arithmetic only; chosen when a sub-ensemble has P_A2 != 0):
-// the second drive -(K6 sin a2 (1 + K9 y2) + K8 y1 cos a2), a2 = 2 pi (phi +
-// K11 tau) + theta, with phi the drive's phase when the integration phase
-// began, carried across phases and stored per system (Sec. 4.2: the drive is
-// a function of the absolute time, while tau restarts with each phase).
+// DUAL (chosen when a sub-ensemble has P_A2 != 0): the second drive
+// -(K6 sin a2 (1 + K9 y2) + K8 y1 cos a2), a2 = 2 pi (phi + K11 tau) + theta,
+// with phi the drive's phase when the integration phase began, carried
+// across phases and stored per system (Sec. 4.2: the drive is a function of
+// the absolute time, while tau restarts with each phase).  Its stage angles
+// 2 pi K11 c_i h need not be small, so each stage takes sincospi.
 template <bool FAST, bool DUAL = false>
 struct MKM {
-  static_assert(!(FAST && DUAL), "the second drive runs on the general variant");
   static constexpr int D = 2;
   static constexpr bool kEvents = false;
   // the second drive's sin/cos needs registers beyond the 4-wave budget
@@ -892,6 +892,9 @@ hipError_t launch_scheme(int model, bool loc, int block, int grid, const RkckArg
     case ENS_KM_DUAL:
       return loc ? launch_model<MKM<false, true>, SC, true>(block, grid, a, s)
                  : launch_model<MKM<false, true>, SC, false>(block, grid, a, s);
+    case ENS_KM_DUAL_FAST:
+      return loc ? launch_model<MKM<true, true>, SC, true>(block, grid, a, s)
+                 : launch_model<MKM<true, true>, SC, false>(block, grid, a, s);
     case ENS_PRV: return launch_model<MPRV, SC, false>(block, grid, a, s);
   }
   return hipErrorInvalidValue;
@@ -911,6 +914,9 @@ int max_blocks_scheme(int model, bool loc, int block) {
     case ENS_KM_DUAL:
       return loc ? max_blocks_model<MKM<false, true>, SC, true>(block)
                  : max_blocks_model<MKM<false, true>, SC, false>(block);
+    case ENS_KM_DUAL_FAST:
+      return loc ? max_blocks_model<MKM<true, true>, SC, true>(block)
+                 : max_blocks_model<MKM<true, true>, SC, false>(block);
     case ENS_PRV: return max_blocks_model<MPRV, SC, false>(block);
   }
   return 0;

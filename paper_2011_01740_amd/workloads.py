@@ -59,6 +59,24 @@ def lorenz(n: int, n_steps: int, seed: Optional[int] = 1, dt: float = 0.01, **la
                       wall_s=wall, launch=e.last_launch())
 
 
+def scalar_rk4(model: int, n: int, n_steps: int = 1000, dt: float = 0.01, **launch) -> Result:
+    """The introductory example (ENS_QUAD) or its division (ENS_DIV) and
+    transcendental (ENS_SIN) variants with fixed-step RK4: p on an equidistant
+    grid in [0.1, 1], x0 = -0.5 (Sec. 3, Sec. 3.3)."""
+    import torch
+    P, y0 = I.quad_linspace(n)
+    with ens.Ensemble(model, ens.ENS_RK4, n) as e:
+        e.set_params(_dev(P))
+        e.set_state(_dev(y0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e.solve(dt=dt, n_steps=n_steps, **launch)
+        ms = e.last_kernel_ms()
+        wall = time.perf_counter() - t0
+        return Result(y=e.read(ens.ENS_STATE), acc=e.read(ens.ENS_ACC), kernel_ms=ms,
+                      wall_s=wall, launch=e.last_launch())
+
+
 def _adaptive(model, P, y0, opts, offsets=None, shared=None, budgets=None, read_records=True,
               rest_opts=None, solver=None):
     """One solve with opts; or, with rest_opts, a pilot solve with opts, the

@@ -23,15 +23,18 @@ def _solver(ens, scheme):
     return ens.ENS_RKDP45 if scheme == O.DORMAND_PRINCE else ens.ENS_RKCK45
 
 
-@pytest.mark.parametrize("scheme,locate", [(O.CASH_KARP, 0), (O.DORMAND_PRINCE, 0),
-                                           (O.CASH_KARP, 1), (O.DORMAND_PRINCE, 1)])
-def test_dual_km_grid_matches_oracle(scheme, locate):
+# dt_max 0.1 runs the fast arithmetic (fifth root, angle addition for the
+# first drive), 0.2 the general one (exp/log, sincospi for both drives)
+@pytest.mark.parametrize("scheme,locate,dt_max", [
+    (O.CASH_KARP, 0, 0.1), (O.DORMAND_PRINCE, 0, 0.1), (O.CASH_KARP, 1, 0.1),
+    (O.DORMAND_PRINCE, 1, 0.1), (O.CASH_KARP, 0, 0.2), (O.DORMAND_PRINCE, 1, 0.2)])
+def test_dual_km_grid_matches_oracle(scheme, locate, dt_max):
     ens = _ens()
     sh = dual_shared()
     # f1 over [20 kHz, 1 MHz]: C11 = f2 / f1 from 7.5 down to 0.15, mostly
     # not an integer, so the second drive's phase moves from phase to phase
     P, y0 = I.km_grid(20, 20)
-    o = O.Opts(n_phases=6, n_record=6, scheme=scheme, locate_max=locate)
+    o = O.Opts(n_phases=6, n_record=6, scheme=scheme, locate_max=locate, dt_max=dt_max)
     g = gpu_ck(2, P, y0, o, shared=sh, solver=_solver(ens, scheme), locate_max=locate)
     a, keep = oracle_pair(O.KM, P, np.array(sh), y0, o)
     check_parity(g, a, keep, min_keep=0.7)
