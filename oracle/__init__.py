@@ -15,7 +15,7 @@ import numpy as np
 
 from . import build as _build
 
-QUAD, LORENZ, KM, PRV, DIV, SIN = 0, 1, 2, 3, 4, 5
+QUAD, LORENZ, KM, PRV, DIV, SIN, KM6 = 0, 1, 2, 3, 4, 5, 6
 SYS_OK, SYS_DT_MIN, SYS_MAX_STEPS, SYS_NONFINITE = 0, 1, 2, 4
 SYS_SETTLED, SYS_EVENT_ITER, SYS_SEATED = 8, 16, 32
 ST_ACCEPTED, ST_REJECTED, ST_NRHS, ST_IMPACTS, ST_PHASES, ST_EVRETRY = range(6)

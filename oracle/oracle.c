@@ -68,6 +68,7 @@ int orc_dim(int model) {
     case ORC_QUAD: return 1;
     case ORC_LORENZ: return 3;
     case ORC_KM: return 2;
+    case ORC_KM6: return 2;
     case ORC_PRV: return 3;
     case ORC_DIV: return 1;
     case ORC_SIN: return 1;
@@ -80,6 +81,7 @@ int orc_nparam(int model) {
     case ORC_QUAD: return 1;
     case ORC_LORENZ: return 1;
     case ORC_KM: return 2;
+    case ORC_KM6: return 6;
     case ORC_PRV: return 1;
     case ORC_DIV: return 1;
     case ORC_SIN: return 1;
@@ -92,6 +94,7 @@ int orc_nshared(int model) {
     case ORC_QUAD: return 0;
     case ORC_LORENZ: return 2;
     case ORC_KM: return 11;
+    case ORC_KM6: return 7;
     case ORC_PRV: return 4;
     case ORC_DIV: return 0;
     case ORC_SIN: return 0;
@@ -137,7 +140,7 @@ void orc_km_coeffs(const double *p, const double *sh, double *C) {
 typedef struct {
   int model;
   int D;
-  double p[2];     /* per-system parameters                                */
+  double p[6];     /* per-system parameters                                */
   const double *sh;/* shared parameters                                    */
   double C[13];    /* Keller--Miksis coefficients                          */
   double phi2;     /* Keller--Miksis: phase of the second drive (cycles of
@@ -215,7 +218,8 @@ static void rhs(const sysctx *s, double t, const double *y, double *f) {
   switch (s->model) {
     case ORC_QUAD: rhs_quad(s, y, f); break;
     case ORC_LORENZ: rhs_lorenz(s, y, f); break;
-    case ORC_KM: rhs_km(s, t, y, f); break;
+    case ORC_KM:
+    case ORC_KM6: rhs_km(s, t, y, f); break;
     case ORC_PRV: rhs_prv(s, y, f); break;
     case ORC_DIV: rhs_div(s, y, f); break;
     case ORC_SIN: rhs_sin(s, y, f); break;
@@ -230,6 +234,13 @@ static int ctx_init(sysctx *s, int model, const double *p, const double *sh) {
   for (int j = 0; j < orc_nparam(model); ++j) s->p[j] = p[j];
   s->sh = sh;
   if (model == ORC_KM) orc_km_coeffs(p, sh, s->C);
+  if (model == ORC_KM6) {
+    /* the same equation with (P_A2, f2, theta, R_E) taken per system */
+    const double p2[2] = {p[0], p[1]};
+    const double sh11[11] = {sh[0], sh[1], sh[2], sh[3], sh[4], sh[5], sh[6],
+                             p[5], p[2], p[3], p[4]};
+    orc_km_coeffs(p2, sh11, s->C);
+  }
   return 0;
 }
 
@@ -268,7 +279,7 @@ int orc_rk4(int model, int64_t n, const double *params, const double *shared,
   if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
   for (int64_t i = 0; i < n; ++i) {
-    double p[2] = {0.0, 0.0}, y[MAXD];
+    double p[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, y[MAXD];
     for (int j = 0; j < P; ++j) p[j] = params[j * n + i];
     sysctx s;
     ctx_init(&s, model, p, shared);
@@ -613,7 +624,8 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
     }
 
     /* fixed-length phases (QUAD, LORENZ, KM) */
-    if (o->locate_max && s->model == ORC_KM && y[1] > 0.0 && y5[1] <= 0.0) {
+    if (o->locate_max && (s->model == ORC_KM || s->model == ORC_KM6) && y[1] > 0.0 &&
+        y5[1] <= 0.0) {
       /* the maximum of y1 between the step points: Dormand--Prince has f at
        * both ends (k1, k7); Cash--Karp evaluates them */
       double f0[MAXD], f1[MAXD];
@@ -643,7 +655,7 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
       st[ORC_ST_PHASES] = phase;
       ymax = -INFINITY;
       t = 0.0;
-      if (s->model == ORC_KM) {
+      if (s->model == ORC_KM || s->model == ORC_KM6) {
         /* the second drive went through C11 x t_phase cycles in the phase */
         const double v = s->phi2 + s->C[11] * o->t_phase;
         s->phi2 = v - floor(v);
@@ -669,11 +681,11 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
       !(opt->dt_max >= opt->dt_min))
     return -1;
   if (model != ORC_PRV && !(opt->t_phase > 0.0)) return -1;
-  if (opt->locate_max && model != ORC_KM) return -1;
+  if (opt->locate_max && model != ORC_KM && model != ORC_KM6) return -1;
   if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
   for (int64_t i = 0; i < n; ++i) {
-    double p[2] = {0.0, 0.0}, y[MAXD];
+    double p[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, y[MAXD];
     for (int j = 0; j < P; ++j) p[j] = params[j * n + i];
     sysctx s;
     ctx_init(&s, model, p, shared);

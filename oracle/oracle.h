@@ -28,6 +28,9 @@
  *               variant of the introductory example) D = 1, p = (p)
  *   ORC_SIN     dx/dt = p sin(x)                 (Sec. 3.3, the
  *               transcendental variant)          D = 1, p = (p)
+ *   ORC_KM6     Keller--Miksis with the six control parameters of Sec. 4.2
+ *               per system: p = (P_A1, f1, P_A2, f2, theta, R_E),
+ *               shared = (rho_L, c_L, p_V, sigma, mu_L, gamma, P_inf)
  */
 #ifndef ENS_ORACLE_H
 #define ENS_ORACLE_H
@@ -37,7 +40,8 @@
 extern "C" {
 #endif
 
-enum { ORC_QUAD = 0, ORC_LORENZ = 1, ORC_KM = 2, ORC_PRV = 3, ORC_DIV = 4, ORC_SIN = 5 };
+enum { ORC_QUAD = 0, ORC_LORENZ = 1, ORC_KM = 2, ORC_PRV = 3, ORC_DIV = 4, ORC_SIN = 5,
+       ORC_KM6 = 6 };
 
 /* Per-system status bits. */
 enum {

@@ -106,6 +106,37 @@ def test_km_dimensionless_rhs_equals_dimensional_model(dual):
         assert got[1] == pytest.approx(want[1], rel=1e-12, abs=1e-14)
 
 
+def test_km6_rhs_equals_dimensional_model_per_system():
+    """The six control parameters of Sec. 4.2 taken per system (ORC_KM6):
+    P_A1, f1, P_A2, f2, theta and R_E all vary from system to system."""
+    rng = np.random.default_rng(17)
+    fluid = np.array(I.KM_WATER[:7])
+    for _ in range(50):
+        tau = rng.uniform(0, 1)
+        y1, y2 = rng.uniform(0.1, 4.0), rng.uniform(-3, 3)
+        p6 = [rng.uniform(2e4, 1.2e5), np.exp(rng.uniform(np.log(2e4), np.log(1e6))),
+              rng.uniform(0, 1e5), np.exp(rng.uniform(np.log(2e4), np.log(1e6))),
+              rng.uniform(-np.pi, np.pi), rng.uniform(2e-6, 20e-6)]
+        got = O.rhs(O.KM6, tau, [y1, y2], p6, fluid)
+        sh = np.concatenate([fluid, [p6[5], p6[2], p6[3], p6[4]]])
+        want = km_dimensionless_from_dimensional(tau, y1, y2, p6[0], p6[1], sh)
+        assert got[0] == y2
+        assert got[1] == pytest.approx(want[1], rel=1e-12, abs=1e-14)
+
+
+def test_km6_solve_equals_km_with_the_same_values():
+    sh = np.array(I.KM_WATER)
+    sh[8], sh[9], sh[10] = 0.4e5, 1.37 * 200e3, 0.7
+    P, y0 = I.km_grid(3, 3)
+    n = P.shape[1]
+    P6 = np.vstack([P, np.tile(sh[[8, 9, 10, 7]].reshape(4, 1), (1, n))])
+    o = O.Opts(n_phases=3, n_record=3)
+    a = O.rkck45(O.KM, P, sh, y0, o)
+    b = O.rkck45(O.KM6, P6, sh[:7], y0, o)
+    assert np.array_equal(a.y, b.y) and np.array_equal(a.records, b.records)
+    assert np.array_equal(a.phi, b.phi)
+
+
 def test_km_rest_state_is_equilibrium():
     # C0 - C2 - C3 = 0: undriven, the bubble at its equilibrium radius rests
     for f in (20e3, 339e3, 1e6):
