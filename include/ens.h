@@ -91,7 +91,14 @@ enum ens_model {
    * (Sec. 3.3), built for RK4 only (measurement of what a division or a
    * sine costs per step against the FMA-only dx/dt = x^2 - p): */
   ENS_DIV = 4,    /* dx/dt = 1/x - p x.        D=1  P=1 (p)           S=0   */
-  ENS_SIN = 5     /* dx/dt = p sin(x).         D=1  P=1 (p)           S=0   */
+  ENS_SIN = 5,    /* dx/dt = p sin(x).         D=1  P=1 (p)           S=0   */
+  ENS_KM6 = 6     /* Keller--Miksis with the six control parameters of
+                     Sec. 4.2 per system, for sweeps over any of them.
+                                              D=2  P=6 (P_A1 [Pa], f1 [Hz],
+                     P_A2 [Pa], f2 [Hz], theta, R_E [m])  S=7: (rho_L, c_L,
+                     p_V, sigma, mu_L, gamma, P_inf).  Adaptive solvers
+                     only; the same equation, phases, records and second-
+                     drive phase as ENS_KM                                 */
 };
 
 /* Solvers: classic RK4 with a fixed step; Runge--Kutta--Cash--Karp 5(4)
@@ -272,8 +279,9 @@ enum ens_field {
                       1 otherwise; slots never written hold NaN             */
   ENS_STATS = 5,   /* int64 [ENS_NSTAT][n]                                   */
   ENS_STATUS = 6,  /* int32 [n]                                              */
-  ENS_DRIVE_PHASE = 7 /* double [n], Keller--Miksis adaptive handles: phase of
-                      the second drive in cycles of omega2, in [0, 1), at
+  ENS_DRIVE_PHASE = 7 /* double [n], Keller--Miksis (ENS_KM, ENS_KM6)
+                      adaptive handles: phase of the second drive in
+                      cycles of omega2, in [0, 1), at
                       the start of the system's current integration phase;
                       its forcing angle is 2 pi (phase + C11 tau) + theta,
                       C11 = f2 / f1 (Sec. 4.2).  Zeroed by ens_set_state,

@@ -22,6 +22,7 @@ ModelInfo model_info(int model) {
     case ENS_QUAD: return {1, 1, 0, 1};
     case ENS_LORENZ: return {3, 1, 2, 1};
     case ENS_KM: return {2, 2, 11, 1};
+    case ENS_KM6: return {2, 6, 7, 1};
     case ENS_PRV: return {3, 1, 4, 2};
     case ENS_DIV: return {1, 1, 0, 1};
     case ENS_SIN: return {1, 1, 0, 1};
@@ -113,10 +114,12 @@ void default_shared(int model, double *sh) {
       sh[0] = 10.0;
       sh[1] = 8.0 / 3.0;
       break;
-    case ENS_KM: {
+    case ENS_KM:
+    case ENS_KM6: {
+      // ENS_KM6 takes the first 7 (the fluid), the rest are per system
       const double w[11] = {997.0, 1497.0, 3166.0, 0.0728, 8.9e-4, 1.4,
                             1.0e5, 10.0e-6, 0.0,    0.0,    0.0};
-      for (int i = 0; i < 11; ++i) sh[i] = w[i];
+      for (int i = 0; i < (model == ENS_KM ? 11 : 7); ++i) sh[i] = w[i];
       break;
     }
     case ENS_PRV:
@@ -392,7 +395,7 @@ int ens_create(const ens_desc *d, ens_t *out) {
   if (!out) return fail(nullptr, ENS_E_INVAL, "ens_create: out is NULL");
   *out = nullptr;
   if (!d) return fail(nullptr, ENS_E_INVAL, "ens_create: desc is NULL");
-  if (d->model < ENS_QUAD || d->model > ENS_SIN)
+  if (d->model < ENS_QUAD || d->model > ENS_KM6)
     return fail(nullptr, ENS_E_INVAL, "ens_create: unknown model");
   if (d->solver != ENS_RK4 && d->solver != ENS_RKCK45 && d->solver != ENS_RKDP45)
     return fail(nullptr, ENS_E_INVAL, "ens_create: unknown solver");
@@ -400,7 +403,7 @@ int ens_create(const ens_desc *d, ens_t *out) {
     return fail(nullptr, ENS_E_INVAL, "ens_create: n must be in [0, 2^31)");
   if (d->n_ensembles < 1 || d->n_ensembles > ENS_MAX_ENSEMBLES)
     return fail(nullptr, ENS_E_INVAL, "ens_create: n_ensembles out of range");
-  if (d->solver == ENS_RK4 && (d->model == ENS_KM || d->model == ENS_PRV))
+  if (d->solver == ENS_RK4 && (d->model == ENS_KM || d->model == ENS_KM6 || d->model == ENS_PRV))
     return fail(nullptr, ENS_E_UNSUPPORTED, "ens_create: RK4 is built for QUAD, LORENZ, DIV, SIN");
   if (d->solver != ENS_RK4 && (d->model == ENS_DIV || d->model == ENS_SIN))
     return fail(nullptr, ENS_E_UNSUPPORTED, "ens_create: DIV and SIN are built for RK4");
@@ -455,7 +458,7 @@ int ens_create(const ens_desc *d, ens_t *out) {
     if (e == hipSuccess) e = dalloc(&h->d_status, n);
     if (e == hipSuccess) e = dalloc(&h->d_queue, 1);
     if (e == hipSuccess) e = dalloc(&h->d_desc, ENS_MAX_ENSEMBLES);
-    if (e == hipSuccess && h->model == ENS_KM) e = dalloc(&h->d_phi, n);
+    if (e == hipSuccess && (h->model == ENS_KM || h->model == ENS_KM6)) e = dalloc(&h->d_phi, n);
   }
   if (e == hipSuccess) e = hipEventCreate(&h->ev0);
   if (e == hipSuccess) e = hipEventCreate(&h->ev1);
@@ -617,7 +620,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     return fail(h, ENS_E_INVAL, "ens_solve: bad phase, record or step counts");
   if (o->max_steps > (int64_t)UINT32_MAX)
     return fail(h, ENS_E_INVAL, "ens_solve: max_steps above 2^32");
-  if (o->locate_max && h->model != ENS_KM)
+  if (o->locate_max && h->model != ENS_KM && h->model != ENS_KM6)
     return fail(h, ENS_E_UNSUPPORTED, "ens_solve: locate_max is built for Keller--Miksis");
   int block = o->block, refill = o->refill;
   TuneVal tv;
@@ -643,6 +646,11 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
       if (h->shared[e][8] != 0.0) dual = true;
     }
     if (dual) kmodel = kmodel == ENS_KM ? ens::ENS_KM_DUAL_FAST : ens::ENS_KM_DUAL;
+  }
+  if (h->model == ENS_KM6) {
+    if (o->dt_max > 0.125) kmodel = ens::ENS_KM6_GENERAL;
+    for (int e = 0; e < h->n_ens; ++e)
+      if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM6_GENERAL;
   }
   int grid = o->grid;
   const int cap = ens::rkck_max_blocks(kmodel, h->solver, o->locate_max != 0, block);

@@ -193,8 +193,11 @@ __device__ __forceinline__ void sincos_taylor(double x, double *s, double *c) {
 // across phases and stored per system (Sec. 4.2: the drive is a function of
 // the absolute time, while tau restarts with each phase).  Its stage angles
 // 2 pi K11 c_i h need not be small, so each stage takes sincospi.
-template <bool FAST, bool DUAL = false>
+// PSYS: (P_A2, f2, theta, R_E) are per-system parameters 2..5 instead of
+// shared ones (the six control parameters of Sec. 4.2 swept together).
+template <bool FAST, bool DUAL = false, bool PSYS = false>
 struct MKM {
+  static_assert(DUAL || !PSYS, "per-system second-drive parameters imply the second drive");
   static constexpr int D = 2;
   static constexpr bool kEvents = false;
   // the second drive's sin/cos needs registers beyond the 4-wave budget
@@ -207,7 +210,8 @@ struct MKM {
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
     const double pa = P[i], f = P[n + i];
     const double rhoL = sh[0], cL = sh[1], pV = sh[2], sig = sh[3], mu = sh[4];
-    const double gam = sh[5], pinf = sh[6], re = sh[7];
+    const double gam = sh[5], pinf = sh[6];
+    const double re = PSYS ? P[5 * n + i] : sh[7];
     const double w = 2.0 * M_PI * f;              // omega1
     const double q = 2.0 * M_PI / (re * w);       // 2 pi / (R_E omega1)
     const double q2 = q * q;
@@ -223,12 +227,14 @@ struct MKM {
     K10 = 3.0 * gam;
     K49 = K4 * K9;
     if constexpr (DUAL) {
-      const double pa2 = sh[8], w2 = 2.0 * M_PI * sh[9];
+      const double pa2 = PSYS ? P[2 * n + i] : sh[8];
+      const double w2 = 2.0 * M_PI * (PSYS ? P[3 * n + i] : sh[9]);
+      const double th = PSYS ? P[4 * n + i] : sh[10];
       dual = pa2 != 0.0;
       K6 = pa2 * q2 / rhoL;
       K8 = re * w2 * pa2 * q2 / (rhoL * cL);
       K11 = w2 / w;                 // omega2 / omega1, correctly rounded
-      thpi = sh[10] * M_1_PI;       // theta / pi
+      thpi = th * M_1_PI;           // theta / pi
     }
   }
   // Second drive: phi = its phase in cycles when the current phase began;
@@ -895,6 +901,12 @@ hipError_t launch_scheme(int model, bool loc, int block, int grid, const RkckArg
     case ENS_KM_DUAL_FAST:
       return loc ? launch_model<MKM<true, true>, SC, true>(block, grid, a, s)
                  : launch_model<MKM<true, true>, SC, false>(block, grid, a, s);
+    case ENS_KM6:
+      return loc ? launch_model<MKM<true, true, true>, SC, true>(block, grid, a, s)
+                 : launch_model<MKM<true, true, true>, SC, false>(block, grid, a, s);
+    case ENS_KM6_GENERAL:
+      return loc ? launch_model<MKM<false, true, true>, SC, true>(block, grid, a, s)
+                 : launch_model<MKM<false, true, true>, SC, false>(block, grid, a, s);
     case ENS_PRV: return launch_model<MPRV, SC, false>(block, grid, a, s);
   }
   return hipErrorInvalidValue;
@@ -917,6 +929,12 @@ int max_blocks_scheme(int model, bool loc, int block) {
     case ENS_KM_DUAL_FAST:
       return loc ? max_blocks_model<MKM<true, true>, SC, true>(block)
                  : max_blocks_model<MKM<true, true>, SC, false>(block);
+    case ENS_KM6:
+      return loc ? max_blocks_model<MKM<true, true, true>, SC, true>(block)
+                 : max_blocks_model<MKM<true, true, true>, SC, false>(block);
+    case ENS_KM6_GENERAL:
+      return loc ? max_blocks_model<MKM<false, true, true>, SC, true>(block)
+                 : max_blocks_model<MKM<false, true, true>, SC, false>(block);
     case ENS_PRV: return max_blocks_model<MPRV, SC, false>(block);
   }
   return 0;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libens.so")
 
 # enums (include/ens.h)
 ENS_OK, ENS_E_INVAL, ENS_E_NOMEM, ENS_E_HIP, ENS_E_ORDER, ENS_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-ENS_QUAD, ENS_LORENZ, ENS_KM, ENS_PRV, ENS_DIV, ENS_SIN = 0, 1, 2, 3, 4, 5
+ENS_QUAD, ENS_LORENZ, ENS_KM, ENS_PRV, ENS_DIV, ENS_SIN, ENS_KM6 = 0, 1, 2, 3, 4, 5, 6
 ENS_RK4, ENS_RKCK45, ENS_RKDP45 = 0, 1, 2
 ENS_HOST, ENS_DEVICE = 0, 1
 ENS_STATE, ENS_TIME, ENS_H, ENS_ACC, ENS_RECORDS, ENS_STATS, ENS_STATUS, ENS_DRIVE_PHASE = range(8)
@@ -30,7 +30,8 @@ ENS_MAX_ENSEMBLES = 16
 
 MODEL_DIMS = {ENS_QUAD: (1, 1, 0, 1), ENS_LORENZ: (3, 1, 2, 1),
               ENS_KM: (2, 2, 11, 1), ENS_PRV: (3, 1, 4, 2),
-              ENS_DIV: (1, 1, 0, 1), ENS_SIN: (1, 1, 0, 1)}   # D, P, S, F
+              ENS_DIV: (1, 1, 0, 1), ENS_SIN: (1, 1, 0, 1),
+              ENS_KM6: (2, 6, 7, 1)}   # D, P, S, F
 
 
 class ens_desc(C.Structure):

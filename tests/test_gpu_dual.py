@@ -106,3 +106,43 @@ def test_drive_phase_field_and_errors():
             e.set_drive_phase(np.zeros(4))
         with pytest.raises(ens.EnsError):
             e.read(ens.ENS_DRIVE_PHASE)
+
+
+def km6_grid(n_side, seed=3):
+    """All six control parameters per system: (P_A1, f1) on the usual grid,
+    (P_A2, f2, theta, R_E) drawn per system."""
+    P, y0 = I.km_grid(n_side, n_side)
+    n = P.shape[1]
+    rng = np.random.default_rng(seed)
+    extra = np.vstack([rng.uniform(0.0, 0.8e5, n),
+                       np.exp(rng.uniform(np.log(50e3), np.log(400e3), n)),
+                       rng.uniform(-np.pi, np.pi, n),
+                       rng.uniform(5e-6, 15e-6, n)])
+    return np.vstack([P, extra]), y0
+
+
+@pytest.mark.parametrize("scheme,dt_max", [(O.CASH_KARP, 0.1), (O.DORMAND_PRINCE, 0.1),
+                                           (O.CASH_KARP, 0.2)])
+def test_km6_per_system_sweep_matches_oracle(scheme, dt_max):
+    ens = _ens()
+    P6, y0 = km6_grid(16)
+    fluid = list(I.KM_WATER[:7])
+    o = O.Opts(n_phases=5, n_record=5, scheme=scheme, dt_max=dt_max)
+    g = gpu_ck(6, P6, y0, o, shared=fluid, solver=_solver(ens, scheme))
+    a, keep = oracle_pair(O.KM6, P6, np.array(fluid), y0, o)
+    check_parity(g, a, keep, min_keep=0.7)
+    assert np.array_equal(g.phi, a.phi)
+
+
+def test_km6_equals_km_with_the_same_values():
+    """Per-system second-drive parameters that happen to be equal give the
+    same bits as the shared ones."""
+    sh = dual_shared()
+    P, y0 = I.km_grid(10, 10)
+    n = P.shape[1]
+    P6 = np.vstack([P, np.tile(np.array([sh[8], sh[9], sh[10], sh[7]]).reshape(4, 1), (1, n))])
+    o = O.Opts(n_phases=4, n_record=4)
+    a = gpu_ck(2, P, y0, o, shared=sh)
+    b = gpu_ck(6, P6, y0, o, shared=sh[:7])
+    assert np.array_equal(a.y, b.y) and np.array_equal(a.records, b.records)
+    assert np.array_equal(a.stats, b.stats) and np.array_equal(a.phi, b.phi)

@@ -53,7 +53,7 @@ def gpu_ck(model, P, y0, opts, t0=None, h0=None, shared=None, offsets=None, budg
         r.records = e.read(ens.ENS_RECORDS)
         r.stats = e.read(ens.ENS_STATS)
         r.status = e.read(ens.ENS_STATUS)
-        r.phi = e.read(ens.ENS_DRIVE_PHASE) if model == 2 else None
+        r.phi = e.read(ens.ENS_DRIVE_PHASE) if model in (2, 6) else None
         r.launch = e.last_launch()
         r.ms = e.last_kernel_ms()
         return r
