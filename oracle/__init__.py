@@ -35,7 +35,7 @@ class _Opts(C.Structure):
                 ("n_phases", C.c_int64), ("n_record", C.c_int64),
                 ("max_impacts", C.c_int64), ("max_steps", C.c_int64),
                 ("max_event_iter", C.c_int32), ("scheme", C.c_int32),
-                ("locate_max", C.c_int32), ("pad_", C.c_int32)]
+                ("locate_max", C.c_int32), ("lyapunov", C.c_int32)]
 
 
 @dataclass
@@ -57,7 +57,7 @@ class Opts:
     max_event_iter: int = 20
     scheme: int = 0                 # CASH_KARP or DORMAND_PRINCE
     locate_max: int = 0             # KM: maxima located on the step interpolant
-    pad_: int = 0
+    lyapunov: int = 0               # variational equation + per-phase renormalisation
 
     def _c(self) -> _Opts:
         o = _Opts()
@@ -84,6 +84,7 @@ def lib():
         L.orc_rkck_tableau.argtypes = [_dp, _dp, _dp, _dp]
         L.orc_rkdp_step.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, C.c_double, _dp, _dp]
         L.orc_rkdp_tableau.argtypes = [_dp, _dp, _dp, _dp]
+        L.orc_jacobian.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, _dp]
         for f in ("orc_dim", "orc_nparam", "orc_nshared", "orc_nrec_fields"):
             getattr(L, f).argtypes = [C.c_int]
         _lib = L
@@ -133,6 +134,17 @@ def rhs(model, t, y, p, shared=None):
     return out
 
 
+def jacobian(model, t, y, p, shared=None):
+    y = _f64(y)
+    p = _f64(p)
+    sh = _shared(model, shared)
+    D = dim(model)
+    out = np.zeros(D * D)
+    if lib().orc_jacobian(model, float(t), _ptr(y), _ptr(p), _ptr(sh), _ptr(out)):
+        raise ValueError("bad model")
+    return out.reshape(D, D)
+
+
 def km_coeffs(p, shared):
     p = _f64(p)
     sh = _f64(shared)
@@ -173,7 +185,7 @@ def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, 
     """Adaptive solve of an ensemble through its phases with the scheme of
     opts.scheme (Cash--Karp by default).  phi0 (Keller--Miksis): the second
     drive's phase in cycles at the start of the current phase (0 if None)."""
-    D = dim(model)
+    D = dim(model) * (2 if opts.lyapunov else 1)
     y0 = _f64(y0)
     n = y0.shape[-1]
     y0 = y0.reshape(D, n)
@@ -183,7 +195,7 @@ def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, 
     h0 = None if h0 is None else _f64(h0).reshape(n)
     phi0 = None if phi0 is None else _f64(phi0).reshape(n)
     R = int(opts.n_record)
-    F = nrec_fields(model)
+    F = 2 if opts.lyapunov else nrec_fields(model)
     y = np.empty((D, n))
     t = np.empty(n)
     h = np.empty(n)

@@ -61,7 +61,7 @@
 #include <omp.h>
 #endif
 
-#define MAXD 4
+#define MAXD 8   /* state dimension, the tangent included */
 
 int orc_dim(int model) {
   switch (model) {
@@ -139,7 +139,9 @@ void orc_km_coeffs(const double *p, const double *sh, double *C) {
 
 typedef struct {
   int model;
-  int D;
+  int D;           /* integrated dimension: Db, or 2 Db with the tangent      */
+  int Db;          /* the model's own dimension                            */
+  int tangent;     /* the variational equation rides along (Lyapunov)      */
   double p[6];     /* per-system parameters                                */
   const double *sh;/* shared parameters                                    */
   double C[13];    /* Keller--Miksis coefficients                          */
@@ -214,7 +216,7 @@ static void rhs_prv(const sysctx *s, const double *y, double *f) {
   f[2] = beta * (q - y[0] * sqrt(y[2]));
 }
 
-static void rhs(const sysctx *s, double t, const double *y, double *f) {
+static void rhs_base(const sysctx *s, double t, const double *y, double *f) {
   switch (s->model) {
     case ORC_QUAD: rhs_quad(s, y, f); break;
     case ORC_LORENZ: rhs_lorenz(s, y, f); break;
@@ -226,11 +228,81 @@ static void rhs(const sysctx *s, double t, const double *y, double *f) {
   }
 }
 
+/* Jacobian J[i][j] = d f_i / d y_j of the model's right-hand side, row-major
+ * [Db][Db], for the variational equation d(dy)/dt = J(t, y) dy. */
+static void jacobian(const sysctx *s, double t, const double *y, double *J) {
+  switch (s->model) {
+    case ORC_QUAD: J[0] = 2.0 * y[0]; break;
+    case ORC_DIV: J[0] = -1.0 / (y[0] * y[0]) - s->p[0]; break;
+    case ORC_SIN: J[0] = s->p[0] * cos(y[0]); break;
+    case ORC_LORENZ: {
+      const double sigma = s->sh[0], beta = s->sh[1], rho = s->p[0];
+      J[0] = -sigma;       J[1] = sigma; J[2] = 0.0;
+      J[3] = rho - y[2];   J[4] = -1.0;  J[5] = -y[0];
+      J[6] = y[1];         J[7] = y[0];  J[8] = -beta;
+      break;
+    }
+    case ORC_KM:
+    case ORC_KM6: {
+      /* f2 = N / D with N, D of the Keller--Miksis right-hand side:
+       * d f2 / d y_j = (dN/dy_j - f2 dD/dy_j) / D */
+      const double *C = s->C;
+      const double pi = 3.14159265358979323846;
+      const double y1 = y[0], y2 = y[1];
+      const double rx = 1.0 / y1;
+      const double a1 = 2.0 * pi * t;
+      const double a2 = 2.0 * pi * (s->phi2 + C[11] * t) + C[12];
+      const double fs = C[5] * sin(a1) + C[6] * sin(a2);
+      const double fc = C[7] * cos(a1) + C[8] * cos(a2);
+      const double gas = pow(rx, C[10]);
+      double f[2];
+      rhs_km(s, t, y, f);
+      const double Dn = y1 - C[9] * y1 * y2 + C[4] * C[9];
+      const double dN1 = -C[10] * (C[0] + C[1] * y2) * gas * rx + C[3] * rx * rx
+                         + C[4] * y2 * rx * rx - fc;
+      const double dN2 = C[1] * gas - C[2] * C[9] - C[4] * rx - 3.0 * y2
+                         + 1.5 * C[9] * y2 * y2 - C[9] * fs;
+      const double dD1 = 1.0 - C[9] * y2, dD2 = -C[9] * y1;
+      J[0] = 0.0;
+      J[1] = 1.0;
+      J[2] = (dN1 - f[1] * dD1) / Dn;
+      J[3] = (dN2 - f[1] * dD2) / Dn;
+      break;
+    }
+    case ORC_PRV: {
+      const double kappa = s->sh[0], beta = s->sh[2], q = s->p[0];
+      const double r = sqrt(y[2]);
+      J[0] = 0.0;          J[1] = 1.0;    J[2] = 0.0;
+      J[3] = -1.0;         J[4] = -kappa; J[5] = 1.0;
+      J[6] = -beta * r;    J[7] = 0.0;    J[8] = -beta * y[0] / (2.0 * r);
+      (void)q;
+      break;
+    }
+  }
+}
+
+/* The integrated right-hand side: the model's, and with the tangent the
+ * variational equation on the second half of the state. */
+static void rhs(const sysctx *s, double t, const double *y, double *f) {
+  rhs_base(s, t, y, f);
+  if (s->tangent) {
+    const int Db = s->Db;
+    double J[(MAXD / 2) * (MAXD / 2)];
+    jacobian(s, t, y, J);
+    for (int i = 0; i < Db; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < Db; ++j) acc += J[i * Db + j] * y[Db + j];
+      f[Db + i] = acc;
+    }
+  }
+}
+
 static int ctx_init(sysctx *s, int model, const double *p, const double *sh) {
   if (orc_dim(model) < 0) return -1;
   memset(s, 0, sizeof(*s));
   s->model = model;
   s->D = orc_dim(model);
+  s->Db = s->D;
   for (int j = 0; j < orc_nparam(model); ++j) s->p[j] = p[j];
   s->sh = sh;
   if (model == ORC_KM) orc_km_coeffs(p, sh, s->C);
@@ -241,6 +313,14 @@ static int ctx_init(sysctx *s, int model, const double *p, const double *sh) {
                              p[5], p[2], p[3], p[4]};
     orc_km_coeffs(p2, sh11, s->C);
   }
+  return 0;
+}
+
+int orc_jacobian(int model, double t, const double *y, const double *p,
+                 const double *shared, double *J) {
+  sysctx s;
+  if (ctx_init(&s, model, p, shared)) return -1;
+  jacobian(&s, t, y, J);
   return 0;
 }
 
@@ -474,7 +554,9 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
                       double *records, int64_t n, int64_t i, int64_t st[ORC_NSTAT],
                       int32_t *status) {
   const int D = s->D;
-  const int F = orc_nrec_fields(s->model);
+  /* with the tangent, the second record field is the phase's log growth */
+  const int F = s->tangent ? 2 : orc_nrec_fields(s->model);
+  const int Db = s->Db;            /* the model's own components      */
   const int fixed_len = (s->model != ORC_PRV);
   const double tol_ev = o->event_tol;
   double t = *tp, h = *hp;
@@ -511,6 +593,9 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
     /* error norm */
     double E = 0.0;
     int finite = 1;
+    /* with the tangent every component is under error control: near a
+     * stable fixed point the model's own components would let the step
+     * grow past the tangent's stability limit */
     for (int c = 0; c < D; ++c) {
       const double sc = o->atol + o->rtol * fmax(fabs(y[c]), fabs(y5[c]));
       const double r = fabs(err[c]) / sc;
@@ -650,7 +735,16 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
       have_k1 = 0;   /* every phase starts with k1 evaluated (the clock resets) */
       /* the phase ends exactly at t_phase; next phase from 0 with the
        * untruncated proposal h */
-      put_record(records, n, F, o->n_record, phase, i, ymax, ymin);
+      double growth = ymin;
+      if (s->tangent) {
+        /* Lyapunov renormalisation: record log |dy| and rescale dy to 1 */
+        double nrm2 = 0.0;
+        for (int c = Db; c < D; ++c) nrm2 += y[c] * y[c];
+        const double nrm = sqrt(nrm2);
+        growth = log(nrm);
+        for (int c = Db; c < D; ++c) y[c] = y[c] / nrm;
+      }
+      put_record(records, n, F, o->n_record, phase, i, ymax, growth);
       phase++;
       st[ORC_ST_PHASES] = phase;
       ymax = -INFINITY;
@@ -682,6 +776,8 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
     return -1;
   if (model != ORC_PRV && !(opt->t_phase > 0.0)) return -1;
   if (opt->locate_max && model != ORC_KM && model != ORC_KM6) return -1;
+  if (opt->lyapunov && (model == ORC_PRV || opt->locate_max)) return -1;
+  const int Dint = opt->lyapunov ? 2 * D : D;   /* integrated dimension */
   if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
   for (int64_t i = 0; i < n; ++i) {
@@ -689,15 +785,19 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
     for (int j = 0; j < P; ++j) p[j] = params[j * n + i];
     sysctx s;
     ctx_init(&s, model, p, shared);
+    if (opt->lyapunov) {
+      s.tangent = 1;
+      s.D = Dint;
+    }
     s.phi2 = phi0 ? phi0[i] : 0.0;
-    for (int c = 0; c < D; ++c) y[c] = y0[c * n + i];
+    for (int c = 0; c < Dint; ++c) y[c] = y0[c * n + i];
     double t = t0 ? t0[i] : 0.0;
     double h = h0 ? h0[i] : opt->dt0;
     int64_t st[ORC_NSTAT] = {0, 0, 0, 0, 0, 0};
     int32_t stat = ORC_SYS_OK;
     solve_one(&s, opt, y, &t, &h, records, n, i, st, &stat);
     if (y_out)
-      for (int c = 0; c < D; ++c) y_out[c * n + i] = y[c];
+      for (int c = 0; c < Dint; ++c) y_out[c * n + i] = y[c];
     if (t_out) t_out[i] = t;
     if (h_out) h_out[i] = h;
     if (phi_out) phi_out[i] = s.phi2;

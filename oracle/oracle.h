@@ -93,7 +93,12 @@ typedef struct {
   int32_t scheme;    /* ORC_CASH_KARP or ORC_DORMAND_PRINCE                  */
   int32_t locate_max; /* KM: also take y1 where y2 falls through 0 inside a
                          step, on the step's cubic Hermite interpolant       */
-  int32_t pad_;
+  int32_t lyapunov;  /* fixed-length phases: integrate the variational
+                        equation d(dy)/dt = J(t, y) dy along (error control
+                        on both y and dy); the state is then
+                        [y; dy] (2D components), at every phase end dy is
+                        rescaled to unit length and the record's second
+                        field is log |dy| before the rescaling            */
 } orc_opts;
 
 /* Adaptive schemes: Cash--Karp 5(4) (six stages) and Dormand--Prince 5(4)
@@ -117,9 +122,16 @@ int orc_nrec_fields(int model);
  *    would try, and the second drive's phase (KM; passing all four back
  *    resumes the solve).
  *  records [n_record][F][n]: a ring, phase k of this call in slot
- *    k % n_record.  stats [ORC_NSTAT][n], status [n].  Any output pointer may
+ *    k % n_record; F = 2 with opt->lyapunov (y1max, log growth).
+ *  With opt->lyapunov, y0 and y_out are [2D][n]: the state, then the
+ *    tangent vector.  stats [ORC_NSTAT][n], status [n].  Any output pointer may
  *    be NULL.
  */
+/* Jacobian d f_i / d y_j of a model's right-hand side at (t, y), row-major
+ * [D][D] (Keller--Miksis: with the second drive's phase 0). */
+int orc_jacobian(int model, double t, const double *y, const double *p,
+                 const double *shared, double *J);
+
 int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
                const double *y0, const double *t0, const double *h0, const double *phi0,
                const orc_opts *opt, double *y_out, double *t_out, double *h_out,

@@ -1,0 +1,137 @@
+"""Pins of the oracle's variational-equation mode (opts.lyapunov): the
+tangent dy rides on the model's steps, d(dy)/dt = J(t, y) dy, and at every
+phase end its log length is recorded and it is rescaled to unit length
+(Benettin's renormalisation; the per-phase trajectory manipulation of the
+paper's introduction, done inside the solve).
+
+* the analytic Jacobians against central differences of the right-hand side;
+* at a fixed point J is constant, so the recorded log growths sum to
+  log |expm(J T) dy0|, whatever the renormalisations in between;
+* dx/dt = x^2 - p along its closed form x(t) = -tanh(t + atanh(1/2)) (p = 1):
+  the log growth is the integral of 2x, -2 log(cosh(T + a) / cosh(a));
+* the Lorenz attractor's largest exponent, 0.9056 (Sprott, Chaos and
+  Time-Series Analysis, 2003), within 0.03 at T = 1000;
+* the model's own state and records agree with the plain solve (the tangent
+  is under error control too, so the steps differ).
+"""
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+import oracle as O
+from paper_2011_01740_amd import inputs as I
+
+LOR = [I.LORENZ_SIGMA, I.LORENZ_BETA]
+
+
+def fd_jacobian(model, t, y, p, sh, eps=1e-6):
+    y = np.asarray(y, dtype=float)
+    D = y.size
+    J = np.zeros((D, D))
+    for j in range(D):
+        d = np.zeros(D)
+        d[j] = eps * max(1.0, abs(y[j]))
+        J[:, j] = (O.rhs(model, t, y + d, p, sh) - O.rhs(model, t, y - d, p, sh)) / (2 * d[j])
+    return J
+
+
+def _km_dual():
+    sh = np.array(I.KM_WATER)
+    sh[8], sh[9], sh[10] = 0.4e5, 130e3, 0.9
+    return sh
+
+
+CASES = [
+    (O.QUAD, [0.7], [0.3], None),
+    (O.DIV, [0.7], [0.3], None),
+    (O.SIN, [0.7], [1.3], None),
+    (O.LORENZ, [1.0, -2.0, 20.0], [28.0], LOR),
+    (O.KM, [1.3, -0.8], [0.9e5, 80e3], I.KM_WATER),
+    (O.KM, [0.6, 2.1], [0.9e5, 80e3], _km_dual()),
+    (O.KM6, [0.8, 0.4], [0.9e5, 80e3, 0.5e5, 200e3, -0.4, 7e-6], I.KM_WATER[:7]),
+    (O.PRV, [0.5, -0.3, 9.0], [3.0], I.PRV_DEFAULT),
+]
+
+
+@pytest.mark.parametrize("model,y,p,sh", CASES)
+def test_jacobian_matches_central_differences(model, y, p, sh):
+    for t in (0.0, 0.37):
+        J = O.jacobian(model, t, y, p, sh)
+        Jfd = fd_jacobian(model, t, y, p, sh)
+        np.testing.assert_allclose(J, Jfd, rtol=1e-6, atol=1e-6 * np.abs(Jfd).max())
+
+
+def _tangent_state(y0, dy0):
+    return np.vstack([y0, dy0])
+
+
+@pytest.mark.parametrize("scheme", [O.CASH_KARP, O.DORMAND_PRINCE])
+def test_constant_jacobian_at_a_fixed_point(scheme):
+    # Keller--Miksis undriven at rest (C0 - C2 - C3 = 0), Lorenz at the origin
+    o = O.Opts(n_phases=6, n_record=6, rtol=1e-12, atol=1e-12, lyapunov=1, scheme=scheme)
+    for model, y0, p, sh in ((O.KM, [1.0, 0.0], [0.0, 50e3], I.KM_WATER),
+                             (O.LORENZ, [0.0, 0.0, 0.0], [0.5], LOR)):
+        D = len(y0)
+        dy0 = np.ones(D) / np.sqrt(D)
+        r = O.rkck45(model, np.array(p).reshape(-1, 1), sh,
+                     _tangent_state(np.array(y0).reshape(D, 1), dy0.reshape(D, 1)), o)
+        J = O.jacobian(model, 0.0, y0, p, sh)
+        want = np.log(np.linalg.norm(expm(J * 6.0) @ dy0))
+        got = r.records[:, 1, 0].sum()
+        assert got == pytest.approx(want, abs=1e-8)
+        # the tangent left at unit length, pointing along expm(J T) dy0
+        v = expm(J * 6.0) @ dy0
+        np.testing.assert_allclose(r.y[D:, 0], v / np.linalg.norm(v), atol=1e-8)
+
+
+def test_quadratic_closed_form_growth():
+    a = np.arctanh(0.5)
+    o = O.Opts(n_phases=5, n_record=5, rtol=1e-12, atol=1e-12, lyapunov=1)
+    r = O.rkck45(O.QUAD, np.array([[1.0]]), None, np.array([[-0.5], [1.0]]), o)
+    T = np.arange(1, 6)
+    want = -2.0 * np.log(np.cosh(T + a) / np.cosh(a))
+    np.testing.assert_allclose(np.cumsum(r.records[:, 1, 0]), want, atol=1e-9)
+
+
+def test_lorenz_largest_exponent():
+    o = O.Opts(n_phases=1000, n_record=1000, lyapunov=1, dt_max=0.05)
+    y0 = np.array([[1.0, -3.0], [1.0, 4.0], [20.0, 25.0]])
+    dy0 = np.full((3, 2), 1.0 / np.sqrt(3.0))
+    r = O.rkck45(O.LORENZ, np.array([[28.0, 28.0]]), LOR, np.vstack([y0, dy0]), o, nthreads=2)
+    lam = r.records[100:, 1, :].mean(axis=0)      # after a 100-unit transient
+    assert np.all(np.abs(lam - 0.9056) < 0.03), lam
+
+
+@pytest.mark.parametrize("scheme", [O.CASH_KARP, O.DORMAND_PRINCE])
+def test_model_state_agrees_with_the_plain_solve(scheme):
+    P, y0 = I.km_grid(3, 3)
+    n = P.shape[1]
+    o = dict(n_phases=4, n_record=4, scheme=scheme)
+    plain = O.rkck45(O.KM, P, I.KM_WATER, y0, O.Opts(**o))
+    tan = O.rkck45(O.KM, P, I.KM_WATER, np.vstack([y0, np.tile([[1.0], [0.0]], (1, n))]),
+                   O.Opts(lyapunov=1, **o))
+    np.testing.assert_allclose(tan.y[:2], plain.y, rtol=1e-7, atol=1e-9)
+    # maxima over the step points: other steps, other points (as between schemes)
+    np.testing.assert_allclose(tan.records[:, 0], plain.records[:, 0], rtol=2e-3)
+    assert np.all(tan.stats[0] >= plain.stats[0])       # the tangent asks for no fewer steps
+    np.testing.assert_allclose(np.linalg.norm(tan.y[2:], axis=0), 1.0, rtol=1e-15)
+
+
+def test_resume_with_tangent_is_bit_identical():
+    P, y0 = I.km_grid(2, 2)
+    n = P.shape[1]
+    Y0 = np.vstack([y0, np.tile([[0.6], [0.8]], (1, n))])
+    full = O.rkck45(O.KM, P, I.KM_WATER, Y0, O.Opts(n_phases=4, n_record=4, lyapunov=1))
+    a = O.rkck45(O.KM, P, I.KM_WATER, Y0, O.Opts(n_phases=2, n_record=2, lyapunov=1))
+    b = O.rkck45(O.KM, P, I.KM_WATER, a.y, O.Opts(n_phases=2, n_record=2, lyapunov=1),
+                 t0=a.t, h0=a.h)
+    assert np.array_equal(full.y, b.y) and np.array_equal(full.records[2:], b.records)
+
+
+def test_lyapunov_rejects_events_and_located_maxima():
+    with pytest.raises(ValueError):
+        O.rkck45(O.PRV, np.array([[3.0]]), I.PRV_DEFAULT, np.ones((6, 1)),
+                 O.Opts(n_phases=1, lyapunov=1))
+    with pytest.raises(ValueError):
+        O.rkck45(O.KM, np.array([[1e5], [50e3]]), I.KM_WATER, np.ones((4, 1)),
+                 O.Opts(n_phases=1, lyapunov=1, locate_max=1))
