@@ -143,6 +143,21 @@ typedef struct {
   const int64_t *ens_offsets; /* host, n_ensembles + 1 ascending offsets from
                              0 to n; NULL means one ensemble [0, n)          */
   void *hip_stream;       /* hipStream_t to enqueue on; NULL = null stream   */
+  int32_t tangent;        /* adaptive solvers, fixed-length-phase models
+                             (QUAD, LORENZ, KM, KM6): integrate the
+                             variational equation d(dy)/dt = J(t, y) dy
+                             along with each system, for its largest
+                             Lyapunov exponent.  The state becomes [2D][n]
+                             (y, then the tangent dy; the caller sets the
+                             initial dy), both under error control; at every
+                             phase end dy is rescaled to unit length and the
+                             record gains a second field, log |dy| before the
+                             rescaling (F = 2).  The exponent over recorded
+                             phases k is sum_k record[k][1] / (their number
+                             x t_phase).  This is the per-phase trajectory
+                             manipulation (renormalisation) of the paper's
+                             introduction, done inside the solve.  0 = off */
+  int32_t reserved_;      /* must be 0                                       */
 } ens_desc;
 
 /* Creates a handle, allocates the parameter and state buffers on `device`

@@ -36,6 +36,7 @@ using ens::EnsDesc;
 
 struct ens_ctx {
   int model = 0, solver = 0;
+  bool tangent = false;  // variational equation along (mi.D and mi.F include it)
   ens::ModelInfo mi{};
   int64_t n = 0;
   int n_ens = 1;
@@ -420,6 +421,11 @@ int ens_create(const ens_desc *d, ens_t *out) {
       return fail(nullptr, ENS_E_INVAL, "ens_create: offsets required for n_ensembles > 1");
     off = {0, d->n};
   }
+  if (d->tangent != 0 && d->tangent != 1)
+    return fail(nullptr, ENS_E_INVAL, "ens_create: tangent must be 0 or 1");
+  if (d->tangent && (d->solver == ENS_RK4 || d->model == ENS_PRV))
+    return fail(nullptr, ENS_E_UNSUPPORTED,
+                "ens_create: tangent is built for the adaptive solvers with fixed-length phases");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
     return fail(nullptr, ENS_E_HIP, "ens_create: no HIP device");
@@ -431,6 +437,11 @@ int ens_create(const ens_desc *d, ens_t *out) {
   h->model = d->model;
   h->solver = d->solver;
   h->mi = ens::model_info(d->model);
+  h->tangent = d->tangent != 0;
+  if (h->tangent) {  // state [y; dy], records (y1max, log growth)
+    h->mi.D *= 2;
+    h->mi.F = 2;
+  }
   h->n = d->n;
   h->n_ens = d->n_ensembles;
   h->off = off;
@@ -620,6 +631,8 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     return fail(h, ENS_E_INVAL, "ens_solve: bad phase, record or step counts");
   if (o->max_steps > (int64_t)UINT32_MAX)
     return fail(h, ENS_E_INVAL, "ens_solve: max_steps above 2^32");
+  if (o->locate_max && h->tangent)
+    return fail(h, ENS_E_UNSUPPORTED, "ens_solve: locate_max is not built with the tangent");
   if (o->locate_max && h->model != ENS_KM && h->model != ENS_KM6)
     return fail(h, ENS_E_UNSUPPORTED, "ens_solve: locate_max is built for Keller--Miksis");
   int block = o->block, refill = o->refill;
@@ -652,6 +665,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     for (int e = 0; e < h->n_ens; ++e)
       if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM6_GENERAL;
   }
+  if (h->tangent) kmodel += ens::kTangentModel;
   int grid = o->grid;
   const int cap = ens::rkck_max_blocks(kmodel, h->solver, o->locate_max != 0, block);
   if (cap <= 0) return fail(h, ENS_E_HIP, "ens_solve: occupancy query failed");

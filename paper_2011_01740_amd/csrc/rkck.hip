@@ -115,12 +115,21 @@ struct MQuad {  // dx/dt = x^2 - p (Sec. 3)
   static constexpr bool kPrio = false;  // issue priority by remaining work
   static constexpr bool kLocate = false;
   static constexpr bool kDrive2 = false;
+  static constexpr int kF = 1;           // record fields
+  static constexpr bool kTangent = false;
   double p;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) { p = P[i]; }
   __device__ void begin(double) {}
   template <int SC, int S>
   __device__ void rhs(double, double, const double *y, double *f) const {
     f[0] = fma(y[0], y[0], -p);
+  }
+  // with the variational equation: df = J dy, J = 2x
+  template <int SC, int S>
+  __device__ void rhs_tan(double t, double h, const double *y, const double *dy, double *f,
+                          double *df) const {
+    rhs<SC, S>(t, h, y, f);
+    df[0] = 2.0 * y[0] * dy[0];
   }
 };
 
@@ -131,6 +140,8 @@ struct MLorenz {  // Sec. 4.1
   static constexpr bool kPrio = false;  // issue priority by remaining work
   static constexpr bool kLocate = false;
   static constexpr bool kDrive2 = false;
+  static constexpr int kF = 1;
+  static constexpr bool kTangent = false;
   double rho, sigma, beta;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
     rho = P[i];
@@ -143,6 +154,15 @@ struct MLorenz {  // Sec. 4.1
     f[0] = sigma * (y[1] - y[0]);
     f[1] = fma(-y[0], y[2], fma(rho, y[0], -y[1]));
     f[2] = fma(y[0], y[1], -beta * y[2]);
+  }
+  // J = [[-sigma, sigma, 0], [rho - z, -1, -x], [y, x, -beta]]
+  template <int SC, int S>
+  __device__ void rhs_tan(double t, double h, const double *y, const double *dy, double *f,
+                          double *df) const {
+    rhs<SC, S>(t, h, y, f);
+    df[0] = sigma * (dy[1] - dy[0]);
+    df[1] = fma(rho - y[2], dy[0], fma(-y[0], dy[2], -dy[1]));
+    df[2] = fma(y[1], dy[0], fma(y[0], dy[1], -beta * dy[2]));
   }
 };
 
@@ -205,6 +225,8 @@ struct MKM {
   static constexpr bool kPrio = true;  // issue priority by remaining work
   static constexpr bool kLocate = true;  // y2 = y1': maxima can be located
   static constexpr bool kDrive2 = DUAL;
+  static constexpr int kF = 1;
+  static constexpr bool kTangent = false;
   double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49;
   double s0, c0;  // sin, cos (2 pi t) at the start of the attempted step
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
@@ -260,6 +282,17 @@ struct MKM {
   // SC: the scheme; S: the stage (1..7); tau: its time; h: the attempted step.
   template <int SC, int S>
   __device__ void rhs(double tau, double h, const double *y, double *f) {
+    eval<SC, S, false>(tau, h, y, nullptr, f, nullptr);
+  }
+  // With the variational equation: df = J dy from the same intermediates.
+  template <int SC, int S>
+  __device__ void rhs_tan(double tau, double h, const double *y, const double *dy, double *f,
+                          double *df) {
+    eval<SC, S, true>(tau, h, y, dy, f, df);
+  }
+  template <int SC, int S, bool TAN>
+  __device__ __forceinline__ void eval(double tau, double h, const double *y, const double *dy,
+                                       double *f, double *df) {
     const double y1 = y[0], y2 = y[1];
     const double Dn = fma(y1, fma(-K9, y2, 1.0), K49);
     const double qd = rcp_nr(y1 * Dn);
@@ -345,6 +378,16 @@ struct MKM {
     N = fma(-fc, y1, N);
     f[0] = y2;
     f[1] = N * (y1 * qd);
+    if constexpr (TAN) {
+      // f2 = N / D: d f2 / d y_j = (dN/dy_j - f2 dD/dy_j) / D, 1/D = y1 qd
+      const double f2 = f[1], iD = y1 * qd;
+      const double dN1 = fma(-K10 * fma(K1, y2, K0) * gas, r1, fma(fma(K4, y2, K3), r1 * r1, -fc));
+      const double dN2 = fma(K1, gas, -K9 * fs) - K4 * r1 + y2 * fma(1.5 * K9, y2, -3.0);
+      const double J21 = fma(-f2, fma(-K9, y2, 1.0), dN1) * iD;
+      const double J22 = fma(f2 * K9, y1, dN2) * iD;
+      df[0] = dy[1];
+      df[1] = fma(J21, dy[0], J22 * dy[1]);
+    }
   }
 };
 
@@ -357,6 +400,8 @@ struct MPRV {
   static constexpr bool kPrio = false;  // issue priority by remaining work
   static constexpr bool kLocate = false;
   static constexpr bool kDrive2 = false;
+  static constexpr int kF = 2;           // (y1 at the Poincare point, y1min)
+  static constexpr bool kTangent = false;
   double q, kappa, delta, beta, r;
   bool seated;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
@@ -464,6 +509,37 @@ __device__ __forceinline__ double clampd(double x, double lo, double hi) {
 }
 
 // Lane-private progress of one system.
+// A fixed-length-phase model with its variational equation d(dy)/dt =
+// J(t, y) dy riding along (the paper's introduction: trajectory manipulation
+// between integration phases, here Benettin's renormalisation for the
+// largest Lyapunov exponent, done in the kernel).  The lane state is [y; dy]
+// (2 M::D components, all under error control); at a phase end dy is
+// rescaled to unit length and log |dy| becomes the phase's second record.
+template <class M>
+struct MTan : M {
+  static_assert(!M::kEvents, "the tangent is built for fixed-length phases");
+  static constexpr int D = 2 * M::D;
+  static constexpr int kMinWaves = M::kMinWaves - 1;
+  static constexpr bool kLocate = false;
+  static constexpr int kF = 2;           // (y1max, log growth of the phase)
+  static constexpr bool kTangent = true;
+  template <int SC, int S>
+  __device__ void rhs(double tau, double h, const double *y, double *f) {
+    M::template rhs_tan<SC, S>(tau, h, y, y + M::D, f, f + M::D);
+  }
+  // Renormalisation at a phase end: returns log |dy|, leaves |dy| = 1.
+  __device__ double renormalise(double *y) const {
+    double s2 = 0.0;
+#pragma unroll
+    for (int c = M::D; c < D; ++c) s2 = fma(y[c], y[c], s2);
+    const double nrm = sqrt(s2);
+    const double inv = 1.0 / nrm;
+#pragma unroll
+    for (int c = M::D; c < D; ++c) y[c] *= inv;
+    return log(nrm);
+  }
+};
+
 struct Lane {
   int64_t sys;
   double t, h, t_ps, ymax, ymin;
@@ -496,7 +572,7 @@ template <class M>
 __device__ __forceinline__ void store_record(const RkckArgs &a, const Lane &L, double v0,
                                              double v1) {
   if (a.R <= 0) return;
-  constexpr int F = M::kEvents ? 2 : 1;
+  constexpr int F = M::kF;
   const int64_t slot = (int64_t)(L.phase % (uint64_t)a.R);
   a.rec[(slot * F) * a.n + L.sys] = v0;
   if (F > 1) a.rec[(slot * F + 1) * a.n + L.sys] = v1;
@@ -616,7 +692,10 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
     L.ymax = y[0] > L.ymax ? y[0] : L.ymax;
     if (trunc) {
       fs.have = false;
-      store_record<M>(a, L, L.ymax, 0.0);
+      if constexpr (M::kTangent)
+        store_record<M>(a, L, L.ymax, m.renormalise(y));
+      else
+        store_record<M>(a, L, L.ymax, 0.0);
       L.phase++;
       if constexpr (M::kPrio) note_phase_end(L);
       if constexpr (M::kDrive2) m.next_phase(a.t_phase);
@@ -883,61 +962,66 @@ int max_blocks_model(int block) {
   return per_cu * cus;
 }
 
+// The kernel instantiation behind a host model id: calls fn(Pick<M, LOC>{})
+// and returns its result, or `none` for an id without a kernel.
+template <class Mo, bool L>
+struct Pick {
+  using M = Mo;
+  static constexpr bool loc = L;
+};
+
+template <class R, class Fn>
+R visit_model(int model, bool loc, R none, Fn &&fn) {
+  if (model >= kTangentModel) {
+    switch (model - kTangentModel) {
+      case ENS_QUAD: return fn(Pick<MTan<MQuad>, false>{});
+      case ENS_LORENZ: return fn(Pick<MTan<MLorenz>, false>{});
+      case ENS_KM: return fn(Pick<MTan<MKM<true>>, false>{});
+      case ENS_KM_GENERAL: return fn(Pick<MTan<MKM<false>>, false>{});
+      case ENS_KM_DUAL: return fn(Pick<MTan<MKM<false, true>>, false>{});
+      case ENS_KM_DUAL_FAST: return fn(Pick<MTan<MKM<true, true>>, false>{});
+      case ENS_KM6: return fn(Pick<MTan<MKM<true, true, true>>, false>{});
+      case ENS_KM6_GENERAL: return fn(Pick<MTan<MKM<false, true, true>>, false>{});
+    }
+    return none;
+  }
+  switch (model) {
+    case ENS_QUAD: return fn(Pick<MQuad, false>{});
+    case ENS_LORENZ: return fn(Pick<MLorenz, false>{});
+    case ENS_KM:
+      return loc ? fn(Pick<MKM<true>, true>{}) : fn(Pick<MKM<true>, false>{});
+    case ENS_KM_GENERAL:
+      return loc ? fn(Pick<MKM<false>, true>{}) : fn(Pick<MKM<false>, false>{});
+    case ENS_KM_DUAL:
+      return loc ? fn(Pick<MKM<false, true>, true>{}) : fn(Pick<MKM<false, true>, false>{});
+    case ENS_KM_DUAL_FAST:
+      return loc ? fn(Pick<MKM<true, true>, true>{}) : fn(Pick<MKM<true, true>, false>{});
+    case ENS_KM6:
+      return loc ? fn(Pick<MKM<true, true, true>, true>{})
+                 : fn(Pick<MKM<true, true, true>, false>{});
+    case ENS_KM6_GENERAL:
+      return loc ? fn(Pick<MKM<false, true, true>, true>{})
+                 : fn(Pick<MKM<false, true, true>, false>{});
+    case ENS_PRV: return fn(Pick<MPRV, false>{});
+  }
+  return none;
+}
+
 template <int SC>
 hipError_t launch_scheme(int model, bool loc, int block, int grid, const RkckArgs &a,
                          hipStream_t s) {
-  switch (model) {
-    case ENS_QUAD: return launch_model<MQuad, SC, false>(block, grid, a, s);
-    case ENS_LORENZ: return launch_model<MLorenz, SC, false>(block, grid, a, s);
-    case ENS_KM:
-      return loc ? launch_model<MKM<true>, SC, true>(block, grid, a, s)
-                 : launch_model<MKM<true>, SC, false>(block, grid, a, s);
-    case ENS_KM_GENERAL:
-      return loc ? launch_model<MKM<false>, SC, true>(block, grid, a, s)
-                 : launch_model<MKM<false>, SC, false>(block, grid, a, s);
-    case ENS_KM_DUAL:
-      return loc ? launch_model<MKM<false, true>, SC, true>(block, grid, a, s)
-                 : launch_model<MKM<false, true>, SC, false>(block, grid, a, s);
-    case ENS_KM_DUAL_FAST:
-      return loc ? launch_model<MKM<true, true>, SC, true>(block, grid, a, s)
-                 : launch_model<MKM<true, true>, SC, false>(block, grid, a, s);
-    case ENS_KM6:
-      return loc ? launch_model<MKM<true, true, true>, SC, true>(block, grid, a, s)
-                 : launch_model<MKM<true, true, true>, SC, false>(block, grid, a, s);
-    case ENS_KM6_GENERAL:
-      return loc ? launch_model<MKM<false, true, true>, SC, true>(block, grid, a, s)
-                 : launch_model<MKM<false, true, true>, SC, false>(block, grid, a, s);
-    case ENS_PRV: return launch_model<MPRV, SC, false>(block, grid, a, s);
-  }
-  return hipErrorInvalidValue;
+  return visit_model(model, loc, hipErrorInvalidValue, [&](auto pick) {
+    using P = decltype(pick);
+    return launch_model<typename P::M, SC, P::loc>(block, grid, a, s);
+  });
 }
 
 template <int SC>
 int max_blocks_scheme(int model, bool loc, int block) {
-  switch (model) {
-    case ENS_QUAD: return max_blocks_model<MQuad, SC, false>(block);
-    case ENS_LORENZ: return max_blocks_model<MLorenz, SC, false>(block);
-    case ENS_KM:
-      return loc ? max_blocks_model<MKM<true>, SC, true>(block)
-                 : max_blocks_model<MKM<true>, SC, false>(block);
-    case ENS_KM_GENERAL:
-      return loc ? max_blocks_model<MKM<false>, SC, true>(block)
-                 : max_blocks_model<MKM<false>, SC, false>(block);
-    case ENS_KM_DUAL:
-      return loc ? max_blocks_model<MKM<false, true>, SC, true>(block)
-                 : max_blocks_model<MKM<false, true>, SC, false>(block);
-    case ENS_KM_DUAL_FAST:
-      return loc ? max_blocks_model<MKM<true, true>, SC, true>(block)
-                 : max_blocks_model<MKM<true, true>, SC, false>(block);
-    case ENS_KM6:
-      return loc ? max_blocks_model<MKM<true, true, true>, SC, true>(block)
-                 : max_blocks_model<MKM<true, true, true>, SC, false>(block);
-    case ENS_KM6_GENERAL:
-      return loc ? max_blocks_model<MKM<false, true, true>, SC, true>(block)
-                 : max_blocks_model<MKM<false, true, true>, SC, false>(block);
-    case ENS_PRV: return max_blocks_model<MPRV, SC, false>(block);
-  }
-  return 0;
+  return visit_model(model, loc, 0, [&](auto pick) {
+    using P = decltype(pick);
+    return max_blocks_model<typename P::M, SC, P::loc>(block);
+  });
 }
 
 }  // namespace

@@ -37,7 +37,8 @@ MODEL_DIMS = {ENS_QUAD: (1, 1, 0, 1), ENS_LORENZ: (3, 1, 2, 1),
 class ens_desc(C.Structure):
     _fields_ = [("model", C.c_int32), ("solver", C.c_int32), ("n", C.c_int64),
                 ("n_ensembles", C.c_int32), ("device", C.c_int32),
-                ("ens_offsets", C.POINTER(C.c_int64)), ("hip_stream", C.c_void_p)]
+                ("ens_offsets", C.POINTER(C.c_int64)), ("hip_stream", C.c_void_p),
+                ("tangent", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class ens_solve_opts(C.Structure):
@@ -133,11 +134,15 @@ class Ensemble:
     """One libens handle: n systems of one model, solved on one device."""
 
     def __init__(self, model: int, solver: int, n: int,
-                 offsets: Optional[Sequence[int]] = None, device: int = 0, stream=None):
+                 offsets: Optional[Sequence[int]] = None, device: int = 0, stream=None,
+                 tangent: bool = False):
         L = load()
         self.model, self.solver, self.n = int(model), int(solver), int(n)
         # an unknown model is passed through: ens_create rejects it
         self.D, self.P, self.S, self.F = MODEL_DIMS.get(self.model, (0, 0, 0, 0))
+        self.tangent = bool(tangent)
+        if self.tangent:   # state [y; dy], records (y1max, log growth)
+            self.D, self.F = 2 * self.D, 2
         self.device = int(device)
         if stream is None:
             import torch
@@ -148,6 +153,7 @@ class Ensemble:
         d.model, d.solver, d.n = self.model, self.solver, self.n
         d.device = self.device
         d.hip_stream = self.stream_ptr
+        d.tangent = 1 if self.tangent else 0
         self._offs = None
         if offsets is not None:
             self._offs = (C.c_int64 * len(offsets))(*[int(v) for v in offsets])

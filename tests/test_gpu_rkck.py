@@ -24,11 +24,11 @@ class Res:
 
 
 def gpu_ck(model, P, y0, opts, t0=None, h0=None, shared=None, offsets=None, budgets=None,
-           solves=1, solver=None, phi0=None, **launch):
+           solves=1, solver=None, phi0=None, tangent=False, **launch):
     ens = _ens()
     n = y0.shape[-1]
     solver = ens.ENS_RKCK45 if solver is None else solver
-    with ens.Ensemble(model, solver, n, offsets=offsets) as e:
+    with ens.Ensemble(model, solver, n, offsets=offsets, tangent=tangent) as e:
         e.set_params(P)
         if shared is not None:
             for k in range(e.n_ensembles):
