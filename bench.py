@@ -148,18 +148,22 @@ def run_case(case, args):
                           "bytes_written": a.numel() * 8}), flush=True)
     elif case == "km":
         from paper_2011_01740_amd import ens
+        import numpy as np
+
         from paper_2011_01740_amd import inputs as I
         solver = ens.ENS_RKDP45 if args.solver == "dp" else ens.ENS_RKCK45
         sh = list(I.KM_WATER)
         sh[8], sh[9], sh[10] = args.km_pa2, args.km_f2, args.km_theta
         r = W.km_sweep(args.km_grid, args.km_grid, n_phases=args.km_phases,
                        n_record=args.km_record or None, pilot=args.km_pilot,
-                       pilot_grid=args.km_blocks, solver=solver, shared=sh)
+                       pilot_grid=args.km_blocks, solver=solver, shared=sh,
+                       tangent=args.km_tangent)
         att = r.stats[0] + r.stats[1]
         steps = int(att.sum())
         line = {"case": "km", "solver": args.solver, "grid": args.km_grid,
                 "phases": args.km_phases,
                 "second_drive": {"P_A2": args.km_pa2, "f2": args.km_f2, "theta": args.km_theta},
+                "tangent": bool(args.km_tangent),
                 "pilot": args.km_pilot, "blocks_after_pilot": args.km_blocks,
                 "kernel_ms": r.kernel_ms, "attempted_steps": steps,
                 "steps_per_s": steps / r.kernel_ms * 1e3,
@@ -167,6 +171,11 @@ def run_case(case, args):
                 "rhs_per_s": float(r.stats[2].sum()) / r.kernel_ms * 1e3,
                 "attempts_max_over_mean": float(att.max() / max(att.mean(), 1e-30)),
                 "launch": r.launch}
+        if args.km_tangent:
+            # largest Lyapunov exponent per system: mean log growth per unit tau
+            lam = r.records[:, 1, :].mean(axis=0)
+            line["lyapunov"] = {"positive_fraction": float((lam > 0).mean()),
+                                "max": float(lam.max()), "median": float(np.median(lam))}
         if args.cpu_sample:
             line["cpu_baseline"] = km_cpu_baseline(args.km_grid, args.km_phases, args.cpu_sample,
                                                    args.solver, sh)
@@ -245,6 +254,8 @@ def main(argv=None):
                     help="second drive amplitude P_A2 [Pa] (0: single frequency)")
     ap.add_argument("--km-f2", type=float, default=0.0, help="second drive frequency f2 [Hz]")
     ap.add_argument("--km-theta", type=float, default=0.0, help="second drive phase shift [rad]")
+    ap.add_argument("--km-tangent", action="store_true",
+                    help="integrate the variational equation (largest Lyapunov exponent)")
     ap.add_argument("--solver", choices=["ck", "dp"], default="ck",
                     help="km/prv cases: Cash--Karp or Dormand--Prince 5(4)")
     ap.add_argument("--cpu-sample", type=int, default=0,

@@ -78,7 +78,7 @@ def scalar_rk4(model: int, n: int, n_steps: int = 1000, dt: float = 0.01, **laun
 
 
 def _adaptive(model, P, y0, opts, offsets=None, shared=None, budgets=None, read_records=True,
-              rest_opts=None, solver=None):
+              rest_opts=None, solver=None, tangent=False):
     """One solve with opts; or, with rest_opts, a pilot solve with opts, the
     queue ordered longest-first by its step counts (ens_order_by_work) and a
     second solve with rest_opts (stats summed, status bits or-ed, kernel
@@ -86,7 +86,7 @@ def _adaptive(model, P, y0, opts, offsets=None, shared=None, budgets=None, read_
     import torch
     n = y0.shape[-1]
     solver = ens.ENS_RKCK45 if solver is None else solver
-    with ens.Ensemble(model, solver, n, offsets=offsets) as e:
+    with ens.Ensemble(model, solver, n, offsets=offsets, tangent=tangent) as e:
         e.set_params(_dev(P))
         if shared is not None:
             for k, sh in enumerate(shared):
@@ -116,18 +116,22 @@ def _adaptive(model, P, y0, opts, offsets=None, shared=None, budgets=None, read_
 def km_sweep(n_pa: int, n_f: int, n_phases: int = 1024, n_record: Optional[int] = None,
              shared: Sequence[float] = I.KM_WATER, rtol: float = 1e-10, atol: float = 1e-10,
              P: Optional[np.ndarray] = None, pilot: int = 0, pilot_grid: int = 0,
-             solver: Optional[int] = None, **launch) -> Result:
+             solver: Optional[int] = None, tangent: bool = False, **launch) -> Result:
     """Keller--Miksis sweep over an (n_pa x n_f) grid (p_A linear in [0.2, 1.2]
     bar, f geometric in [20 kHz, 1 MHz]), IC (1, 0), one y1max record per
     acoustic cycle (the last n_record cycles).  P overrides the grid.  With
     pilot > 0 the first `pilot` cycles run in index order and the rest
     longest-first (on pilot_grid blocks; 0: all); the record ring then holds
     the phases in order only if n_phases - pilot is a multiple of n_record.
-    solver: ENS_RKCK45 (default) or ENS_RKDP45."""
+    solver: ENS_RKCK45 (default) or ENS_RKDP45.  tangent: the variational
+    equation rides along from dy = (1, 1)/sqrt 2, and each record gains the
+    phase's log growth (the largest Lyapunov exponent is its mean)."""
     if P is None:
         P, y0 = I.km_grid(n_pa, n_f)
     else:
         y0 = np.vstack([np.ones(P.shape[1]), np.zeros(P.shape[1])])
+    if tangent:
+        y0 = np.vstack([y0, np.full_like(y0, 1.0 / np.sqrt(2.0))])
     R = n_phases if n_record is None else n_record
     if 0 < pilot < n_phases:
         if (n_phases - pilot) % R:
@@ -136,9 +140,9 @@ def km_sweep(n_pa: int, n_f: int, n_phases: int = 1024, n_record: Optional[int] 
         rest = dict(launch, grid=pilot_grid or launch.get("grid", 0))
         o2 = ens.default_opts(n_phases=n_phases - pilot, n_record=R, rtol=rtol, atol=atol, **rest)
         return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], rest_opts=o2,
-                         solver=solver)
+                         solver=solver, tangent=tangent)
     o = ens.default_opts(n_phases=n_phases, n_record=R, rtol=rtol, atol=atol, **launch)
-    return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], solver=solver)
+    return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], solver=solver, tangent=tangent)
 
 
 PRV_ENSEMBLES: Tuple[Tuple[int, int, int], ...] = ((1 << 15, 100000, 3), (1 << 16, 10000, 4),
