@@ -52,7 +52,7 @@ class Config:
     target_wrong: float = 0.007    # hold-out error allowed outside the band
     judge_n: int = 1 << 18         # plain-solved judge points, whole grid rows (0: all)
     judge_chunk: int = 1 << 22     # points per plain-sweep launch
-    pilot: int = 64                # phases before the longest-first queue order (0: off)
+    pilot: int = 16                # phases before the longest-first queue order (0: off)
     data_grid: int = 256           # blocks of the training sweep after its pilot: one wave
                                    # per SIMD, the fastest for its longest systems (0: all)
     resolve_grid: int = 512        # blocks of the re-solve after its pilot: two waves per
@@ -145,8 +145,8 @@ def _attempts(e):
 
 def km_solve_records(P_dev, n_phases, n_last, idx_dev=None, n_full=None, pilot=0, grid=0):
     """Solve the Keller--Miksis points (all of P_dev, or the columns idx_dev of
-    a [2][n_full] sweep).  With 0 < pilot < n_phases (and n_phases - pilot a
-    multiple of n_last) the first `pilot` phases run in index order, then the
+    a [2][n_full] sweep).  With 0 < pilot and n_phases - pilot >= n_last the
+    first `pilot` phases run in index order, then the
     work queue hands out the systems longest-first by their pilot step counts
     for the remaining phases (ens_order_by_work); the results equal those of
     one uninterrupted solve.  grid (> 0): persistent blocks of the solve after
@@ -160,7 +160,7 @@ def km_solve_records(P_dev, n_phases, n_last, idx_dev=None, n_full=None, pilot=0
     y0 = torch.empty((2, n), dtype=torch.float64, device="cuda")
     y0[0].fill_(1.0)
     y0[1].zero_()
-    use_pilot = 0 < pilot < n_phases and (n_phases - pilot) % n_last == 0
+    use_pilot = 0 < pilot and n_phases - pilot >= n_last
     with ens.Ensemble(ens.ENS_KM, ens.ENS_RKCK45, n) as e:
         if idx_dev is not None:
             L = ens.load()
@@ -184,9 +184,11 @@ def km_solve_records(P_dev, n_phases, n_last, idx_dev=None, n_full=None, pilot=0
         att += _attempts(e)
         rec = e.read(ens.ENS_RECORDS, device=True)      # [n_last][1][n]
         status = status | e.read(ens.ENS_STATUS)
-    # records are a ring over the last n_last phases; with the phases of the
-    # (last) solve a multiple of n_last the slots hold the phases in order
-    return rec.reshape(n_last, n).contiguous(), status, ms / 1e3, att
+    # records are a ring over the last n_last phases of the last solve (m
+    # phases): slot m % n_last holds the oldest, so rotate it to the front
+    m = n_phases - pilot if use_pilot else n_phases
+    rec = torch.roll(rec.reshape(n_last, n), shifts=-(m % n_last), dims=0)
+    return rec.contiguous(), status, ms / 1e3, att
 
 
 def run(cfg: Config, log=print) -> Report:

@@ -120,9 +120,9 @@ def km_sweep(n_pa: int, n_f: int, n_phases: int = 1024, n_record: Optional[int] 
     """Keller--Miksis sweep over an (n_pa x n_f) grid (p_A linear in [0.2, 1.2]
     bar, f geometric in [20 kHz, 1 MHz]), IC (1, 0), one y1max record per
     acoustic cycle (the last n_record cycles).  P overrides the grid.  With
-    pilot > 0 the first `pilot` cycles run in index order and the rest
-    longest-first (on pilot_grid blocks; 0: all); the record ring then holds
-    the phases in order only if n_phases - pilot is a multiple of n_record.
+    pilot > 0 (and n_phases - pilot >= n_record) the first `pilot` cycles run
+    in index order and the rest longest-first (on pilot_grid blocks; 0: all);
+    the records come back in phase order either way.
     solver: ENS_RKCK45 (default) or ENS_RKDP45.  tangent: the variational
     equation rides along from dy = (1, 1)/sqrt 2, and each record gains the
     phase's log growth (the largest Lyapunov exponent is its mean)."""
@@ -133,16 +133,22 @@ def km_sweep(n_pa: int, n_f: int, n_phases: int = 1024, n_record: Optional[int] 
     if tangent:
         y0 = np.vstack([y0, np.full_like(y0, 1.0 / np.sqrt(2.0))])
     R = n_phases if n_record is None else n_record
-    if 0 < pilot < n_phases:
-        if (n_phases - pilot) % R:
-            raise ValueError("n_phases - pilot must be a multiple of n_record")
+    if 0 < pilot and n_phases - pilot >= R:
         o = ens.default_opts(n_phases=pilot, n_record=R, rtol=rtol, atol=atol, **launch)
         rest = dict(launch, grid=pilot_grid or launch.get("grid", 0))
         o2 = ens.default_opts(n_phases=n_phases - pilot, n_record=R, rtol=rtol, atol=atol, **rest)
-        return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], rest_opts=o2,
-                         solver=solver, tangent=tangent)
-    o = ens.default_opts(n_phases=n_phases, n_record=R, rtol=rtol, atol=atol, **launch)
-    return _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], solver=solver, tangent=tangent)
+        r = _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], rest_opts=o2,
+                      solver=solver, tangent=tangent)
+        m = n_phases - pilot
+    else:
+        o = ens.default_opts(n_phases=n_phases, n_record=R, rtol=rtol, atol=atol, **launch)
+        r = _adaptive(ens.ENS_KM, P, y0, o, shared=[list(shared)], solver=solver,
+                      tangent=tangent)
+        m = n_phases
+    # the ring's oldest slot is m % R: rotate the phases into order
+    if r.records is not None and R > 0:
+        r.records = np.roll(r.records, -(m % R), axis=0)
+    return r
 
 
 PRV_ENSEMBLES: Tuple[Tuple[int, int, int], ...] = ((1 << 15, 100000, 3), (1 << 16, 10000, 4),

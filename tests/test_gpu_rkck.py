@@ -359,3 +359,17 @@ def test_located_maxima_match_oracle(scheme):
     assert (g.records > plain.records).mean() > 0.5
     with pytest.raises(ens.EnsError):
         gpu_ck(3, *I.prv_linspace(4), O.Opts(n_phases=2), solver=solver, locate_max=1)
+
+
+def test_km_sweep_records_come_back_in_phase_order():
+    """A pilot whose remainder is not a multiple of the ring: the records are
+    rotated into phase order and equal the uninterrupted solve's."""
+    from paper_2011_01740_amd import workloads as W
+    P, y0 = I.km_grid(8, 8)
+    a = W.km_sweep(8, 8, n_phases=20, n_record=8, pilot=5)
+    b = W.km_sweep(8, 8, n_phases=20, n_record=8)
+    assert np.array_equal(a.records, b.records) and np.array_equal(a.y, b.y)
+    o = O.Opts(n_phases=20, n_record=20)
+    ref = O.rkck45(O.KM, P, I.KM_WATER, y0, o, nthreads=8)
+    ok = close(b.records, ref.records[12:], CK_RTOL, CK_ATOL)
+    assert ok.mean() > 0.9
