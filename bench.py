@@ -237,9 +237,18 @@ def run_case(case, args):
     elif case == "prv":
         from paper_2011_01740_amd import ens
         ensm = tuple((m, max(1, K // args.prv_div), sd) for m, K, sd in W.PRV_ENSEMBLES)
-        r = W.prv_batched(ensm, solver=ens.ENS_RKDP45 if args.solver == "dp" else None)
+        if args.prv_n:   # one ensemble of the first sub-ensemble's kind (latency studies)
+            ensm = ((args.prv_n, max(1, W.PRV_ENSEMBLES[0][1] // args.prv_div),
+                     W.PRV_ENSEMBLES[0][2]),)
+        launch = {"grid": args.prv_grid} if args.prv_grid else {}
+        r = W.prv_batched(ensm, solver=ens.ENS_RKDP45 if args.solver == "dp" else None,
+                          spread=args.prv_spread if args.prv_spread >= 0 else None, **launch)
         steps = int(r.stats[0].sum() + r.stats[1].sum() + r.stats[5].sum())
+        att = r.stats[0] + r.stats[1] + r.stats[5]
         line = {"case": "prv", "solver": args.solver, "budget_divisor": args.prv_div,
+                "ensembles": [list(e) for e in ensm],
+                "attempts_max": int(att.max()),
+                "us_per_attempt_longest": r.kernel_ms * 1e3 / max(int(att.max()), 1),
                 "kernel_ms": r.kernel_ms, "attempted_steps": steps,
                 "steps_per_s": steps / r.kernel_ms * 1e3,
                 "impacts_per_s": float(r.stats[3].sum()) / r.kernel_ms * 1e3,
@@ -288,6 +297,11 @@ def main(argv=None):
                     help="km/prv cases: time the oracle on a sample (km: side of a sub-grid, "
                          "prv: systems per ensemble; 0: off)")
     ap.add_argument("--prv-div", type=int, default=100)
+    ap.add_argument("--prv-n", type=int, default=0,
+                    help="one valve ensemble of this size (the first ensemble's budget / div)")
+    ap.add_argument("--prv-grid", type=int, default=0, help="persistent blocks (0: capacity)")
+    ap.add_argument("--prv-spread", type=int, default=-1,
+                    help="queue head spread one wave per SIMD (-1: the first ensemble)")
     ap.add_argument("--sur-train", type=int, default=512)
     ap.add_argument("--sur-screen", type=int, default=4096)
     ap.add_argument("--sur-phases", type=int, default=1024)

@@ -262,6 +262,16 @@ typedef struct {
                          step's cubic Hermite interpolant (f at both ends:
                          free with RKDP45, two evaluations with RKCK45) by
                          bisection; other models: ENS_E_UNSUPPORTED        */
+  int32_t reserved_;  /* must be 0                                           */
+  int64_t spread;     /* RKCK45/RKDP45 launch: the first `spread` positions
+                         of the queue order (the longest systems, e.g. the
+                         largest-budget sub-ensemble first in index order,
+                         or after ens_order_by_work) are handed to the
+                         first wave slot of each SIMD and the rest to the
+                         others, so that long systems start one per SIMD
+                         instead of sharing one; either group takes from the
+                         other once its own is empty.  Results do not depend
+                         on it.  0 = one queue; 0 <= spread <= n           */
 } ens_solve_opts;
 
 /* Fills opts with the defaults: dt 0.01, n_steps 1000, t_phase 1, dt0 1e-2,

@@ -467,7 +467,7 @@ int ens_create(const ens_desc *d, ens_t *out) {
   if (e == hipSuccess && h->solver != ENS_RK4) {
     e = dalloc(&h->d_stats, (size_t)ENS_NSTAT * n);
     if (e == hipSuccess) e = dalloc(&h->d_status, n);
-    if (e == hipSuccess) e = dalloc(&h->d_queue, 1);
+    if (e == hipSuccess) e = dalloc(&h->d_queue, 2);
     if (e == hipSuccess) e = dalloc(&h->d_desc, ENS_MAX_ENSEMBLES);
     if (e == hipSuccess && (h->model == ENS_KM || h->model == ENS_KM6)) e = dalloc(&h->d_phi, n);
   }
@@ -631,6 +631,8 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     return fail(h, ENS_E_INVAL, "ens_solve: bad phase, record or step counts");
   if (o->max_steps > (int64_t)UINT32_MAX)
     return fail(h, ENS_E_INVAL, "ens_solve: max_steps above 2^32");
+  if (o->spread < 0 || o->spread > h->n || o->reserved_ != 0)
+    return fail(h, ENS_E_INVAL, "ens_solve: spread must be in [0, n], reserved_ 0");
   if (o->locate_max && h->tangent)
     return fail(h, ENS_E_UNSUPPORTED, "ens_solve: locate_max is not built with the tangent");
   if (o->locate_max && h->model != ENS_KM && h->model != ENS_KM6)
@@ -718,6 +720,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   a.stats = h->d_stats;
   a.status = h->d_status;
   a.queue = h->d_queue;
+  a.spread = o->spread;
   a.order = h->use_order ? h->d_order : nullptr;
   a.desc = h->d_desc;
   a.n = h->n;
@@ -739,7 +742,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   const bool fill_h = !h->h_init;
 
   auto enqueue = [&](hipStream_t s) -> hipError_t {
-    hipError_t e = ens::launch_fill_u64(h->d_queue, 0ull, 1, s);
+    hipError_t e = ens::launch_fill_u64(h->d_queue, 0ull, 2, s);
     if (e == hipSuccess && rec_count)
       e = ens::launch_fill_f64(h->d_rec, std::numeric_limits<double>::quiet_NaN(),
                                (int64_t)rec_count, s);

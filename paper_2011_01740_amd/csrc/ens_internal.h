@@ -36,7 +36,8 @@ struct RkckArgs {
   double *rec;              // [R][F][n] or null
   int64_t *stats;           // [ENS_NSTAT][n]
   int32_t *status;          // [n]
-  unsigned long long *queue;// next unclaimed queue position
+  unsigned long long *queue;// [2]: positions taken from the rest, from the head
+  int64_t spread;           // head [0, spread) of the queue order: one wave per SIMD
   const int64_t *order;     // [n] system taken at each queue position, or null
   const EnsDesc *desc;      // [n_ens]
   int64_t n;

@@ -83,6 +83,22 @@ __device__ __forceinline__ double rcp_nr(double d) {
   return r;
 }
 
+// sqrt(x) for the valve's chamber pressure: r = v_rsq_f64 (relative error
+// ~2^-23), one coupled Newton step on g = x r and h = r/2 (~2^-46), one
+// residual correction g + (x - g^2) h: within an ulp of the correctly
+// rounded root for normal x, in 8 dependent VALU against 17 for the library
+// sqrt, which also rescales tiny and huge arguments (not needed here: the
+// pressure stays O(1..10)).  x < 0 gives NaN like sqrt; x == 0 gives 0.
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  double g = x * r, h = 0.5 * r;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  g = fma(fma(-g, g, x), h, g);
+  return x == 0.0 ? x : g;
+}
+
 // x^(-1/5) for x in [1e-30, 1e30]: an FP32 estimate r0 from the hardware
 // base-2 logarithm and exponential (relative error ~1e-7), then in FP64 with
 // e = 1 - x r0^5 the series r = r0 (1 - e)^(-1/5) = r0 (1 + e/5 + 3 e^2/25
@@ -422,7 +438,7 @@ struct MPRV {
     } else {
       f[0] = y[1];
       f[1] = fma(-kappa, y[1], y[2] - (y[0] + delta));
-      f[2] = beta * fma(-y[0], sqrt(y[2]), q);
+      f[2] = beta * fma(-y[0], sqrt_nr(y[2]), q);
     }
   }
 };
@@ -549,6 +565,7 @@ struct Lane {
   float rem;           // estimated attempts left: last phase's x phases left
   uint32_t nrhs;       // Dormand--Prince: RHS evaluations (6 or 7 per attempt)
   int32_t status, ev_iter;
+  bool head;           // taken from the spread head of the queue
 };
 
 // Dormand--Prince: k1 = f(t, y) of the next attempt, valid when `have`.  An
@@ -861,19 +878,38 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
   double y[D];
   bool active = false;
   bool drained = false;
+  // Two queues over the positions of the queue order: the head [0, spread)
+  // and the rest [spread, n), each with its own counter.  The wave in slot 0
+  // of its SIMD (one per SIMD, from the hardware id) prefers the head, all
+  // others the rest; a wave takes from the other queue once its own is
+  // empty.  Systems at the head (the longest) thus start one wave per SIMD
+  // instead of sharing a SIMD with each other.
+  const uint64_t spread = (uint64_t)a.spread, nsys = (uint64_t)a.n;
+  const bool slot0 = (__builtin_amdgcn_s_getreg((3 << 11) | 4) & 0xF) == 0;  // HW_ID.WAVE_ID
+  bool head_done = spread == 0, rest_done = spread >= nsys;
+  bool head_prio = false;  // the wave raised its issue priority for head systems
 
   while (true) {
     const unsigned long long idle = __ballot(!active);
     const int n_idle = __popcll(idle);
     if (!drained && n_idle > 0 && (n_idle >= a.refill || idle == ~0ull)) {
+      const bool use_head = !head_done && (slot0 || rest_done);
       const int leader = __ffsll((long long)idle) - 1;
       unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)n_idle);
+      if (lane == leader) base = atomicAdd(a.queue + (use_head ? 1 : 0), (unsigned long long)n_idle);
       base = __shfl(base, leader);
-      if (base + (unsigned long long)n_idle >= (unsigned long long)a.n) drained = true;
+      const uint64_t first = use_head ? 0 : spread, limit = use_head ? spread : nsys - spread;
+      if (base + (unsigned long long)n_idle >= limit) {
+        if (use_head)
+          head_done = true;
+        else
+          rest_done = true;
+      }
+      drained = head_done && rest_done;
       if (!active) {
-        const unsigned long long me = base + (unsigned long long)__popcll(idle & below);
-        if (me < (unsigned long long)a.n) {
+        const unsigned long long k = base + (unsigned long long)__popcll(idle & below);
+        const unsigned long long me = first + k;
+        if (k < limit) {
           const int64_t i = a.order ? a.order[me] : (int64_t)me;
           int e = 0;
           while (e + 1 < a.n_ens && i >= sdesc[e].last) ++e;
@@ -897,6 +933,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
           L.status = 0;
           L.ev_iter = 0;
           L.nrhs = 0;
+          L.head = use_head;
           fs.have = false;
           active = true;
           if (L.n_phases <= 0) {
@@ -904,6 +941,19 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
             if constexpr (M::kDrive2) a.phi2[i] = m.phi;
             active = false;
           }
+        }
+      }
+      // A wave that carries head systems raises its issue priority, so that
+      // the long systems are not slowed by short ones sharing the SIMD (models
+      // without their own remaining-work priority; results do not change).
+      if constexpr (!M::kPrio) {
+        const bool want = spread > 0 && __ballot(active && L.head) != 0ull;
+        if (want != head_prio) {
+          head_prio = want;
+          if (want)
+            __builtin_amdgcn_s_setprio(3);
+          else
+            __builtin_amdgcn_s_setprio(0);
         }
       }
     }

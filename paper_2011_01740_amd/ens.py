@@ -49,7 +49,7 @@ class ens_solve_opts(C.Structure):
                 ("n_phases", C.c_int64), ("n_record", C.c_int64), ("max_steps", C.c_int64),
                 ("max_event_iter", C.c_int32), ("block", C.c_int32), ("spl", C.c_int32),
                 ("refill", C.c_int32), ("grid", C.c_int32), ("use_graph", C.c_int32),
-                ("locate_max", C.c_int32)]
+                ("locate_max", C.c_int32), ("reserved_", C.c_int32), ("spread", C.c_int64)]
 
 
 _lib = None

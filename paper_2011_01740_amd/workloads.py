@@ -166,12 +166,17 @@ def prv_inputs(ensembles=PRV_ENSEMBLES):
 
 
 def prv_batched(ensembles=PRV_ENSEMBLES, n_record: int = 32, use_graph: int = 1,
-                solver: Optional[int] = None, **launch) -> Result:
+                solver: Optional[int] = None, spread: Optional[int] = None,
+                **launch) -> Result:
     """Relief-valve ensembles (size, budget K, seed): each system runs until K
     Poincare phases or K impacts, whichever comes first; the last n_record
-    phases (y1max, y1min) are kept.  One persistent launch for all."""
+    phases (y1max, y1min) are kept.  One persistent launch for all.  spread
+    (default: the first ensemble, which holds the largest budget): queue head
+    handed out one wave per SIMD."""
     P, y0, off = prv_inputs(ensembles)
     budgets = [(K, K) for _, K, _ in ensembles]
+    if spread is None:
+        spread = ensembles[0][0] if len(ensembles) > 1 else 0
     o = ens.default_opts(n_phases=max(K for _, K, _ in ensembles), n_record=n_record,
-                         use_graph=use_graph, **launch)
+                         use_graph=use_graph, spread=spread, **launch)
     return _adaptive(ens.ENS_PRV, P, y0, o, offsets=off, budgets=budgets, solver=solver)

@@ -46,7 +46,7 @@ def test_default_opts_are_the_documented_readings():
 
 def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(ens.ens_desc) == 48
-    assert ctypes.sizeof(ens.ens_solve_opts) == 144
+    assert ctypes.sizeof(ens.ens_solve_opts) == 152
 
 
 def test_create_validates_before_touching_the_device():

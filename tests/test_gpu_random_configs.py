@@ -1,7 +1,7 @@
 """Seeded random configurations of the adaptive solvers against the oracle:
 model, scheme, size, tolerances, phase length, ring length (also longer than
 the run), step cap, located maxima, tangent, second drive, and launch shape
-(block, refill threshold, grid), each drawn per case.  Parity is checked on
+(block, refill threshold, grid, spread head), each drawn per case.  Parity is checked on
 the systems whose oracle result is insensitive to a 1e-13 perturbation of
 the initial state; on those, state, records, status, phases and (for >= 95%)
 step counts must agree."""
@@ -33,7 +33,8 @@ def draw(seed):
     if model in (2, 6) and not c.get("tangent"):
         o["locate_max"] = int(rng.random() < 0.3)
     c["launch"] = dict(block=int(rng.choice([64, 128, 192, 256])),
-                       refill=int(rng.choice([1, 7, 64])), grid=int(rng.choice([0, 1, 3])))
+                       refill=int(rng.choice([1, 7, 64])), grid=int(rng.choice([0, 1, 3])),
+                       spread=int(rng.choice([0, n // 3, n])))
     # inputs
     if model == 0:
         P, y0 = I.quad_linspace(n, 0.1, 1.0)

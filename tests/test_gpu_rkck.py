@@ -373,3 +373,36 @@ def test_km_sweep_records_come_back_in_phase_order():
     ref = O.rkck45(O.KM, P, I.KM_WATER, y0, o, nthreads=8)
     ok = close(b.records, ref.records[12:], CK_RTOL, CK_ATOL)
     assert ok.mean() > 0.9
+
+
+def test_spread_head_does_not_change_results():
+    """Queue positions [0, spread) go to the first wave slot of each SIMD:
+    only the placement changes, not a bit of any result."""
+    ens = _ens()
+    # valve batch: the largest-budget sub-ensemble first
+    Ps, ys, off = [], [], [0]
+    for m, seed in ((700, 3), (1500, 4), (2600, 5)):
+        P, y0 = I.prv_random(m, seed=seed)
+        Ps.append(P)
+        ys.append(y0)
+        off.append(off[-1] + m)
+    P, y0 = np.concatenate(Ps, axis=1), np.concatenate(ys, axis=1)
+    budgets = [(60, 60), (12, 12), (3, 3)]
+    o = O.Opts(n_phases=60, n_record=4)
+    sh = [list(I.PRV_DEFAULT)] * 3
+    ref = gpu_ck(3, P, y0, o, shared=sh, offsets=off, budgets=budgets)
+    for spread in (700, 1, off[-1]):
+        g = gpu_ck(3, P, y0, o, shared=sh, offsets=off, budgets=budgets, spread=spread)
+        # (slots of phases a short-budget system never reached hold NaN)
+        assert np.array_equal(g.y, ref.y)
+        assert np.array_equal(g.records, ref.records, equal_nan=True)
+        assert np.array_equal(g.stats, ref.stats) and np.array_equal(g.status, ref.status)
+    # Keller--Miksis, spread over a small grid and a single block
+    P, y0 = I.km_grid(12, 12)
+    o = O.Opts(n_phases=3, n_record=3)
+    ref = gpu_ck(2, P, y0, o)
+    for launch in (dict(spread=50), dict(spread=144, grid=1), dict(spread=7, block=64, refill=5)):
+        g = gpu_ck(2, P, y0, o, **launch)
+        assert np.array_equal(g.y, ref.y) and np.array_equal(g.records, ref.records)
+    with pytest.raises(ens.EnsError):
+        gpu_ck(2, P, y0, o, spread=145)
