@@ -57,7 +57,7 @@ class Opts:
     max_event_iter: int = 20
     scheme: int = 0                 # CASH_KARP or DORMAND_PRINCE
     locate_max: int = 0             # KM: maxima located on the step interpolant
-    lyapunov: int = 0               # variational equation + per-phase renormalisation
+    lyapunov: int = 0               # tangents of the variational equation (Lyapunov)
 
     def _c(self) -> _Opts:
         o = _Opts()
@@ -185,7 +185,7 @@ def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, 
     """Adaptive solve of an ensemble through its phases with the scheme of
     opts.scheme (Cash--Karp by default).  phi0 (Keller--Miksis): the second
     drive's phase in cycles at the start of the current phase (0 if None)."""
-    D = dim(model) * (2 if opts.lyapunov else 1)
+    D = dim(model) * (1 + int(opts.lyapunov))
     y0 = _f64(y0)
     n = y0.shape[-1]
     y0 = y0.reshape(D, n)
@@ -195,7 +195,7 @@ def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, 
     h0 = None if h0 is None else _f64(h0).reshape(n)
     phi0 = None if phi0 is None else _f64(phi0).reshape(n)
     R = int(opts.n_record)
-    F = 2 if opts.lyapunov else nrec_fields(model)
+    F = 1 + int(opts.lyapunov) if opts.lyapunov else nrec_fields(model)
     y = np.empty((D, n))
     t = np.empty(n)
     h = np.empty(n)

@@ -61,7 +61,8 @@
 #include <omp.h>
 #endif
 
-#define MAXD 8   /* state dimension, the tangent included */
+#define MAXD 12  /* state dimension, the tangents included (Lorenz: 3 + 3 x 3) */
+#define MAXDB 3  /* a model's own dimension */
 
 int orc_dim(int model) {
   switch (model) {
@@ -139,9 +140,10 @@ void orc_km_coeffs(const double *p, const double *sh, double *C) {
 
 typedef struct {
   int model;
-  int D;           /* integrated dimension: Db, or 2 Db with the tangent      */
+  int D;           /* integrated dimension: Db (1 + tangent)                  */
   int Db;          /* the model's own dimension                            */
-  int tangent;     /* the variational equation rides along (Lyapunov)      */
+  int tangent;     /* tangent vectors of the variational equation riding
+                      along (Lyapunov exponents), 0 .. Db                  */
   double p[6];     /* per-system parameters                                */
   const double *sh;/* shared parameters                                    */
   double C[13];    /* Keller--Miksis coefficients                          */
@@ -287,13 +289,14 @@ static void rhs(const sysctx *s, double t, const double *y, double *f) {
   rhs_base(s, t, y, f);
   if (s->tangent) {
     const int Db = s->Db;
-    double J[(MAXD / 2) * (MAXD / 2)];
+    double J[MAXDB * MAXDB];
     jacobian(s, t, y, J);
-    for (int i = 0; i < Db; ++i) {
-      double acc = 0.0;
-      for (int j = 0; j < Db; ++j) acc += J[i * Db + j] * y[Db + j];
-      f[Db + i] = acc;
-    }
+    for (int v = 1; v <= s->tangent; ++v)
+      for (int i = 0; i < Db; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < Db; ++j) acc += J[i * Db + j] * y[v * Db + j];
+        f[v * Db + i] = acc;
+      }
   }
 }
 
@@ -523,6 +526,15 @@ static void put_record(double *records, int64_t n, int F, int64_t R, int64_t pha
   if (F > 1) records[(slot * F + 1) * n + i] = ymin;
 }
 
+/* The record fields after the first with the tangents: the phase's log
+ * growth of each tangent after Gram--Schmidt. */
+static void put_growth(double *records, int64_t n, int F, int64_t R, int64_t phase, int64_t i,
+                       const double *g, int k) {
+  if (!records || R <= 0) return;
+  const int64_t slot = phase % R;
+  for (int v = 0; v < k; ++v) records[(slot * F + 1 + v) * n + i] = g[v];
+}
+
 /* Dense output of a step from (t, y0) to (t + h, y1) with derivatives f0,
  * f1 at its ends: the cubic Hermite interpolant, component c at theta in
  * [0, 1]. */
@@ -554,8 +566,8 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
                       double *records, int64_t n, int64_t i, int64_t st[ORC_NSTAT],
                       int32_t *status) {
   const int D = s->D;
-  /* with the tangent, the second record field is the phase's log growth */
-  const int F = s->tangent ? 2 : orc_nrec_fields(s->model);
+  /* with k tangents the record fields 1 .. k are the phase's log growths */
+  const int F = s->tangent ? 1 + s->tangent : orc_nrec_fields(s->model);
   const int Db = s->Db;            /* the model's own components      */
   const int fixed_len = (s->model != ORC_PRV);
   const double tol_ev = o->event_tol;
@@ -735,16 +747,31 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
       have_k1 = 0;   /* every phase starts with k1 evaluated (the clock resets) */
       /* the phase ends exactly at t_phase; next phase from 0 with the
        * untruncated proposal h */
-      double growth = ymin;
+      double growth[MAXDB];
       if (s->tangent) {
-        /* Lyapunov renormalisation: record log |dy| and rescale dy to 1 */
-        double nrm2 = 0.0;
-        for (int c = Db; c < D; ++c) nrm2 += y[c] * y[c];
-        const double nrm = sqrt(nrm2);
-        growth = log(nrm);
-        for (int c = Db; c < D; ++c) y[c] = y[c] / nrm;
+        /* Lyapunov renormalisation (Benettin et al.): Gram--Schmidt on the
+         * tangents in order, each first made orthogonal to the ones before
+         * it and then scaled to unit length; its log length before the
+         * scaling is the phase's growth along that direction */
+        for (int v = 1; v <= s->tangent; ++v) {
+          double *w = y + v * Db;
+          for (int u = 1; u < v; ++u) {
+            const double *q = y + u * Db;
+            double dot = 0.0;
+            for (int c = 0; c < Db; ++c) dot += q[c] * w[c];
+            for (int c = 0; c < Db; ++c) w[c] = w[c] - dot * q[c];
+          }
+          double nrm2 = 0.0;
+          for (int c = 0; c < Db; ++c) nrm2 += w[c] * w[c];
+          const double nrm = sqrt(nrm2);
+          growth[v - 1] = log(nrm);
+          for (int c = 0; c < Db; ++c) w[c] = w[c] / nrm;
+        }
+        put_record(records, n, F, o->n_record, phase, i, ymax, 0.0);
+        put_growth(records, n, F, o->n_record, phase, i, growth, s->tangent);
+      } else {
+        put_record(records, n, F, o->n_record, phase, i, ymax, ymin);
       }
-      put_record(records, n, F, o->n_record, phase, i, ymax, growth);
       phase++;
       st[ORC_ST_PHASES] = phase;
       ymax = -INFINITY;
@@ -777,7 +804,8 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
   if (model != ORC_PRV && !(opt->t_phase > 0.0)) return -1;
   if (opt->locate_max && model != ORC_KM && model != ORC_KM6) return -1;
   if (opt->lyapunov && (model == ORC_PRV || opt->locate_max)) return -1;
-  const int Dint = opt->lyapunov ? 2 * D : D;   /* integrated dimension */
+  if (opt->lyapunov < 0 || opt->lyapunov > D || (D > MAXDB && opt->lyapunov)) return -1;
+  const int Dint = D * (1 + opt->lyapunov);   /* integrated dimension */
   if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
   for (int64_t i = 0; i < n; ++i) {
@@ -786,7 +814,7 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
     sysctx s;
     ctx_init(&s, model, p, shared);
     if (opt->lyapunov) {
-      s.tangent = 1;
+      s.tangent = opt->lyapunov;
       s.D = Dint;
     }
     s.phi2 = phi0 ? phi0[i] : 0.0;

@@ -93,12 +93,13 @@ typedef struct {
   int32_t scheme;    /* ORC_CASH_KARP or ORC_DORMAND_PRINCE                  */
   int32_t locate_max; /* KM: also take y1 where y2 falls through 0 inside a
                          step, on the step's cubic Hermite interpolant       */
-  int32_t lyapunov;  /* fixed-length phases: integrate the variational
-                        equation d(dy)/dt = J(t, y) dy along (error control
-                        on both y and dy); the state is then
-                        [y; dy] (2D components), at every phase end dy is
-                        rescaled to unit length and the record's second
-                        field is log |dy| before the rescaling            */
+  int32_t lyapunov;  /* fixed-length phases: k = lyapunov tangents (0 .. D)
+                        of the variational equation d(dv)/dt = J(t, y) dv
+                        ride along (error control on everything); the
+                        state is [y; v_1; ...; v_k] (D (1 + k) components);
+                        at every phase end the tangents are orthonormalised
+                        in order (Gram--Schmidt) and record fields 1 .. k
+                        hold the log lengths before the scaling          */
 } orc_opts;
 
 /* Adaptive schemes: Cash--Karp 5(4) (six stages) and Dormand--Prince 5(4)
@@ -122,9 +123,10 @@ int orc_nrec_fields(int model);
  *    would try, and the second drive's phase (KM; passing all four back
  *    resumes the solve).
  *  records [n_record][F][n]: a ring, phase k of this call in slot
- *    k % n_record; F = 2 with opt->lyapunov (y1max, log growth).
- *  With opt->lyapunov, y0 and y_out are [2D][n]: the state, then the
- *    tangent vector.  stats [ORC_NSTAT][n], status [n].  Any output pointer may
+ *    k % n_record; F = 1 + k with k = opt->lyapunov tangents (y1max, then
+ *    their log growths).
+ *  With k tangents, y0 and y_out are [D (1 + k)][n]: the state, then the
+ *    tangent vectors.  stats [ORC_NSTAT][n], status [n].  Any output pointer may
  *    be NULL.
  */
 /* Jacobian d f_i / d y_j of a model's right-hand side at (t, y), row-major

@@ -135,3 +135,44 @@ def test_lyapunov_rejects_events_and_located_maxima():
     with pytest.raises(ValueError):
         O.rkck45(O.KM, np.array([[1e5], [50e3]]), I.KM_WATER, np.ones((4, 1)),
                  O.Opts(n_phases=1, lyapunov=1, locate_max=1))
+
+
+def test_spectrum_at_a_fixed_point_is_the_qr_of_the_propagator():
+    # Lorenz origin (rho < 1) and undriven Keller--Miksis at rest: with k = D
+    # tangents from an orthonormal V0, one phase's log growths are log |R_jj|
+    # of the QR factorisation of expm(J t_phase) V0 (one phase, so that the
+    # fastest-contracting direction is still resolved in double precision);
+    # over several phases they sum to trace(J) T (the frame's volume)
+    V0 = np.linalg.qr(np.array([[1.0, 0.3, -0.2], [0.4, 1.0, 0.1], [-0.5, 0.2, 1.0]]))[0]
+    y = np.concatenate([[0.0, 0.0, 0.0], V0.T.ravel()]).reshape(-1, 1)
+    J = O.jacobian(O.LORENZ, 0.0, [0.0, 0.0, 0.0], [0.5], LOR)
+    o = O.Opts(n_phases=1, n_record=1, rtol=1e-12, atol=1e-12, lyapunov=3)
+    r = O.rkck45(O.LORENZ, np.array([[0.5]]), LOR, y, o)
+    R = np.linalg.qr(expm(J) @ V0)[1]
+    np.testing.assert_allclose(r.records[0, 1:, 0], np.log(np.abs(np.diag(R))), atol=1e-8)
+    o5 = O.Opts(n_phases=5, n_record=5, rtol=1e-12, atol=1e-12, lyapunov=3)
+    r = O.rkck45(O.LORENZ, np.array([[0.5]]), LOR, y, o5)
+    assert r.records[:, 1:, 0].sum() == pytest.approx(np.trace(J) * 5.0, rel=1e-9)
+    V0 = np.array([[0.6, 0.8], [-0.8, 0.6]])
+    y = np.concatenate([[1.0, 0.0], V0.T.ravel()]).reshape(-1, 1)
+    J = O.jacobian(O.KM, 0.0, [1.0, 0.0], [0.0, 50e3], I.KM_WATER)
+    o2 = O.Opts(n_phases=4, n_record=4, rtol=1e-12, atol=1e-12, lyapunov=2)
+    r = O.rkck45(O.KM, np.array([[0.0], [50e3]]), I.KM_WATER, y, o2)
+    R = np.linalg.qr(expm(J * 4.0) @ V0)[1]
+    np.testing.assert_allclose(r.records[:, 1:, 0].sum(axis=0), np.log(np.abs(np.diag(R))),
+                               atol=1e-8)
+
+
+def test_lorenz_spectrum_sums_to_the_trace():
+    # Liouville: the volume of the tangent frame grows by the integral of
+    # trace J = -(sigma + 1 + beta) per unit time, exactly; on the attractor
+    # the middle exponent (along the flow) is zero
+    o = O.Opts(n_phases=300, n_record=300, lyapunov=3, dt_max=0.05)
+    y = np.concatenate([[1.0, 1.0, 20.0], np.eye(3).ravel()]).reshape(-1, 1)
+    r = O.rkck45(O.LORENZ, np.array([[28.0]]), LOR, y, o)
+    per_phase = r.records[:, 1:, 0].sum(axis=1)
+    tr = -(10.0 + 1.0 + 8.0 / 3.0)
+    assert np.abs(per_phase - tr).max() < 1e-3 * abs(tr)
+    assert per_phase.mean() == pytest.approx(tr, rel=1e-6)
+    lam = r.records[50:, 1:, 0].mean(axis=0)
+    assert abs(lam[0] - 0.9056) < 0.05 and abs(lam[1]) < 0.03, lam
