@@ -144,17 +144,19 @@ typedef struct {
                              0 to n; NULL means one ensemble [0, n)          */
   void *hip_stream;       /* hipStream_t to enqueue on; NULL = null stream   */
   int32_t tangent;        /* adaptive solvers, fixed-length-phase models
-                             (QUAD, LORENZ, KM, KM6): integrate the
-                             variational equation d(dy)/dt = J(t, y) dy
-                             along with each system, for its largest
-                             Lyapunov exponent.  The state becomes [2D][n]
-                             (y, then the tangent dy; the caller sets the
-                             initial dy), both under error control; at every
-                             phase end dy is rescaled to unit length and the
-                             record gains a second field, log |dy| before the
-                             rescaling (F = 2).  The exponent over recorded
-                             phases k is sum_k record[k][1] / (their number
-                             x t_phase).  This is the per-phase trajectory
+                             (QUAD, LORENZ, KM, KM6): K = tangent vectors
+                             (0 .. D) of the variational equation
+                             d(v)/dt = J(t, y) v integrated along with each
+                             system, for its K largest Lyapunov exponents.
+                             The state becomes [D (1 + K)][n] (y, then
+                             v_1 .. v_K; the caller sets the initial
+                             tangents), all under error control; at every
+                             phase end the tangents are orthonormalised in
+                             order (Gram--Schmidt) and the record gains K
+                             fields, the log length of each before its
+                             scaling (F = 1 + K).  Exponent j over recorded
+                             phases k: sum_k record[k][j] / (their number x
+                             t_phase).  This is the per-phase trajectory
                              manipulation (renormalisation) of the paper's
                              introduction, done inside the solve.  0 = off */
   int32_t reserved_;      /* must be 0                                       */

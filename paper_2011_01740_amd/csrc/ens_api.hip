@@ -36,7 +36,7 @@ using ens::EnsDesc;
 
 struct ens_ctx {
   int model = 0, solver = 0;
-  bool tangent = false;  // variational equation along (mi.D and mi.F include it)
+  int tangent = 0;  // tangents of the variational equation (mi.D, mi.F include them)
   ens::ModelInfo mi{};
   int64_t n = 0;
   int n_ens = 1;
@@ -421,8 +421,8 @@ int ens_create(const ens_desc *d, ens_t *out) {
       return fail(nullptr, ENS_E_INVAL, "ens_create: offsets required for n_ensembles > 1");
     off = {0, d->n};
   }
-  if (d->tangent != 0 && d->tangent != 1)
-    return fail(nullptr, ENS_E_INVAL, "ens_create: tangent must be 0 or 1");
+  if (d->tangent < 0 || d->tangent > 3)
+    return fail(nullptr, ENS_E_INVAL, "ens_create: tangent must be in [0, D]");
   if (d->tangent && (d->solver == ENS_RK4 || d->model == ENS_PRV))
     return fail(nullptr, ENS_E_UNSUPPORTED,
                 "ens_create: tangent is built for the adaptive solvers with fixed-length phases");
@@ -437,10 +437,14 @@ int ens_create(const ens_desc *d, ens_t *out) {
   h->model = d->model;
   h->solver = d->solver;
   h->mi = ens::model_info(d->model);
-  h->tangent = d->tangent != 0;
-  if (h->tangent) {  // state [y; dy], records (y1max, log growth)
-    h->mi.D *= 2;
-    h->mi.F = 2;
+  h->tangent = d->tangent;
+  if (h->tangent > h->mi.D) {
+    delete h;
+    return fail(nullptr, ENS_E_INVAL, "ens_create: more tangents than the model's dimension");
+  }
+  if (h->tangent) {  // state [y; v_1 .. v_K], records (y1max, K log growths)
+    h->mi.D *= 1 + h->tangent;
+    h->mi.F = 1 + h->tangent;
   }
   h->n = d->n;
   h->n_ens = d->n_ensembles;
@@ -667,7 +671,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     for (int e = 0; e < h->n_ens; ++e)
       if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM6_GENERAL;
   }
-  if (h->tangent) kmodel += ens::kTangentModel;
+  if (h->tangent) kmodel += h->tangent * ens::kTangentModel;
   int grid = o->grid;
   const int cap = ens::rkck_max_blocks(kmodel, h->solver, o->locate_max != 0, block);
   if (cap <= 0) return fail(h, ENS_E_HIP, "ens_solve: occupancy query failed");

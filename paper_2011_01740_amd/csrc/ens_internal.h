@@ -59,7 +59,8 @@ constexpr int ENS_KM_GENERAL = 100;
 constexpr int ENS_KM_DUAL = 101;       // general arithmetic + second drive
 constexpr int ENS_KM_DUAL_FAST = 102;  // fast arithmetic + second drive
 constexpr int ENS_KM6_GENERAL = 103;   // ENS_KM6 on the general arithmetic
-// Added to any of the above: the same model with its variational equation.
+// K x kTangentModel added to any of the above: the same model with K
+// tangents of its variational equation.
 constexpr int kTangentModel = 1000;
 
 // Kernel launchers (stream-ordered; return hipSuccess or the launch error).

@@ -140,12 +140,14 @@ struct MQuad {  // dx/dt = x^2 - p (Sec. 3)
   __device__ void rhs(double, double, const double *y, double *f) const {
     f[0] = fma(y[0], y[0], -p);
   }
-  // with the variational equation: df = J dy, J = 2x
-  template <int SC, int S>
+  // with K tangents of the variational equation: df_v = J dy_v, J = 2x
+  template <int SC, int S, int K>
   __device__ void rhs_tan(double t, double h, const double *y, const double *dy, double *f,
                           double *df) const {
     rhs<SC, S>(t, h, y, f);
-    df[0] = 2.0 * y[0] * dy[0];
+    const double j = 2.0 * y[0];
+#pragma unroll
+    for (int v = 0; v < K; ++v) df[v] = j * dy[v];
   }
 };
 
@@ -171,14 +173,21 @@ struct MLorenz {  // Sec. 4.1
     f[1] = fma(-y[0], y[2], fma(rho, y[0], -y[1]));
     f[2] = fma(y[0], y[1], -beta * y[2]);
   }
-  // J = [[-sigma, sigma, 0], [rho - z, -1, -x], [y, x, -beta]]
-  template <int SC, int S>
+  // J = [[-sigma, sigma, 0], [rho - z, -1, -x], [y, x, -beta]], applied to
+  // each of the K tangents
+  template <int SC, int S, int K>
   __device__ void rhs_tan(double t, double h, const double *y, const double *dy, double *f,
                           double *df) const {
     rhs<SC, S>(t, h, y, f);
-    df[0] = sigma * (dy[1] - dy[0]);
-    df[1] = fma(rho - y[2], dy[0], fma(-y[0], dy[2], -dy[1]));
-    df[2] = fma(y[1], dy[0], fma(y[0], dy[1], -beta * dy[2]));
+    const double rz = rho - y[2];
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      const double *d = dy + 3 * v;
+      double *g = df + 3 * v;
+      g[0] = sigma * (d[1] - d[0]);
+      g[1] = fma(rz, d[0], fma(-y[0], d[2], -d[1]));
+      g[2] = fma(y[1], d[0], fma(y[0], d[1], -beta * d[2]));
+    }
   }
 };
 
@@ -298,15 +307,15 @@ struct MKM {
   // SC: the scheme; S: the stage (1..7); tau: its time; h: the attempted step.
   template <int SC, int S>
   __device__ void rhs(double tau, double h, const double *y, double *f) {
-    eval<SC, S, false>(tau, h, y, nullptr, f, nullptr);
+    eval<SC, S, 0>(tau, h, y, nullptr, f, nullptr);
   }
   // With the variational equation: df = J dy from the same intermediates.
-  template <int SC, int S>
+  template <int SC, int S, int K>
   __device__ void rhs_tan(double tau, double h, const double *y, const double *dy, double *f,
                           double *df) {
-    eval<SC, S, true>(tau, h, y, dy, f, df);
+    eval<SC, S, K>(tau, h, y, dy, f, df);
   }
-  template <int SC, int S, bool TAN>
+  template <int SC, int S, int K>
   __device__ __forceinline__ void eval(double tau, double h, const double *y, const double *dy,
                                        double *f, double *df) {
     const double y1 = y[0], y2 = y[1];
@@ -394,15 +403,18 @@ struct MKM {
     N = fma(-fc, y1, N);
     f[0] = y2;
     f[1] = N * (y1 * qd);
-    if constexpr (TAN) {
+    if constexpr (K > 0) {
       // f2 = N / D: d f2 / d y_j = (dN/dy_j - f2 dD/dy_j) / D, 1/D = y1 qd
       const double f2 = f[1], iD = y1 * qd;
       const double dN1 = fma(-K10 * fma(K1, y2, K0) * gas, r1, fma(fma(K4, y2, K3), r1 * r1, -fc));
       const double dN2 = fma(K1, gas, -K9 * fs) - K4 * r1 + y2 * fma(1.5 * K9, y2, -3.0);
       const double J21 = fma(-f2, fma(-K9, y2, 1.0), dN1) * iD;
       const double J22 = fma(f2 * K9, y1, dN2) * iD;
-      df[0] = dy[1];
-      df[1] = fma(J21, dy[0], J22 * dy[1]);
+#pragma unroll
+      for (int v = 0; v < K; ++v) {
+        df[2 * v] = dy[2 * v + 1];
+        df[2 * v + 1] = fma(J21, dy[2 * v], J22 * dy[2 * v + 1]);
+      }
     }
   }
 };
@@ -531,28 +543,46 @@ __device__ __forceinline__ double clampd(double x, double lo, double hi) {
 // largest Lyapunov exponent, done in the kernel).  The lane state is [y; dy]
 // (2 M::D components, all under error control); at a phase end dy is
 // rescaled to unit length and log |dy| becomes the phase's second record.
-template <class M>
+template <class M, int K>
 struct MTan : M {
   static_assert(!M::kEvents, "the tangent is built for fixed-length phases");
-  static constexpr int D = 2 * M::D;
-  static constexpr int kMinWaves = M::kMinWaves - 1;
+  static_assert(K >= 1 && K <= M::D, "1 .. D tangents");
+  static constexpr int D = M::D * (1 + K);
+  static constexpr int kMinWaves = M::kMinWaves > K + 1 ? M::kMinWaves - K : 2;
   static constexpr bool kLocate = false;
-  static constexpr int kF = 2;           // (y1max, log growth of the phase)
+  static constexpr int kF = 1 + K;       // (y1max, log growth of each tangent)
   static constexpr bool kTangent = true;
+  static constexpr int kK = K;
   template <int SC, int S>
   __device__ void rhs(double tau, double h, const double *y, double *f) {
-    M::template rhs_tan<SC, S>(tau, h, y, y + M::D, f, f + M::D);
+    M::template rhs_tan<SC, S, K>(tau, h, y, y + M::D, f, f + M::D);
   }
-  // Renormalisation at a phase end: returns log |dy|, leaves |dy| = 1.
-  __device__ double renormalise(double *y) const {
-    double s2 = 0.0;
+  // Renormalisation at a phase end (Gram--Schmidt in order): tangent v is
+  // made orthogonal to those before it, g[v] receives its log length, and
+  // it is scaled to unit length.
+  __device__ void renormalise(double *y, double *g) const {
+    constexpr int B = M::D;
 #pragma unroll
-    for (int c = M::D; c < D; ++c) s2 = fma(y[c], y[c], s2);
-    const double nrm = sqrt(s2);
-    const double inv = 1.0 / nrm;
+    for (int v = 0; v < K; ++v) {
+      double *w = y + B * (1 + v);
 #pragma unroll
-    for (int c = M::D; c < D; ++c) y[c] *= inv;
-    return log(nrm);
+      for (int u = 0; u < v; ++u) {
+        const double *q = y + B * (1 + u);
+        double dot = 0.0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) dot = fma(q[c], w[c], dot);
+#pragma unroll
+        for (int c = 0; c < B; ++c) w[c] = fma(-dot, q[c], w[c]);
+      }
+      double s2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < B; ++c) s2 = fma(w[c], w[c], s2);
+      const double nrm = sqrt(s2);
+      const double inv = 1.0 / nrm;
+#pragma unroll
+      for (int c = 0; c < B; ++c) w[c] *= inv;
+      g[v] = log(nrm);
+    }
   }
 };
 
@@ -593,6 +623,15 @@ __device__ __forceinline__ void store_record(const RkckArgs &a, const Lane &L, d
   const int64_t slot = (int64_t)(L.phase % (uint64_t)a.R);
   a.rec[(slot * F) * a.n + L.sys] = v0;
   if (F > 1) a.rec[(slot * F + 1) * a.n + L.sys] = v1;
+}
+
+// Record fields 1 .. K of a phase with tangents: their log growths.
+template <class M, int K>
+__device__ __forceinline__ void store_growth(const RkckArgs &a, const Lane &L, const double *g) {
+  if (a.R <= 0) return;
+  const int64_t slot = (int64_t)(L.phase % (uint64_t)a.R);
+#pragma unroll
+  for (int v = 0; v < K; ++v) a.rec[(slot * M::kF + 1 + v) * a.n + L.sys] = g[v];
 }
 
 template <class M, int SC>
@@ -709,10 +748,14 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
     L.ymax = y[0] > L.ymax ? y[0] : L.ymax;
     if (trunc) {
       fs.have = false;
-      if constexpr (M::kTangent)
-        store_record<M>(a, L, L.ymax, m.renormalise(y));
-      else
+      if constexpr (M::kTangent) {
+        double g[M::kK];
+        m.renormalise(y, g);
+        store_record<M>(a, L, L.ymax, g[0]);
+        store_growth<M, M::kK>(a, L, g);
+      } else {
         store_record<M>(a, L, L.ymax, 0.0);
+      }
       L.phase++;
       if constexpr (M::kPrio) note_phase_end(L);
       if constexpr (M::kDrive2) m.next_phase(a.t_phase);
@@ -1023,15 +1066,30 @@ struct Pick {
 template <class R, class Fn>
 R visit_model(int model, bool loc, R none, Fn &&fn) {
   if (model >= kTangentModel) {
-    switch (model - kTangentModel) {
-      case ENS_QUAD: return fn(Pick<MTan<MQuad>, false>{});
-      case ENS_LORENZ: return fn(Pick<MTan<MLorenz>, false>{});
-      case ENS_KM: return fn(Pick<MTan<MKM<true>>, false>{});
-      case ENS_KM_GENERAL: return fn(Pick<MTan<MKM<false>>, false>{});
-      case ENS_KM_DUAL: return fn(Pick<MTan<MKM<false, true>>, false>{});
-      case ENS_KM_DUAL_FAST: return fn(Pick<MTan<MKM<true, true>>, false>{});
-      case ENS_KM6: return fn(Pick<MTan<MKM<true, true, true>>, false>{});
-      case ENS_KM6_GENERAL: return fn(Pick<MTan<MKM<false, true, true>>, false>{});
+    const int K = model / kTangentModel, base = model % kTangentModel;
+    if (K == 1) {
+      switch (base) {
+        case ENS_QUAD: return fn(Pick<MTan<MQuad, 1>, false>{});
+        case ENS_LORENZ: return fn(Pick<MTan<MLorenz, 1>, false>{});
+        case ENS_KM: return fn(Pick<MTan<MKM<true>, 1>, false>{});
+        case ENS_KM_GENERAL: return fn(Pick<MTan<MKM<false>, 1>, false>{});
+        case ENS_KM_DUAL: return fn(Pick<MTan<MKM<false, true>, 1>, false>{});
+        case ENS_KM_DUAL_FAST: return fn(Pick<MTan<MKM<true, true>, 1>, false>{});
+        case ENS_KM6: return fn(Pick<MTan<MKM<true, true, true>, 1>, false>{});
+        case ENS_KM6_GENERAL: return fn(Pick<MTan<MKM<false, true, true>, 1>, false>{});
+      }
+    } else if (K == 2) {
+      switch (base) {
+        case ENS_LORENZ: return fn(Pick<MTan<MLorenz, 2>, false>{});
+        case ENS_KM: return fn(Pick<MTan<MKM<true>, 2>, false>{});
+        case ENS_KM_GENERAL: return fn(Pick<MTan<MKM<false>, 2>, false>{});
+        case ENS_KM_DUAL: return fn(Pick<MTan<MKM<false, true>, 2>, false>{});
+        case ENS_KM_DUAL_FAST: return fn(Pick<MTan<MKM<true, true>, 2>, false>{});
+        case ENS_KM6: return fn(Pick<MTan<MKM<true, true, true>, 2>, false>{});
+        case ENS_KM6_GENERAL: return fn(Pick<MTan<MKM<false, true, true>, 2>, false>{});
+      }
+    } else if (K == 3 && base == ENS_LORENZ) {
+      return fn(Pick<MTan<MLorenz, 3>, false>{});
     }
     return none;
   }

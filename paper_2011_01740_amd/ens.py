@@ -135,14 +135,14 @@ class Ensemble:
 
     def __init__(self, model: int, solver: int, n: int,
                  offsets: Optional[Sequence[int]] = None, device: int = 0, stream=None,
-                 tangent: bool = False):
+                 tangent: int = 0):
         L = load()
         self.model, self.solver, self.n = int(model), int(solver), int(n)
         # an unknown model is passed through: ens_create rejects it
         self.D, self.P, self.S, self.F = MODEL_DIMS.get(self.model, (0, 0, 0, 0))
-        self.tangent = bool(tangent)
-        if self.tangent:   # state [y; dy], records (y1max, log growth)
-            self.D, self.F = 2 * self.D, 2
+        self.tangent = int(tangent)   # tangent vectors (True = 1)
+        if self.tangent:   # state [y; v_1 .. v_K], records (y1max, K log growths)
+            self.D, self.F = self.D * (1 + self.tangent), 1 + self.tangent
         self.device = int(device)
         if stream is None:
             import torch
@@ -153,7 +153,7 @@ class Ensemble:
         d.model, d.solver, d.n = self.model, self.solver, self.n
         d.device = self.device
         d.hip_stream = self.stream_ptr
-        d.tangent = 1 if self.tangent else 0
+        d.tangent = self.tangent
         self._offs = None
         if offsets is not None:
             self._offs = (C.c_int64 * len(offsets))(*[int(v) for v in offsets])
