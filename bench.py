@@ -196,6 +196,8 @@ def run_case(case, args):
                 "accepted_per_s": float(r.stats[0].sum()) / r.kernel_ms * 1e3,
                 "rhs_per_s": float(r.stats[2].sum()) / r.kernel_ms * 1e3,
                 "attempts_max_over_mean": float(att.max() / max(att.mean(), 1e-30)),
+                "attempts_max": int(att.max()),
+                "us_per_attempt_longest": r.kernel_ms * 1e3 / max(int(att.max()), 1),
                 "launch": r.launch}
         if args.km_tangent:
             # largest Lyapunov exponent per system: mean log growth per unit tau

@@ -57,6 +57,7 @@ struct ens_ctx {
   int64_t *d_stats = nullptr;
   int32_t *d_status = nullptr;
   unsigned long long *d_queue = nullptr;
+  ens::RkckCold *d_cold = nullptr;   // the kernel's cold pointers, in device memory
   int64_t *d_order = nullptr;  // queue order (ens_set_order), valid if use_order
   bool use_order = false;
   EnsDesc *d_desc = nullptr;
@@ -472,6 +473,8 @@ int ens_create(const ens_desc *d, ens_t *out) {
     e = dalloc(&h->d_stats, (size_t)ENS_NSTAT * n);
     if (e == hipSuccess) e = dalloc(&h->d_status, n);
     if (e == hipSuccess) e = dalloc(&h->d_queue, 2);
+    if (e == hipSuccess)
+      e = hipMalloc((void **)&h->d_cold, sizeof(ens::RkckCold));
     if (e == hipSuccess) e = dalloc(&h->d_desc, ENS_MAX_ENSEMBLES);
     if (e == hipSuccess && (h->model == ENS_KM || h->model == ENS_KM6)) e = dalloc(&h->d_phi, n);
   }
@@ -503,6 +506,7 @@ int ens_destroy(ens_t h) {
   (void)hipFree(h->d_stats);
   (void)hipFree(h->d_status);
   (void)hipFree(h->d_queue);
+  (void)hipFree(h->d_cold);
   (void)hipFree(h->d_order);
   (void)hipFree(h->d_desc);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -713,19 +717,25 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
     h->desc_dev_copy = desc;
   }
 
+  // the cold pointers go to device memory ahead of the launch, stream-ordered
+  // and outside any captured graph (the graph's kernel reads them at replay)
+  ens::RkckCold c{};
+  c.p = h->d_p;
+  c.y = h->d_y;
+  c.phi2 = h->d_phi;
+  c.t = h->d_t;
+  c.h = h->d_h;
+  c.rec = R > 0 ? h->d_rec : nullptr;
+  c.stats = h->d_stats;
+  c.status = h->d_status;
+  c.queue = h->d_queue;
+  c.order = h->use_order ? h->d_order : nullptr;
+  ENS_HIP(h, ens::launch_set_cold(h->d_cold, c, h->stream));
+
   ens::RkckArgs a;
   std::memset(&a, 0, sizeof(a));  // padding too: the struct is compared bytewise
-  a.p = h->d_p;
-  a.y = h->d_y;
-  a.phi2 = h->d_phi;
-  a.t = h->d_t;
-  a.h = h->d_h;
-  a.rec = R > 0 ? h->d_rec : nullptr;
-  a.stats = h->d_stats;
-  a.status = h->d_status;
-  a.queue = h->d_queue;
+  a.cold = h->d_cold;
   a.spread = o->spread;
-  a.order = h->use_order ? h->d_order : nullptr;
   a.desc = h->d_desc;
   a.n = h->n;
   a.R = R;

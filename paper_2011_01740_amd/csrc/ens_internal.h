@@ -27,7 +27,11 @@ struct alignas(16) EnsDesc {
 };
 
 // Everything the persistent adaptive kernel needs, passed by value.
-struct RkckArgs {
+// The per-system arrays and the queue: the persistent kernel touches them
+// only when a lane takes up or puts down a system or ends a phase, so it
+// reads these pointers from device memory at those points instead of holding
+// them in scalar registers through the step loop.
+struct RkckCold {
   const double *p;          // [P][n]
   double *y;                // [D][n] in/out
   double *phi2;             // [n] in/out: Keller--Miksis second drive's phase, or null
@@ -37,8 +41,12 @@ struct RkckArgs {
   int64_t *stats;           // [ENS_NSTAT][n]
   int32_t *status;          // [n]
   unsigned long long *queue;// [2]: positions taken from the rest, from the head
-  int64_t spread;           // head [0, spread) of the queue order: one wave per SIMD
   const int64_t *order;     // [n] system taken at each queue position, or null
+};
+
+struct RkckArgs {
+  const RkckCold *cold;     // device copy of the pointers above
+  int64_t spread;           // head [0, spread) of the queue order: one wave per SIMD
   const EnsDesc *desc;      // [n_ens]
   int64_t n;
   int64_t R;
@@ -64,6 +72,7 @@ constexpr int ENS_KM6_GENERAL = 103;   // ENS_KM6 on the general arithmetic
 constexpr int kTangentModel = 1000;
 
 // Kernel launchers (stream-ordered; return hipSuccess or the launch error).
+hipError_t launch_set_cold(RkckCold *dst, const RkckCold &c, hipStream_t s);
 hipError_t launch_rk4(int model, int block, int spl, const double *p, double *y,
                       double *acc, int64_t n, double dt, int64_t nsteps,
                       const double *shared, hipStream_t s);

@@ -615,14 +615,24 @@ __device__ __forceinline__ void note_phase_end(Lane &L) {
   L.phase_att = L.attempts;
 }
 
+// The cold pointers, read from device memory where they are used (the
+// empty asm hides that the address is the same on every iteration, so the
+// loads are not hoisted out of the step loop into scalar registers).
+__device__ __forceinline__ const RkckCold *cold(const RkckArgs &a) {
+  const RkckCold *c = a.cold;
+  asm volatile("" : "+s"(c));
+  return c;
+}
+
 template <class M>
 __device__ __forceinline__ void store_record(const RkckArgs &a, const Lane &L, double v0,
                                              double v1) {
   if (a.R <= 0) return;
   constexpr int F = M::kF;
   const int64_t slot = (int64_t)(L.phase % (uint64_t)a.R);
-  a.rec[(slot * F) * a.n + L.sys] = v0;
-  if (F > 1) a.rec[(slot * F + 1) * a.n + L.sys] = v1;
+  double *rec = cold(a)->rec;
+  rec[(slot * F) * a.n + L.sys] = v0;
+  if (F > 1) rec[(slot * F + 1) * a.n + L.sys] = v1;
 }
 
 // Record fields 1 .. K of a phase with tangents: their log growths.
@@ -630,27 +640,30 @@ template <class M, int K>
 __device__ __forceinline__ void store_growth(const RkckArgs &a, const Lane &L, const double *g) {
   if (a.R <= 0) return;
   const int64_t slot = (int64_t)(L.phase % (uint64_t)a.R);
+  double *rec = cold(a)->rec;
 #pragma unroll
-  for (int v = 0; v < K; ++v) a.rec[(slot * M::kF + 1 + v) * a.n + L.sys] = g[v];
+  for (int v = 0; v < K; ++v) rec[(slot * M::kF + 1 + v) * a.n + L.sys] = g[v];
 }
 
 template <class M, int SC>
 __device__ __forceinline__ void store_lane(const RkckArgs &a, const Lane &L, const double *y) {
   constexpr int D = M::D;
   const int64_t n = a.n, i = L.sys;
+  const RkckCold *cp = cold(a);
 #pragma unroll
-  for (int c = 0; c < D; ++c) a.y[c * n + i] = y[c];
-  a.t[i] = L.t;
-  a.h[i] = L.h;
+  for (int c = 0; c < D; ++c) cp->y[c * n + i] = y[c];
+  cp->t[i] = L.t;
+  cp->h[i] = L.h;
   const int64_t att = (int64_t)L.accepted + L.rejected + L.evretry;
-  a.stats[ENS_ST_ACCEPTED * n + i] = L.accepted;
-  a.stats[ENS_ST_REJECTED * n + i] = L.rejected;
+  int64_t *stats = cp->stats;
+  stats[ENS_ST_ACCEPTED * n + i] = L.accepted;
+  stats[ENS_ST_REJECTED * n + i] = L.rejected;
   // Cash--Karp: 6 per attempt plus the evaluations of located maxima
-  a.stats[ENS_ST_NRHS * n + i] = SC == kDP ? (int64_t)L.nrhs : 6 * att + (int64_t)L.nrhs;
-  a.stats[ENS_ST_IMPACTS * n + i] = L.impacts;
-  a.stats[ENS_ST_PHASES * n + i] = L.phase;
-  a.stats[ENS_ST_EVRETRY * n + i] = L.evretry;
-  a.status[i] = L.status;
+  stats[ENS_ST_NRHS * n + i] = SC == kDP ? (int64_t)L.nrhs : 6 * att + (int64_t)L.nrhs;
+  stats[ENS_ST_IMPACTS * n + i] = L.impacts;
+  stats[ENS_ST_PHASES * n + i] = L.phase;
+  stats[ENS_ST_EVRETRY * n + i] = L.evretry;
+  cp->status[i] = L.status;
 }
 
 // Dense output of a step from y0 to y1 with end derivatives f0, f1 and step
@@ -939,7 +952,8 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
       const bool use_head = !head_done && (slot0 || rest_done);
       const int leader = __ffsll((long long)idle) - 1;
       unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(a.queue + (use_head ? 1 : 0), (unsigned long long)n_idle);
+      if (lane == leader)
+        base = atomicAdd(cold(a)->queue + (use_head ? 1 : 0), (unsigned long long)n_idle);
       base = __shfl(base, leader);
       const uint64_t first = use_head ? 0 : spread, limit = use_head ? spread : nsys - spread;
       if (base + (unsigned long long)n_idle >= limit) {
@@ -953,16 +967,18 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
         const unsigned long long k = base + (unsigned long long)__popcll(idle & below);
         const unsigned long long me = first + k;
         if (k < limit) {
-          const int64_t i = a.order ? a.order[me] : (int64_t)me;
+          const RkckCold *cp = cold(a);
+          const int64_t *order = cp->order;
+          const int64_t i = order ? order[me] : (int64_t)me;
           int e = 0;
           while (e + 1 < a.n_ens && i >= sdesc[e].last) ++e;
-          m.init(a.p, a.n, i, sdesc[e].shared);
-          if constexpr (M::kDrive2) m.phi = a.phi2[i];
+          m.init(cp->p, a.n, i, sdesc[e].shared);
+          if constexpr (M::kDrive2) m.phi = cp->phi2[i];
 #pragma unroll
-          for (int c = 0; c < D; ++c) y[c] = a.y[c * a.n + i];
+          for (int c = 0; c < D; ++c) y[c] = cp->y[c * a.n + i];
           L.sys = i;
-          L.t = a.t[i];
-          L.h = a.h[i];
+          L.t = cp->t[i];
+          L.h = cp->h[i];
           L.t_ps = L.t;
           L.ymax = -INFINITY;
           L.ymin = INFINITY;
@@ -981,7 +997,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
           active = true;
           if (L.n_phases <= 0) {
             store_lane<M, SC>(a, L, y);
-            if constexpr (M::kDrive2) a.phi2[i] = m.phi;
+            if constexpr (M::kDrive2) cold(a)->phi2[i] = m.phi;
             active = false;
           }
         }
@@ -1013,7 +1029,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
         done = step_fixed<M, SC, LOC>(a, m, L, y, fs);
       if (done) {
         store_lane<M, SC>(a, L, y);
-        if constexpr (M::kDrive2) a.phi2[L.sys] = m.phi;
+        if constexpr (M::kDrive2) cold(a)->phi2[L.sys] = m.phi;
         active = false;
       }
     }
@@ -1133,6 +1149,18 @@ int max_blocks_scheme(int model, bool loc, int block) {
 }
 
 }  // namespace
+
+namespace {
+// Writes the cold pointers to device memory, stream-ordered (one lane).
+__global__ void k_set_cold(RkckCold *dst, RkckCold c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = c;
+}
+}  // namespace
+
+hipError_t launch_set_cold(RkckCold *dst, const RkckCold &c, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_cold, dim3(1), dim3(64), 0, s, dst, c);
+  return hipGetLastError();
+}
 
 hipError_t launch_rkck(int model, int solver, int block, int grid, const RkckArgs &a,
                        hipStream_t s) {
