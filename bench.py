@@ -211,7 +211,8 @@ def run_case(case, args):
     elif case == "surrogate":
         from paper_2011_01740_amd import surrogate as S
         cfg = S.Config(train_grid=args.sur_train, screen_grid=args.sur_screen,
-                       n_phases=args.sur_phases, epochs=args.sur_epochs, judge_n=args.sur_judge)
+                       n_phases=args.sur_phases, epochs=args.sur_epochs, judge_n=args.sur_judge,
+                       target_wrong=args.sur_target)
         rep = S.run(cfg, log=lambda *a: print(*a, file=sys.stderr, flush=True))
         d = {k: v for k, v in rep.__dict__.items() if k != "extra"}
         d["case"] = "surrogate"
@@ -309,6 +310,8 @@ def main(argv=None):
     ap.add_argument("--sur-phases", type=int, default=1024)
     ap.add_argument("--sur-epochs", type=int, default=200)
     ap.add_argument("--sur-judge", type=int, default=1 << 18)
+    ap.add_argument("--sur-target", type=float, default=0.007,
+                    help="hold-out wrong fraction the screening flags are calibrated to")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 23)
