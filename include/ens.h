@@ -272,8 +272,10 @@ typedef struct {
                          first wave slot of each SIMD and the rest to the
                          others, so that long systems start one per SIMD
                          instead of sharing one; either group takes from the
-                         other once its own is empty.  Results do not depend
-                         on it.  0 = one queue; 0 <= spread <= n           */
+                         other once its own is empty.  Waves that carry head
+                         systems raise their issue priority (models without
+                         their own remaining-work priority).  Results do not
+                         depend on it.  0 = one queue; 0 <= spread <= n    */
 } ens_solve_opts;
 
 /* Fills opts with the defaults: dt 0.01, n_steps 1000, t_phase 1, dt0 1e-2,
