@@ -323,9 +323,9 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the systems are independent; see the sharding notes in DESIGN.md).",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path. "
+              "The systems are independent, so an ensemble would shard by contiguous "
+              "index ranges, one process per GPU.", file=sys.stderr)
         return 2
     if args.case != "bench":
         return run_case(args.case, args)
