@@ -57,6 +57,7 @@ class Config:
                                    # per SIMD, the fastest for its longest systems (0: all)
     resolve_grid: int = 512        # blocks of the re-solve after its pilot: two waves per
                                    # SIMD (it is 1-2 resident waves of long systems; 0: all)
+    compare: bool = True           # judge the interpolation screen beside the network's
 
 
 def loo_disagreement(nlab, node_idx, net_label):
@@ -100,6 +101,178 @@ def calibrate_labels(d, wrong, k, target, n_valid):
     return best[1], best[2]
 
 
+# ------------------------------------------------------------ comparison
+# A screen without the network, to show what the network gains: the training
+# grid's max_j ln y1max interpolated bilinearly at the dense grid's points
+# (both grids are evenly spaced in p_A and ln f over the same box), under the
+# same band rule.  Host-side evaluation after the screened sweep; the sweep
+# itself never uses it.
+
+def _cells(G_t, G_s):
+    """Lower training node and weight of each dense-grid coordinate."""
+    u = np.arange(G_s, dtype=np.float64) * ((G_t - 1) / (G_s - 1))
+    i0 = np.minimum(u.astype(np.int64), G_t - 2)
+    return i0, u - i0
+
+
+def bilinear_values(vt, G_t, G_s):
+    """Bilinear interpolation of the G_t x G_t node values vt (km-grid order)
+    at the points of the G_s x G_s grid over the same box; [G_s * G_s]."""
+    V = np.asarray(vt, dtype=np.float64).reshape(G_t, G_t)
+    i0, w = _cells(G_t, G_s)
+    A = V[:, i0] * (1.0 - w) + V[:, i0 + 1] * w
+    return (A[i0, :] * (1.0 - w)[:, None] + A[i0 + 1, :] * w[:, None]).ravel()
+
+
+def corner_disagreement(nlab, G_t, G_s, label):
+    """For each dense-grid point, how many (0..4) of the four training nodes
+    of its grid cell carry an exact label other than `label` (an unknown
+    label, -1, counts as different): the screen's label flag."""
+    Lb = np.asarray(nlab).reshape(G_t, G_t)
+    lab = np.asarray(label).reshape(G_s, G_s)
+    i0, _ = _cells(G_t, G_s)
+    k = np.zeros((G_s, G_s), dtype=np.int8)
+    for di in (0, 1):
+        rows = Lb[i0 + di]
+        for dj in (0, 1):
+            k += rows[:, i0 + dj] != lab
+    return k.ravel()
+
+
+def loo_values(vt, G, nodes):
+    """Value at each of the given nodes from its four axis neighbours alone
+    (their mean, NaN neighbours left out; reflected at the border)."""
+    V = np.asarray(vt, dtype=np.float64).reshape(G, G)
+    i, j = np.divmod(np.asarray(nodes), G)
+    def refl(a):
+        return np.where(a < 0, -a, np.where(a >= G, 2 * (G - 1) - a, a))
+    nb = np.stack([V[refl(i + di), refl(j + dj)]
+                   for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1))])
+    ok = np.isfinite(nb)
+    cnt = ok.sum(axis=0)
+    return np.where(cnt > 0, np.where(ok, nb, 0.0).sum(axis=0) / np.maximum(cnt, 1), np.nan)
+
+
+def band_distance(v):
+    """|v - ln 2|, with -1 where v is not finite (such points are always
+    re-solved)."""
+    v = np.asarray(v, dtype=np.float64)
+    return np.where(np.isfinite(v), np.abs(v - LN2), -1.0)
+
+
+def band_resolve(d, k, m0, m1):
+    """The band rule: re-solve if k = 4, or 1 <= k < 4 and d < m1, or d < m0."""
+    return (k == 4) | ((k >= 1) & (d < m1)) | (d < m0)
+
+
+def band_tradeoff(d, k, jsel, wrong_j, budget):
+    """Fewest re-solved points of the band rule over all points (d, k) when at
+    most `budget` of the judged points jsel (wrong_j: their screen label is
+    wrong) may stay wrong outside it.  The thresholds are chosen on the judged
+    points themselves, so this bounds from below what any calibration of the
+    same screen could reach.  Returns (fraction, m0, m1); with a list of
+    budgets, a list of those."""
+    n = d.size
+    part = (k >= 1) & (k < 4)
+    n4 = int((k == 4).sum())
+    dp = np.sort(d[part])
+    dz = np.sort(d[k == 0])
+    dj, kj = d[jsel], k[jsel]
+    pj = (kj >= 1) & (kj < 4)
+    wp = np.sort(dj[wrong_j & pj])
+    wz = np.sort(dj[wrong_j & (kj == 0)])
+    eps = 1e-12
+
+    def uncovered(m0, m1):
+        t = max(m0, m1)
+        return (wp.size - np.searchsorted(wp, t)) + (wz.size - np.searchsorted(wz, m0))
+
+    m0c = np.unique(np.concatenate([[0.0], wz + eps, wp + eps]))
+    # the optimum has m1 = 0 or just above a wrong point's d (exact for up to
+    # 256 such points, quantiles beyond)
+    q = wp if wp.size <= 256 else np.quantile(wp, np.linspace(0.0, 1.0, 257))
+    m1c = [0.0] + list(np.unique(q + eps))
+
+    def one(b):
+        best = None
+        for m1 in m1c:
+            lo, hi = 0, m0c.size - 1          # uncovered(m0c[-1], .) == 0
+            while lo < hi:
+                mid = (lo + hi) // 2
+                if uncovered(m0c[mid], m1) <= b:
+                    hi = mid
+                else:
+                    lo = mid + 1
+            m0 = float(m0c[lo])
+            frac = (n4 + np.searchsorted(dp, max(m0, m1)) + np.searchsorted(dz, m0)) / n
+            if best is None or frac < best[0]:
+                best = (float(frac), m0, float(m1))
+        return best
+
+    if np.ndim(budget):
+        return [one(int(b)) for b in budget]
+    return one(int(budget))
+
+
+def compare_screens(vt, nlab, hold, G_t, G_s, jidx, exact_j, net_label, net_pmax, budget,
+                    target):
+    """The network's screen against the interpolation screen (no network) on
+    the same dense grid, judged on the same plain-solved points (jidx,
+    exact_j).  For each: the re-solved fraction and judged error when its
+    thresholds are calibrated on the hold-out nodes (the network's are the
+    pipeline's own), and the fewest re-solves that reach the network
+    pipeline's judged error (`budget` wrong points) with thresholds tuned on
+    the judged points."""
+    vj = exact_j >= 0
+    n_j = max(int(vj.sum()), 1)
+    out = {}
+    # interpolation: values, labels, corner flags on the dense grid
+    vi = bilinear_values(vt, G_t, G_s)
+    lab_i = (vi >= LN2).astype(np.int8)
+    d_i = band_distance(vi)
+    k_i = corner_disagreement(nlab, G_t, G_s, lab_i)
+    # hold-out calibration as the network's: a held-out node seen from its
+    # neighbours only
+    est = loo_values(vt, G_t, hold)
+    exact_h = nlab[hold]
+    valid_h = exact_h >= 0
+    lab_h = (est >= LN2).astype(np.int8)
+    wrong_h = (lab_h != exact_h) & valid_h
+    k_h = loo_disagreement(nlab, hold, lab_h)
+    m0, m1 = calibrate_labels(band_distance(est), wrong_h, k_h, target, int(valid_h.sum()))
+    res = band_resolve(d_i, k_i, m0, m1)
+    wrong_ij = (lab_i[jidx] != exact_j) & vj
+    out["interp_holdout"] = {"resolve_frac": float(res.mean()),
+                             "judge_wrong_frac": float((wrong_ij & ~res[jidx]).sum() / n_j),
+                             "margin": m0, "label_margin": m1}
+    out["interp_alone_wrong_frac"] = float(wrong_ij.sum() / n_j)
+    f, m0, m1 = band_tradeoff(d_i, k_i, jidx, wrong_ij, budget)
+    out["interp_equal_error"] = {"resolve_frac": f, "margin": m0, "label_margin": m1}
+    # the network's own screen, tuned the same way
+    lab_n = np.asarray(net_label).astype(np.int8)
+    d_n = band_distance(net_pmax)
+    k_n = corner_disagreement(nlab, G_t, G_s, lab_n)
+    wrong_nj = (lab_n[jidx] != exact_j) & vj
+    f, m0, m1 = band_tradeoff(d_n, k_n, jidx, wrong_nj, budget)
+    out["network_equal_error"] = {"resolve_frac": f, "margin": m0, "label_margin": m1}
+    out["budget_wrong_points"] = int(budget)
+    # re-solve fraction against judged error, each screen with its own tuned
+    # thresholds; "both": the interpolation's label and band, and every point
+    # where the network's label differs from it re-solved as well
+    w_i = int(wrong_ij.sum())
+    budgets = sorted({int(budget), w_i, w_i // 2, w_i // 4, w_i // 10})
+    disagree = lab_n != lab_i
+    k_b = np.where(disagree, 4, k_i).astype(np.int8)
+    curves = {"judged_wrong_frac": [b / n_j for b in budgets]}
+    for name, (d, k, w) in (("interp", (d_i, k_i, wrong_ij)), ("network", (d_n, k_n, wrong_nj)),
+                            ("both", (d_i, k_b, wrong_ij))):
+        curves[name] = [r[0] for r in band_tradeoff(d, k, jidx, w, budgets)]
+    out["tradeoff"] = curves
+    out["disagree_frac"] = float(disagree.mean())
+    out["interp_wrong_in_disagreement"] = float((wrong_ij & disagree[jidx]).sum() / max(w_i, 1))
+    return out
+
+
 @dataclass
 class Report:
     config: Dict = field(default_factory=dict)
@@ -125,6 +298,7 @@ class Report:
     resolve_attempts: int = 0       # ... of the re-solve
     plain_attempts: int = 0         # ... of the plain sweep (of the judged points)
     train_loss: float = 0.0
+    compare: Dict = field(default_factory=dict)  # against the screen without the network
     extra: Dict = field(default_factory=dict)
 
 
@@ -351,6 +525,20 @@ def run(cfg: Config, log=print) -> Report:
         f"({rep.speedup_excl_data:.2f} without the training sweep)")
     log(f"attempted steps: training sweep {rep.data_attempts:.4g}, re-solve "
         f"{rep.resolve_attempts:.4g}, plain {rep.plain_attempts:.4g}")
+    if cfg.compare:
+        t0 = time.perf_counter()
+        vt = torch.log(rec_t.max(dim=0).values).cpu().numpy()
+        rep.compare = compare_screens(vt, nlab, hold, cfg.train_grid, cfg.screen_grid, jidx,
+                                      exact_j, net_label.cpu().numpy(),
+                                      pmax.cpu().numpy().astype(np.float64), rep.judge_wrong,
+                                      cfg.target_wrong)
+        c = rep.compare
+        log(f"no network (bilinear): hold-out calibrated re-solve "
+            f"{c['interp_holdout']['resolve_frac']:.4f} at wrong "
+            f"{c['interp_holdout']['judge_wrong_frac']:.5f}; at the network's judged error "
+            f"re-solve {c['interp_equal_error']['resolve_frac']:.4f} against the network's "
+            f"{c['network_equal_error']['resolve_frac']:.4f} "
+            f"({time.perf_counter() - t0:.1f} s on the host)")
     rep.extra = {"judge_idx": jidx, "judge_exact": exact_j, "nlab": nlab,
                  "judge_pmax": pmax[jidx_d].cpu().numpy(), "judge_final": final_j,
                  "judge_resolve": resolve[jidx_d].cpu().numpy(),

@@ -74,3 +74,13 @@ def test_screened_sweep_reduced_configuration():
     jfinal, jexact = rep.extra["judge_final"], rep.extra["judge_exact"]
     band = np.abs(rep.extra["judge_pmax"] - np.log(2.0)) < rep.margin
     assert np.array_equal(jfinal[band], jexact[band])
+    # the screen without the network, judged on the same points
+    c = rep.compare
+    for key in ("interp_holdout", "interp_equal_error", "network_equal_error"):
+        assert 0.0 <= c[key]["resolve_frac"] <= 1.0
+    assert c["budget_wrong_points"] == rep.judge_wrong
+    # thresholds tuned on the judged points never need more re-solves than
+    # the pipeline's hold-out calibrated ones (up to the kernel's FP32 cell
+    # lookup at cell borders)
+    assert c["network_equal_error"]["resolve_frac"] <= rep.resolve_frac + 0.01
+    print("compare:", c)
