@@ -65,6 +65,37 @@ constexpr double DE1 = D71 - 5179.0 / 57600.0, DE3 = D73 - 7571.0 / 16695.0,
                  DE4 = D74 - 393.0 / 640.0, DE5 = D75 + 92097.0 / 339200.0,
                  DE6 = D76 - 187.0 / 2100.0, DE7 = -1.0 / 40.0;
 
+// Both tableaux again as tables in constant memory.  An attempt reads its
+// coefficients through scalar_table(): a handful of wide scalar loads per
+// attempt instead of two 32-bit immediates per double, which also leaves the
+// scalar registers that the immediates took to the rest of the loop.
+struct CkTab {
+  double a21, a31, a32, a41, a42, a43, a51, a52, a53, a54, a61, a62, a63, a64, a65;
+  double b1, b3, b4, b6, e1, e3, e4, e5, e6;
+};
+__constant__ CkTab kCkTab = {A21, A31, A32, A41, A42, A43, A51, A52, A53, A54,
+                             A61, A62, A63, A64, A65, B1,  B3,  B4,  B6,  E1,
+                             E3,  E4,  E5,  E6};
+struct DpTab {
+  double a21, a31, a32, a41, a42, a43, a51, a52, a53, a54, a61, a62, a63, a64, a65;
+  double b1, b3, b4, b5, b6, e1, e3, e4, e5, e6, e7;
+};
+__constant__ DpTab kDpTab = {D21, D31, D32, D41, D42, D43, D51, D52, D53, D54,
+                             D61, D62, D63, D64, D65, D71, D73, D74, D75, D76,
+                             DE1, DE3, DE4, DE5, DE6, DE7};
+
+// A table in constant memory as the attempt sees it.  The pointer passes
+// through an empty asm in scalar registers, so the compiler cannot hoist the
+// loads out of the step loop (which would pin the values in scalar registers
+// for the whole loop and spill others); the constant address space lets it
+// use scalar loads.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T &scalar_table(const T &t) {
+  const T *p = &t;
+  asm volatile("" : "+s"(p));
+  return *(const __attribute__((address_space(4))) T *)p;
+}
+
 // Occupancy floor per (model, scheme, located maxima): the seventh stage and
 // the carried k1 of Dormand--Prince, or Cash--Karp's end-point evaluations
 // for located maxima, cost one wave per SIMD.
@@ -442,16 +473,15 @@ struct MPRV {
   }
   __device__ void begin(double) {}
   template <int SC, int S>
+  // Seated, the body rests with y1 = y2 = +0 (the seating sets both and
+  // every stage keeps them), so the free-flight expressions give dy1/dt = 0
+  // and dy3/dt = beta q exactly; only the acceleration is held at 0.  No
+  // branch: the attempt stays one basic block.
   __device__ void rhs(double, double, const double *y, double *f) const {
-    if (seated) {
-      f[0] = 0.0;
-      f[1] = 0.0;
-      f[2] = beta * q;
-    } else {
-      f[0] = y[1];
-      f[1] = fma(-kappa, y[1], y[2] - (y[0] + delta));
-      f[2] = beta * fma(-y[0], sqrt_nr(y[2]), q);
-    }
+    const double acc = fma(-kappa, y[1], y[2] - (y[0] + delta));
+    f[0] = y[1];
+    f[1] = seated ? 0.0 : acc;
+    f[2] = beta * fma(-y[0], sqrt_nr(y[2]), q);
   }
 };
 
@@ -461,31 +491,32 @@ __device__ __forceinline__ void ck_attempt(M &m, double t, const double *y, doub
                                            double *y5, double *err) {
   constexpr int D = M::D;
   double k1[D], k2[D], k3[D], k4[D], k5[D], k6[D], yt[D];
+  const auto &T = scalar_table(kCkTab);
   m.begin(t);
   m.template rhs<kCK, 1>(t, h, y, k1);
 #pragma unroll
-  for (int c = 0; c < D; ++c) yt[c] = fma(h, A21 * k1[c], y[c]);
+  for (int c = 0; c < D; ++c) yt[c] = fma(h, T.a21 * k1[c], y[c]);
   m.template rhs<kCK, 2>(fma(C2, h, t), h, yt, k2);
 #pragma unroll
-  for (int c = 0; c < D; ++c) yt[c] = fma(h, fma(A32, k2[c], A31 * k1[c]), y[c]);
+  for (int c = 0; c < D; ++c) yt[c] = fma(h, fma(T.a32, k2[c], T.a31 * k1[c]), y[c]);
   m.template rhs<kCK, 3>(fma(C3, h, t), h, yt, k3);
 #pragma unroll
   for (int c = 0; c < D; ++c)
-    yt[c] = fma(h, fma(A43, k3[c], fma(A42, k2[c], A41 * k1[c])), y[c]);
+    yt[c] = fma(h, fma(T.a43, k3[c], fma(T.a42, k2[c], T.a41 * k1[c])), y[c]);
   m.template rhs<kCK, 4>(fma(C4, h, t), h, yt, k4);
 #pragma unroll
   for (int c = 0; c < D; ++c)
-    yt[c] = fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], A51 * k1[c]))), y[c]);
+    yt[c] = fma(h, fma(T.a54, k4[c], fma(T.a53, k3[c], fma(T.a52, k2[c], T.a51 * k1[c]))), y[c]);
   m.template rhs<kCK, 5>(t + C5 * h, h, yt, k5);
 #pragma unroll
   for (int c = 0; c < D; ++c)
-    yt[c] = fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], A61 * k1[c])))),
+    yt[c] = fma(h, fma(T.a65, k5[c], fma(T.a64, k4[c], fma(T.a63, k3[c], fma(T.a62, k2[c], T.a61 * k1[c])))),
                 y[c]);
   m.template rhs<kCK, 6>(fma(C6, h, t), h, yt, k6);
 #pragma unroll
   for (int c = 0; c < D; ++c) {
-    y5[c] = fma(h, fma(B6, k6[c], fma(B4, k4[c], fma(B3, k3[c], B1 * k1[c]))), y[c]);
-    err[c] = h * fma(E6, k6[c], fma(E5, k5[c], fma(E4, k4[c], fma(E3, k3[c], E1 * k1[c]))));
+    y5[c] = fma(h, fma(T.b6, k6[c], fma(T.b4, k4[c], fma(T.b3, k3[c], T.b1 * k1[c]))), y[c]);
+    err[c] = h * fma(T.e6, k6[c], fma(T.e5, k5[c], fma(T.e4, k4[c], fma(T.e3, k3[c], T.e1 * k1[c]))));
   }
 }
 
@@ -498,37 +529,38 @@ __device__ __forceinline__ int dp_attempt(M &m, double t, const double *y, doubl
                                           double *k7) {
   constexpr int D = M::D;
   double k2[D], k3[D], k4[D], k5[D], k6[D], yt[D];
+  const auto &T = scalar_table(kDpTab);
   m.begin(t);
   if (!have_k1) m.template rhs<kDP, 1>(t, h, y, kf);
   const double *k1 = kf;
 #pragma unroll
-  for (int c = 0; c < D; ++c) yt[c] = fma(h, D21 * k1[c], y[c]);
+  for (int c = 0; c < D; ++c) yt[c] = fma(h, T.a21 * k1[c], y[c]);
   m.template rhs<kDP, 2>(fma(DC2, h, t), h, yt, k2);
 #pragma unroll
-  for (int c = 0; c < D; ++c) yt[c] = fma(h, fma(D32, k2[c], D31 * k1[c]), y[c]);
+  for (int c = 0; c < D; ++c) yt[c] = fma(h, fma(T.a32, k2[c], T.a31 * k1[c]), y[c]);
   m.template rhs<kDP, 3>(fma(DC3, h, t), h, yt, k3);
 #pragma unroll
   for (int c = 0; c < D; ++c)
-    yt[c] = fma(h, fma(D43, k3[c], fma(D42, k2[c], D41 * k1[c])), y[c]);
+    yt[c] = fma(h, fma(T.a43, k3[c], fma(T.a42, k2[c], T.a41 * k1[c])), y[c]);
   m.template rhs<kDP, 4>(fma(DC4, h, t), h, yt, k4);
 #pragma unroll
   for (int c = 0; c < D; ++c)
-    yt[c] = fma(h, fma(D54, k4[c], fma(D53, k3[c], fma(D52, k2[c], D51 * k1[c]))), y[c]);
+    yt[c] = fma(h, fma(T.a54, k4[c], fma(T.a53, k3[c], fma(T.a52, k2[c], T.a51 * k1[c]))), y[c]);
   m.template rhs<kDP, 5>(fma(DC5, h, t), h, yt, k5);
 #pragma unroll
   for (int c = 0; c < D; ++c)
-    yt[c] = fma(h, fma(D65, k5[c], fma(D64, k4[c], fma(D63, k3[c], fma(D62, k2[c], D61 * k1[c])))),
+    yt[c] = fma(h, fma(T.a65, k5[c], fma(T.a64, k4[c], fma(T.a63, k3[c], fma(T.a62, k2[c], T.a61 * k1[c])))),
                 y[c]);
   m.template rhs<kDP, 6>(t + h, h, yt, k6);
 #pragma unroll
   for (int c = 0; c < D; ++c)
-    y5[c] = fma(h, fma(D76, k6[c], fma(D75, k5[c], fma(D74, k4[c], fma(D73, k3[c], D71 * k1[c])))),
+    y5[c] = fma(h, fma(T.b6, k6[c], fma(T.b5, k5[c], fma(T.b4, k4[c], fma(T.b3, k3[c], T.b1 * k1[c])))),
                 y[c]);
   m.template rhs<kDP, 7>(t + h, h, y5, k7);
 #pragma unroll
   for (int c = 0; c < D; ++c)
-    err[c] = h * fma(DE7, k7[c], fma(DE6, k6[c], fma(DE5, k5[c], fma(DE4, k4[c],
-                                                      fma(DE3, k3[c], DE1 * k1[c])))));
+    err[c] = h * fma(T.e7, k7[c], fma(T.e6, k6[c], fma(T.e5, k5[c], fma(T.e4, k4[c],
+                                                      fma(T.e3, k3[c], T.e1 * k1[c])))));
   return have_k1 ? 6 : 7;
 }
 
