@@ -10,7 +10,10 @@
  * parallelism (the paper's unrolling over systems), FMAs, the state held in
  * registers for all steps, and OpenMP threads over blocks of systems.  The
  * arithmetic is the GPU kernel's accumulated stage form: the RK4 combination
- * is summed stage by stage and sigma is folded into the stage coefficients.
+ * is summed stage by stage, sigma is folded into the stage coefficients, and
+ * the third variable is carried as w = rho - z, in which the right-hand side
+ * is all multiply-adds (y' = x w - y, w' = beta rho - beta w - x y; RK4
+ * commutes with the change of variable, so only rounding differs).
  * Function multiversioning picks AVX-512, AVX2 or plain SSE2 code at load
  * time for the machine it runs on.
  *
@@ -45,54 +48,56 @@ typedef long long v8i __attribute__((vector_size(64)));
 __attribute__((target_clones("avx512f", "arch=haswell", "default")))
 static void block8(const double *P, double *Y, double *M, int64_t n, int64_t i0,
                    int64_t nsteps, coef c) {
-  v8 x[U], y[U], z[U], r[U], m[U];
+  v8 x[U], y[U], w[U], r[U], br[U], m[U];
+  const v8 be = BC(c.beta);
   for (int u = 0; u < U; ++u) {
     const int64_t i = i0 + (int64_t)u * W;
     r[u] = LD(P + i);
+    br[u] = be * r[u];
     x[u] = LD(Y + i);
     y[u] = LD(Y + n + i);
-    z[u] = LD(Y + 2 * n + i);
+    w[u] = r[u] - LD(Y + 2 * n + i);
     m[u] = x[u];
   }
   const v8 dt = BC(c.dt), h2 = BC(c.h2), h3 = BC(c.h3), h6 = BC(c.h6);
-  const v8 sh = BC(c.sh), sh2 = BC(c.sh2), sh3 = BC(c.sh3), sh6 = BC(c.sh6), be = BC(c.beta);
+  const v8 sh = BC(c.sh), sh2 = BC(c.sh2), sh3 = BC(c.sh3), sh6 = BC(c.sh6);
   for (int64_t s = 0; s < nsteps; ++s) {
     for (int u = 0; u < U; ++u) {
-      const v8 x0 = x[u], y0 = y[u], z0 = z[u], rh = r[u];
-      v8 d, ky, kz, ax, ay, az, xs, ys, zs;
+      const v8 x0 = x[u], y0 = y[u], w0 = w[u], b = br[u];
+      v8 d, ky, kw, ax, ay, aw, xs, ys, ws;
       d = y0 - x0;
-      ky = rh * x0 - y0 - x0 * z0;
-      kz = x0 * y0 - be * z0;
+      ky = x0 * w0 - y0;
+      kw = b - be * w0 - x0 * y0;
       ax = x0 + sh6 * d;
       ay = y0 + h6 * ky;
-      az = z0 + h6 * kz;
+      aw = w0 + h6 * kw;
       xs = x0 + sh2 * d;
       ys = y0 + h2 * ky;
-      zs = z0 + h2 * kz;
+      ws = w0 + h2 * kw;
       d = ys - xs;
-      ky = rh * xs - ys - xs * zs;
-      kz = xs * ys - be * zs;
+      ky = xs * ws - ys;
+      kw = b - be * ws - xs * ys;
       ax += sh3 * d;
       ay += h3 * ky;
-      az += h3 * kz;
+      aw += h3 * kw;
       xs = x0 + sh2 * d;
       ys = y0 + h2 * ky;
-      zs = z0 + h2 * kz;
+      ws = w0 + h2 * kw;
       d = ys - xs;
-      ky = rh * xs - ys - xs * zs;
-      kz = xs * ys - be * zs;
+      ky = xs * ws - ys;
+      kw = b - be * ws - xs * ys;
       ax += sh3 * d;
       ay += h3 * ky;
-      az += h3 * kz;
+      aw += h3 * kw;
       xs = x0 + sh * d;
       ys = y0 + dt * ky;
-      zs = z0 + dt * kz;
+      ws = w0 + dt * kw;
       d = ys - xs;
-      ky = rh * xs - ys - xs * zs;
-      kz = xs * ys - be * zs;
+      ky = xs * ws - ys;
+      kw = b - be * ws - xs * ys;
       x[u] = ax + sh6 * d;
       y[u] = ay + h6 * ky;
-      z[u] = az + h6 * kz;
+      w[u] = aw + h6 * kw;
       m[u] = VMAX(x[u], m[u]);
     }
   }
@@ -100,7 +105,7 @@ static void block8(const double *P, double *Y, double *M, int64_t n, int64_t i0,
     const int64_t i = i0 + (int64_t)u * W;
     ST(Y + i, x[u]);
     ST(Y + n + i, y[u]);
-    ST(Y + 2 * n + i, z[u]);
+    if (nsteps > 0) ST(Y + 2 * n + i, r[u] - w[u]);
     ST(M + i, m[u]);
   }
 }
@@ -108,47 +113,48 @@ static void block8(const double *P, double *Y, double *M, int64_t n, int64_t i0,
 /* One system at a time, for the tail of n that does not fill a block. */
 static void one(const double *P, double *Y, double *M, int64_t n, int64_t i, int64_t nsteps,
                 coef c) {
-  double x = Y[i], y = Y[n + i], z = Y[2 * n + i], r = P[i], m = x;
+  const double r = P[i], b = c.beta * r;
+  double x = Y[i], y = Y[n + i], w = r - Y[2 * n + i], m = x;
   for (int64_t s = 0; s < nsteps; ++s) {
-    double d, ky, kz, ax, ay, az, xs, ys, zs;
+    double d, ky, kw, ax, ay, aw, xs, ys, ws;
     d = y - x;
-    ky = r * x - y - x * z;
-    kz = x * y - c.beta * z;
+    ky = x * w - y;
+    kw = b - c.beta * w - x * y;
     ax = x + c.sh6 * d;
     ay = y + c.h6 * ky;
-    az = z + c.h6 * kz;
+    aw = w + c.h6 * kw;
     xs = x + c.sh2 * d;
     ys = y + c.h2 * ky;
-    zs = z + c.h2 * kz;
+    ws = w + c.h2 * kw;
     d = ys - xs;
-    ky = r * xs - ys - xs * zs;
-    kz = xs * ys - c.beta * zs;
+    ky = xs * ws - ys;
+    kw = b - c.beta * ws - xs * ys;
     ax += c.sh3 * d;
     ay += c.h3 * ky;
-    az += c.h3 * kz;
+    aw += c.h3 * kw;
     xs = x + c.sh2 * d;
     ys = y + c.h2 * ky;
-    zs = z + c.h2 * kz;
+    ws = w + c.h2 * kw;
     d = ys - xs;
-    ky = r * xs - ys - xs * zs;
-    kz = xs * ys - c.beta * zs;
+    ky = xs * ws - ys;
+    kw = b - c.beta * ws - xs * ys;
     ax += c.sh3 * d;
     ay += c.h3 * ky;
-    az += c.h3 * kz;
+    aw += c.h3 * kw;
     xs = x + c.sh * d;
     ys = y + c.dt * ky;
-    zs = z + c.dt * kz;
+    ws = w + c.dt * kw;
     d = ys - xs;
-    ky = r * xs - ys - xs * zs;
-    kz = xs * ys - c.beta * zs;
+    ky = xs * ws - ys;
+    kw = b - c.beta * ws - xs * ys;
     x = ax + c.sh6 * d;
     y = ay + c.h6 * ky;
-    z = az + c.h6 * kz;
+    w = aw + c.h6 * kw;
     m = x > m ? x : m;
   }
   Y[i] = x;
   Y[n + i] = y;
-  Y[2 * n + i] = z;
+  if (nsteps > 0) Y[2 * n + i] = r - w;
   M[i] = m;
 }
 

@@ -32,3 +32,9 @@ def test_threads_do_not_change_results(B):
     a = B.lorenz_rk4(P, y0, 0.01, 200, *LOR, nthreads=1)
     b = B.lorenz_rk4(P, y0, 0.01, 200, *LOR, nthreads=8)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_zero_steps_returns_the_initial_state(B):
+    P, y0 = I.lorenz_random(100, seed=3)
+    Y, M = B.lorenz_rk4(P, y0, 0.01, 0, *LOR, nthreads=2)
+    assert np.array_equal(Y, y0) and np.array_equal(M, y0[0])
