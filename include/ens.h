@@ -174,8 +174,10 @@ int ens_create(const ens_desc *desc, ens_t *out);
  * stream.  NULL is accepted.  Returns ENS_OK or ENS_E_HIP. */
 int ens_destroy(ens_t h);
 
-/* Message of the last failed call on h (on any handle if h is NULL).  The
- * string stays valid until the next call on that handle. */
+/* Message of the last failed call on h; with h NULL, of the calling thread's
+ * last failed call on any handle (or one that had no handle yet, such as a
+ * failed ens_create).  The string stays valid until the next call on that
+ * handle (NULL: the thread's next failing call). */
 const char *ens_last_error(ens_t h);
 
 /* Per-system parameters p: [P][n] doubles (see ens_model), copied in.
