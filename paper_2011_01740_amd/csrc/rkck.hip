@@ -755,62 +755,64 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
     return true;
   }
   const double fac = step_factor(E);
-  if (E > 1.0 && h_try > a.dt_min) {
-    L.rejected++;
-    L.h = clampd(h_try * fmin(fac, 1.0), a.dt_min, a.dt_max);
-  } else {
-    if (E > 1.0) L.status |= ENS_SYS_DT_MIN;
-    const double h_next = clampd(h_try * fac, a.dt_min, a.dt_max);
-    if constexpr (LOC) {
-      if (y[1] > 0.0 && y5[1] <= 0.0) {
-        // the maximum of y1 between the step points, on the interpolant
-        // (Dormand--Prince has f at both ends; Cash--Karp evaluates them)
-        double f0[D], f1[D];
-        if constexpr (SC == kDP) {
+  // Accept (E <= 1, or at the step-size floor) or reject, by selects: only
+  // the rare phase end and located maximum branch.  After a rejection the
+  // step only shrinks.
+  const bool acc = !(E > 1.0 && h_try > a.dt_min);
+  const double h_new = clampd(h_try * (acc ? fac : fmin(fac, 1.0)), a.dt_min, a.dt_max);
+  L.status |= (acc && E > 1.0) ? ENS_SYS_DT_MIN : 0;
+  L.accepted += acc ? 1 : 0;
+  L.rejected += acc ? 0 : 1;
+  if constexpr (LOC) {
+    if (acc && y[1] > 0.0 && y5[1] <= 0.0) {
+      // the maximum of y1 between the step points, on the interpolant
+      // (Dormand--Prince has f at both ends; Cash--Karp evaluates them)
+      double f0[D], f1[D];
+      if constexpr (SC == kDP) {
 #pragma unroll
-          for (int c = 0; c < D; ++c) {
-            f0[c] = fs.k[c];
-            f1[c] = k7[c];
-          }
-        } else {
-          m.begin(L.t);
-          m.template rhs<SC, 1>(L.t, h_try, y, f0);
-          m.begin(L.t + h_try);
-          m.template rhs<SC, 1>(L.t + h_try, h_try, y5, f1);
-          L.nrhs += 2;
+        for (int c = 0; c < D; ++c) {
+          f0[c] = fs.k[c];
+          f1[c] = k7[c];
         }
-        const double ym = located_max<D>(y, y5, f0, f1, h_try);
-        L.ymax = ym > L.ymax ? ym : L.ymax;
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < D; ++c) y[c] = y5[c];
-    if constexpr (SC == kDP) {
-#pragma unroll
-      for (int c = 0; c < D; ++c) fs.k[c] = k7[c];
-    }
-    L.accepted++;
-    L.ymax = y[0] > L.ymax ? y[0] : L.ymax;
-    if (trunc) {
-      fs.have = false;
-      if constexpr (M::kTangent) {
-        double g[M::kK];
-        m.renormalise(y, g);
-        store_record<M>(a, L, L.ymax, g[0]);
-        store_growth<M, M::kK>(a, L, g);
       } else {
-        store_record<M>(a, L, L.ymax, 0.0);
+        m.begin(L.t);
+        m.template rhs<SC, 1>(L.t, h_try, y, f0);
+        m.begin(L.t + h_try);
+        m.template rhs<SC, 1>(L.t + h_try, h_try, y5, f1);
+        L.nrhs += 2;
       }
-      L.phase++;
-      if constexpr (M::kPrio) note_phase_end(L);
-      if constexpr (M::kDrive2) m.next_phase(a.t_phase);
-      L.t = 0.0;
-      L.ymax = -INFINITY;
-      if (L.phase >= L.n_phases) return true;
-    } else {
-      L.t += h_try;
-      L.h = h_next;
+      const double ym = located_max<D>(y, y5, f0, f1, h_try);
+      L.ymax = ym > L.ymax ? ym : L.ymax;
     }
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) y[c] = acc ? y5[c] : y[c];
+  if constexpr (SC == kDP) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) fs.k[c] = acc ? k7[c] : fs.k[c];
+  }
+  L.ymax = (acc && y[0] > L.ymax) ? y[0] : L.ymax;
+  if (acc && trunc) {
+    // phase end: the next phase starts with the step proposed before the
+    // truncation (L.h is left as it was)
+    fs.have = false;
+    if constexpr (M::kTangent) {
+      double g[M::kK];
+      m.renormalise(y, g);
+      store_record<M>(a, L, L.ymax, g[0]);
+      store_growth<M, M::kK>(a, L, g);
+    } else {
+      store_record<M>(a, L, L.ymax, 0.0);
+    }
+    L.phase++;
+    if constexpr (M::kPrio) note_phase_end(L);
+    if constexpr (M::kDrive2) m.next_phase(a.t_phase);
+    L.t = 0.0;
+    L.ymax = -INFINITY;
+    if (L.phase >= L.n_phases) return true;
+  } else {
+    L.t += acc ? h_try : 0.0;
+    L.h = h_new;
   }
   if (a.max_steps > 0 && L.attempts >= a.max_steps) {
     L.status |= ENS_SYS_MAX_STEPS;

@@ -5,6 +5,7 @@ import pytest
 
 import oracle as O
 from paper_2011_01740_amd import inputs as I
+from tests.parity import CK_ATOL, CK_RTOL, PERTURB, close, per_system, sensitivity_mask
 
 pytestmark = pytest.mark.gpu
 
@@ -38,4 +39,11 @@ def test_usage_example():
     assert rec.shape == (8, 1, 64) and stats.shape == (ens.ENS_NSTAT, 64)
     assert np.all((status & ~ens.ENS_SYS_DT_MIN) == 0)
     assert np.all(stats[ens.ENS_ST_PHASES] == 16)
-    assert np.all(rec[:, 0, :] >= 1.0 - 1e-3)    # the bubble grows from rest
+    # the records of every tenth system against the oracle (insensitive ones)
+    idx = np.arange(0, 64, 10)
+    o = O.Opts(n_phases=16, n_record=8)
+    a = O.rkck45(O.KM, P[:, idx], I.KM_WATER, y0[:, idx], o)
+    b = O.rkck45(O.KM, P[:, idx], I.KM_WATER, y0[:, idx] * (1 + PERTURB), o)
+    keep = sensitivity_mask([a.records], [b.records], 1e-9, 1e-11)
+    ok = per_system(close(rec[:, :, idx], a.records, CK_RTOL, CK_ATOL))
+    assert keep.any() and not (keep & ~ok).any()
