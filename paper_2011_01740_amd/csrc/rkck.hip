@@ -857,28 +857,22 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
     if (E > 1.0) L.status |= ENS_SYS_DT_MIN;
     const double h_next = clampd(h_try * fac, a.dt_min, a.dt_max);
     const double tol = a.event_tol;
-    // event detection: overshoot -> secant retry from the same point
+    // event detection: overshoot -> secant retry from the same point.  The
+    // tests are plain compares; the secant steps (divisions) are formed only
+    // when one of them fired, which few steps do.
+    const double g3o = y[2] - m.delta, g3n = y5[2] - m.delta;  // lift-off
+    const bool free = !m.seated;
+    const bool ev_imp = free && y[0] > 0.0 && y5[0] < -tol;   // impact, y1 decreasing through 0
+    const bool ev_swal = free && y[0] == 0.0 && y5[0] < -tol; // rebound swallowed by one step
+    const bool ev_max = free && y[1] > 0.0 && y5[1] < -tol;   // local maximum, y2 decreasing
+    const bool ev_lift = !free && g3o < 0.0 && g3n > tol;
+    const bool over = ev_imp || ev_swal || ev_max || ev_lift;
     double hs = INFINITY;
-    bool over = false;
-    if (!m.seated) {
-      if (y[0] > 0.0 && y5[0] < -tol) {  // impact, y1 decreasing through 0
-        hs = fmin(hs, h_try * y[0] / (y[0] - y5[0]));
-        over = true;
-      }
-      if (y[0] == 0.0 && y5[0] < -tol) {  // rebound swallowed by one step
-        hs = fmin(hs, 0.5 * h_try);
-        over = true;
-      }
-      if (y[1] > 0.0 && y5[1] < -tol) {  // local maximum, y2 decreasing
-        hs = fmin(hs, h_try * y[1] / (y[1] - y5[1]));
-        over = true;
-      }
-    } else {
-      const double g3o = y[2] - m.delta, g3n = y5[2] - m.delta;  // lift-off
-      if (g3o < 0.0 && g3n > tol) {
-        hs = fmin(hs, h_try * (-g3o) / (g3n - g3o));
-        over = true;
-      }
+    if (over) {
+      if (ev_imp) hs = fmin(hs, h_try * y[0] / (y[0] - y5[0]));
+      if (ev_swal) hs = fmin(hs, 0.5 * h_try);
+      if (ev_max) hs = fmin(hs, h_try * y[1] / (y[1] - y5[1]));
+      if (ev_lift) hs = fmin(hs, h_try * (-g3o) / (g3n - g3o));
     }
     if (over && L.ev_iter < a.max_event_iter) {
       L.ev_iter++;

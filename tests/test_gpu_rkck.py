@@ -119,6 +119,38 @@ def test_prv_closed_form_events_on_gpu():
     assert close(g.t, a.t, 1e-9, 1e-9).all()
 
 
+@pytest.mark.parametrize("scheme", [O.CASH_KARP, O.DORMAND_PRINCE])
+def test_prv_seating_and_lift_off_on_gpu(scheme):
+    """A valve dropped from 1e-20 lands slower than v_stick and seats; while
+    seated the chamber fills until y3 = delta and the valve lifts off.  The
+    seated right-hand side must hold y1 = y2 = 0 exactly and fill y3 at
+    beta q, as the oracle does."""
+    ens = _ens()
+    solver = ens.ENS_RKDP45 if scheme == O.DORMAND_PRINCE else ens.ENS_RKCK45
+    P = np.array([[1.0, 1.0, 2.0]])
+    y0 = np.array([[1e-20, 1e-20, 1e-20], [0.0, 0.0, 0.0], [9.9, 9.5, 9.9]])
+    # one impact: the state right after seating
+    o1 = O.Opts(n_phases=2, n_record=2, max_impacts=1, scheme=scheme)
+    g = gpu_ck(3, P, y0, o1, solver=solver, budgets=[(2, 1)])
+    a = O.rkck45(O.PRV, P, I.PRV_DEFAULT, y0, o1)
+    # the first two seat; the third (q = 2) lands fast enough to rebound
+    seated = np.array([True, True, False])
+    assert np.array_equal((a.status & O.SYS_SEATED) != 0, seated)
+    assert np.array_equal((g.status & O.SYS_SEATED) != 0, seated)
+    assert np.all(g.y[0] == 0.0) and np.all(g.y[1, seated] == 0.0)
+    assert close(g.y, a.y, CK_RTOL, CK_ATOL).all()
+    # two phases: seated, filled, lifted off, next local maximum
+    o2 = O.Opts(n_phases=2, n_record=2, scheme=scheme)
+    g = gpu_ck(3, P, y0, o2, solver=solver)
+    a = O.rkck45(O.PRV, P, I.PRV_DEFAULT, y0, o2)
+    assert np.array_equal(g.status, a.status)
+    assert np.array_equal(g.stats[O.ST_PHASES], a.stats[O.ST_PHASES])
+    assert np.array_equal(g.stats[O.ST_IMPACTS], a.stats[O.ST_IMPACTS])
+    assert close(g.records, a.records, CK_RTOL, CK_ATOL).all()
+    assert close(g.y, a.y, CK_RTOL, CK_ATOL).all()
+    assert close(g.t, a.t, CK_RTOL, CK_ATOL).all()
+
+
 def test_resume_is_bit_identical():
     P, y0 = I.km_grid(8, 8)
     full = gpu_ck(2, P, y0, O.Opts(n_phases=4, n_record=4))
