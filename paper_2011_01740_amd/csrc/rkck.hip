@@ -247,6 +247,31 @@ __device__ __forceinline__ void sincos_taylor(double x, double *s, double *c) {
   *c = fma(-pc, x2, 1.0);
 }
 
+// sin(pi x) and cos(pi x), |x| < 2^30: x minus the nearest multiple of 1/2
+// (exact) leaves |r| <= 1/4; pi r is formed as a rounded product plus its
+// error (FMA) and the error of pi's double, the series above gives sin and
+// cos of the rounded part, a first-order term adds the rest, and the quarter
+// turns swap and negate.  Within an ulp of the correctly rounded values;
+// about half the instructions of the general library routine, which
+// reduces any argument.
+__device__ __forceinline__ void sincospi_quarter(double x, double *s, double *c) {
+  constexpr double kPiLo = 1.2246467991473532e-16;  // pi - (double)pi
+  const double q = rint(2.0 * x);
+  const double r = fma(q, -0.5, x);
+  const double t = M_PI * r;
+  const double tl = fma(M_PI, r, -t) + kPiLo * r;
+  double sr, cr;
+  sincos_taylor<9, 10>(t, &sr, &cr);
+  const double sr1 = fma(tl, cr, sr), cr1 = fma(-tl, sr, cr);
+  sr = sr1;
+  cr = cr1;
+  const int k = (int)q & 3;           // quarter turns modulo 4 (two's complement)
+  const double ss = (k & 1) ? cr : sr;
+  const double cc = (k & 1) ? sr : cr;
+  *s = (k & 2) ? -ss : ss;            // k = 2, 3
+  *c = ((k + 1) & 2) ? -cc : cc;      // k = 1, 2
+}
+
 // Dimensionless Keller--Miksis equation (Sec. 4.2), single-frequency drive.
 // The lane derives its coefficients from (P_A1, f1) and the shared material
 // constants when it picks the system up; only the nine that are non-zero for
@@ -260,7 +285,8 @@ __device__ __forceinline__ void sincos_taylor(double x, double *s, double *c) {
 // FAST (chosen by the host when 3 gamma = 21/5, the polytropic exponent of
 // air, and dt_max <= 1/8): the gas term is (1/y1)^4 y1^(-1/5) with the Newton
 // fifth root, and the forcing phase of each stage, 2 pi (t + c_i h), comes
-// from sin/cos of 2 pi t (once per attempted step) by angle addition with the
+// from sin/cos of 2 pi t (once per attempted step, by quarter-turn reduction
+// and a series) by angle addition with the
 // small offset 2 pi c_i h <= pi/4.  Otherwise exp(-K10 log y1) and sincospi
 // per stage.
 // DUAL (chosen when a sub-ensemble has P_A2 != 0): the second drive
@@ -268,7 +294,7 @@ __device__ __forceinline__ void sincos_taylor(double x, double *s, double *c) {
 // with phi the drive's phase when the integration phase began, carried
 // across phases and stored per system (Sec. 4.2: the drive is a function of
 // the absolute time, while tau restarts with each phase).  Its stage angles
-// 2 pi K11 c_i h need not be small, so each stage takes sincospi.
+// 2 pi K11 c_i h need not be small, so each stage reduces its own angle.
 // PSYS: (P_A2, f2, theta, R_E) are per-system parameters 2..5 instead of
 // shared ones (the six control parameters of Sec. 4.2 swept together).
 template <bool FAST, bool DUAL = false, bool PSYS = false>
@@ -333,7 +359,7 @@ struct MKM {
   // stage 4's plus stage 2's, stage 7 the same angle as stage 6.
   double so2, co2, so4, co4, so1, co1;
   __device__ void begin(double t) {
-    if constexpr (FAST) sincospi(2.0 * t, &s0, &c0);
+    if constexpr (FAST) sincospi_quarter(2.0 * t, &s0, &c0);
   }
   // SC: the scheme; S: the stage (1..7); tau: its time; h: the attempted step.
   template <int SC, int S>
@@ -421,7 +447,7 @@ struct MKM {
     if constexpr (DUAL) {
       if (dual) {
         double s2, c2;
-        sincospi(fma(2.0, fma(K11, tau, phi), thpi), &s2, &c2);
+        sincospi_quarter(fma(2.0, fma(K11, tau, phi), thpi), &s2, &c2);
         fs = fma(K6, s2, fs);
         fc = fma(K8, c2, fc);
       }
