@@ -309,7 +309,7 @@ struct MKM {
   static constexpr bool kDrive2 = DUAL;
   static constexpr int kF = 1;
   static constexpr bool kTangent = false;
-  double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49;
+  double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49, K9d3;  // K9d3 = K9 / 3
   double s0, c0;  // sin, cos (2 pi t) at the start of the attempted step
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
     const double pa = P[i], f = P[n + i];
@@ -330,6 +330,7 @@ struct MKM {
     K9 = re * w / (2.0 * M_PI * cL);
     K10 = 3.0 * gam;
     K49 = K4 * K9;
+    K9d3 = K9 / 3.0;   // once per system, not per attempt
     if constexpr (DUAL) {
       const double pa2 = PSYS ? P[2 * n + i] : sh[8];
       const double w2 = 2.0 * M_PI * (PSYS ? P[3 * n + i] : sh[9]);
@@ -456,7 +457,7 @@ struct MKM {
     double N = fma(K1, y2, K0) * gas;
     N = fma(-fs, u, N);
     N = fma(-fma(K4, y2, K3), r1, N);
-    N = fma(-(fma(-K9 / 3.0, y2, 1.0) * 1.5) * y2, y2, N);
+    N = fma(-(fma(-K9d3, y2, 1.0) * 1.5) * y2, y2, N);
     N = fma(-fc, y1, N);
     f[0] = y2;
     f[1] = N * (y1 * qd);
