@@ -72,3 +72,16 @@ def test_surrogate_create_validates_batch():
     h = ctypes.c_void_p()
     assert L.sur_create(0, None, 100, ctypes.byref(h)) == ens.ENS_E_INVAL
     assert L.sur_create(0, None, 0, ctypes.byref(h)) == ens.ENS_E_INVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus N > 1 exits with status 2 and says so,
+    before touching any device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
