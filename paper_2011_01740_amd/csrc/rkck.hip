@@ -247,7 +247,7 @@ __device__ __forceinline__ void sincos_taylor(double x, double *s, double *c) {
   *c = fma(-pc, x2, 1.0);
 }
 
-// sin(pi x) and cos(pi x), |x| < 2^30: x minus the nearest multiple of 1/2
+// sin(pi x) and cos(pi x), |x| < 2^50: x minus the nearest multiple of 1/2
 // (exact) leaves |r| <= 1/4; pi r is formed as a rounded product plus its
 // error (FMA) and the error of pi's double, the series above gives sin and
 // cos of the rounded part, a first-order term adds the rest, and the quarter
@@ -265,7 +265,7 @@ __device__ __forceinline__ void sincospi_quarter(double x, double *s, double *c)
   const double sr1 = fma(tl, cr, sr), cr1 = fma(-tl, sr, cr);
   sr = sr1;
   cr = cr1;
-  const int k = (int)q & 3;           // quarter turns modulo 4 (two's complement)
+  const int k = (int)(q - 4.0 * floor(0.25 * q));  // quarter turns modulo 4 (exact)
   const double ss = (k & 1) ? cr : sr;
   const double cc = (k & 1) ? sr : cr;
   *s = (k & 2) ? -ss : ss;            // k = 2, 3
