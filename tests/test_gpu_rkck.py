@@ -151,16 +151,21 @@ def test_prv_seating_and_lift_off_on_gpu(scheme):
     assert close(g.t, a.t, CK_RTOL, CK_ATOL).all()
 
 
-def test_km_long_phase_matches_oracle():
+@pytest.mark.parametrize("second_drive", [False, True])
+def test_km_long_phase_matches_oracle(second_drive):
     """One phase of 200 acoustic cycles: the forcing angle runs to 400
-    half-turns within the phase, so the kernel's reduction of sin/cos of
-    2 pi t to the nearest quarter turn covers hundreds of turns.  A small
-    drive keeps the response near-linear (insensitive) so the oracle's own
-    rounding of the large radian argument does not matter."""
+    half-turns within the phase (the second drive's, at f2 = 150 kHz, to
+    ~3000), so the kernel's reduction of the drive angles to the nearest
+    quarter turn covers hundreds of turns.  Small drives keep the response
+    near-linear (insensitive) so the oracle's own rounding of the large
+    radian arguments does not matter."""
     P, y0 = I.km_grid(4, 4, pa_lo=2e3, pa_hi=2e4)
+    sh = list(I.KM_WATER)
+    if second_drive:
+        sh[8], sh[9], sh[10] = 5e3, 150e3, 0.7
     o = O.Opts(t_phase=200.0, n_phases=1, n_record=1)
-    g = gpu_ck(2, P, y0, o)
-    a, keep = oracle_pair(O.KM, P, I.KM_WATER, y0, o)
+    g = gpu_ck(2, P, y0, o, shared=sh)
+    a, keep = oracle_pair(O.KM, P, np.array(sh), y0, o)
     # values to the adaptive tolerance; over the thousands of steps of one
     # long phase an accept/reject decision at E ~ 1 may fall differently
     # (the oracle divides and rounds a radian argument up to ~1257), so the
