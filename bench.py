@@ -153,6 +153,15 @@ def prv_cpu_baseline(ensembles, m_each, solver="ck"):
             "sample": f"first {m_each} systems of each ensemble with its budget, {el:.1f} s"}
 
 
+def lane_busy(steps, att, launch):
+    """Share of the lane-attempt slots of an adaptive launch that carried an
+    attempt: attempted steps / (resident lanes x the longest system's
+    attempts), taking every attempt as equally long.  1 means no lane idled
+    while the longest system ran; the rest is the tail."""
+    lanes = int(launch["grid"]) * int(launch["block"])
+    return float(steps) / max(lanes * int(att.max()), 1)
+
+
 def run_case(case, args):
     """Single launches for counter runs: a 1 GiB device copy (the scale of the
     FETCH_SIZE / WRITE_SIZE counters), a Keller--Miksis grid, or the valve
@@ -198,6 +207,7 @@ def run_case(case, args):
                 "rhs_per_s": float(r.stats[2].sum()) / r.kernel_ms * 1e3,
                 "attempts_max_over_mean": float(att.max() / max(att.mean(), 1e-30)),
                 "attempts_max": int(att.max()),
+                "lane_busy_fraction": lane_busy(steps, att, r.launch),
                 "us_per_attempt_longest": r.kernel_ms * 1e3 / max(int(att.max()), 1),
                 "launch": r.launch}
         if args.km_tangent:
@@ -252,6 +262,7 @@ def run_case(case, args):
         line = {"case": "prv", "solver": args.solver, "budget_divisor": args.prv_div,
                 "ensembles": [list(e) for e in ensm],
                 "attempts_max": int(att.max()),
+                "lane_busy_fraction": lane_busy(steps, att, r.launch),
                 "us_per_attempt_longest": r.kernel_ms * 1e3 / max(int(att.max()), 1),
                 "kernel_ms": r.kernel_ms, "attempted_steps": steps,
                 "steps_per_s": steps / r.kernel_ms * 1e3,
