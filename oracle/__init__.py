@@ -20,6 +20,10 @@ SYS_OK, SYS_DT_MIN, SYS_MAX_STEPS, SYS_NONFINITE = 0, 1, 2, 4
 SYS_SETTLED, SYS_EVENT_ITER, SYS_SEATED = 8, 16, 32
 ST_ACCEPTED, ST_REJECTED, ST_NRHS, ST_IMPACTS, ST_PHASES, ST_EVRETRY = range(6)
 NSTAT = 6
+# rows of the carried accessories (orc_rkck45_ext): running phase y1max, y1min,
+# phase start time, valve seated (1/0)
+CARRY_YMAX, CARRY_YMIN, CARRY_TPS, CARRY_SEATED = range(4)
+NCARRY = 4
 CASH_KARP, DORMAND_PRINCE = 0, 1
 
 _lib = None
@@ -69,7 +73,9 @@ class Opts:
 def lib():
     global _lib
     if _lib is None:
-        path = _build.LIB
+        # ORACLE_LIB selects another build of the same source (the sanitized
+        # one of the CPU sanitizer test)
+        path = os.environ.get("ORACLE_LIB") or _build.LIB
         if not os.path.exists(path):
             _build.build()
         L = C.CDLL(path)
@@ -80,6 +86,9 @@ def lib():
         L.orc_rkck45.argtypes = [C.c_int, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp,
                                  C.POINTER(_Opts), _dp, _dp, _dp, _dp, _dp, _i64p, _i32p,
                                  C.c_int]
+        L.orc_rkck45_ext.argtypes = [C.c_int, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp,
+                                     C.POINTER(_Opts), _dp, _dp, _dp, _dp, _dp, _i64p, _i32p,
+                                     _dp, _dp, _dp, C.c_int]
         L.orc_rkck_step.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, C.c_double, _dp, _dp]
         L.orc_rkck_tableau.argtypes = [_dp, _dp, _dp, _dp]
         L.orc_rkdp_step.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, C.c_double, _dp, _dp]
@@ -179,12 +188,17 @@ class AdaptiveResult:
     stats: np.ndarray    # [NSTAT][n] int64
     status: np.ndarray   # [n] int32
     phi: np.ndarray      # [n] Keller--Miksis: second drive's phase at the phase start
+    carry: np.ndarray    # [NCARRY][n] running phase y1max, y1min, phase start, seated
+    hx: np.ndarray       # [2][n] smallest, largest accepted step (phase-end cuts excluded)
 
 
-def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, phi0=None):
+def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, phi0=None,
+           carry0=None):
     """Adaptive solve of an ensemble through its phases with the scheme of
     opts.scheme (Cash--Karp by default).  phi0 (Keller--Miksis): the second
-    drive's phase in cycles at the start of the current phase (0 if None)."""
+    drive's phase in cycles at the start of the current phase (0 if None).
+    carry0: a previous result's `carry` (None: every system starts fresh);
+    with y, t, h, phi and carry passed back a solve resumes exactly."""
     D = dim(model) * (1 + int(opts.lyapunov))
     y0 = _f64(y0)
     n = y0.shape[-1]
@@ -203,15 +217,18 @@ def rkck45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, 
     rec = np.full((max(R, 0), F, n), np.nan)
     stats = np.zeros((NSTAT, n), dtype=np.int64)
     status = np.zeros(n, dtype=np.int32)
+    carry0 = None if carry0 is None else _f64(carry0).reshape(NCARRY, n)
+    carry = np.empty((NCARRY, n))
+    hx = np.empty((2, n))
     o = opts._c()
-    rc = lib().orc_rkck45(model, n, _ptr(params), _ptr(sh), _ptr(y0), _ptr(t0), _ptr(h0),
-                          _ptr(phi0), C.byref(o), _ptr(y), _ptr(t), _ptr(h), _ptr(phi),
-                          _ptr(rec) if R > 0 else None,
-                          stats.ctypes.data_as(_i64p), status.ctypes.data_as(_i32p),
-                          int(nthreads))
+    rc = lib().orc_rkck45_ext(model, n, _ptr(params), _ptr(sh), _ptr(y0), _ptr(t0), _ptr(h0),
+                              _ptr(phi0), C.byref(o), _ptr(y), _ptr(t), _ptr(h), _ptr(phi),
+                              _ptr(rec) if R > 0 else None,
+                              stats.ctypes.data_as(_i64p), status.ctypes.data_as(_i32p),
+                              _ptr(carry0), _ptr(carry), _ptr(hx), int(nthreads))
     if rc:
         raise ValueError("orc_rkck45 rejected its arguments")
-    return AdaptiveResult(y, t, h, rec, stats, status, phi)
+    return AdaptiveResult(y, t, h, rec, stats, status, phi, carry, hx)
 
 
 def rkck_step(model, t, y, p, shared, h):
@@ -234,11 +251,12 @@ def rkck_tableau():
     return a, b5, b4, c
 
 
-def rkdp45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, phi0=None):
+def rkdp45(model, params, shared, y0, opts: Opts, t0=None, h0=None, nthreads=1, phi0=None,
+           carry0=None):
     """Adaptive Dormand--Prince solve (first same as last) of an ensemble."""
     o = Opts(**{f.name: getattr(opts, f.name) for f in fields(opts)})
     o.scheme = DORMAND_PRINCE
-    return rkck45(model, params, shared, y0, o, t0, h0, nthreads, phi0)
+    return rkck45(model, params, shared, y0, o, t0, h0, nthreads, phi0, carry0)
 
 
 def rkdp_step(model, t, y, p, shared, h):

@@ -13,17 +13,25 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# the same source built with AddressSanitizer and UndefinedBehaviorSanitizer
+# (every report fatal), for a CPU test run of the oracle's pins; the process
+# loading it needs the ASan runtime preloaded (LD_PRELOAD)
+LIB_SANITIZED = os.path.join(HERE, "liboracle_san.so")
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all"]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    out = LIB_SANITIZED if sanitize else LIB
+    opt = SANITIZE_FLAGS if sanitize else ["-O2"]
+    cmd = ["gcc", "-std=c11", *opt, "-ffp-contract=off", "-fno-fast-math",
            "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-Wno-unused-parameter", SRC, "-o", LIB + ".tmp", "-lm"]
+           "-Wno-unused-parameter", SRC, "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

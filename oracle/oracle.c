@@ -50,7 +50,13 @@
  *     h * g_old / (g_old - g_new); the smallest such step wins; at most
  *     max_event_iter retries, after which the step is taken as located;
  *   - records are a ring: phase k (0-based, counted within one call) is
- *     stored in slot k mod n_record.
+ *     stored in slot k mod n_record;
+ *   - a call may stop inside a phase (step cap, impact budget); what the
+ *     phase has gathered so far -- its running y1 maximum and minimum (the
+ *     accessories of Sec. 4.2.1, per-system values updated after every
+ *     successful step), its start time, and whether the valve rests on its
+ *     seat -- is carried out of the call with (y, t, h) and, passed back,
+ *     continues the phase exactly (orc_rkck45_ext).
  */
 #include "oracle.h"
 
@@ -561,10 +567,19 @@ static double located_max(const double *y0, const double *y1, const double *f0,
   return hermite(y0, y1, f0, f1, h, 0, 0.5 * (lo + hi));
 }
 
+/* Smallest and largest accepted step (hx may be NULL).  Steps cut short to
+ * land on a phase end are not counted: their length is set by the phase
+ * end, not by the error control. */
+static void note_step(double hx[2], double h) {
+  if (!hx) return;
+  if (h < hx[0]) hx[0] = h;
+  if (h > hx[1]) hx[1] = h;
+}
+
 /* Integrate one system through its phases.  y, t, h are updated in place. */
 static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, double *hp,
                       double *records, int64_t n, int64_t i, int64_t st[ORC_NSTAT],
-                      int32_t *status) {
+                      int32_t *status, double carry[ORC_NCARRY], double hx[2]) {
   const int D = s->D;
   /* with k tangents the record fields 1 .. k are the phase's log growths */
   const int F = s->tangent ? 1 + s->tangent : orc_nrec_fields(s->model);
@@ -572,8 +587,12 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
   const int fixed_len = (s->model != ORC_PRV);
   const double tol_ev = o->event_tol;
   double t = *tp, h = *hp;
-  double t_ps = t;                 /* start time of the current phase */
-  double ymax = -INFINITY, ymin = INFINITY;
+  /* the running phase's accessories and the seated state, carried over
+   * from the previous call (a solve that stopped inside a phase resumes
+   * it) */
+  double t_ps = carry[ORC_CARRY_TPS];     /* start time of the current phase */
+  double ymax = carry[ORC_CARRY_YMAX], ymin = carry[ORC_CARRY_YMIN];
+  s->seated = carry[ORC_CARRY_SEATED] != 0.0;
   int64_t phase = 0, attempts = 0;
   int ev_iter = 0;
   double y5[MAXD], err[MAXD];
@@ -672,6 +691,7 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
       for (int c = 0; c < D; ++c) y[c] = y5[c];
       t = t + h_try;
       st[ORC_ST_ACCEPTED]++;
+      note_step(hx, h_try);
       h = h_next;
       for (int c = 0; c < D; ++c) k1[c] = k7[c];   /* first same as last */
       int phase_end = 0, stop = 0;
@@ -776,18 +796,24 @@ static void solve_one(sysctx *s, const orc_opts *o, double *y, double *tp, doubl
       st[ORC_ST_PHASES] = phase;
       ymax = -INFINITY;
       t = 0.0;
+      t_ps = 0.0;
       if (s->model == ORC_KM || s->model == ORC_KM6) {
         /* the second drive went through C11 x t_phase cycles in the phase */
         const double v = s->phi2 + s->C[11] * o->t_phase;
         s->phi2 = v - floor(v);
       }
     } else {
+      note_step(hx, h_try);
       t = t + h_try;
       h = h_next;
     }
   }
   *tp = t;
   *hp = h;
+  carry[ORC_CARRY_YMAX] = ymax;
+  carry[ORC_CARRY_YMIN] = ymin;
+  carry[ORC_CARRY_TPS] = t_ps;
+  carry[ORC_CARRY_SEATED] = s->seated ? 1.0 : 0.0;
 }
 
 int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
@@ -795,6 +821,15 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
                const orc_opts *opt, double *y_out, double *t_out, double *h_out,
                double *phi_out, double *records, int64_t *stats, int32_t *status,
                int nthreads) {
+  return orc_rkck45_ext(model, n, params, shared, y0, t0, h0, phi0, opt, y_out, t_out, h_out,
+                        phi_out, records, stats, status, NULL, NULL, NULL, nthreads);
+}
+
+int orc_rkck45_ext(int model, int64_t n, const double *params, const double *shared,
+                   const double *y0, const double *t0, const double *h0, const double *phi0,
+                   const orc_opts *opt, double *y_out, double *t_out, double *h_out,
+                   double *phi_out, double *records, int64_t *stats, int32_t *status,
+                   const double *carry_in, double *carry_out, double *hx, int nthreads) {
   const int D = orc_dim(model), P = orc_nparam(model);
   if (D < 0 || n < 0 || !opt) return -1;
   if (opt->n_record < 0 || opt->n_phases < 0) return -1;
@@ -823,7 +858,17 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
     double h = h0 ? h0[i] : opt->dt0;
     int64_t st[ORC_NSTAT] = {0, 0, 0, 0, 0, 0};
     int32_t stat = ORC_SYS_OK;
-    solve_one(&s, opt, y, &t, &h, records, n, i, st, &stat);
+    double hxi[2] = {INFINITY, -INFINITY};
+    double cy[ORC_NCARRY] = {-INFINITY, INFINITY, t, 0.0};   /* a fresh start */
+    if (carry_in)
+      for (int k = 0; k < ORC_NCARRY; ++k) cy[k] = carry_in[k * n + i];
+    solve_one(&s, opt, y, &t, &h, records, n, i, st, &stat, cy, hx ? hxi : NULL);
+    if (carry_out)
+      for (int k = 0; k < ORC_NCARRY; ++k) carry_out[k * n + i] = cy[k];
+    if (hx) {
+      hx[i] = hxi[0];
+      hx[n + i] = hxi[1];
+    }
     if (y_out)
       for (int c = 0; c < Dint; ++c) y_out[c * n + i] = y[c];
     if (t_out) t_out[i] = t;

@@ -140,6 +140,29 @@ int orc_rkck45(int model, int64_t n, const double *params, const double *shared,
                double *phi_out, double *records, int64_t *stats, int32_t *status,
                int nthreads);
 
+/* What a system carries from one call to the next besides (y, t, h, phi):
+ * the running phase's y1max and y1min, the start time of the current phase
+ * (the valve's settled guard measures from it) and the valve's seated state
+ * (1 or 0).  Rows of the [ORC_NCARRY][n] carry arrays. */
+enum { ORC_CARRY_YMAX = 0, ORC_CARRY_YMIN = 1, ORC_CARRY_TPS = 2, ORC_CARRY_SEATED = 3,
+       ORC_NCARRY = 4 };
+
+/* orc_rkck45 with three optional arrays (NULL: not used):
+ *  carry_in [ORC_NCARRY][n]: the carried values from a previous call's
+ *    carry_out; NULL starts every system fresh (no running maximum or
+ *    minimum, phase start at t0, not seated).  Passing carry_out back with
+ *    y_out, t_out, h_out and phi_out resumes a solve exactly, also one that
+ *    stopped inside a phase (step cap, impact budget).
+ *  carry_out [ORC_NCARRY][n].
+ *  hx [2][n]: the smallest and the largest accepted step of the call (steps
+ *    cut short to land on a phase end are not counted); +inf / -inf when no
+ *    step was accepted. */
+int orc_rkck45_ext(int model, int64_t n, const double *params, const double *shared,
+                   const double *y0, const double *t0, const double *h0, const double *phi0,
+                   const orc_opts *opt, double *y_out, double *t_out, double *h_out,
+                   double *phi_out, double *records, int64_t *stats, int32_t *status,
+                   const double *carry_in, double *carry_out, double *hx, int nthreads);
+
 /* One Cash--Karp step without error control, for order and stability tests:
  * y5 = fifth-order result, y4 = embedded fourth-order result. */
 int orc_rkck_step(int model, double t, const double *y, const double *p,

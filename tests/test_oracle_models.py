@@ -523,3 +523,94 @@ def test_prv_impact_budget_stops_the_system():
     assert np.all(r.stats[O.ST_IMPACTS] == 25)
     assert np.all(r.stats[O.ST_PHASES] < 1000)
     assert np.all(r.y[0] == 0.0) and np.all(r.y[1] > 0.0)
+
+
+# ------------------------------------------------------------------ resuming inside a phase
+def _split_run(model, P, sh, y0, opts_a, n_total, scheme=O.CASH_KARP):
+    """One system solved by a first call (opts_a, stopping early) and a
+    second call resuming it (state, clock, step, carried accessories) for
+    the remaining phases; returns (first, second)."""
+    a = O.rkck45(model, P, sh, y0, opts_a)
+    left = n_total - int(a.stats[O.ST_PHASES, 0])
+    ob = O.Opts(n_phases=left, n_record=max(left, 1), scheme=scheme,
+                t_cap=opts_a.t_cap, t_phase=opts_a.t_phase)
+    b = O.rkck45(model, P, sh, a.y, ob, t0=a.t, h0=a.h, phi0=a.phi, carry0=a.carry)
+    return a, b
+
+
+@pytest.mark.parametrize("scheme", [O.CASH_KARP, O.DORMAND_PRINCE])
+@pytest.mark.parametrize("q", [0.6, 2.5, 6.0])
+def test_prv_resume_inside_a_phase_equals_one_solve(q, scheme):
+    """A valve solve stopped by its impact budget (right after an impact,
+    inside a Poincare phase) and resumed with its carried accessories gives
+    the uninterrupted solve's phases, records and final state bit for bit."""
+    N = 12
+    P, y0 = I.prv_linspace(1, q, q)
+    whole = O.rkck45(O.PRV, P, PRV_SH, y0, O.Opts(n_phases=N, n_record=N, scheme=scheme))
+    a, b = _split_run(O.PRV, P, PRV_SH, y0,
+                      O.Opts(n_phases=N, n_record=N, max_impacts=4, scheme=scheme), N, scheme)
+    assert a.stats[O.ST_IMPACTS, 0] == 4
+    p1 = int(a.stats[O.ST_PHASES, 0])
+    assert 0 < p1 < N
+    assert b.stats[O.ST_PHASES, 0] == N - p1
+    both = np.concatenate([a.records[:p1], b.records[:N - p1]])
+    np.testing.assert_array_equal(both, whole.records)
+    np.testing.assert_array_equal(b.y, whole.y)
+    assert b.t[0] == whole.t[0]
+    for k in (O.ST_ACCEPTED, O.ST_REJECTED, O.ST_IMPACTS, O.ST_EVRETRY):
+        assert a.stats[k, 0] + b.stats[k, 0] == whole.stats[k, 0]
+
+
+def test_prv_resume_of_a_seated_valve_equals_one_solve():
+    """The valve stopped seated (the impact budget ends the call at the
+    seating impact) stays seated when resumed: the chamber fills and it
+    lifts off exactly as in one solve (a restart in free flight would drop
+    below the seat and impact again)."""
+    y0 = np.array([[1e-20], [0.0], [9.9]])
+    P = np.array([[1.0]])
+    whole = O.rkck45(O.PRV, P, PRV_SH, y0, O.Opts(n_phases=2, n_record=2))
+    a, b = _split_run(O.PRV, P, PRV_SH, y0, O.Opts(n_phases=2, n_record=2, max_impacts=1), 2)
+    assert a.carry[O.CARRY_SEATED, 0] == 1.0 and a.carry[O.CARRY_YMIN, 0] == 0.0
+    assert b.stats[O.ST_IMPACTS, 0] + 1 == whole.stats[O.ST_IMPACTS, 0]
+    np.testing.assert_array_equal(b.y, whole.y)
+    p1 = int(a.stats[O.ST_PHASES, 0])
+    np.testing.assert_array_equal(np.concatenate([a.records[:p1], b.records[:2 - p1]]),
+                                  whole.records)
+    # without the carried seated state the resumed valve takes another impact
+    fresh = O.rkck45(O.PRV, P, PRV_SH, a.y, O.Opts(n_phases=2, n_record=2), t0=a.t, h0=a.h)
+    assert fresh.stats[O.ST_IMPACTS, 0] > b.stats[O.ST_IMPACTS, 0]
+
+
+def test_prv_settled_guard_counts_from_the_carried_phase_start():
+    """The settled guard measures from the phase start carried over: a
+    solve stopped at t = 30 of an overdamped release and resumed ends its
+    phase at t = 50, not at 80."""
+    sh = np.array([5.0, 10.0, 0.0, 0.8])
+    P, y0 = np.array([[1.0]]), np.array([[3.0], [0.0], [11.0]])
+    whole = O.rkck45(O.PRV, P, sh, y0, O.Opts(n_phases=1, n_record=1, t_cap=50.0))
+    a, b = _split_run(O.PRV, P, sh, y0, O.Opts(n_phases=1, n_record=1, t_cap=50.0,
+                                               max_steps=40), 1)
+    assert a.stats[O.ST_PHASES, 0] == 0 and a.carry[O.CARRY_TPS, 0] == 0.0
+    assert b.status[0] & O.SYS_SETTLED
+    assert b.t[0] == whole.t[0] and b.t[0] < 50.2
+    np.testing.assert_array_equal(b.records, whole.records)
+
+
+def test_km_resume_inside_a_phase_equals_one_solve():
+    """A Keller--Miksis solve stopped by the step cap inside a phase keeps
+    its running maximum in the carried accessories: the records of the
+    resumed solve equal one solve's."""
+    P, y0 = I.km_grid(2, 2)
+    sh = I.KM_WATER
+    N = 6
+    whole = O.rkck45(O.KM, P, sh, y0, O.Opts(n_phases=N, n_record=N))
+    for i in range(P.shape[1]):
+        Pi, yi = P[:, i:i + 1], y0[:, i:i + 1]
+        cap = int(whole.stats[O.ST_ACCEPTED, i] + whole.stats[O.ST_REJECTED, i]) // 3
+        a, b = _split_run(O.KM, Pi, sh, yi, O.Opts(n_phases=N, n_record=N, max_steps=cap), N)
+        p1 = int(a.stats[O.ST_PHASES, 0])
+        assert a.status[0] & O.SYS_MAX_STEPS and p1 < N
+        assert np.isfinite(a.carry[O.CARRY_YMAX, 0])
+        np.testing.assert_array_equal(np.concatenate([a.records[:p1], b.records[:N - p1]]),
+                                      whole.records[:, :, i:i + 1])
+        np.testing.assert_array_equal(b.y[:, 0], whole.y[:, i])
