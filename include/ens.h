@@ -128,8 +128,32 @@ enum ens_stat_row {
   ENS_ST_IMPACTS = 3, ENS_ST_PHASES = 4, ENS_ST_EVRETRY = 5, ENS_NSTAT = 6
 };
 
+/* Rows of the ENS_CARRY double [ENS_NCARRY][n] array (adaptive solvers):
+ * what a system's current integration phase has gathered so far.  A solve
+ * that stops inside a phase (step cap, the valve's impact budget) leaves it
+ * here, and the next solve on the handle continues that phase from it: the
+ * running y1 maximum and minimum over the phase's step points (the
+ * accessories of Sec. 4.2.1, per-system values updated after every
+ * successful step), the time at which the phase began (the valve's settled
+ * guard counts from it) and whether the valve rests on its seat (1) or not
+ * (0).  ens_set_state resets every system to a fresh phase (-inf, +inf, its
+ * t0, 0). */
+enum ens_carry_row {
+  ENS_CARRY_YMAX = 0, ENS_CARRY_YMIN = 1, ENS_CARRY_TPS = 2, ENS_CARRY_SEATED = 3,
+  ENS_NCARRY = 4
+};
+
 #define ENS_MAX_ENSEMBLES 16
 #define ENS_MAX_SHARED 16
+
+/* Caller-supplied device allocator (ens_desc.alloc / free): alloc returns
+ * `bytes` of device memory on the handle's device, at least 256-byte
+ * aligned, or NULL on failure; free releases what alloc returned.  ctx is
+ * ens_desc.alloc_ctx, passed through untouched.  Both run on the calling
+ * thread, inside ens_create and the first calls that need a buffer (never
+ * inside ens_solve or ens_order_by_work once the handle's buffers exist). */
+typedef void *(*ens_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*ens_free_fn)(void *ptr, void *ctx);
 
 /* Handle description.  The n systems may be split into n_ensembles
  * sub-ensembles (contiguous index ranges, each with its own shared
@@ -160,9 +184,19 @@ typedef struct {
                              manipulation (renormalisation) of the paper's
                              introduction, done inside the solve.  0 = off */
   int32_t reserved_;      /* must be 0                                       */
+  ens_alloc_fn alloc;     /* device allocator for every buffer the handle
+                             owns, or NULL for hipMalloc / hipFree; alloc and
+                             free are given together or not at all          */
+  ens_free_fn free;
+  void *alloc_ctx;        /* passed to alloc and free                        */
 } ens_desc;
 
-/* Creates a handle, allocates the parameter and state buffers on `device`
+/* Creates a handle, allocates every buffer a solve on it needs on `device`
+ * (parameters, state, outputs, and for the adaptive solvers the queue, the
+ * queue order and the scratch of ens_order_by_work; records are allocated by
+ * the first solve that keeps more of them than before; ens_set_order,
+ * ens_set_params_gather and ens_tune allocate their scratch on first use and
+ * keep it)
  * and sets every sub-ensemble's shared parameters to the model defaults
  * (Lorenz sigma = 10, beta = 8/3; Keller--Miksis water at 25 C with R_E =
  * 10 um; valve kappa = 1.25, delta = 10, beta = 20, r = 0.8).
@@ -225,9 +259,21 @@ int ens_set_budget(ens_t h, int32_t ensemble, int64_t n_phases, int64_t max_impa
  * absolute for the valve.  Keller--Miksis adaptive handles: the second
  * drive's phase (ENS_DRIVE_PHASE) is set to 0.  Passing the ENS_STATE /
  * ENS_TIME / ENS_H outputs of a solve (and, for a dual-frequency Keller--
- * Miksis drive, ENS_DRIVE_PHASE through ens_set_drive_phase) resumes it. */
+ * Miksis drive, ENS_DRIVE_PHASE through ens_set_drive_phase) resumes it;
+ * so does a further ens_solve without ens_set_state, which also continues a
+ * phase that the previous solve stopped inside (ENS_CARRY).  Adaptive
+ * handles: every system starts a fresh phase (ENS_CARRY reset). */
 int ens_set_state(ens_t h, const double *y0, const double *t0, const double *h0,
                   int32_t where);
+
+/* Adaptive solvers: sets the carried phase accessories, [ENS_NCARRY][n]
+ * doubles in the ENS_CARRY layout (for instance read from another handle
+ * after its solve), after ens_set_state.  Together with ens_set_state's
+ * y0 / t0 / h0 (and ENS_DRIVE_PHASE) a solve stopped inside a phase resumes
+ * exactly.  ENS_HOST copies and waits; ENS_DEVICE is stream-ordered.
+ * Errors: ENS_E_UNSUPPORTED (RK4), ENS_E_ORDER (no state yet), ENS_E_INVAL,
+ * ENS_E_HIP. */
+int ens_set_carry(ens_t h, const double *carry, int32_t where);
 
 /* Keller--Miksis, adaptive solvers (Sec. 4.2, dual-frequency forcing): sets
  * the second drive's phase per system, [n] doubles in cycles (the
@@ -310,13 +356,15 @@ enum ens_field {
                       1 otherwise; slots never written hold NaN             */
   ENS_STATS = 5,   /* int64 [ENS_NSTAT][n]                                   */
   ENS_STATUS = 6,  /* int32 [n]                                              */
-  ENS_DRIVE_PHASE = 7 /* double [n], Keller--Miksis (ENS_KM, ENS_KM6)
+  ENS_DRIVE_PHASE = 7, /* double [n], Keller--Miksis (ENS_KM, ENS_KM6)
                       adaptive handles: phase of the second drive in
                       cycles of omega2, in [0, 1), at
                       the start of the system's current integration phase;
                       its forcing angle is 2 pi (phase + C11 tau) + theta,
                       C11 = f2 / f1 (Sec. 4.2).  Zeroed by ens_set_state,
                       advanced by C11 t_phase (modulo 1) at every phase end */
+  ENS_CARRY = 8    /* double [ENS_NCARRY][n], adaptive handles: the running
+                      phase's accessories (enum ens_carry_row)              */
 };
 
 /* Copies a result field into dst (bytes must equal the field size).
@@ -332,8 +380,11 @@ size_t ens_field_bytes(ens_t h, int32_t field);
  * lane {1, 2, 4} on min(n_steps, trial_len) steps; RKCK45: block {64, 128,
  * 256} x refill threshold {1, 8, 32, 64} with every system capped at
  * min(phases, trial_len) phases and impacts -- timing each with HIP events
- * (best of two), restores the state it started from, and stores the fastest
- * choice in a process-wide cache keyed by (model, solver, device
+ * (best of three), restores the state it started from (state, clock, step,
+ * drive phase, carried accessories), and stores the fastest choice (a
+ * candidate displaces an earlier one only when faster by more than 2%, so
+ * that near-ties resolve to the same choice from run to run) in a
+ * process-wide cache keyed by (model, solver, device
  * architecture, floor(log2 n)).  Later ens_solve calls whose launch fields
  * are 0 use the cached choice.  If the environment variable ENS_TUNE_CACHE
  * names a file, the cache is read from it on first use and rewritten after

@@ -1,28 +1,45 @@
 """Build libens.so (HIP, gfx950) in-tree.
 
-Every source is compiled by hipcc for gfx950 only.  Packed FP32 instructions
-are disabled (-packed-fp32-ops) for all device code.
+Every source is compiled by hipcc for gfx950 only, each to its own object
+(in parallel), then linked into one shared library.  Packed FP32
+instructions are disabled (-packed-fp32-ops) for all device code.
 """
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libens.so")
-SOURCES = ["ens_api.hip", "rk4.hip", "rkck.hip", "mlp.hip", "micro.hip"]
+SOURCES = ["ens_api.hip", "rk4.hip", "rkck.hip", "mlp.hip", "micro.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+ARCH = ["--offload-arch=gfx950"]
+FLAGS = [*ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+
+    def compile_one(src):
+        obj = os.path.join(OBJ, src.replace(".hip", ".o"))
+        cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", "8"))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *extra, *srcs, "-o", tmp]
+    cmd = [HIPCC, *ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

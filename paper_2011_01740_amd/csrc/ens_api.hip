@@ -30,6 +30,82 @@ ModelInfo model_info(int model) {
   return {0, 0, 0, 0};
 }
 
+int check_adaptive_opts(int model, int tangent, int64_t n, const ens_solve_opts *o,
+                        std::string *msg) {
+  auto pos = [](double v) { return v > 0.0 && std::isfinite(v); };
+  auto bad = [&](int code, const char *m) {
+    *msg = m;
+    return code;
+  };
+  if (!pos(o->dt0) || !pos(o->dt_min) || !pos(o->dt_max) || o->dt_max < o->dt_min)
+    return bad(ENS_E_INVAL, "need 0 < dt_min <= dt_max and dt0 > 0");
+  if (!(o->rtol >= 0.0) || !pos(o->atol)) return bad(ENS_E_INVAL, "need rtol >= 0 and atol > 0");
+  if (model != ENS_PRV && !pos(o->t_phase)) return bad(ENS_E_INVAL, "t_phase must be > 0");
+  if (model == ENS_PRV && (!pos(o->event_tol) || !pos(o->t_cap) || !(o->v_stick >= 0.0)))
+    return bad(ENS_E_INVAL, "bad event_tol, t_cap or v_stick");
+  if (o->n_phases < 0 || o->n_phases > (int64_t)UINT32_MAX || o->n_record < 0 ||
+      o->max_steps < 0 || o->max_event_iter < 0)
+    return bad(ENS_E_INVAL, "bad phase, record or step counts");
+  if (o->max_steps > (int64_t)UINT32_MAX) return bad(ENS_E_INVAL, "max_steps above 2^32");
+  if (o->spread < 0 || o->spread > n || o->reserved_ != 0)
+    return bad(ENS_E_INVAL, "spread must be in [0, n], reserved_ 0");
+  if (o->locate_max && tangent)
+    return bad(ENS_E_UNSUPPORTED, "locate_max is not built with the tangent");
+  if (o->locate_max && model != ENS_KM && model != ENS_KM6)
+    return bad(ENS_E_UNSUPPORTED, "locate_max is built for Keller--Miksis");
+  return ENS_OK;
+}
+
+// Keller--Miksis: the fast kernel (Newton fifth root, angle-addition forcing
+// phase) needs 3 gamma = 21/5 in every sub-ensemble and dt_max <= 1/8;
+// otherwise the general variant runs, and a second drive (P_A2 != 0) in any
+// sub-ensemble selects the variant that carries it.
+int kernel_model(int model, int tangent, const double (*shared)[ENS_MAX_SHARED], int n_ens,
+                 double dt_max) {
+  int kmodel = model;
+  if (model == ENS_KM) {
+    bool dual = false;
+    if (dt_max > 0.125) kmodel = ENS_KM_GENERAL;
+    for (int e = 0; e < n_ens; ++e) {
+      if (std::fabs(3.0 * shared[e][5] - 4.2) >= 1e-12) kmodel = ENS_KM_GENERAL;
+      if (shared[e][8] != 0.0) dual = true;
+    }
+    if (dual) kmodel = kmodel == ENS_KM ? ENS_KM_DUAL_FAST : ENS_KM_DUAL;
+  }
+  if (model == ENS_KM6) {
+    if (dt_max > 0.125) kmodel = ENS_KM6_GENERAL;
+    for (int e = 0; e < n_ens; ++e)
+      if (std::fabs(3.0 * shared[e][5] - 4.2) >= 1e-12) kmodel = ENS_KM6_GENERAL;
+  }
+  if (tangent) kmodel += tangent * kTangentModel;
+  return kmodel;
+}
+
+void default_shared(int model, double *sh) {
+  switch (model) {
+    case ENS_LORENZ:
+      sh[0] = 10.0;
+      sh[1] = 8.0 / 3.0;
+      break;
+    case ENS_KM:
+    case ENS_KM6: {
+      // ENS_KM6 takes the first 7 (the fluid), the rest are per system
+      const double w[11] = {997.0, 1497.0, 3166.0, 0.0728, 8.9e-4, 1.4,
+                            1.0e5, 10.0e-6, 0.0,    0.0,    0.0};
+      for (int i = 0; i < (model == ENS_KM ? 11 : 7); ++i) sh[i] = w[i];
+      break;
+    }
+    case ENS_PRV:
+      sh[0] = 1.25;
+      sh[1] = 10.0;
+      sh[2] = 20.0;
+      sh[3] = 0.8;
+      break;
+    default: break;
+  }
+}
+
+
 }  // namespace ens
 
 using ens::EnsDesc;
@@ -60,6 +136,17 @@ struct ens_ctx {
   ens::RkckCold *d_cold = nullptr;   // the kernel's cold pointers, in device memory
   int64_t *d_order = nullptr;  // queue order (ens_set_order), valid if use_order
   bool use_order = false;
+  double *d_carry = nullptr;   // adaptive: [ENS_NCARRY][n] carried phase accessories
+  // scratch kept for the handle's lifetime (allocated at create or first use)
+  char *d_sort = nullptr;      // ens_order_by_work: keys, indices, sort temporaries
+  size_t sort_tmp = 0;         // bytes of rocPRIM temporaries inside d_sort
+  unsigned *d_seen = nullptr;  // ens_set_order: permutation check [n] + flag
+  int *d_flag = nullptr;       // ens_set_params_gather: index check flag
+  double *d_snap = nullptr;    // ens_tune: snapshot of y, t, h, phi, carry
+  // caller's allocator (ens_desc.alloc / free), or null for hipMalloc / hipFree
+  ens_alloc_fn ualloc = nullptr;
+  ens_free_fn ufree = nullptr;
+  void *uctx = nullptr;
   EnsDesc *d_desc = nullptr;
   size_t rec_cap = 0;   // doubles allocated in d_rec
   int64_t R = 0;        // record ring length of the last adaptive solve
@@ -110,36 +197,38 @@ struct DeviceGuard {
   }
 };
 
-void default_shared(int model, double *sh) {
-  switch (model) {
-    case ENS_LORENZ:
-      sh[0] = 10.0;
-      sh[1] = 8.0 / 3.0;
-      break;
-    case ENS_KM:
-    case ENS_KM6: {
-      // ENS_KM6 takes the first 7 (the fluid), the rest are per system
-      const double w[11] = {997.0, 1497.0, 3166.0, 0.0728, 8.9e-4, 1.4,
-                            1.0e5, 10.0e-6, 0.0,    0.0,    0.0};
-      for (int i = 0; i < (model == ENS_KM ? 11 : 7); ++i) sh[i] = w[i];
-      break;
-    }
-    case ENS_PRV:
-      sh[0] = 1.25;
-      sh[1] = 10.0;
-      sh[2] = 20.0;
-      sh[3] = 0.8;
-      break;
-    default: break;
+
+// Every device buffer of a handle comes from here: the caller's allocator
+// when the handle has one, else hipMalloc.
+hipError_t h_alloc_bytes(ens_ctx *h, void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (h->ualloc) {
+    *p = h->ualloc(bytes, h->uctx);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
   }
+  return hipMalloc(p, bytes);
 }
 
 template <class T>
-hipError_t dalloc(T **p, size_t count) {
-  *p = nullptr;
-  if (count == 0) count = 1;
-  return hipMalloc((void **)p, count * sizeof(T));
+hipError_t dalloc(ens_ctx *h, T **p, size_t count) {
+  return h_alloc_bytes(h, (void **)p, count * sizeof(T));
 }
+
+template <class T>
+void dfree(ens_ctx *h, T *&p) {
+  if (p) {
+    if (h->ufree)
+      h->ufree((void *)p, h->uctx);
+    else
+      (void)hipFree((void *)p);
+  }
+  p = nullptr;
+}
+
+// Bytes of the ens_order_by_work scratch for n systems: two key arrays and
+// one index array (256-byte aligned each), then the sort's temporaries.
+size_t sort_key_bytes(int64_t n) { return ((size_t)n * 8 + 255) & ~(size_t)255; }
 
 hipMemcpyKind kind_in(int where) {
   return where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -173,6 +262,18 @@ __global__ void k_check_order(const int64_t *__restrict__ order, int64_t n,
   if (i >= n) return;
   const int64_t v = order[i];
   if (v < 0 || v >= n || atomicAdd(&seen[v], 1u) != 0u) *bad = 1;
+}
+
+// A fresh phase for every system: no running maximum or minimum, the phase
+// starting at the system's clock, not seated.
+__global__ void k_fresh_carry(double *__restrict__ carry, const double *__restrict__ t,
+                              int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  carry[ENS_CARRY_YMAX * n + i] = -INFINITY;
+  carry[ENS_CARRY_YMIN * n + i] = INFINITY;
+  carry[ENS_CARRY_TPS * n + i] = t[i];
+  carry[ENS_CARRY_SEATED * n + i] = 0.0;
 }
 
 // Sort keys for a longest-first queue: attempted steps of the last solve.
@@ -259,6 +360,17 @@ void tune_store(int model, int solver, int device, int64_t n, const TuneVal &v) 
 
 }  // namespace
 
+namespace ens {
+hipError_t launch_fresh_carry(double *carry, const double *t, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fresh_carry, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, carry, t,
+                     n);
+  return hipGetLastError();
+}
+
+void set_thread_error(const char *msg) { g_err = msg; }
+}  // namespace ens
+
 extern "C" {
 
 int ens_set_order(ens_t h, const int64_t *order, int32_t where) {
@@ -271,25 +383,19 @@ int ens_set_order(ens_t h, const int64_t *order, int32_t where) {
   }
   DeviceGuard g(h->device);
   const size_t bytes = (size_t)h->n * sizeof(int64_t);
-  if (!h->d_order) {
-    hipError_t e = hipMalloc((void **)&h->d_order, bytes);
-    if (e != hipSuccess) {
-      h->d_order = nullptr;
-      return fail(h, ENS_E_NOMEM, "ens_set_order: device allocation failed");
-    }
+  if (h->solver == ENS_RK4) return ENS_OK;  // no work queue
+  if (!h->d_seen) {
+    hipError_t e = dalloc(h, &h->d_seen, (size_t)h->n + 16);
+    if (e != hipSuccess) return fail(h, ENS_E_NOMEM, "ens_set_order: device allocation failed");
   }
   h->use_order = false;
-  unsigned *seen = nullptr;
-  int *bad = nullptr;
+  unsigned *seen = h->d_seen;
+  int *bad = (int *)(seen + h->n);
   int hb = 0;
   hipError_t e = hipMemcpyAsync(h->d_order, order, bytes,
                                 where == ENS_HOST ? hipMemcpyHostToDevice
                                                   : hipMemcpyDeviceToDevice, h->stream);
-  if (e == hipSuccess) e = hipMalloc((void **)&seen, (size_t)h->n * sizeof(unsigned) + 64);
-  if (e == hipSuccess) {
-    bad = (int *)((char *)seen + (size_t)h->n * sizeof(unsigned));
-    e = hipMemsetAsync(seen, 0, (size_t)h->n * sizeof(unsigned) + 64, h->stream);
-  }
+  if (e == hipSuccess) e = ens::launch_fill_u32(seen, 0u, h->n + 16, h->stream);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_check_order, dim3((unsigned)((h->n + 255) / 256)), dim3(256), 0,
                        h->stream, h->d_order, h->n, seen, bad);
@@ -297,7 +403,6 @@ int ens_set_order(ens_t h, const int64_t *order, int32_t where) {
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (seen) (void)hipFree(seen);
   if (e != hipSuccess) return hip_fail(h, e, "ens_set_order");
   if (hb) return fail(h, ENS_E_INVAL, "ens_set_order: not a permutation of 0..n-1");
   h->use_order = true;
@@ -311,35 +416,22 @@ int ens_order_by_work(ens_t h) {
   if (h->n == 0) return ENS_OK;
   DeviceGuard g(h->device);
   const int64_t n = h->n;
-  if (!h->d_order) {
-    hipError_t e = hipMalloc((void **)&h->d_order, (size_t)n * sizeof(int64_t));
-    if (e != hipSuccess) {
-      h->d_order = nullptr;
-      return fail(h, ENS_E_NOMEM, "ens_order_by_work: device allocation failed");
-    }
-  }
+  // the order and the sort's scratch were allocated with the handle: no
+  // allocation and no wait between a pilot solve and the solve it orders
   h->use_order = false;
-  size_t tmp_bytes = 0;
-  hipError_t e = rocprim::radix_sort_pairs_desc(
-      nullptr, tmp_bytes, (const unsigned long long *)nullptr, (unsigned long long *)nullptr,
-      (const int64_t *)nullptr, (int64_t *)nullptr, (size_t)n, 0u, 48u, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "ens_order_by_work");
-  const size_t kb = ((size_t)n * 8 + 255) & ~(size_t)255;
-  char *buf = nullptr;
-  e = hipMalloc((void **)&buf, 3 * kb + tmp_bytes);
-  if (e != hipSuccess) return fail(h, ENS_E_NOMEM, "ens_order_by_work: device allocation failed");
+  size_t tmp_bytes = h->sort_tmp;
+  const size_t kb = sort_key_bytes(n);
+  char *buf = h->d_sort;
   auto *key_in = (unsigned long long *)buf;
   auto *key_out = (unsigned long long *)(buf + kb);
   auto *idx_in = (int64_t *)(buf + 2 * kb);
   hipLaunchKernelGGL(k_work_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
                      h->d_stats, n, key_in, idx_in);
-  e = hipGetLastError();
   // radix sort is stable: systems of equal work keep their index order
+  hipError_t e = hipGetLastError();
   if (e == hipSuccess)
     e = rocprim::radix_sort_pairs_desc(buf + 3 * kb, tmp_bytes, key_in, key_out, idx_in,
                                        h->d_order, (size_t)n, 0u, 48u, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  (void)hipFree(buf);
   if (e != hipSuccess) return hip_fail(h, e, "ens_order_by_work");
   h->use_order = true;
   return ENS_OK;
@@ -351,10 +443,11 @@ int ens_set_params_gather(ens_t h, const double *p_full, int64_t n_full, const i
     return fail(h, ENS_E_INVAL, "ens_set_params_gather: bad arguments");
   DeviceGuard g(h->device);
   if (h->n > 0) {
-    int *bad = nullptr;
-    ENS_HIP(h, hipMalloc((void **)&bad, sizeof(int)));
-    int zero = 0, hb = 0;
-    hipError_t e = hipMemcpyAsync(bad, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream);
+    if (!h->d_flag && dalloc(h, &h->d_flag, 64) != hipSuccess)
+      return fail(h, ENS_E_NOMEM, "ens_set_params_gather: device allocation failed");
+    int *bad = h->d_flag;
+    int hb = 0;
+    hipError_t e = ens::launch_fill_u32((unsigned *)bad, 0u, 1, h->stream);
     if (e == hipSuccess) {
       hipLaunchKernelGGL(k_gather_params, dim3((unsigned)((h->n + 255) / 256)), dim3(256), 0,
                          h->stream, p_full, n_full, idx, h->n, h->mi.P, h->d_p, bad);
@@ -362,7 +455,6 @@ int ens_set_params_gather(ens_t h, const double *p_full, int64_t n_full, const i
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    (void)hipFree(bad);
     if (e != hipSuccess) return hip_fail(h, e, "ens_set_params_gather");
     if (hb) return fail(h, ENS_E_INVAL, "ens_set_params_gather: index out of range");
   }
@@ -422,6 +514,9 @@ int ens_create(const ens_desc *d, ens_t *out) {
       return fail(nullptr, ENS_E_INVAL, "ens_create: offsets required for n_ensembles > 1");
     off = {0, d->n};
   }
+  if ((d->alloc == nullptr) != (d->free == nullptr))
+    return fail(nullptr, ENS_E_INVAL, "ens_create: alloc and free go together");
+  if (d->reserved_ != 0) return fail(nullptr, ENS_E_INVAL, "ens_create: reserved_ must be 0");
   if (d->tangent < 0 || d->tangent > 3)
     return fail(nullptr, ENS_E_INVAL, "ens_create: tangent must be in [0, D]");
   if (d->tangent && (d->solver == ENS_RK4 || d->model == ENS_PRV))
@@ -452,8 +547,11 @@ int ens_create(const ens_desc *d, ens_t *out) {
   h->off = off;
   h->stream = (hipStream_t)d->hip_stream;
   h->device = d->device;
+  h->ualloc = d->alloc;
+  h->ufree = d->free;
+  h->uctx = d->alloc_ctx;
   for (int e = 0; e < ENS_MAX_ENSEMBLES; ++e) {
-    default_shared(h->model, h->shared[e]);
+    ens::default_shared(h->model, h->shared[e]);
     h->ens_phases[e] = -1;
     h->ens_impacts[e] = 0;
   }
@@ -464,19 +562,27 @@ int ens_create(const ens_desc *d, ens_t *out) {
   }
   const size_t n = (size_t)h->n;
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = dalloc(&h->d_p, (size_t)h->mi.P * n);
-  if (e == hipSuccess) e = dalloc(&h->d_y, (size_t)h->mi.D * n);
-  if (e == hipSuccess) e = dalloc(&h->d_t, n);
-  if (e == hipSuccess) e = dalloc(&h->d_h, n);
-  if (e == hipSuccess && h->solver == ENS_RK4) e = dalloc(&h->d_acc, n);
+  if (e == hipSuccess) e = dalloc(h, &h->d_p, (size_t)h->mi.P * n);
+  if (e == hipSuccess) e = dalloc(h, &h->d_y, (size_t)h->mi.D * n);
+  if (e == hipSuccess) e = dalloc(h, &h->d_t, n);
+  if (e == hipSuccess) e = dalloc(h, &h->d_h, n);
+  if (e == hipSuccess && h->solver == ENS_RK4) e = dalloc(h, &h->d_acc, n);
   if (e == hipSuccess && h->solver != ENS_RK4) {
-    e = dalloc(&h->d_stats, (size_t)ENS_NSTAT * n);
-    if (e == hipSuccess) e = dalloc(&h->d_status, n);
-    if (e == hipSuccess) e = dalloc(&h->d_queue, 2);
+    e = dalloc(h, &h->d_stats, (size_t)ENS_NSTAT * n);
+    if (e == hipSuccess) e = dalloc(h, &h->d_status, n);
+    if (e == hipSuccess) e = dalloc(h, &h->d_queue, 2);
+    if (e == hipSuccess) e = dalloc(h, &h->d_cold, 1);
+    if (e == hipSuccess) e = dalloc(h, &h->d_desc, ENS_MAX_ENSEMBLES);
+    if (e == hipSuccess && (h->model == ENS_KM || h->model == ENS_KM6)) e = dalloc(h, &h->d_phi, n);
+    if (e == hipSuccess) e = dalloc(h, &h->d_carry, (size_t)ENS_NCARRY * n);
+    if (e == hipSuccess) e = dalloc(h, &h->d_order, n);
+    // ens_order_by_work's scratch: sort keys in and out, indices, rocPRIM
+    // temporaries (sized by a query that allocates nothing)
     if (e == hipSuccess)
-      e = hipMalloc((void **)&h->d_cold, sizeof(ens::RkckCold));
-    if (e == hipSuccess) e = dalloc(&h->d_desc, ENS_MAX_ENSEMBLES);
-    if (e == hipSuccess && (h->model == ENS_KM || h->model == ENS_KM6)) e = dalloc(&h->d_phi, n);
+      e = rocprim::radix_sort_pairs_desc(nullptr, h->sort_tmp, (const unsigned long long *)nullptr,
+                                         (unsigned long long *)nullptr, (const int64_t *)nullptr,
+                                         (int64_t *)nullptr, n, 0u, 48u, h->stream);
+    if (e == hipSuccess) e = dalloc(h, &h->d_sort, 3 * sort_key_bytes(h->n) + h->sort_tmp);
   }
   if (e == hipSuccess) e = hipEventCreate(&h->ev0);
   if (e == hipSuccess) e = hipEventCreate(&h->ev1);
@@ -496,19 +602,24 @@ int ens_destroy(ens_t h) {
   hipError_t e = hipSuccess;
   if (g.ok) e = hipStreamSynchronize(h->stream);
   free_graph(h);
-  (void)hipFree(h->d_p);
-  (void)hipFree(h->d_y);
-  (void)hipFree(h->d_t);
-  (void)hipFree(h->d_h);
-  (void)hipFree(h->d_acc);
-  (void)hipFree(h->d_rec);
-  (void)hipFree(h->d_phi);
-  (void)hipFree(h->d_stats);
-  (void)hipFree(h->d_status);
-  (void)hipFree(h->d_queue);
-  (void)hipFree(h->d_cold);
-  (void)hipFree(h->d_order);
-  (void)hipFree(h->d_desc);
+  dfree(h, h->d_p);
+  dfree(h, h->d_y);
+  dfree(h, h->d_t);
+  dfree(h, h->d_h);
+  dfree(h, h->d_acc);
+  dfree(h, h->d_rec);
+  dfree(h, h->d_phi);
+  dfree(h, h->d_stats);
+  dfree(h, h->d_status);
+  dfree(h, h->d_queue);
+  dfree(h, h->d_cold);
+  dfree(h, h->d_order);
+  dfree(h, h->d_desc);
+  dfree(h, h->d_carry);
+  dfree(h, h->d_sort);
+  dfree(h, h->d_seen);
+  dfree(h, h->d_flag);
+  dfree(h, h->d_snap);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -572,6 +683,7 @@ int ens_set_state(ens_t h, const double *y0, const double *t0, const double *h0,
     if (h0)
       ENS_HIP(h, hipMemcpyAsync(h->d_h, h0, n * sizeof(double), kind_in(where), h->stream));
     if (h->d_phi) ENS_HIP(h, ens::launch_fill_f64(h->d_phi, 0.0, (int64_t)n, h->stream));
+    if (h->d_carry) ENS_HIP(h, ens::launch_fresh_carry(h->d_carry, h->d_t, (int64_t)n, h->stream));
     if (where == ENS_HOST) ENS_HIP(h, hipStreamSynchronize(h->stream));
   }
   h->h_init = h0 != nullptr;
@@ -592,6 +704,22 @@ int ens_set_drive_phase(ens_t h, const double *phi, int32_t where) {
   const size_t bytes = (size_t)h->n * sizeof(double);
   if (bytes) {
     ENS_HIP(h, hipMemcpyAsync(h->d_phi, phi, bytes, kind_in(where), h->stream));
+    if (where == ENS_HOST) ENS_HIP(h, hipStreamSynchronize(h->stream));
+  }
+  return ENS_OK;
+}
+
+int ens_set_carry(ens_t h, const double *carry, int32_t where) {
+  if (!h) return fail(nullptr, ENS_E_INVAL, "ens_set_carry: NULL handle");
+  if (!h->d_carry) return fail(h, ENS_E_UNSUPPORTED, "ens_set_carry: adaptive handles only");
+  if (!h->have_y) return fail(h, ENS_E_ORDER, "ens_set_carry: set the state first");
+  if (!carry && h->n > 0) return fail(h, ENS_E_INVAL, "ens_set_carry: carry is NULL");
+  if (where != ENS_HOST && where != ENS_DEVICE)
+    return fail(h, ENS_E_INVAL, "ens_set_carry: bad where");
+  DeviceGuard g(h->device);
+  const size_t bytes = (size_t)ENS_NCARRY * h->n * sizeof(double);
+  if (bytes) {
+    ENS_HIP(h, hipMemcpyAsync(h->d_carry, carry, bytes, kind_in(where), h->stream));
     if (where == ENS_HOST) ENS_HIP(h, hipStreamSynchronize(h->stream));
   }
   return ENS_OK;
@@ -625,26 +753,11 @@ static int solve_rk4(ens_t h, const ens_solve_opts *o) {
 }
 
 static int solve_rkck(ens_t h, const ens_solve_opts *o) {
-  auto pos = [](double v) { return v > 0.0 && std::isfinite(v); };
-  if (!pos(o->dt0) || !pos(o->dt_min) || !pos(o->dt_max) || o->dt_max < o->dt_min)
-    return fail(h, ENS_E_INVAL, "ens_solve: need 0 < dt_min <= dt_max and dt0 > 0");
-  if (!(o->rtol >= 0.0) || !pos(o->atol))
-    return fail(h, ENS_E_INVAL, "ens_solve: need rtol >= 0 and atol > 0");
-  if (h->model != ENS_PRV && !pos(o->t_phase))
-    return fail(h, ENS_E_INVAL, "ens_solve: t_phase must be > 0");
-  if (h->model == ENS_PRV && (!pos(o->event_tol) || !pos(o->t_cap) || !(o->v_stick >= 0.0)))
-    return fail(h, ENS_E_INVAL, "ens_solve: bad event_tol, t_cap or v_stick");
-  if (o->n_phases < 0 || o->n_phases > (int64_t)UINT32_MAX || o->n_record < 0 ||
-      o->max_steps < 0 || o->max_event_iter < 0)
-    return fail(h, ENS_E_INVAL, "ens_solve: bad phase, record or step counts");
-  if (o->max_steps > (int64_t)UINT32_MAX)
-    return fail(h, ENS_E_INVAL, "ens_solve: max_steps above 2^32");
-  if (o->spread < 0 || o->spread > h->n || o->reserved_ != 0)
-    return fail(h, ENS_E_INVAL, "ens_solve: spread must be in [0, n], reserved_ 0");
-  if (o->locate_max && h->tangent)
-    return fail(h, ENS_E_UNSUPPORTED, "ens_solve: locate_max is not built with the tangent");
-  if (o->locate_max && h->model != ENS_KM && h->model != ENS_KM6)
-    return fail(h, ENS_E_UNSUPPORTED, "ens_solve: locate_max is built for Keller--Miksis");
+  {
+    std::string msg;
+    const int rc = ens::check_adaptive_opts(h->model, h->tangent, h->n, o, &msg);
+    if (rc != ENS_OK) return fail(h, rc, "ens_solve: " + msg);
+  }
   int block = o->block, refill = o->refill;
   TuneVal tv;
   if ((!block || !refill) && tune_lookup(h->model, h->solver, h->device, h->n, &tv)) {
@@ -656,26 +769,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   if (block < 64 || block > 256 || block % 64)
     return fail(h, ENS_E_INVAL, "ens_solve: adaptive block must be 64, 128, 192 or 256");
   if (refill < 1 || refill > 64) return fail(h, ENS_E_INVAL, "ens_solve: refill must be in [1, 64]");
-  // Keller--Miksis: the fast kernel (Newton fifth root, angle-addition
-  // forcing phase) needs 3 gamma = 21/5 in every sub-ensemble and dt_max <=
-  // 1/8; otherwise the general variant runs, and a second drive (P_A2 != 0)
-  // in any sub-ensemble selects the general variant that carries it
-  int kmodel = h->model;
-  if (h->model == ENS_KM) {
-    bool dual = false;
-    if (o->dt_max > 0.125) kmodel = ens::ENS_KM_GENERAL;
-    for (int e = 0; e < h->n_ens; ++e) {
-      if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM_GENERAL;
-      if (h->shared[e][8] != 0.0) dual = true;
-    }
-    if (dual) kmodel = kmodel == ENS_KM ? ens::ENS_KM_DUAL_FAST : ens::ENS_KM_DUAL;
-  }
-  if (h->model == ENS_KM6) {
-    if (o->dt_max > 0.125) kmodel = ens::ENS_KM6_GENERAL;
-    for (int e = 0; e < h->n_ens; ++e)
-      if (std::fabs(3.0 * h->shared[e][5] - 4.2) >= 1e-12) kmodel = ens::ENS_KM6_GENERAL;
-  }
-  if (h->tangent) kmodel += h->tangent * ens::kTangentModel;
+  const int kmodel = ens::kernel_model(h->model, h->tangent, h->shared, h->n_ens, o->dt_max);
   int grid = o->grid;
   const int cap = ens::rkck_max_blocks(kmodel, h->solver, o->locate_max != 0, block);
   if (cap <= 0) return fail(h, ENS_E_HIP, "ens_solve: occupancy query failed");
@@ -687,10 +781,9 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   const size_t rec_count = (size_t)R * h->mi.F * (size_t)h->n;
   if (rec_count > h->rec_cap) {
     free_graph(h);
-    (void)hipFree(h->d_rec);
-    h->d_rec = nullptr;
+    dfree(h, h->d_rec);
     h->rec_cap = 0;
-    ENS_HIP(h, hipMalloc((void **)&h->d_rec, rec_count * sizeof(double)));
+    ENS_HIP(h, dalloc(h, &h->d_rec, rec_count));
     h->rec_cap = rec_count;
   }
   // sub-ensemble descriptors: upload only when they change
@@ -730,6 +823,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   c.status = h->d_status;
   c.queue = h->d_queue;
   c.order = h->use_order ? h->d_order : nullptr;
+  c.carry = h->d_carry;
   ENS_HIP(h, ens::launch_set_cold(h->d_cold, c, h->stream));
 
   ens::RkckArgs a;
@@ -833,6 +927,7 @@ size_t ens_field_bytes(ens_t h, int32_t field) {
     case ENS_STATS: return h->have_adaptive ? (size_t)ENS_NSTAT * n * sizeof(int64_t) : 0;
     case ENS_STATUS: return h->have_adaptive ? n * sizeof(int32_t) : 0;
     case ENS_DRIVE_PHASE: return (h->have_y && h->d_phi) ? n * sizeof(double) : 0;
+    case ENS_CARRY: return (h->have_y && h->d_carry) ? ENS_NCARRY * n * sizeof(double) : 0;
   }
   return 0;
 }
@@ -841,10 +936,12 @@ int ens_read(ens_t h, int32_t field, void *dst, size_t bytes, int32_t where) {
   if (!h) return fail(nullptr, ENS_E_INVAL, "ens_read: NULL handle");
   if (where != ENS_HOST && where != ENS_DEVICE)
     return fail(h, ENS_E_INVAL, "ens_read: bad where");
-  if (field < ENS_STATE || field > ENS_DRIVE_PHASE)
+  if (field < ENS_STATE || field > ENS_CARRY)
     return fail(h, ENS_E_INVAL, "ens_read: bad field");
   if (field == ENS_DRIVE_PHASE && !h->d_phi)
     return fail(h, ENS_E_UNSUPPORTED, "ens_read: ENS_DRIVE_PHASE is Keller--Miksis adaptive only");
+  if (field == ENS_CARRY && !h->d_carry)
+    return fail(h, ENS_E_UNSUPPORTED, "ens_read: ENS_CARRY is for adaptive handles");
   const size_t need = ens_field_bytes(h, field);
   const bool produced = need > 0 || h->n == 0 || (field == ENS_RECORDS && h->have_adaptive);
   if (!produced) return fail(h, ENS_E_ORDER, "ens_read: field not produced yet");
@@ -861,6 +958,7 @@ int ens_read(ens_t h, int32_t field, void *dst, size_t bytes, int32_t where) {
     case ENS_STATS: src = h->d_stats; break;
     case ENS_STATUS: src = h->d_status; break;
     case ENS_DRIVE_PHASE: src = h->d_phi; break;
+    case ENS_CARRY: src = h->d_carry; break;
   }
   DeviceGuard g(h->device);
   const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -876,31 +974,39 @@ int ens_tune(ens_t h, const ens_solve_opts *opts, int64_t trial_len, ens_solve_o
   if (!h->have_p || !h->have_y) return fail(h, ENS_E_ORDER, "ens_tune: set params and state first");
   DeviceGuard g(h->device);
   const size_t n = (size_t)h->n;
-  const size_t ybytes = (size_t)h->mi.D * n * sizeof(double);
-  // snapshot of the state, restored before every trial and at the end
-  double *sy = nullptr, *st = nullptr, *sh = nullptr, *sp = nullptr;
+  // snapshot of everything a solve changes in the state (y, t, h, second
+  // drive phase, carried accessories), taken once and restored before every
+  // trial and at the end; its buffer stays with the handle
+  const size_t nd = n ? n : 1;
+  const size_t D = (size_t)h->mi.D;
+  const size_t snap_count = (D + 3 + ENS_NCARRY) * nd;
   const bool had_h = h->h_init;
-  ENS_HIP(h, hipMalloc((void **)&sy, ybytes ? ybytes : 8));
-  hipError_t e = hipMalloc((void **)&st, n ? n * sizeof(double) : 8);
-  if (e == hipSuccess) e = hipMalloc((void **)&sh, n ? n * sizeof(double) : 8);
-  if (e == hipSuccess && h->d_phi) e = hipMalloc((void **)&sp, n ? n * sizeof(double) : 8);
-  if (e == hipSuccess && n && sp)
-    e = hipMemcpyAsync(sp, h->d_phi, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
-  if (e == hipSuccess && n) e = hipMemcpyAsync(sy, h->d_y, ybytes, hipMemcpyDeviceToDevice, h->stream);
-  if (e == hipSuccess && n) e = hipMemcpyAsync(st, h->d_t, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
-  if (e == hipSuccess && n && had_h)
-    e = hipMemcpyAsync(sh, h->d_h, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+  if (!h->d_snap) ENS_HIP(h, dalloc(h, &h->d_snap, snap_count));
+  double *sy = h->d_snap, *st = sy + D * nd, *sh = st + nd, *sp = sh + nd, *sc = sp + nd;
+  auto copies = [&](bool save) -> hipError_t {
+    struct {
+      double *dev;
+      double *snap;
+      size_t count;
+      bool use;
+    } parts[] = {{h->d_y, sy, D * n, true},
+                 {h->d_t, st, n, true},
+                 {h->d_h, sh, n, had_h},
+                 {h->d_phi, sp, n, h->d_phi != nullptr},
+                 {h->d_carry, sc, ENS_NCARRY * n, h->d_carry != nullptr}};
+    for (auto &pt : parts) {
+      if (!pt.use || pt.count == 0) continue;
+      hipError_t r = hipMemcpyAsync(save ? pt.snap : pt.dev, save ? pt.dev : pt.snap,
+                                    pt.count * sizeof(double), hipMemcpyDeviceToDevice,
+                                    h->stream);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  };
+  hipError_t e = copies(true);
   auto restore = [&]() -> hipError_t {
-    hipError_t r = hipSuccess;
-    if (n) r = hipMemcpyAsync(h->d_y, sy, ybytes, hipMemcpyDeviceToDevice, h->stream);
-    if (r == hipSuccess && n)
-      r = hipMemcpyAsync(h->d_t, st, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
-    if (r == hipSuccess && n && had_h)
-      r = hipMemcpyAsync(h->d_h, sh, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
-    if (r == hipSuccess && n && sp)
-      r = hipMemcpyAsync(h->d_phi, sp, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
     h->h_init = had_h;
-    return r;
+    return copies(false);
   };
   ens_solve_opts trial = *opts;
   std::vector<std::tuple<int, int, int>> cands;  // block, spl, refill
@@ -924,7 +1030,7 @@ int ens_tune(ens_t h, const ens_solve_opts *opts, int64_t trial_len, ens_solve_o
     trial.refill = std::get<2>(cands[c]);
     trial.grid = 0;
     float tmin = std::numeric_limits<float>::infinity();
-    for (int rep = 0; rc == ENS_OK && rep < 2; ++rep) {
+    for (int rep = 0; rc == ENS_OK && rep < 3; ++rep) {
       hipError_t r = restore();
       if (r != hipSuccess) {
         rc = hip_fail(h, r, "ens_tune: restore");
@@ -941,7 +1047,10 @@ int ens_tune(ens_t h, const ens_solve_opts *opts, int64_t trial_len, ens_solve_o
       }
       if (ms < tmin) tmin = ms;
     }
-    if (rc == ENS_OK && tmin < bestv.ms) {
+    // a challenger replaces the incumbent only if it is faster by more than
+    // the trials' run-to-run spread (2%), so that near-ties do not flip the
+    // choice from one run to the next
+    if (rc == ENS_OK && tmin < bestv.ms * 0.98f) {
       bestv.block = trial.block;
       bestv.spl = trial.spl;
       bestv.refill = trial.refill;
@@ -952,10 +1061,6 @@ int ens_tune(ens_t h, const ens_solve_opts *opts, int64_t trial_len, ens_solve_o
   hipError_t r = restore();
   if (rc == ENS_OK && r != hipSuccess) rc = hip_fail(h, r, "ens_tune: restore");
   if (r == hipSuccess) r = hipStreamSynchronize(h->stream);
-  (void)hipFree(sy);
-  (void)hipFree(st);
-  (void)hipFree(sh);
-  (void)hipFree(sp);
   // the trial solves produced results that belong to no real solve
   h->have_acc = false;
   h->have_adaptive = false;

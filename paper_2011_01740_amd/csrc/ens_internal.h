@@ -42,6 +42,8 @@ struct RkckCold {
   int32_t *status;          // [n]
   unsigned long long *queue;// [2]: positions taken from the rest, from the head
   const int64_t *order;     // [n] system taken at each queue position, or null
+  double *carry;            // [ENS_NCARRY][n] in/out: the running phase's
+                            // y1max, y1min, start time, valve seated (1/0)
 };
 
 struct RkckArgs {
@@ -71,7 +73,23 @@ constexpr int ENS_KM6_GENERAL = 103;   // ENS_KM6 on the general arithmetic
 // tangents of its variational equation.
 constexpr int kTangentModel = 1000;
 
+// Validation of the adaptive solve options for a model (ENS_OK, or an
+// ens_status with the reason in *msg).
+int check_adaptive_opts(int model, int tangent, int64_t n, const ens_solve_opts *o,
+                        std::string *msg);
+// The kernel variant that integrates `model` with these sub-ensembles'
+// shared parameters and step cap (fast or general Keller--Miksis arithmetic,
+// second drive, tangents).
+int kernel_model(int model, int tangent, const double (*shared)[ENS_MAX_SHARED], int n_ens,
+                 double dt_max);
+// A model's default shared parameters (ENS_MAX_SHARED doubles).
+void default_shared(int model, double *sh);
+// The calling thread's last error message (ens_last_error(NULL)).
+void set_thread_error(const char *msg);
+
 // Kernel launchers (stream-ordered; return hipSuccess or the launch error).
+// Fresh phase accessories [ENS_NCARRY][n] from the clock t [n].
+hipError_t launch_fresh_carry(double *carry, const double *t, int64_t n, hipStream_t s);
 hipError_t launch_set_cold(RkckCold *dst, const RkckCold &c, hipStream_t s);
 hipError_t launch_rk4(int model, int block, int spl, const double *p, double *y,
                       double *acc, int64_t n, double dt, int64_t nsteps,
@@ -84,5 +102,6 @@ int rkck_max_blocks(int model, int solver, bool locate_max, int block);
 hipError_t launch_fill_f64(double *p, double v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count,
                            hipStream_t s);
+hipError_t launch_fill_u32(unsigned *p, unsigned v, int64_t count, hipStream_t s);
 
 }  // namespace ens

@@ -75,6 +75,12 @@ __device__ __forceinline__ void lorenz_step(double &x, double &y, double &w, dou
   m = fmax(m, x);
 }
 
+__global__ void k_fill_u32(unsigned *p, unsigned v, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    p[i] = v;
+}
+
 template <int SPL>
 __global__ __launch_bounds__(1024) void k_rk4_lorenz(const double *__restrict__ P,
                                                      double *__restrict__ Y,
@@ -283,6 +289,14 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
   int64_t blocks = (count + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned *p, unsigned v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
   return hipGetLastError();
 }
 

@@ -705,7 +705,8 @@ __device__ __forceinline__ void store_growth(const RkckArgs &a, const Lane &L, c
 }
 
 template <class M, int SC>
-__device__ __forceinline__ void store_lane(const RkckArgs &a, const Lane &L, const double *y) {
+__device__ __forceinline__ void store_lane(const RkckArgs &a, const Lane &L, const double *y,
+                                           bool seated) {
   constexpr int D = M::D;
   const int64_t n = a.n, i = L.sys;
   const RkckCold *cp = cold(a);
@@ -723,6 +724,20 @@ __device__ __forceinline__ void store_lane(const RkckArgs &a, const Lane &L, con
   stats[ENS_ST_PHASES * n + i] = L.phase;
   stats[ENS_ST_EVRETRY * n + i] = L.evretry;
   cp->status[i] = L.status;
+  double *cy = cp->carry;
+  cy[ENS_CARRY_YMAX * n + i] = L.ymax;
+  cy[ENS_CARRY_YMIN * n + i] = L.ymin;
+  cy[ENS_CARRY_TPS * n + i] = L.t_ps;
+  cy[ENS_CARRY_SEATED * n + i] = seated ? 1.0 : 0.0;
+}
+
+// The valve's seated state (false for the models without a seat).
+template <class M>
+__device__ __forceinline__ bool seated_of(const M &m) {
+  if constexpr (M::kEvents)
+    return m.seated;
+  else
+    return false;
 }
 
 // Dense output of a step from y0 to y1 with end derivatives f0, f1 and step
@@ -835,6 +850,7 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
     if constexpr (M::kPrio) note_phase_end(L);
     if constexpr (M::kDrive2) m.next_phase(a.t_phase);
     L.t = 0.0;
+    L.t_ps = 0.0;
     L.ymax = -INFINITY;
     if (L.phase >= L.n_phases) return true;
   } else {
@@ -1034,9 +1050,13 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
           L.sys = i;
           L.t = cp->t[i];
           L.h = cp->h[i];
-          L.t_ps = L.t;
-          L.ymax = -INFINITY;
-          L.ymin = INFINITY;
+          // the running phase as the previous solve left it (a fresh state
+          // carries no maximum or minimum, its phase starting at t0)
+          const double *cy = cp->carry;
+          L.ymax = cy[ENS_CARRY_YMAX * a.n + i];
+          L.ymin = cy[ENS_CARRY_YMIN * a.n + i];
+          L.t_ps = cy[ENS_CARRY_TPS * a.n + i];
+          if constexpr (M::kEvents) m.seated = cy[ENS_CARRY_SEATED * a.n + i] != 0.0;
           L.n_phases = sdesc[e].n_phases;
           L.max_impacts = sdesc[e].max_impacts;
           L.phase = L.accepted = L.rejected = L.evretry = L.impacts = L.attempts = 0;
@@ -1051,7 +1071,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
           fs.have = false;
           active = true;
           if (L.n_phases <= 0) {
-            store_lane<M, SC>(a, L, y);
+            store_lane<M, SC>(a, L, y, seated_of(m));
             if constexpr (M::kDrive2) cold(a)->phi2[i] = m.phi;
             active = false;
           }
@@ -1083,7 +1103,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
       else
         done = step_fixed<M, SC, LOC>(a, m, L, y, fs);
       if (done) {
-        store_lane<M, SC>(a, L, y);
+        store_lane<M, SC>(a, L, y, seated_of(m));
         if constexpr (M::kDrive2) cold(a)->phi2[L.sys] = m.phi;
         active = false;
       }

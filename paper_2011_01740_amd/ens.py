@@ -21,12 +21,16 @@ ENS_OK, ENS_E_INVAL, ENS_E_NOMEM, ENS_E_HIP, ENS_E_ORDER, ENS_E_UNSUPPORTED = 0,
 ENS_QUAD, ENS_LORENZ, ENS_KM, ENS_PRV, ENS_DIV, ENS_SIN, ENS_KM6 = 0, 1, 2, 3, 4, 5, 6
 ENS_RK4, ENS_RKCK45, ENS_RKDP45 = 0, 1, 2
 ENS_HOST, ENS_DEVICE = 0, 1
-ENS_STATE, ENS_TIME, ENS_H, ENS_ACC, ENS_RECORDS, ENS_STATS, ENS_STATUS, ENS_DRIVE_PHASE = range(8)
+(ENS_STATE, ENS_TIME, ENS_H, ENS_ACC, ENS_RECORDS, ENS_STATS, ENS_STATUS, ENS_DRIVE_PHASE,
+ ENS_CARRY) = range(9)
+ENS_CARRY_YMAX, ENS_CARRY_YMIN, ENS_CARRY_TPS, ENS_CARRY_SEATED = range(4)
+ENS_NCARRY = 4
 ENS_SYS_OK, ENS_SYS_DT_MIN, ENS_SYS_MAX_STEPS, ENS_SYS_NONFINITE = 0, 1, 2, 4
 ENS_SYS_SETTLED, ENS_SYS_EVENT_ITER, ENS_SYS_SEATED = 8, 16, 32
 ENS_ST_ACCEPTED, ENS_ST_REJECTED, ENS_ST_NRHS, ENS_ST_IMPACTS, ENS_ST_PHASES, ENS_ST_EVRETRY = range(6)
 ENS_NSTAT = 6
 ENS_MAX_ENSEMBLES = 16
+ENS_MAX_SHARED = 16
 
 MODEL_DIMS = {ENS_QUAD: (1, 1, 0, 1), ENS_LORENZ: (3, 1, 2, 1),
               ENS_KM: (2, 2, 11, 1), ENS_PRV: (3, 1, 4, 2),
@@ -34,11 +38,16 @@ MODEL_DIMS = {ENS_QUAD: (1, 1, 0, 1), ENS_LORENZ: (3, 1, 2, 1),
               ENS_KM6: (2, 6, 7, 1)}   # D, P, S, F
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class ens_desc(C.Structure):
     _fields_ = [("model", C.c_int32), ("solver", C.c_int32), ("n", C.c_int64),
                 ("n_ensembles", C.c_int32), ("device", C.c_int32),
                 ("ens_offsets", C.POINTER(C.c_int64)), ("hip_stream", C.c_void_p),
-                ("tangent", C.c_int32), ("reserved_", C.c_int32)]
+                ("tangent", C.c_int32), ("reserved_", C.c_int32),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
 
 
 class ens_solve_opts(C.Structure):
@@ -77,6 +86,7 @@ def load():
     L.ens_set_budget.argtypes = [vp, i32, i64, i64]
     L.ens_set_state.argtypes = [vp, vp, vp, vp, i32]
     L.ens_set_drive_phase.argtypes = [vp, vp, i32]
+    L.ens_set_carry.argtypes = [vp, vp, i32]
     L.ens_default_opts.argtypes = [C.POINTER(ens_solve_opts)]
     L.ens_default_opts.restype = None
     L.ens_solve.argtypes = [vp, C.POINTER(ens_solve_opts)]
@@ -135,7 +145,10 @@ class Ensemble:
 
     def __init__(self, model: int, solver: int, n: int,
                  offsets: Optional[Sequence[int]] = None, device: int = 0, stream=None,
-                 tangent: int = 0):
+                 tangent: int = 0, allocator=None):
+        """allocator: None (the library's hipMalloc / hipFree) or a pair of
+        callables (alloc(nbytes) -> device address, free(address)) through
+        which the handle obtains and releases all its device memory."""
         L = load()
         self.model, self.solver, self.n = int(model), int(solver), int(n)
         # an unknown model is passed through: ens_create rejects it
@@ -154,6 +167,13 @@ class Ensemble:
         d.device = self.device
         d.hip_stream = self.stream_ptr
         d.tangent = self.tangent
+        self._alloc_fns = None
+        if allocator is not None:
+            ua, uf = allocator
+            # the C callbacks stay referenced as long as the handle lives
+            self._alloc_fns = (ALLOC_FN(lambda nb, ctx: int(ua(int(nb))) or None),
+                               FREE_FN(lambda ptr, ctx: uf(int(ptr))))
+            d.alloc, d.free = self._alloc_fns
         self._offs = None
         if offsets is not None:
             self._offs = (C.c_int64 * len(offsets))(*[int(v) for v in offsets])
@@ -237,6 +257,14 @@ class Ensemble:
         _check(load().ens_set_drive_phase(self.h, p, w), self.h)
         self._keep_phi = k
 
+    def set_carry(self, carry):
+        """Adaptive solvers: the carried phase accessories [ENS_NCARRY][n]
+        (the ENS_CARRY output of a solve), after set_state, to resume a solve
+        that stopped inside a phase."""
+        p, w, k = self._in(carry, (ENS_NCARRY, self.n))
+        _check(load().ens_set_carry(self.h, p, w), self.h)
+        self._keep_carry = k
+
     def solve(self, opts: Optional[ens_solve_opts] = None, **kw):
         o = opts if opts is not None else default_opts(**kw)
         if opts is not None and kw:
@@ -257,6 +285,8 @@ class Ensemble:
             return (R, self.F, n)
         if field == ENS_STATS:
             return (ENS_NSTAT, n)
+        if field == ENS_CARRY:
+            return (ENS_NCARRY, n)
         return (n,)
 
     def read(self, field: int, device: bool = False):

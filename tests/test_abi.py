@@ -44,9 +44,30 @@ def test_default_opts_are_the_documented_readings():
         ens.default_opts(no_such_option=1)
 
 
-def test_struct_layouts_match_the_header():
-    assert ctypes.sizeof(ens.ens_desc) == 48
-    assert ctypes.sizeof(ens.ens_solve_opts) == 152
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and field offsets of a struct of include/ens.h as the C compiler
+    lays it out."""
+    import subprocess
+    src = tmp_path / "probe.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ens.h"',
+             "int main(void) {", f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("name", ["ens_desc", "ens_solve_opts"])
+def test_struct_layouts_match_the_header(name, tmp_path):
+    cls = getattr(ens, name)
+    fields = [f[0] for f in cls._fields_]
+    size, offs = _c_layout(name, fields, tmp_path)
+    assert ctypes.sizeof(cls) == size
+    assert [getattr(cls, f).offset for f in fields] == offs
 
 
 def test_create_validates_before_touching_the_device():
