@@ -9,8 +9,12 @@ and integrate all systems for all 10^4 steps (final state and running max of
 x written back).
 
 Output: one JSON line with system-steps/s, the FP64 roofline of the RK4
-kernel (75 algorithmic flop per system-step, peak 78.6 TFLOP/s), and the CPU
+kernel (71 algorithmic flop per system-step, peak 78.6 TFLOP/s), and the CPU
 oracle timed on a bounded sample of the same workload on the host's cores.
+The same line carries the Keller--Miksis half of the metric (Sec. 4.2): the
+512 x 512 x 1024-cycle sweep (`km_sweep`, with the oracle on a sub-grid) and
+the surrogate-screened 4096 x 4096 sweep against the plain sweep of all its
+points (`km_screened`).
 """
 from __future__ import annotations
 
@@ -26,7 +30,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128)
-FLOP_PER_STEP = 75               # Lorenz RK4: 4 x 9 (RHS) + 3 x 6 (stage inputs) + 21 (update)
+# Lorenz RK4, textbook step: 4 x 8 (RHS: sigma (y - x) 2, x (rho - z) - y 3,
+# x y - beta z 3) + 3 x 6 (stage inputs y + (h/2) k: a multiply and an add per
+# component) + 21 (update y + h/6 (k1 + 2 k2 + 2 k3 + k4): 7 per component)
+FLOP_PER_STEP = 71
 HW_FLOP_PER_STEP = 70            # what the kernel executes: 33 FMA (x 2) + 4 subtractions
 BYTES_PER_SYSTEM = 8 * 8         # reads p, x, y, z; writes x, y, z, max x
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lorenz_rk4_traffic.json")
@@ -162,6 +169,53 @@ def lane_busy(steps, att, launch):
     return float(steps) / max(lanes * int(att.max()), 1)
 
 
+def km_sweep_line(args):
+    """The Keller--Miksis sweep of the paper's Sec. 4.2 study on a 512 x 512
+    (p_A, f) grid, 1024 acoustic cycles, per-cycle maximum radius: a 16-cycle
+    pilot in index order, then the rest with the queue longest-first.  Timed
+    around the two launches (HIP events) and on the wall clock; the oracle
+    beside it on an evenly spaced sub-grid."""
+    from paper_2011_01740_amd import workloads as W
+    r = W.km_sweep(args.km_grid, args.km_grid, n_phases=args.km_phases, n_record=64,
+                   pilot=16, pilot_grid=256)
+    att = r.stats[0] + r.stats[1]
+    steps = int(att.sum())
+    line = {"workload": f"keller_miksis_rkck45_{args.km_grid}x{args.km_grid}x{args.km_phases}",
+            "systems": args.km_grid * args.km_grid, "cycles": args.km_phases,
+            "time_s": r.kernel_ms / 1e3, "wall_s": r.wall_s,
+            "attempted_steps": steps, "attempted_steps_per_s": steps / r.kernel_ms * 1e3,
+            "accepted_steps_per_s": float(r.stats[0].sum()) / r.kernel_ms * 1e3,
+            "rhs_per_s": float(r.stats[2].sum()) / r.kernel_ms * 1e3,
+            "attempts_max_over_mean": float(att.max() / max(att.mean(), 1e-30)),
+            "lane_busy_fraction": lane_busy(steps, att, r.launch),
+            "status_ok_frac": float(((r.status & ~1) == 0).mean()),
+            "launch": r.launch}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = km_cpu_baseline(args.km_grid, args.km_phases, 16)
+    return line
+
+
+def km_screened_line(args):
+    """The surrogate-screened 4096 x 4096 Keller--Miksis sweep (training sweep
+    of the 512 x 512 grid, network training, calibration, screening, re-solve)
+    against the plain FP64 sweep of all 2^24 points, which also judges every
+    screened label; plus the screen without the network beside it."""
+    from paper_2011_01740_amd import surrogate as S
+    cfg = S.Config(train_grid=args.km_grid, screen_grid=args.sur_screen,
+                   n_phases=args.km_phases, epochs=args.sur_epochs, judge_n=0,
+                   target_wrong=args.sur_target)
+    rep = S.run(cfg, log=lambda *a: print(*a, file=sys.stderr, flush=True))
+    return {"workload": f"keller_miksis_screened_{args.sur_screen}x{args.sur_screen}",
+            "points": rep.n_screen, "plain_s": rep.plain_time_s,
+            "screened_s": rep.screened_time_s, "speedup": rep.speedup,
+            "speedup_excl_training_sweep": rep.speedup_excl_data,
+            "wrong_frac": rep.judge_wrong_frac, "resolve_frac": rep.resolve_frac,
+            "network_alone_wrong_frac": rep.network_only_wrong_frac,
+            "judged_points": rep.judge_points, "times_s": rep.times_s,
+            "screen_rule": rep.extra.get("rule", "network"),
+            "compare": rep.compare}
+
+
 def run_case(case, args):
     """Single launches for counter runs: a 1 GiB device copy (the scale of the
     FETCH_SIZE / WRITE_SIZE counters), a Keller--Miksis grid, or the valve
@@ -288,7 +342,7 @@ def main(argv=None):
                     default="bench",
                     help="bench: the benchmark line; others: one launch for counter runs")
     ap.add_argument("--km-grid", type=int, default=512)
-    ap.add_argument("--km-phases", type=int, default=16)
+    ap.add_argument("--km-phases", type=int, default=1024)
     ap.add_argument("--km-pilot", type=int, default=0,
                     help="cycles before the longest-first queue order (0: one solve)")
     ap.add_argument("--km-blocks", type=int, default=0,
@@ -332,6 +386,8 @@ def main(argv=None):
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--spl", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-km", action="store_true",
+                    help="leave the Keller--Miksis sweep and the screened sweep out of the line")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -432,6 +488,12 @@ def main(argv=None):
             line["cpu_simd"] = cpu_simd_baseline(n, nsteps, dt, seed)
         except (OSError, RuntimeError) as exc:   # context only: never fail the line
             line["cpu_simd"] = {"error": str(exc)}
+    if not args.no_km:
+        print("bench: Keller--Miksis sweep", file=sys.stderr, flush=True)
+        line["km_sweep"] = km_sweep_line(args)
+        print("bench: screened Keller--Miksis sweep and its plain sweep", file=sys.stderr,
+              flush=True)
+        line["km_screened"] = km_screened_line(args)
     print(json.dumps(line), flush=True)
     return 0
 

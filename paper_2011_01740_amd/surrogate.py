@@ -488,6 +488,7 @@ def run(cfg: Config, log=print) -> Report:
         jidx = np.arange(ns)
     jidx_d = _dev(jidx.astype(np.int64))
     exact_d = torch.empty(jidx.size, dtype=torch.int8, device="cuda")
+    lnmax_d = torch.empty(jidx.size, dtype=torch.float64, device="cuda")
     # the plain sweep runs in launches of at most judge_chunk points (each far
     # above the resident capacity, so the queue stays full), in grid order
     t_plain_sample = 0.0
@@ -503,6 +504,7 @@ def run(cfg: Config, log=print) -> Report:
         t_plain_sample += time.perf_counter() - t0
         sur._check(L.sur_exact_labels(s.h, ens.C.c_void_p(rec_j.data_ptr()), int(sl.numel()),
                                       None, ens.C.c_void_p(exact_d[c0:].data_ptr())), s.h)
+        lnmax_d[c0:c0 + sl.numel()] = torch.log(rec_j.max(dim=0).values)
         del rec_j
         log(f"plain: {min(c0 + cfg.judge_chunk, jidx.size)} of {jidx.size} points, "
             f"{t_plain_sample:.1f} s")
@@ -549,6 +551,7 @@ def run(cfg: Config, log=print) -> Report:
             f"{c['network_equal_error']['resolve_frac']:.4f} "
             f"({time.perf_counter() - t0:.1f} s on the host)")
     rep.extra = {"judge_idx": jidx, "judge_exact": exact_j, "nlab": nlab,
+                 "judge_lnmax": lnmax_d.cpu().numpy(),
                  "judge_pmax": pmax[jidx_d].cpu().numpy(), "judge_final": final_j,
                  "judge_resolve": resolve[jidx_d].cpu().numpy(),
                  "final_all": label.cpu().numpy(),

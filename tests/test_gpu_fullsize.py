@@ -75,3 +75,52 @@ def test_relief_valve_three_ensembles_one_graph_launch():
         assert not (keep & ~ok).any(), (k, idx[keep & ~ok])
         assert np.array_equal(r.stats[O.ST_IMPACTS, idx][keep], a.stats[O.ST_IMPACTS][keep])
         assert np.array_equal(r.status[idx][keep] & ~O.SYS_DT_MIN, a.status[keep] & ~O.SYS_DT_MIN)
+
+
+def test_relief_valve_full_budgets_one_graph_launch():
+    """The valve workload as specified: 2^15 systems with budget 10^5, 2^16
+    with 10^4 and 2^17 with 10^3 (Poincare phases or impacts, whichever
+    first), in one graph-captured persistent launch (~10^12 attempted steps).
+    The oracle integrates a seeded sample of each ensemble, the system with
+    the most attempted steps included, with the same budgets; systems its own
+    1e-13 perturbation moves are checked for invariants only."""
+    from paper_2011_01740_amd import workloads as W
+    ensm = W.PRV_ENSEMBLES
+    r = W.prv_batched(ensm, n_record=32)
+    P, y0, off = W.prv_inputs(ensm)
+    allowed = O.SYS_DT_MIN | O.SYS_SETTLED | O.SYS_EVENT_ITER
+    assert np.all((r.status & ~allowed) == 0)
+    assert ((r.status & O.SYS_EVENT_ITER) != 0).mean() < 0.01
+    att = r.stats[O.ST_ACCEPTED] + r.stats[O.ST_REJECTED] + r.stats[O.ST_EVRETRY]
+    assert att.sum() > 5e11
+    for k, (m, K, seed) in enumerate(ensm):
+        sl = slice(off[k], off[k + 1])
+        ph, imp = r.stats[O.ST_PHASES, sl], r.stats[O.ST_IMPACTS, sl]
+        settled = (r.status[sl] & O.SYS_SETTLED) != 0
+        assert np.all((ph == K) | (imp == K) | settled)
+        # impacting valves (q up to ~7.5, Sec. 4.3) reach the impact budget,
+        # the others the phase budget or settle
+        longest = int(np.argmax(att[sl]))
+        idx = off[k] + _sample(m, 10, 60 + k, extra=[0, m - 1, longest])
+        o = O.Opts(n_phases=K, n_record=32, max_impacts=K)
+        a = O.rkck45(O.PRV, P[:, idx], I.PRV_DEFAULT, y0[:, idx], o, nthreads=THREADS)
+        b = O.rkck45(O.PRV, P[:, idx], I.PRV_DEFAULT, y0[:, idx] * (1 + PERTURB), o,
+                     nthreads=THREADS)
+        keep = sensitivity_mask([a.y, a.records], [b.y, b.records], 1e-9, 1e-11)
+        ok = (per_system(close(r.y[:, idx], a.y, CK_RTOL, CK_ATOL))
+              & per_system(close(r.records[:, :, idx], a.records, CK_RTOL, CK_ATOL)))
+        assert not (keep & ~ok).any(), (k, idx[keep & ~ok])
+        # in the parity set every count and status bit agrees; outside it the
+        # budget that ended a system is reached on both sides
+        for row in (O.ST_PHASES, O.ST_IMPACTS):
+            assert np.array_equal(r.stats[row, idx][keep], a.stats[row][keep])
+        assert np.array_equal(r.status[idx][keep] & ~O.SYS_DT_MIN,
+                              a.status[keep] & ~O.SYS_DT_MIN)
+        hit_imp = a.stats[O.ST_IMPACTS] == K
+        assert np.all(r.stats[O.ST_IMPACTS, idx][hit_imp] == K)
+        hit_ph = (a.stats[O.ST_PHASES] == K) & ~hit_imp
+        assert np.all((r.stats[O.ST_PHASES, idx][hit_ph] == K)
+                      | (r.stats[O.ST_IMPACTS, idx][hit_ph] == K))
+        # the rest: bounded, finite, minimum at the seat (0) or above it
+        assert np.isfinite(r.records[:, :, idx]).all()
+        assert (r.records[:, 1, idx] >= 0.0).all()
