@@ -376,7 +376,7 @@ def main(argv=None):
     ap.add_argument("--sur-phases", type=int, default=1024)
     ap.add_argument("--sur-epochs", type=int, default=200)
     ap.add_argument("--sur-judge", type=int, default=0)   # 0: every point (the plain time)
-    ap.add_argument("--sur-target", type=float, default=0.007,
+    ap.add_argument("--sur-target", type=float, default=0.002,
                     help="hold-out wrong fraction the screening flags are calibrated to")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)

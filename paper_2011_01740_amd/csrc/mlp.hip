@@ -13,10 +13,12 @@
 // backward epilogue each gradient transposed, and the optimiser refreshes
 // both W and W^T in BF16.  Operands are read as 16-byte vectors straight
 // from global memory (the weights stay in L2), a whole group of K steps at a
-// time.  Weight gradients are split over the batch; bias and layer-1
-// gradients are column sums that the backward epilogue forms per 32-row
-// tile; one kernel then reduces every partial sum in a fixed order, so every
-// result is deterministic.  A training step is 13 launches.
+// time.  Weight gradients are split over the batch; bias gradients are column
+// sums that the backward epilogue forms per 32-row tile; one kernel then
+// reduces every partial sum in a fixed order, so every result is
+// deterministic.  The first layer is a fixed random Fourier-feature map of the
+// two inputs (sin of x W1^T + b1, on the vector unit) and is not trained, so
+// no gradient is propagated to it.  A training step is 12 launches.
 //
 // MFMA 16x16x32 BF16 operand layout (lane l, 64 lanes): A fragment = row
 // (l mod 16), k = 8 (l / 16) + 0..7; B fragment = column (l mod 16), same k;
@@ -46,6 +48,14 @@ constexpr int64_t oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH 
                   kNP = ob4 + kOut;
 static_assert(kNP == SUR_N_PARAMS, "parameter count");
 
+// Loss weight of output column c: the first output (the largest of the
+// recorded maxima, the value the screen labels by) counts kW0 times, the
+// others once, normalised to mean 1.
+constexpr float kW0 = 32.0f;
+__device__ __forceinline__ float out_weight(int c) {
+  return (c == 0 ? kW0 : 1.0f) * ((float)kOut / (kW0 + (float)(kOut - 1)));
+}
+
 __device__ __forceinline__ float gelu_f(float z) {
   return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
 }
@@ -72,9 +82,6 @@ struct GemmArgs {
   bf16 *out_bf16T;       // [C][R]
   // backward epilogue: column sums of the result over each 32-row tile
   float *colpart;        // [R/32][C]: sum_r dZ[r][c]              (bias gradient)
-  const float *xin;      // [R][2] layer inputs; with it also
-  float *colpart_x0;     // [R/32][C]: sum_r dZ[r][c] x[r][0]      (layer-1 weights)
-  float *colpart_x1;     // [R/32][C]: sum_r dZ[r][c] x[r][1]
 };
 
 constexpr int kTile = 32;  // output tile edge per wave
@@ -102,16 +109,6 @@ __global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           zp[i][j][q] = g.zprev[(r0 + 16 * i + lrow + q) * g.C + c0 + 16 * j + lc];
-  }
-  float xr[2][4][2];
-  if (EPI == EPI_BWD_GELU && g.xin) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        xr[i][q][0] = g.xin[2 * (r0 + 16 * i + lrow + q)];
-        xr[i][q][1] = g.xin[2 * (r0 + 16 * i + lrow + q) + 1];
-      }
   }
   float bj[2] = {0.f, 0.f};
   if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR || EPI == EPI_FWD_GELU_ACT) {
@@ -203,43 +200,26 @@ __global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
     // per column: the lane's 8 rows, then the 4 lane groups, in a fixed order
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      float s0 = 0.f;
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          s0 += res[i][j][q];
-          if (g.xin) {
-            s1 = fmaf(res[i][j][q], xr[i][q][0], s1);
-            s2 = fmaf(res[i][j][q], xr[i][q][1], s2);
-          }
-        }
+        for (int q = 0; q < 4; ++q) s0 += res[i][j][q];
       s0 += __shfl_xor(s0, 16);
       s0 += __shfl_xor(s0, 32);
-      if (g.xin) {
-        s1 += __shfl_xor(s1, 16);
-        s1 += __shfl_xor(s1, 32);
-        s2 += __shfl_xor(s2, 16);
-        s2 += __shfl_xor(s2, 32);
-      }
-      if (l < 16) {
-        const int64_t o = (int64_t)blockIdx.x * g.C + c0 + 16 * j + lc;
-        g.colpart[o] = s0;
-        if (g.xin) {
-          g.colpart_x0[o] = s1;
-          g.colpart_x1[o] = s2;
-        }
-      }
+      if (l < 16) g.colpart[(int64_t)blockIdx.x * g.C + c0 + 16 * j + lc] = s0;
     }
   }
 }
 
 // ---------------------------------------------------------------- small kernels
-// Layer 1 (K = 2) on the vector unit: z = x W1^T + b1, a = GELU(z).
+// Layer 1 (K = 2) on the vector unit: the random Fourier features of the
+// input, a = sin(x W1^T + b1) (W1: fixed frequencies, b1: phases 0 or pi/2,
+// so a holds sin and cos of each frequency).  The layer is not trained.
 // With rows != NULL, batch row r is dataset row rows[r] of x, and the
-// gathered inputs are also written to xg (for the layer-1 gradients).  Each
-// thread computes one element in row-major order (z, a) and, when aT is
-// wanted, one in transposed order, so that both stores are coalesced.
+// gathered inputs are also written to xg.  Each thread computes one element
+// in row-major order (z, a) and, when aT is wanted, one in transposed order,
+// so that both stores are coalesced.
 __global__ void k_layer1(const float *__restrict__ x, const int64_t *__restrict__ rows,
                          float *xg, const float *__restrict__ P, int64_t m, float *z, bf16 *a,
                          bf16 *aT) {
@@ -255,21 +235,21 @@ __global__ void k_layer1(const float *__restrict__ x, const int64_t *__restrict_
     }
     const float v = fmaf(x1, P[oW1 + 2 * n + 1], fmaf(x0, P[oW1 + 2 * n], P[ob1 + n]));
     if (z) z[idx] = v;
-    a[idx] = (bf16)gelu_f(v);
+    a[idx] = (bf16)sinf(v);
   }
   if (aT) {
     const int64_t n = idx / m, r = idx % m;
     const int64_t src = rows ? rows[r] : r;
     const float v = fmaf(x[2 * src + 1], P[oW1 + 2 * n + 1],
                          fmaf(x[2 * src], P[oW1 + 2 * n], P[ob1 + n]));
-    aT[idx] = (bf16)gelu_f(v);
+    aT[idx] = (bf16)sinf(v);
   }
 }
 
-// dZ of the output layer, 2 (out - t) / (m * 64), for a block of 32 rows
+// dZ of the output layer, 2 w_c (out - t) / (m * 64), for a block of 32 rows
 // (256 threads: column t mod 64, rows 8 (t / 64) + 0..7).  Target row r is
 // t[rows[r]] when rows is given.  Per block: column sums of dZ (bias
-// gradient) and the sum of (out - t)^2 (loss), in a fixed order.
+// gradient) and the sum of w_c (out - t)^2 (loss), in a fixed order.
 __global__ __launch_bounds__(256) void k_loss_grad(const float *__restrict__ out,
                                                    const float *__restrict__ t,
                                                    const int64_t *__restrict__ rows, int64_t m,
@@ -279,14 +259,15 @@ __global__ __launch_bounds__(256) void k_loss_grad(const float *__restrict__ out
   __shared__ float sq4[4][kOut];
   const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * 32 + rg * 8;
-  const float scale = 2.0f / (float)(m * kOut);
+  const float w = out_weight(c);
+  const float scale = 2.0f * w / (float)(m * kOut);
   float cs_ = 0.f, sq = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int64_t r = r0 + k;
     const int64_t src = rows ? rows[r] : r;
     const float d = out[r * kOut + c] - t[src * kOut + c];
-    sq = fmaf(d, d, sq);
+    sq = fmaf(w * d, d, sq);
     const float g = scale * d;
     cs_ += g;
     const bf16 gb = (bf16)g;
@@ -312,7 +293,6 @@ __global__ __launch_bounds__(256) void k_loss_grad(const float *__restrict__ out
 // (T = m / 32 row tiles, S weight-gradient splits), each summed in a fixed
 // order, and the batch loss; acc (optional) accumulates the loss.
 struct GradParts {
-  const float *w1x0, *w1x1, *b1;  // [T][256]
   const float *w2, *w3;           // [S][256][256]
   const float *b2, *b3;           // [T][256]
   const float *w4;                // [S][64][256]
@@ -351,12 +331,12 @@ __global__ __launch_bounds__(256) void k_reduce_grads(GradParts p, int64_t T, in
   const float *src;
   int64_t ld;
   float *dst;
-  if (e < kH) {
-    src = p.w1x0 + e; ld = kH; dst = G + oW1 + 2 * e;
+  if (e < kH) {          // the fixed feature layer: no partial sums, gradient 0
+    src = nullptr; ld = 0; dst = G + oW1 + 2 * e;
   } else if (e < 2 * kH) {
-    src = p.w1x1 + (e - kH); ld = kH; dst = G + oW1 + 2 * (e - kH) + 1;
+    src = nullptr; ld = 0; dst = G + oW1 + 2 * (e - kH) + 1;
   } else if (e < 3 * kH) {
-    src = p.b1 + (e - 2 * kH); ld = kH; dst = G + ob1 + (e - 2 * kH);
+    src = nullptr; ld = 0; dst = G + ob1 + (e - 2 * kH);
   } else if (e < 4 * kH) {
     src = p.b2 + (e - 3 * kH); ld = kH; dst = G + ob2 + (e - 3 * kH);
   } else if (e < 5 * kH) {
@@ -367,7 +347,8 @@ __global__ __launch_bounds__(256) void k_reduce_grads(GradParts p, int64_t T, in
     src = p.lpart; ld = 1; dst = nullptr;
   }
   float v = 0.f;
-  for (int64_t t = l; t < T; t += 64) v += src[t * ld];
+  if (src)
+    for (int64_t t = l; t < T; t += 64) v += src[t * ld];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   if (l == 0) {
@@ -391,7 +372,7 @@ __global__ void k_adam(float *__restrict__ P, const float *__restrict__ G, float
                        double b1_, double b2_, double eps_, double t_base, int step, bf16 *W2,
                        bf16 *W2T, bf16 *W3, bf16 *W3T, bf16 *W4, bf16 *W4T) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kNP) return;
+  if (i >= kNP || i < oW2) return;   // W1, b1: the fixed feature layer
   if (hyper) {
     lr_ = hyper[0];
     b1_ = hyper[1];
@@ -459,6 +440,28 @@ __global__ void k_inputs(const double *__restrict__ prm, int64_t n, int64_t firs
     x[2 * r] = 0.f;
     x[2 * r + 1] = 0.f;
   }
+}
+
+// The recorded maxima of each point in decreasing order: one wave per point,
+// lane j holding rec[j][i], sorted across the lanes by a bitonic network
+// (the first output then is the point's largest maximum; the order does not
+// depend on the phase of a periodic or chaotic response within the window).
+__global__ __launch_bounds__(256) void k_sort_desc(const double *__restrict__ rec, int64_t n,
+                                                   double *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (i >= n) return;   // the whole wave shares i
+  double v = rec[(int64_t)l * n + i];
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const double o = __shfl_xor(v, j);
+      const bool keep_max = ((l & k) == 0) == ((l & j) == 0);
+      v = keep_max ? fmax(v, o) : fmin(v, o);
+    }
+  }
+  out[(int64_t)l * n + i] = v;
 }
 
 // Standardised targets: y[i][j] = (ln rec[j][i] - mean_j) / std_j.
@@ -654,14 +657,14 @@ struct sur_ctx {
   float *d_mean = nullptr, *d_std = nullptr;
   double *d_dmean = nullptr, *d_dstd = nullptr;
   // activations of one batch
-  float *x = nullptr, *tgt = nullptr, *z1 = nullptr, *z2 = nullptr, *z3 = nullptr, *out = nullptr;
+  float *x = nullptr, *tgt = nullptr, *z2 = nullptr, *z3 = nullptr, *out = nullptr;
   bf16 *a1 = nullptr, *a1T = nullptr, *a2 = nullptr, *a2T = nullptr, *a3 = nullptr, *a3T = nullptr;
   bf16 *dz4b = nullptr, *dz4bT = nullptr, *dz3b = nullptr, *dz3bT = nullptr, *dz2b = nullptr,
        *dz2bT = nullptr;
   // partial sums of the gradients: split-K weight products, per-32-row-tile
   // column sums (biases, layer-1 weights), loss
   float *part2 = nullptr, *part3 = nullptr, *part4 = nullptr;
-  float *cp1 = nullptr, *cpx0 = nullptr, *cpx1 = nullptr, *cp2 = nullptr, *cp3 = nullptr,
+  float *cp2 = nullptr, *cp3 = nullptr,
         *cp4 = nullptr;
   float *lpart = nullptr;     // loss partials
   float *loss = nullptr;      // device scalar
@@ -669,6 +672,8 @@ struct sur_ctx {
   int64_t *scan = nullptr;    // compaction scratch
   int64_t scan_cap = 0;
   int8_t *nlab = nullptr;     // exact labels of the training grid [G][G]
+  double *srec = nullptr;     // records sorted per point (fit_norm, build_dataset)
+  int64_t srec_n = 0;
   int nlab_G = 0;
   // captured training epoch (sur_train_epoch), replayed while the dataset,
   // row list and batch are the same
@@ -768,7 +773,7 @@ struct Fwd {
 };
 
 Fwd train_bufs(sur_ctx *s) {
-  return Fwd{s->x, s->a1, s->a2, s->a3, s->z1, s->z2, s->z3, s->a1T, s->a2T, s->a3T, s->out};
+  return Fwd{s->x, s->a1, s->a2, s->a3, nullptr, s->z2, s->z3, s->a1T, s->a2T, s->a3T, s->out};
 }
 
 constexpr int64_t kInferRows = 65536;
@@ -800,7 +805,7 @@ hipError_t ensure_infer(sur_ctx *s) {
 hipError_t forward_batch(sur_ctx *s, const Fwd &b, int64_t m, const int64_t *rows = nullptr,
                          const float *xsrc = nullptr) {
   hipStream_t st = s->stream;
-  const bool train = b.z1 != nullptr;
+  const bool train = b.z2 != nullptr;
   hipLaunchKernelGGL(k_layer1, dim3(nblk(m * kH, 256)), dim3(256), 0, st, rows ? xsrc : b.x,
                      rows, b.x, s->P, m, b.z1, b.a1, b.a1T);
   hipError_t e = hipGetLastError();
@@ -857,20 +862,11 @@ hipError_t backward_batch(sur_ctx *s, int64_t m, const float *tgt, const int64_t
   g.out_bf16T = s->dz2bT;
   g.colpart = s->cp2;
   if ((e = gemm<EPI_BWD_GELU>(st, g)) != hipSuccess) return e;
-  // layer 2
+  // layer 2 (its input, the feature layer, is fixed: no gradient flows further)
   g = gargs(s->dz2bT, m, s->a1T, m, kH, kH, m);
   g.out_f32 = s->part2;
   if ((e = gemm<EPI_PARTIAL>(st, g, split)) != hipSuccess) return e;
-  // layer 1: only the column sums of dZ1 (bias, and weights with the inputs)
-  g = gargs(s->dz2b, kH, s->W2T, kH, m, kH, kH);
-  g.zprev = s->z1;
-  g.colpart = s->cp1;
-  g.xin = s->x;
-  g.colpart_x0 = s->cpx0;
-  g.colpart_x1 = s->cpx1;
-  if ((e = gemm<EPI_BWD_GELU>(st, g)) != hipSuccess) return e;
-  GradParts p{s->cpx0, s->cpx1, s->cp1, s->part2, s->part3, s->cp2, s->cp3, s->part4, s->cp4,
-              s->lpart};
+  GradParts p{s->part2, s->part3, s->cp2, s->cp3, s->part4, s->cp4, s->lpart};
   hipLaunchKernelGGL(k_reduce_grads, dim3(kReduceWBlocks + (kNColSums + 3) / 4), dim3(256), 0,
                      st, p, T, split,
                      (float)(m * kOut), s->G, s->loss, loss_acc, first ? 1 : 0);
@@ -904,6 +900,23 @@ hipError_t refresh(sur_ctx *s) {
   hipLaunchKernelGGL(k_refresh, dim3(nblk(kH * kH, 256)), dim3(256), 0, s->stream, s->P, s->W2,
                      s->W2T, s->W3, s->W3T, s->W4, s->W4T);
   return hipGetLastError();
+}
+
+// The records [kOut][n] sorted in decreasing order per point, in the
+// handle's scratch (grown as needed); NULL on allocation failure.
+const double *sorted_records(sur_ctx *s, const double *rec, int64_t n, hipError_t *e) {
+  *e = hipSuccess;
+  if (n > s->srec_n) {
+    (void)hipFree(s->srec);
+    s->srec = nullptr;
+    s->srec_n = 0;
+    *e = alloc(&s->srec, n * kOut);
+    if (*e != hipSuccess) return nullptr;
+    s->srec_n = n;
+  }
+  hipLaunchKernelGGL(k_sort_desc, dim3(nblk(n, 4)), dim3(256), 0, s->stream, rec, n, s->srec);
+  *e = hipGetLastError();
+  return *e == hipSuccess ? s->srec : nullptr;
 }
 
 int check_batch(sur_ctx *s, int64_t m) {
@@ -1004,13 +1017,13 @@ int sur_create(int32_t device, void *hip_stream, int64_t max_batch, sur_t *out) 
   A(W2, kH * kH); A(W2T, kH * kH); A(W3, kH * kH); A(W3T, kH * kH);
   A(W4, kOut * kH); A(W4T, kOut * kH);
   A(d_mean, kOut); A(d_std, kOut); A(d_dmean, kOut); A(d_dstd, kOut);
-  A(x, B * kIn); A(tgt, B * kOut); A(z1, B * kH); A(z2, B * kH); A(z3, B * kH); A(out, B * kOut);
+  A(x, B * kIn); A(tgt, B * kOut); A(z2, B * kH); A(z3, B * kH); A(out, B * kOut);
   A(a1, B * kH); A(a1T, B * kH); A(a2, B * kH); A(a2T, B * kH); A(a3, B * kH); A(a3T, B * kH);
   A(dz4b, B * kOut); A(dz4bT, B * kOut); A(dz3b, B * kH); A(dz3bT, B * kH);
   A(dz2b, B * kH); A(dz2bT, B * kH);
   A(part2, (int64_t)kSplit * kH * kH); A(part3, (int64_t)kSplit * kH * kH);
   A(part4, (int64_t)kSplit * kOut * kH);
-  A(cp1, B / 32 * kH); A(cpx0, B / 32 * kH); A(cpx1, B / 32 * kH); A(cp2, B / 32 * kH);
+  A(cp2, B / 32 * kH);
   A(cp3, B / 32 * kH); A(cp4, B / 32 * kOut);
   A(lpart, B / 32); A(loss, 1);
   A(loss_acc, 1);
@@ -1037,11 +1050,11 @@ int sur_destroy(sur_t s) {
   DevGuard dg(s->device);
   (void)hipStreamSynchronize(s->stream);
   void *ptrs[] = {s->P, s->G, s->Mm, s->V, s->W2, s->W2T, s->W3, s->W3T, s->W4, s->W4T,
-                  s->d_mean, s->d_std, s->d_dmean, s->d_dstd, s->x, s->tgt, s->z1, s->z2,
+                  s->d_mean, s->d_std, s->d_dmean, s->d_dstd, s->x, s->tgt, s->z2,
                   s->z3, s->out, s->a1, s->a1T, s->a2, s->a2T, s->a3, s->a3T, s->dz4b,
                   s->dz4bT, s->dz3b, s->dz3bT, s->dz2b, s->dz2bT, s->part2, s->part3,
-                  s->part4, s->cp1, s->cpx0, s->cpx1, s->cp2, s->cp3, s->cp4, s->lpart,
-                  s->loss, s->loss_acc, s->scan, s->nlab, s->ix, s->iout, s->ia1, s->ia2,
+                  s->part4, s->cp2, s->cp3, s->cp4, s->lpart,
+                  s->loss, s->loss_acc, s->scan, s->nlab, s->srec, s->ix, s->iout, s->ia1, s->ia2,
                   s->ia3};
   for (void *p : ptrs) (void)hipFree(p);
   free_epoch_graph(s);
@@ -1121,7 +1134,10 @@ int sur_build_dataset(sur_t s, const double *params, const double *records, int6
   hipLaunchKernelGGL(k_inputs, dim3(nblk(n, 256)), dim3(256), 0, s->stream, params, n, (int64_t)0,
                      n, s->in_lo[0], sc0, s->in_lo[1], sc1, x);
   SUR_HIP(s, hipGetLastError());
-  hipLaunchKernelGGL(k_targets, dim3(nblk(n * kOut, 256)), dim3(256), 0, s->stream, records, n,
+  hipError_t se;
+  const double *sorted = sorted_records(s, records, n, &se);
+  SUR_HIP(s, se);
+  hipLaunchKernelGGL(k_targets, dim3(nblk(n * kOut, 256)), dim3(256), 0, s->stream, sorted, n,
                      s->d_dmean, s->d_dstd, y);
   SUR_HIP(s, hipGetLastError());
   SUR_HIP(s, hipStreamSynchronize(s->stream));
@@ -1256,8 +1272,11 @@ int sur_fit_norm(sur_t s, const double *in_lo, const double *in_hi, const double
   if (!in_lo || !in_hi || !records || n <= 0)
     return sfail(s, ENS_E_INVAL, "sur_fit_norm: bad arguments");
   DevGuard dg(s->device);
-  hipLaunchKernelGGL(k_logmean, dim3(kOut), dim3(256), 0, s->stream, records, n, s->d_dmean);
-  hipLaunchKernelGGL(k_logstd, dim3(kOut), dim3(256), 0, s->stream, records, n, s->d_dmean,
+  hipError_t se;
+  const double *sorted = sorted_records(s, records, n, &se);
+  SUR_HIP(s, se);
+  hipLaunchKernelGGL(k_logmean, dim3(kOut), dim3(256), 0, s->stream, sorted, n, s->d_dmean);
+  hipLaunchKernelGGL(k_logstd, dim3(kOut), dim3(256), 0, s->stream, sorted, n, s->d_dmean,
                      s->d_dstd);
   SUR_HIP(s, hipGetLastError());
   double m[kOut], sd[kOut];

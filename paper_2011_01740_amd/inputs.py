@@ -158,13 +158,19 @@ def prv_linspace(n: int, lo: float = 0.2, hi: float = 10.0):
     return q, y0
 
 
-def mlp_init(seed: int = 4, dims=(2, 256, 256, 256, 64)):
-    """Initial surrogate weights: He-uniform U[-sqrt(6/fan_in), sqrt(6/fan_in)]
-    per weight matrix (shape (out, in), row-major), zero biases, packed as
-    W1, b1, W2, b2, ...; float64 (both implementations round as they need)."""
+def mlp_init(seed: int = 4, dims=(2, 256, 256, 256, 64), ff_scale: float = 16.0):
+    """Initial surrogate parameters, packed W1, b1, W2, b2, ... (float64; both
+    implementations round as they need).  Layer 1 is the fixed random
+    Fourier-feature map: dims[1] / 2 frequency vectors f_k ~ N(0, ff_scale^2 I)
+    (rows k and k + dims[1] / 2 of W1), phases b1 = 0 (sine) and pi / 2
+    (cosine).  The trained layers: He-uniform U[-sqrt(6/fan_in),
+    sqrt(6/fan_in)] weights (shape (out, in), row-major), zero biases."""
     rng = np.random.default_rng(seed)
-    parts = []
-    for i in range(len(dims) - 1):
+    half = dims[1] // 2
+    F = rng.normal(size=(half, dims[0])) * ff_scale
+    parts = [np.vstack([F, F]).ravel(),
+             np.concatenate([np.zeros(half), np.full(dims[1] - half, np.pi / 2)])]
+    for i in range(1, len(dims) - 1):
         lim = (6.0 / dims[i]) ** 0.5
         parts.append(rng.uniform(-lim, lim, size=(dims[i + 1], dims[i])).ravel())
         parts.append(np.zeros(dims[i + 1]))

@@ -49,7 +49,7 @@ class Config:
     shuffle_seed: int = 12
     judge_seed: int = 13
     holdout: float = 0.1
-    target_wrong: float = 0.007    # hold-out error allowed outside the band
+    target_wrong: float = 0.002    # hold-out error allowed outside the band
     judge_n: int = 0               # plain-solved judge points, whole grid rows (0: all;
                                    # the plain time, and so the speed-up, only then)
     judge_chunk: int = 1 << 22     # points per plain-sweep launch

@@ -60,21 +60,24 @@ def test_exact_labels_from_records():
 
 
 def test_screened_sweep_reduced_configuration():
+    """The screened sweep end to end on a reduced configuration (256 x 256
+    training grid, 1024 x 1024 screen, 128 cycles: a 64-cycle pilot, then the
+    longest-first queue order), every screened point judged by a plain solve,
+    and the screen without the network (the same band rule on bilinear
+    interpolation of the training grid) judged on the same points."""
     from paper_2011_01740_amd import surrogate as S
-    # 128 cycles: a 64-cycle pilot, then the longest-first queue order
-    cfg = S.Config(train_grid=64, screen_grid=256, n_phases=128, epochs=40, batch=512,
-                   judge_n=0, target_wrong=0.005, pilot=64)
+    cfg = S.Config(train_grid=256, screen_grid=1024, n_phases=128, epochs=200, batch=4096,
+                   judge_n=0, target_wrong=0.002, pilot=64)
     rep = S.run(cfg, log=lambda *a: print(*a, flush=True))
     # every re-solved point carries the exact label, so errors sit outside the band
-    assert rep.judge_points == 256 * 256
-    assert rep.resolve_frac < 0.5
+    assert rep.judge_points == 1024 * 1024
+    assert rep.resolve_frac < 0.1
     assert rep.judge_wrong_frac <= rep.network_only_wrong_frac
-    assert rep.judge_wrong_frac < 0.03, rep.judge_wrong_frac
+    assert rep.judge_wrong_frac < 0.01, rep.judge_wrong_frac
     # inside the band the final label is the integrator's own
     jfinal, jexact = rep.extra["judge_final"], rep.extra["judge_exact"]
     band = np.abs(rep.extra["judge_pmax"] - np.log(2.0)) < rep.margin
     assert np.array_equal(jfinal[band], jexact[band])
-    # the screen without the network, judged on the same points
     c = rep.compare
     for key in ("interp_holdout", "interp_equal_error", "network_equal_error"):
         assert 0.0 <= c[key]["resolve_frac"] <= 1.0
@@ -83,4 +86,13 @@ def test_screened_sweep_reduced_configuration():
     # the pipeline's hold-out calibrated ones (up to the kernel's FP32 cell
     # lookup at cell borders)
     assert c["network_equal_error"]["resolve_frac"] <= rep.resolve_frac + 0.01
+    # what the network gains on this grid: at the strictest error of the
+    # trade-off (a tenth of the interpolation's own errors) it re-solves
+    # fewer points than the interpolation screen (measured 4.7% against
+    # 5.6%; at looser errors the two are within a few percent of each other
+    # here, and the full-size sweep shows the gain at the pipeline's own
+    # error, tests/test_gpu_screened_fullsize.py)
+    t = c["tradeoff"]
+    assert t["judged_wrong_frac"][0] < c["interp_alone_wrong_frac"] / 5
+    assert t["network"][0] < t["interp"][0], t
     print("compare:", c)

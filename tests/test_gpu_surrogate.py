@@ -3,9 +3,15 @@ oracle evaluated with the same BF16 rounding points.
 
 Tolerances.  Both sides round the same operands to BF16; they differ in the
 accumulation (FP32 on the GPU, FP64 in the oracle) and in the FP32 versus FP64
-GELU, which occasionally moves a value across a BF16 rounding boundary (one
-BF16 unit, 2^-8 relative).  Per tensor the relative Frobenius error is held to
-2e-3 and every element to 2e-2 of the tensor's largest magnitude.
+sine and GELU, which now and then move an operand across a BF16 rounding
+boundary (one BF16 unit, 2^-8 relative, in that one term of a sum).  So:
+per tensor the relative Frobenius error is at most 1e-3; element by element,
+every entry of at least a tenth of the tensor's RMS is within 10% of its own
+value (a weight-gradient entry sums 64 to 4096 row terms; where they cancel
+to a tenth of their sizes, one or two flipped terms move it by up to
+2 x 2^-8 x 10, about 8%), and the smaller entries within 1% of the RMS.  A
+transposed operand, a wrong index, sign or scale moves entries by O(1) of
+their value and fails both.
 """
 import numpy as np
 import pytest
@@ -15,7 +21,9 @@ from paper_2011_01740_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-TOL_NORM, TOL_ELEM = 2e-3, 2e-2
+TOL_NORM = 1e-3          # per tensor, relative Frobenius
+TOL_REL = 0.1            # entries >= 0.1 RMS, relative to themselves
+TOL_ABS = 1e-2           # smaller entries, relative to the tensor's RMS
 
 
 def _sur():
@@ -35,9 +43,18 @@ def _data(m, seed):
 def _close(g, o, name):
     g = np.asarray(g, dtype=np.float64)
     o = np.asarray(o, dtype=np.float64)
-    rel = np.linalg.norm(g - o) / max(np.linalg.norm(o), 1e-30)
-    el = np.abs(g - o).max() / max(np.abs(o).max(), 1e-30)
-    assert rel <= TOL_NORM and el <= TOL_ELEM, (name, rel, el)
+    if not np.any(o):
+        assert not np.any(g), (name, np.abs(g).max())
+        return 0.0
+    rel = np.linalg.norm(g - o) / np.linalg.norm(o)
+    rms = np.sqrt(np.mean(o * o))
+    big = np.abs(o) >= 0.1 * rms
+    d = np.abs(g - o)
+    er_big = (d[big] / np.abs(o[big])).max()
+    er_small = d[~big].max() / rms if (~big).any() else 0.0
+    print(f"{name}: frobenius {rel:.2e}, large entries {er_big:.2e}, small entries {er_small:.2e}")
+    assert rel <= TOL_NORM and er_big <= TOL_REL and er_small <= TOL_ABS, (name, rel, er_big,
+                                                                          er_small)
     return rel
 
 
@@ -68,12 +85,72 @@ def test_gradients_match_oracle(m):
     assert np.array_equal(g, g2) and loss == loss2          # deterministic
     ps = M.unpack(flat)
     out, cache = M.forward(ps, x.astype(np.float64), bf16=True)
-    ref = M.backward(ps, cache, out, t.astype(np.float64), bf16=True)
-    assert loss == pytest.approx(M.mse(out, t), rel=1e-4)
+    ref = M.backward(ps, cache, out, t.astype(np.float64), bf16=True, w=M.OUT_WEIGHTS)
+    assert loss == pytest.approx(M.mse(out, t, M.OUT_WEIGHTS), rel=1e-4)
     gs = M.unpack(g.astype(np.float64))
     names = ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"]
     for name, gg, rr in zip(names, gs, ref):
         _close(gg, rr, name)
+
+
+def test_adam_steps_follow_the_oracle():
+    """Five Adam steps on the GPU against five oracle steps (BF16-mode forward
+    and backward, the oracle's Adam with its bias corrections, pinned by the
+    constant-gradient test): the parameters agree to 1e-3 per tensor, and the
+    feature layer never moves.  (Per element, Adam's first steps are about
+    lr times the gradient's sign, so an entry whose tiny gradient the two
+    sides round to opposite signs moves the other way; the comparison is per
+    tensor for that reason.)"""
+    sur = _sur()
+    flat = _f32_params(13)
+    x, t = _data(1024, 14)
+    ps = M.unpack(flat)
+    mm = [np.zeros_like(p) for p in ps]
+    vv = [np.zeros_like(p) for p in ps]
+    names = ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"]
+    with sur.Surrogate(max_batch=1024) as s:
+        s.set_params(flat)
+        s.set_adam(lr=1e-3)
+        for k in range(1, 6):
+            s.train_step(x, t)
+            out, cache = M.forward(ps, x.astype(np.float64), bf16=True)
+            g = M.backward(ps, cache, out, t.astype(np.float64), bf16=True, w=M.OUT_WEIGHTS)
+            ps, mm, vv = M.adam_step(ps, g, mm, vv, k, lr=1e-3, fixed=2)
+            got = M.unpack(s.get_params())
+            for name, a, b in zip(names, got, ps):
+                rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+                assert rel <= 1e-3, (k, name, rel)
+            assert np.array_equal(got[0], M.unpack(flat)[0])
+            assert np.array_equal(got[1], M.unpack(flat)[1])
+
+
+def test_dataset_targets_are_sorted_standardised_maxima():
+    """sur_fit_norm and sur_build_dataset take each point's recorded maxima in
+    decreasing order: mean / std per rank, targets (ln - mean) / std."""
+    import torch
+    sur = _sur()
+    rng = np.random.default_rng(15)
+    n = 1000
+    rec = np.exp(rng.normal(size=(64, n)) * 0.3)
+    rec[:, 5] = 1.7                                    # ties
+    P = np.stack([rng.uniform(0.2e5, 1.2e5, n), np.exp(rng.uniform(np.log(20e3), np.log(1e6), n))])
+    lo = np.array([0.2e5, np.log(20e3)])
+    hi = np.array([1.2e5, np.log(1e6)])
+    srt = -np.sort(-np.log(rec), axis=0)
+    with sur.Surrogate(max_batch=64) as s:
+        mean = np.empty(64)
+        std = np.empty(64)
+        rd = torch.from_numpy(rec).cuda()
+        sur._check(sur._lib().sur_fit_norm(s.h, sur._dptr(lo), sur._dptr(hi),
+                                           sur.ens.C.c_void_p(rd.data_ptr()), n,
+                                           sur._dptr(mean), sur._dptr(std)), s.h)
+        x, y = s.build_dataset(torch.from_numpy(P).cuda(), rd, n)
+        y = y.cpu().numpy()
+    assert np.allclose(mean, srt.mean(axis=1), rtol=1e-12, atol=1e-14)
+    assert np.allclose(std, srt.std(axis=1), rtol=1e-10)
+    want = ((srt - mean[:, None]) / std[:, None]).T
+    assert np.allclose(y, want, rtol=1e-6, atol=1e-6)
+    assert np.all(np.diff(y * std + mean, axis=1) <= 1e-6)
 
 
 def test_adam_step_matches_formula():

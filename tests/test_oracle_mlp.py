@@ -18,7 +18,22 @@ def test_parameter_count_of_the_surrogate():
     assert [p.shape for p in ps] == M.param_shapes()
     assert np.array_equal(M.pack(ps), flat)
     lim = math.sqrt(6.0 / 256)
-    assert np.abs(ps[2]).max() <= lim and np.all(ps[1] == 0)
+    assert np.abs(ps[2]).max() <= lim and np.all(ps[3] == 0)
+    # the feature layer: each frequency twice, phases 0 and pi/2
+    assert np.array_equal(ps[0][:128], ps[0][128:])
+    assert np.all(ps[1][:128] == 0) and np.all(ps[1][128:] == np.pi / 2)
+    assert 10 < ps[0].std() < 22
+
+
+def test_feature_layer_is_sine_and_cosine_of_each_frequency():
+    ps = M.unpack(I.mlp_init(4))
+    x = np.random.default_rng(3).uniform(-1, 1, size=(50, 2))
+    _, cache = M.forward(ps, x)
+    a1 = cache["a"][1]
+    z = x @ ps[0][:128].T
+    assert np.allclose(a1[:, :128], np.sin(z), rtol=0, atol=1e-12)
+    assert np.allclose(a1[:, 128:], np.cos(z), rtol=0, atol=1e-12)
+    assert np.allclose(a1[:, :128] ** 2 + a1[:, 128:] ** 2, 1.0, atol=1e-12)
 
 
 def test_bf16_rounding_matches_torch():
@@ -56,22 +71,29 @@ def _rand_params(dims, seed):
     return ps
 
 
-def test_gradient_matches_central_differences():
+@pytest.mark.parametrize("weighted", [False, True])
+def test_gradient_matches_central_differences(weighted):
+    """Gradients of the trained layers (2 .. 4) against central differences of
+    the loss; the fixed feature layer's are zero by definition."""
     rng = np.random.default_rng(1)
     ps = _rand_params(SMALL, 2)
     x = rng.normal(size=(7, 2))
     t = rng.normal(size=(7, 2))
+    w = np.array([3.0, 0.5]) if weighted else None
     out, cache = M.forward(ps, x)
-    grads = M.backward(ps, cache, out, t)
+    grads = M.backward(ps, cache, out, t, w=w)
+    assert np.all(grads[0] == 0) and np.all(grads[1] == 0)
     h = 1e-6
     for k, p in enumerate(ps):
+        if k < 2:
+            continue
         fd = np.zeros_like(p)
         for idx in np.ndindex(p.shape):
             old = p[idx]
             p[idx] = old + h
-            lp = M.mse(M.forward(ps, x)[0], t)
+            lp = M.mse(M.forward(ps, x)[0], t, w)
             p[idx] = old - h
-            lm = M.mse(M.forward(ps, x)[0], t)
+            lm = M.mse(M.forward(ps, x)[0], t, w)
             p[idx] = old
             fd[idx] = (lp - lm) / (2 * h)
         err = np.abs(grads[k] - fd).max() / max(np.abs(fd).max(), 1e-12)
@@ -79,7 +101,7 @@ def test_gradient_matches_central_differences():
 
 
 def test_forward_closed_form_tiny_network():
-    # one hidden unit per layer, identity-like weights: out = w4 * g(g(g(w1 . x + b1)))
+    # one unit per layer: out = w4 * g(g(sin(w1 . x + b1))) - 1
     dims = (2, 1, 1, 1, 1)
     ps = [np.array([[1.0, -2.0]]), np.array([0.5]), np.array([[1.0]]), np.array([0.0]),
           np.array([[1.0]]), np.array([0.0]), np.array([[3.0]]), np.array([-1.0])]
@@ -87,7 +109,7 @@ def test_forward_closed_form_tiny_network():
     z = 0.3 - 0.2 + 0.5
     def g(v):
         return 0.5 * v * (1 + math.erf(v / math.sqrt(2)))
-    want = 3.0 * g(g(g(z))) - 1.0
+    want = 3.0 * g(g(math.sin(z))) - 1.0
     out, _ = M.forward(ps, x)
     assert out[0, 0] == pytest.approx(want, rel=1e-15)
 
