@@ -376,8 +376,8 @@ int ens_read(ens_t h, int32_t field, void *dst, size_t bytes, int32_t where);
 size_t ens_field_bytes(ens_t h, int32_t field);
 
 /* Autotuner.  Runs short trial solves of the handle's current problem for
- * each launch candidate -- RK4: block {64, 128, 256, 512, 1024} x systems per
- * lane {1, 2, 4} on min(n_steps, trial_len) steps; RKCK45: block {64, 128,
+ * each launch candidate -- RK4: block {1024, 512, 256, 128, 64} x systems per
+ * lane {4, 2, 1} (in that order) on min(n_steps, trial_len) steps; RKCK45: block {64, 128,
  * 256} x refill threshold {1, 8, 32, 64} with every system capped at
  * min(phases, trial_len) phases and impacts -- timing each with HIP events
  * (best of three), restores the state it started from (state, clock, step,

@@ -1013,8 +1013,10 @@ int ens_tune(ens_t h, const ens_solve_opts *opts, int64_t trial_len, ens_solve_o
   if (h->solver == ENS_RK4) {
     const int64_t len = trial_len > 0 ? trial_len : 256;
     if (trial.n_steps > len) trial.n_steps = len;
-    for (int b : {64, 128, 256, 512, 1024})
-      for (int sp : {1, 2, 4}) cands.emplace_back(b, sp, 0);
+    // largest blocks and most systems per lane first: among candidates
+    // within the 2% margin below, the first one tried is kept
+    for (int b : {1024, 512, 256, 128, 64})
+      for (int sp : {4, 2, 1}) cands.emplace_back(b, sp, 0);
   } else {
     h->trial_cap = trial_len > 0 ? trial_len : 2;
     trial.use_graph = 0;
