@@ -36,6 +36,10 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak (256 CU x 2.4 GHz x 1
 FLOP_PER_STEP = 71
 HW_FLOP_PER_STEP = 70            # what the kernel executes: 33 FMA (x 2) + 4 subtractions
 BYTES_PER_SYSTEM = 8 * 8         # reads p, x, y, z; writes x, y, z, max x
+BF16_PEAK_TFLOPS = 2500.0        # MI355X dense BF16 matrix peak
+# the surrogate network's matrix products per point: 2 x (256 x 256 + 256 x 256
+# + 64 x 256) multiply-adds (the 2 -> 256 feature layer runs on the vector unit)
+SCREEN_FLOP_PER_POINT = 2 * (256 * 256 + 256 * 256 + 64 * 256)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lorenz_rk4_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2011_01740_amd", "csrc", "rk4.hip")
 
@@ -282,6 +286,39 @@ def run_case(case, args):
         d = {k: v for k, v in rep.__dict__.items() if k != "extra"}
         d["case"] = "surrogate"
         print(json.dumps(d), flush=True)
+    elif case == "screen":
+        # the screening forward alone: the seeded network (the weights' values
+        # do not change the work) over the sweep grid, timed with HIP events
+        # on the handle's stream around each sur_screen call (the fused
+        # network kernel, the three weight-layout kernels and the compaction)
+        import numpy as np
+
+        from paper_2011_01740_amd import inputs as I
+        from paper_2011_01740_amd import sur
+        G = args.sur_screen
+        P, _ = I.km_grid(G, G)
+        lo = np.array([P[0].min(), np.log(P[1].min())])
+        hi = np.array([P[0].max(), np.log(P[1].max())])
+        Pd = torch.from_numpy(P).cuda()
+        st = torch.cuda.current_stream()
+        times = []
+        with sur.Surrogate(max_batch=4096, stream=st) as s:
+            s.set_params(I.mlp_init(4))
+            s.set_norm(lo, hi, np.zeros(64), np.ones(64))
+            for rep in range(args.warmup + args.steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                s.screen(Pd, 0.05, 0.5, 0.1)
+                e1.record(st)
+                e1.synchronize()
+                if rep >= args.warmup:
+                    times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        flop = SCREEN_FLOP_PER_POINT * G * G
+        print(json.dumps({"case": "screen", "points": G * G, "screen_ms": ms,
+                          "screen_ms_all": times, "mfma_flop": flop,
+                          "tflops": flop / ms / 1e9,
+                          "frac_of_bf16_peak": flop / ms / 1e9 / BF16_PEAK_TFLOPS}), flush=True)
     elif case == "micro":
         # the (B, N) table of the introductory example and its division and
         # sine variants: one JSON line per configuration
@@ -338,7 +375,8 @@ def run_case(case, args):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--case", choices=["bench", "lorenz", "km", "prv", "copy", "surrogate", "micro"],
+    ap.add_argument("--case", choices=["bench", "lorenz", "km", "prv", "copy", "surrogate", "micro",
+                                       "screen"],
                     default="bench",
                     help="bench: the benchmark line; others: one launch for counter runs")
     ap.add_argument("--km-grid", type=int, default=512)

@@ -22,7 +22,11 @@
  *     the response's sharp resonance and bifurcation edges away (spectral
  *     bias): on the 4096 x 4096 sweep it mislabels 2.2% of the points alone,
  *     five times the 0.43% of bilinear interpolation of its training grid;
- *   - layers 2 and 3: GELU (exact erf form);
+ *   - layers 2 and 3: GELU, z Phi(z) with Phi the standard normal CDF; on
+ *     the GPU the normal tail comes from the rational approximation of
+ *     Abramowitz and Stegun eq. 7.1.26 (|error| <= 1.5e-7) and the features'
+ *     sine from the hardware sine of an FP32 argument, in training and in
+ *     inference alike;
  *   - input: (p_A, ln f) mapped linearly to [-1, 1] with the bounds given to
  *     sur_set_norm; output: the 64 values ln y1max of the last 64 cycles in
  *     decreasing order (sur_fit_norm and sur_build_dataset sort each point's
@@ -143,7 +147,10 @@ int sur_train_epochs(sur_t s, const float *x, const float *y, const int64_t *row
 int sur_gradients(sur_t s, const float *x, const float *target, int64_t m, float *grads,
                   float *loss, int32_t where);
 
-/* Network output (standardised) for m inputs x [m][2] -> out [m][SUR_OUT]. */
+/* Network output (standardised) for m inputs x [m][2] -> out [m][SUR_OUT].
+ * One launch of the fused inference kernel (every layer, 32 points per
+ * wave) for device arrays; host arrays pass through the handle's staging
+ * buffers 65,536 rows at a time.  m may be any size >= 0. */
 int sur_forward(sur_t s, const float *x, int64_t m, float *out, int32_t where);
 
 typedef struct {
@@ -170,7 +177,10 @@ int sur_fit_label_map(sur_t s, const double *records, int32_t G, int8_t *map_out
  * (predicted max_j ln y1max), resolve_idx [n] int64 receiving the indices of
  * the points to re-solve in ascending order; *n_resolve (host) their count.
  * Any output pointer except n_resolve may be NULL.  All array pointers are
- * device memory. */
+ * device memory.  The network and the screening rule run as one launch over
+ * all n points (the inputs normalised in the kernel, no intermediate arrays);
+ * the re-solve list is then compacted in a fixed order.  Returns when the
+ * outputs are complete. */
 int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *opts,
                int8_t *label, uint8_t *resolve, float *pred_max, int64_t *resolve_idx,
                int64_t *n_resolve);

@@ -56,18 +56,55 @@ __device__ __forceinline__ float out_weight(int c) {
   return (c == 0 ? kW0 : 1.0f) * ((float)kOut / (kW0 + (float)(kOut - 1)));
 }
 
-__device__ __forceinline__ float gelu_f(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+// The network's two nonlinear functions, in the form every kernel uses:
+//
+// Fourier feature sin(v): the hardware sine (v_sin_f32, which takes its
+// argument in turns) of the fractional part of v / (2 pi).  Rounding v / (2 pi)
+// to FP32 moves the angle by at most |v| 2^-24 (under 1e-5 for the |v| < 200
+// the features reach), the size of the rounding of v itself, and far below
+// the BF16 unit (2^-8) the feature is rounded to.
+__device__ __forceinline__ float feature_sin(float v) {
+  return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(v * 0.15915494309189534f));
 }
+
+// GELU(z) = z Phi(z), Phi the standard normal CDF.  The tail
+// T(z) = Phi(-|z|) = erfc(|z| / sqrt 2) / 2 comes from the rational-times-
+// Gaussian approximation of Abramowitz and Stegun (eq. 7.1.26, after
+// Hastings; |error in erfc| <= 1.5e-7):
+//   erfc(u) ~ t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-u^2),
+//   t = 1 / (1 + p u),
+// evaluated with u' = u sqrt(log2 e) so that exp(-u^2) = 2^(-u'^2) (p scaled
+// to match, the a_i halved).  Then GELU(z) = max(z, 0) - |z| T(z), which
+// holds for either sign and forms the small negative tail without the
+// cancellation of 1 + erf.  Branch-free: one reciprocal, one exp2.
+constexpr float kTailU = 0.84932180028801907f;   // sqrt(log2 e / 2)
+constexpr float kTailP = 0.27273748f;            // 0.3275911 / sqrt(log2 e)
+constexpr float kTailA1 = 0.127414796f, kTailA2 = -0.142248368f, kTailA3 = 0.7107068705f,
+                kTailA4 = -0.7265760135f, kTailA5 = 0.5307027145f;
+__device__ __forceinline__ float normal_tail(float z, float *gauss = nullptr) {
+  const float u = fabsf(z) * kTailU;
+  const float t = __builtin_amdgcn_rcpf(fmaf(kTailP, u, 1.0f));
+  float p = fmaf(t, kTailA5, kTailA4);
+  p = fmaf(t, p, kTailA3);
+  p = fmaf(t, p, kTailA2);
+  p = fmaf(t, p, kTailA1);
+  const float e = __builtin_amdgcn_exp2f(-(u * u));   // exp(-z^2 / 2)
+  if (gauss) *gauss = e;
+  return (t * p) * e;
+}
+__device__ __forceinline__ float gelu_f(float z) {
+  return fmaf(-fabsf(z), normal_tail(z), fmaxf(z, 0.0f));
+}
+// d GELU / dz = Phi(z) + z phi(z)
 __device__ __forceinline__ float gelu_grad_f(float z) {
-  const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
-  const float pdf = expf(-0.5f * z * z) * 0.39894228040143268f;
-  return fmaf(z, pdf, cdf);
+  float e;
+  const float tail = normal_tail(z, &e);
+  const float cdf = z < 0.0f ? tail : 1.0f - tail;
+  return fmaf(z, e * 0.39894228040143268f, cdf);
 }
 
 // ---------------------------------------------------------------- GEMM tile
-enum Epi { EPI_FWD_GELU = 0, EPI_FWD_LINEAR = 1, EPI_BWD_GELU = 2, EPI_PARTIAL = 3,
-           EPI_FWD_GELU_ACT = 4 };
+enum Epi { EPI_FWD_GELU = 0, EPI_FWD_LINEAR = 1, EPI_BWD_GELU = 2, EPI_PARTIAL = 3 };
 
 struct GemmArgs {
   const bf16 *X;
@@ -111,7 +148,7 @@ __global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
           zp[i][j][q] = g.zprev[(r0 + 16 * i + lrow + q) * g.C + c0 + 16 * j + lc];
   }
   float bj[2] = {0.f, 0.f};
-  if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR || EPI == EPI_FWD_GELU_ACT) {
+  if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR) {
     bj[0] = g.bias[c0 + lc];
     bj[1] = g.bias[c0 + 16 + lc];
   }
@@ -158,7 +195,7 @@ __global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
         for (int q = 0; q < 4; ++q) o[(rb + q) * g.C + c] = v[q];
         continue;
       }
-      if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR || EPI == EPI_FWD_GELU_ACT) {
+      if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] += bj[j];
       }
@@ -168,11 +205,9 @@ __global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
         continue;
       }
       float a[4];
-      if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_GELU_ACT) {
-        if (EPI == EPI_FWD_GELU) {
+      if (EPI == EPI_FWD_GELU) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) g.out_f32[(rb + q) * g.C + c] = v[q];
-        }
+        for (int q = 0; q < 4; ++q) g.out_f32[(rb + q) * g.C + c] = v[q];
 #pragma unroll
         for (int q = 0; q < 4; ++q) a[q] = gelu_f(v[q]);
       } else {  // EPI_BWD_GELU
@@ -235,14 +270,14 @@ __global__ void k_layer1(const float *__restrict__ x, const int64_t *__restrict_
     }
     const float v = fmaf(x1, P[oW1 + 2 * n + 1], fmaf(x0, P[oW1 + 2 * n], P[ob1 + n]));
     if (z) z[idx] = v;
-    a[idx] = (bf16)sinf(v);
+    a[idx] = (bf16)feature_sin(v);
   }
   if (aT) {
     const int64_t n = idx / m, r = idx % m;
     const int64_t src = rows ? rows[r] : r;
     const float v = fmaf(x[2 * src + 1], P[oW1 + 2 * n + 1],
                          fmaf(x[2 * src], P[oW1 + 2 * n], P[ob1 + n]));
-    aT[idx] = (bf16)sinf(v);
+    aT[idx] = (bf16)feature_sin(v);
   }
 }
 
@@ -427,19 +462,14 @@ __global__ void k_refresh(const float *__restrict__ P, bf16 *W2, bf16 *W2T, bf16
   }
 }
 
-// Sweep inputs -> normalised network inputs: (p_A, ln f) mapped to [-1, 1].
-__global__ void k_inputs(const double *__restrict__ prm, int64_t n, int64_t first, int64_t m,
-                         double lo0, double sc0, double lo1, double sc1, float *x) {
+// Sweep inputs -> normalised network inputs: (p_A, ln f) mapped to [-1, 1]
+// (k_fused<true> normalises its inputs the same way).
+__global__ void k_inputs(const double *__restrict__ prm, int64_t n, double lo0, double sc0,
+                         double lo1, double sc1, float *x) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= m) return;
-  const int64_t i = first + r;
-  if (i < n) {
-    x[2 * r] = (float)(fma(prm[i] - lo0, sc0, -1.0));
-    x[2 * r + 1] = (float)(fma(log(prm[n + i]) - lo1, sc1, -1.0));
-  } else {
-    x[2 * r] = 0.f;
-    x[2 * r + 1] = 0.f;
-  }
+  if (r >= n) return;
+  x[2 * r] = (float)(fma(prm[r] - lo0, sc0, -1.0));
+  x[2 * r + 1] = (float)(fma(log(prm[n + r]) - lo1, sc1, -1.0));
 }
 
 // The recorded maxima of each point in decreasing order: one wave per point,
@@ -473,42 +503,256 @@ __global__ void k_targets(const double *__restrict__ rec, int64_t n, const doubl
   y[idx] = (float)((log(rec[j * n + i]) - mean[j]) / stdv[j]);
 }
 
-// Screening epilogue: de-standardise, label, unsure / flag, re-solve mask.
-__global__ void k_screen_epi(const float *__restrict__ out, const float *__restrict__ x,
-                             int64_t first, int64_t m, int64_t n, const float *mean,
-                             const float *stdv, float margin, float spread, float flag_margin,
-                             const int8_t *__restrict__ nlab, int GL,
-                             float label_margin, int8_t *label, uint8_t *resolve, float *pmax) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= m || first + r >= n) return;
-  float mx = -INFINITY, mn = INFINITY;
-  for (int j = 0; j < kOut; ++j) {
-    const float v = fmaf(out[r * kOut + j], stdv[j], mean[j]);
-    mx = fmaxf(mx, v);
-    mn = fminf(mn, v);
+// ---------------------------------------------------------------- fused inference
+// The whole network for 32 points per wave in one kernel.  The products are
+// taken transposed, Z^T = W A^T (MFMA rows = output features, columns =
+// points), so the accumulator of feature block fb and point block j holds, in
+// lane 16 g + i, features 16 fb + 4 g + q of point 16 j + i.  Packed pairwise
+// ((fb, fb + 1) = (2c, 2c + 1)) these are already the B fragments of the next
+// layer's k chunk c, in the permuted k order
+//     k slot 8 g + s  <->  feature 32 c + 16 (s / 4) + 4 g + s mod 4,
+// so the weights of layers 3 and 4 are read with their columns permuted the
+// same way; the feature layer's fragments are formed directly in the standard
+// order.  Weights come from L2 (288 KB in all) in fragment order (k_frag_layout),
+// each fragment serving both point blocks; between layers the activations wait
+// in the wave's slice of LDS.  The arithmetic of every element is the training
+// path's (same features, GELU and roundings to BF16) except for the order of
+// the FP32 sums: the bias starts the accumulation here, and the k order inside
+// an MFMA differs for layers 3 and 4.
+
+// The weights of one layer in fragment order, so that each wave load of an A
+// fragment is 1 KB contiguous: Wf[((fb * 8 + c) * 64 + lane) * 8 + s] holds
+// W[16 fb + lane mod 16][k], k = 32 c + 8 g + s in the standard order, or
+// k = 32 c + 16 (s / 4) + 4 g + s mod 4 in the permuted one (g = lane / 16).
+__global__ void k_frag_layout(const bf16 *__restrict__ W, int64_t rows, int permuted,
+                              bf16 *__restrict__ Wf) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * kH) return;
+  const int s = (int)(e & 7), lane = (int)(e >> 3) & 63;
+  const int64_t c = (e >> 9) & 7, fb = e >> 12;
+  const int g = lane >> 4;
+  const int64_t k = permuted ? 32 * c + 16 * (s >> 2) + 4 * g + (s & 3) : 32 * c + 8 * g + s;
+  Wf[e] = W[(16 * fb + (lane & 15)) * kH + k];
+}
+
+struct FusedArgs {
+  int64_t n;                       // points
+  const double *prm;               // screen: sweep parameters [2][n] (p_A, f)
+  double lo0, sc0, lo1, sc1;       //   and their normalisation
+  const float *x;                  // forward: normalised inputs [n][2]
+  float *out;                      // forward: network outputs [n][64]
+  const float *P;                  // master parameters (W1, b1, b2, b3, b4)
+  const bf16 *W2f, *W3f, *W4f;     // BF16 weights in fragment order (k_frag_layout;
+                                   // 3 and 4 k-permuted)
+  // screen epilogue (k_screen_epi's rule)
+  const float *mean, *stdv;
+  float margin, spread, flag_margin, label_margin;
+  const int8_t *nlab;
+  int GL;
+  int8_t *label;
+  uint8_t *resolve;
+  float *pmax;
+};
+
+// One hidden layer, Z^T = W A^T, for the wave's 32 points: the input's B
+// fragments in[c][j] (k chunk c, point block j) in registers, W's rows read in
+// the permuted k order of the fragments (or the standard one for the feature
+// layer).  Output feature blocks are taken in pairs (2c', 2c' + 1), each pair
+// accumulated over the 8 k chunks (4 independent accumulators, starting from
+// the bias) and at once turned into the next layer's chunk c' (GELU, BF16),
+// which goes to the wave's slice of LDS, out[c'][j][lane].  A pair's 16
+// weight fragments are loaded while the previous pair is computed (two
+// register buffers), so one L2 latency is exposed per layer rather than per
+// MFMA group.  The loop over pairs stays rolled (by two): the kernel is a few
+// thousand instructions, which the waves of a CU share in the instruction
+// cache.
+// Wp: the pair's first fragment for this lane, fragments (fb, c) 8 KB x
+// (fb - 2 cp) + 1 KB x c apart.
+__device__ __forceinline__ void load_pair(const bf16 *__restrict__ Wp,
+                                          const float *__restrict__ bp, bf16x8 (&w)[8][2],
+                                          f32x4 (&bb)[2]) {
+  // the bias first: the products wait for loads in issue order
+  bb[0] = *(const f32x4 *)bp;
+  bb[1] = *(const f32x4 *)(bp + 16);
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) w[c][h] = *(const bf16x8 *)(Wp + (h * 8 + c) * 512);
+}
+
+__device__ __forceinline__ void pair_out(const bf16x8 (&w)[8][2], const f32x4 (&bb)[2],
+                                         const bf16x8 (&in)[8][2], int l, bf16x8 *out) {
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[h][j] = bb[h];
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[h][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[c][h], in[c][j], acc[h][j], 0, 0, 0);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    bf16x8 v;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[4 * h + q] = (bf16)gelu_f(acc[h][j][q]);
+    out[j * 64 + l] = v;
   }
+}
+
+__device__ __forceinline__ void hidden_layer(const bf16 *__restrict__ W,
+                                             const float *__restrict__ b, int g, int l,
+                                             const bf16x8 (&in)[8][2], bf16x8 *out) {
+  const bf16 *W0 = W + l * 8;
+  const float *b0 = b + 4 * g;
+  bf16x8 wa[8][2], wb[8][2];
+  f32x4 ba[2], bb[2];
+  load_pair(W0, b0, wa, ba);
+#pragma unroll 1
+  for (int cp = 0; cp < 8; cp += 2) {
+    load_pair(W0 + (cp + 1) * 8192, b0 + 32 * (cp + 1), wb, bb);
+    __builtin_amdgcn_sched_barrier(0);
+    pair_out(wa, ba, in, l, out + 2 * cp * 64);
+    // the last round reloads pair 0 (a harmless L2 hit) rather than branch
+    load_pair(W0 + ((cp + 2) & 7) * 8192, b0 + 32 * ((cp + 2) & 7), wa, ba);
+    __builtin_amdgcn_sched_barrier(0);
+    pair_out(wb, bb, in, l, out + 2 * (cp + 1) * 64);
+  }
+}
+
+__device__ __forceinline__ void load_act(const bf16x8 *act, int l, bf16x8 (&in)[8][2]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) in[c][j] = act[(2 * c + j) * 64 + l];
+}
+
+template <bool SCREEN>
+__global__ __launch_bounds__(256, 2) void k_fused(FusedArgs a) {
+  // each wave's activations between layers: [chunk][point block][lane]
+  __shared__ bf16x8 lds[4][8 * 2 * 64];
+  const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+  if (r0 >= a.n) return;   // the whole wave
+  bf16x8 *act = lds[threadIdx.x >> 6];
+  const float *__restrict__ P = a.P;
+  float x0[2], x1[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int64_t r = r0 + 16 * j + i;
+    x0[j] = x1[j] = 0.f;
+    if (r < a.n) {
+      if (SCREEN) {
+        x0[j] = (float)(fma(a.prm[r] - a.lo0, a.sc0, -1.0));
+        x1[j] = (float)(fma(log(a.prm[a.n + r]) - a.lo1, a.sc1, -1.0));
+      } else {
+        x0[j] = a.x[2 * r];
+        x1[j] = a.x[2 * r + 1];
+      }
+    }
+  }
+  // the Fourier features, in the standard k order: chunk c, slot 8 g + s
+  bf16x8 fa[8][2];
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int f = 32 * c + 8 * g + s;
+      const float w0 = P[oW1 + 2 * f], w1 = P[oW1 + 2 * f + 1], bb = P[ob1 + f];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        fa[c][j][s] = (bf16)feature_sin(fmaf(x1[j], w1, fmaf(x0[j], w0, bb)));
+    }
+  hidden_layer(a.W2f, P + ob2, g, l, fa, act);    // layer 2
+  load_act(act, l, fa);
+  hidden_layer(a.W3f, P + ob3, g, l, fa, act);    // layer 3
+  load_act(act, l, fa);
+  // output layer
+  f32x4 o4[4][2];
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    const f32x4 bb = *(const f32x4 *)(P + ob4 + 16 * ob + 4 * g);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) o4[ob][j] = bb;
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+      const bf16x8 w = *(const bf16x8 *)(a.W4f + ((ob * 8 + c) * 64 + l) * 8);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        o4[ob][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, fa[c][j], o4[ob][j], 0, 0, 0);
+    }
+  if (!SCREEN) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t r = r0 + 16 * j + i;
+      if (r < a.n)
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) *(f32x4 *)(a.out + r * kOut + 16 * ob + 4 * g) = o4[ob][j];
+    }
+    return;
+  }
+  // de-standardised maximum and minimum over the 64 outputs of each point:
+  // 16 in the lane, then across the four lane groups
+  float mx[2], mn[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    mx[j] = -INFINITY;
+    mn[j] = INFINITY;
+  }
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    const f32x4 sd = *(const f32x4 *)(a.stdv + 16 * ob + 4 * g);
+    const f32x4 mu = *(const f32x4 *)(a.mean + 16 * ob + 4 * g);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float v = fmaf(o4[ob][j][q], sd[q], mu[q]);
+        mx[j] = fmaxf(mx[j], v);
+        mn[j] = fminf(mn[j], v);
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+      mx[j] = fmaxf(mx[j], __shfl_xor(mx[j], off));
+      mn[j] = fminf(mn[j], __shfl_xor(mn[j], off));
+    }
+  // lane group j (j < 2) finishes point 16 j + i
+  if (g >= 2) return;
+  const int64_t r = r0 + 16 * g + i;
+  if (r >= a.n) return;
+  const float xmx = g ? mx[1] : mx[0], xmn = g ? mn[1] : mn[0];
+  const float u0f = g ? x0[1] : x0[0], v0f = g ? x1[1] : x1[0];
   const float ln2 = 0.69314718055994531f;
-  const float d = fabsf(mx - ln2);
-  const bool unsure = d < margin;
-  bool flag = (mx - mn > spread) && d < flag_margin;
-  if (nlab) {
-    // labels of the four training nodes around the point (cell corners);
-    // k = how many differ from the network's label (an unknown label counts)
-    const float u = (x[2 * r] + 1.0f) * 0.5f * (float)(GL - 1);
-    const float v = (x[2 * r + 1] + 1.0f) * 0.5f * (float)(GL - 1);
+  const float d = fabsf(xmx - ln2);
+  const bool unsure = d < a.margin;
+  bool flag = (xmx - xmn > a.spread) && d < a.flag_margin;
+  const int8_t lab = xmx >= ln2 ? 1 : 0;
+  if (a.nlab) {
+    const int GL = a.GL;
+    const float u = (u0f + 1.0f) * 0.5f * (float)(GL - 1);
+    const float v = (v0f + 1.0f) * 0.5f * (float)(GL - 1);
     int u0 = (int)floorf(u), v0 = (int)floorf(v);
     u0 = u0 < 0 ? 0 : (u0 > GL - 2 ? GL - 2 : u0);
     v0 = v0 < 0 ? 0 : (v0 > GL - 2 ? GL - 2 : v0);
-    const int8_t lab = mx >= ln2 ? 1 : 0;
     const int64_t b = (int64_t)u0 * GL + v0;
-    const int k = (nlab[b] != lab) + (nlab[b + 1] != lab) + (nlab[b + GL] != lab) +
-                  (nlab[b + GL + 1] != lab);
-    flag = flag || k == 4 || (k > 0 && d < label_margin);
+    const int k = (a.nlab[b] != lab) + (a.nlab[b + 1] != lab) + (a.nlab[b + GL] != lab) +
+                  (a.nlab[b + GL + 1] != lab);
+    flag = flag || k == 4 || (k > 0 && d < a.label_margin);
   }
-  const int64_t i = first + r;
-  if (label) label[i] = mx >= ln2 ? 1 : 0;
-  if (resolve) resolve[i] = (unsure || flag) ? 1 : 0;
-  if (pmax) pmax[i] = mx;
+  if (a.label) a.label[r] = lab;
+  if (a.resolve) a.resolve[r] = (unsure || flag) ? 1 : 0;
+  if (a.pmax) a.pmax[r] = xmx;
 }
 
 // Exact label of each training node: [max_j rec[j][i] >= 2], -1 if a record
@@ -685,10 +929,11 @@ struct sur_ctx {
   int64_t ep_n = 0, ep_batch = 0;
   double *hyper = nullptr;   // device: lr, beta1, beta2, eps, t_base
   double hyper_host[5] = {0, 0, 0, 0, 0};
-  // inference workspace (sur_forward, sur_screen): kInferRows rows, allocated
-  // on first use
+  // inference: W2, W3, W4 in fragment order (k_frag_layout), and staging of
+  // host inputs and outputs (sur_forward from host memory: kInferRows rows,
+  // allocated on first use)
+  bf16 *W2f = nullptr, *W3f = nullptr, *W4f = nullptr;
   float *ix = nullptr, *iout = nullptr;
-  bf16 *ia1 = nullptr, *ia2 = nullptr, *ia3 = nullptr;
 };
 
 namespace {
@@ -762,8 +1007,8 @@ GemmArgs gargs(const bf16 *X, int64_t ldx, const bf16 *Y, int64_t ldy, int64_t R
   return g;
 }
 
-// Buffers of one forward pass; z* and a*T (kept for the backward pass) are
-// NULL for inference.
+// Buffers of one training forward pass (z* and a*T are kept for the
+// backward pass).
 struct Fwd {
   float *x;
   bf16 *a1, *a2, *a3;
@@ -778,34 +1023,46 @@ Fwd train_bufs(sur_ctx *s) {
 
 constexpr int64_t kInferRows = 65536;
 
-Fwd infer_bufs(sur_ctx *s) {
-  return Fwd{s->ix, s->ia1, s->ia2, s->ia3, nullptr, nullptr, nullptr, nullptr, nullptr,
-             nullptr, s->iout};
-}
-
 hipError_t ensure_infer(sur_ctx *s) {
   if (s->ix) return hipSuccess;
-  hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = hipMalloc((void **)&s->ix, kInferRows * kIn * sizeof(float));
+  hipError_t e = hipMalloc((void **)&s->ix, kInferRows * kIn * sizeof(float));
   if (e == hipSuccess) e = hipMalloc((void **)&s->iout, kInferRows * kOut * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc((void **)&s->ia1, kInferRows * kH * sizeof(bf16));
-  if (e == hipSuccess) e = hipMalloc((void **)&s->ia2, kInferRows * kH * sizeof(bf16));
-  if (e == hipSuccess) e = hipMalloc((void **)&s->ia3, kInferRows * kH * sizeof(bf16));
   if (e != hipSuccess) {
-    (void)hipFree(s->ix); (void)hipFree(s->iout); (void)hipFree(s->ia1);
-    (void)hipFree(s->ia2); (void)hipFree(s->ia3);
+    (void)hipFree(s->ix);
+    (void)hipFree(s->iout);
     s->ix = s->iout = nullptr;
-    s->ia1 = s->ia2 = s->ia3 = nullptr;
   }
   return e;
 }
 
-// Forward pass of one batch of m rows (m % 64 == 0): inputs from b.x, or
-// with rows != NULL dataset rows rows[0..m) of xsrc (gathered into b.x).
+// The fragment-order weight copies of the current parameters, then the fused
+// inference of n points (n > 0).
+hipError_t fused(sur_ctx *s, FusedArgs a, bool screen) {
+  hipStream_t st = s->stream;
+  hipLaunchKernelGGL(k_frag_layout, dim3(nblk(kH * kH, 256)), dim3(256), 0, st, s->W2,
+                     (int64_t)kH, 0, s->W2f);
+  hipLaunchKernelGGL(k_frag_layout, dim3(nblk(kH * kH, 256)), dim3(256), 0, st, s->W3,
+                     (int64_t)kH, 1, s->W3f);
+  hipLaunchKernelGGL(k_frag_layout, dim3(nblk(kOut * kH, 256)), dim3(256), 0, st, s->W4,
+                     (int64_t)kOut, 1, s->W4f);
+  a.P = s->P;
+  a.W2f = s->W2f;
+  a.W3f = s->W3f;
+  a.W4f = s->W4f;
+  const dim3 grid(nblk(a.n, 128));   // 4 waves of 32 points
+  if (screen)
+    hipLaunchKernelGGL(k_fused<true>, grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_fused<false>, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// Training forward pass of one batch of m rows (m % 64 == 0): inputs from
+// b.x, or with rows != NULL dataset rows rows[0..m) of xsrc (gathered into
+// b.x).
 hipError_t forward_batch(sur_ctx *s, const Fwd &b, int64_t m, const int64_t *rows = nullptr,
                          const float *xsrc = nullptr) {
   hipStream_t st = s->stream;
-  const bool train = b.z2 != nullptr;
   hipLaunchKernelGGL(k_layer1, dim3(nblk(m * kH, 256)), dim3(256), 0, st, rows ? xsrc : b.x,
                      rows, b.x, s->P, m, b.z1, b.a1, b.a1T);
   hipError_t e = hipGetLastError();
@@ -815,14 +1072,14 @@ hipError_t forward_batch(sur_ctx *s, const Fwd &b, int64_t m, const int64_t *row
   g.out_f32 = b.z2;
   g.out_bf16 = b.a2;
   g.out_bf16T = b.a2T;
-  e = train ? gemm<EPI_FWD_GELU>(st, g) : gemm<EPI_FWD_GELU_ACT>(st, g);
+  e = gemm<EPI_FWD_GELU>(st, g);
   if (e != hipSuccess) return e;
   g = gargs(b.a2, kH, s->W3, kH, m, kH, kH);
   g.bias = s->P + ob3;
   g.out_f32 = b.z3;
   g.out_bf16 = b.a3;
   g.out_bf16T = b.a3T;
-  e = train ? gemm<EPI_FWD_GELU>(st, g) : gemm<EPI_FWD_GELU_ACT>(st, g);
+  e = gemm<EPI_FWD_GELU>(st, g);
   if (e != hipSuccess) return e;
   g = gargs(b.a3, kH, s->W4, kH, m, kOut, kH);
   g.bias = s->P + ob4;
@@ -1015,7 +1272,8 @@ int sur_create(int32_t device, void *hip_stream, int64_t max_batch, sur_t *out) 
   if (e == hipSuccess) e = alloc(&s->ptr, (cnt))
   A(P, kNP); A(G, kNP); A(Mm, kNP); A(V, kNP);
   A(W2, kH * kH); A(W2T, kH * kH); A(W3, kH * kH); A(W3T, kH * kH);
-  A(W4, kOut * kH); A(W4T, kOut * kH);
+  A(W4, kOut * kH); A(W4T, kOut * kH); A(W2f, kH * kH); A(W3f, kH * kH);
+  A(W4f, kOut * kH);
   A(d_mean, kOut); A(d_std, kOut); A(d_dmean, kOut); A(d_dstd, kOut);
   A(x, B * kIn); A(tgt, B * kOut); A(z2, B * kH); A(z3, B * kH); A(out, B * kOut);
   A(a1, B * kH); A(a1T, B * kH); A(a2, B * kH); A(a2T, B * kH); A(a3, B * kH); A(a3T, B * kH);
@@ -1054,8 +1312,8 @@ int sur_destroy(sur_t s) {
                   s->z3, s->out, s->a1, s->a1T, s->a2, s->a2T, s->a3, s->a3T, s->dz4b,
                   s->dz4bT, s->dz3b, s->dz3bT, s->dz2b, s->dz2bT, s->part2, s->part3,
                   s->part4, s->cp2, s->cp3, s->cp4, s->lpart,
-                  s->loss, s->loss_acc, s->scan, s->nlab, s->srec, s->ix, s->iout, s->ia1, s->ia2,
-                  s->ia3};
+                  s->loss, s->loss_acc, s->scan, s->nlab, s->srec, s->ix, s->iout, s->W2f,
+                  s->W3f, s->W4f};
   for (void *p : ptrs) (void)hipFree(p);
   free_epoch_graph(s);
   (void)hipFree(s->hyper);
@@ -1131,8 +1389,8 @@ int sur_build_dataset(sur_t s, const double *params, const double *records, int6
   if (n == 0) return ENS_OK;
   DevGuard dg(s->device);
   const double sc0 = 2.0 / (s->in_hi[0] - s->in_lo[0]), sc1 = 2.0 / (s->in_hi[1] - s->in_lo[1]);
-  hipLaunchKernelGGL(k_inputs, dim3(nblk(n, 256)), dim3(256), 0, s->stream, params, n, (int64_t)0,
-                     n, s->in_lo[0], sc0, s->in_lo[1], sc1, x);
+  hipLaunchKernelGGL(k_inputs, dim3(nblk(n, 256)), dim3(256), 0, s->stream, params, n,
+                     s->in_lo[0], sc0, s->in_lo[1], sc1, x);
   SUR_HIP(s, hipGetLastError());
   hipError_t se;
   const double *sorted = sorted_records(s, records, n, &se);
@@ -1193,20 +1451,30 @@ int sur_forward(sur_t s, const float *x, int64_t m, float *out, int32_t where) {
   if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_forward: NULL handle");
   if (m < 0 || (m > 0 && (!x || !out))) return sfail(s, ENS_E_INVAL, "sur_forward: bad arguments");
   DevGuard dg(s->device);
-  const hipMemcpyKind kin = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  const hipMemcpyKind kout = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  if (m > 0) SUR_HIP(s, ensure_infer(s));
-  const Fwd b = infer_bufs(s);
+  if (m == 0) return ENS_OK;
+  FusedArgs a;
+  std::memset(&a, 0, sizeof(a));
+  if (where == ENS_DEVICE) {
+    a.n = m;
+    a.x = x;
+    a.out = out;
+    SUR_HIP(s, fused(s, a, false));
+    return ENS_OK;
+  }
+  // host buffers: staged through the handle's buffers kInferRows rows at a time
+  SUR_HIP(s, ensure_infer(s));
   for (int64_t first = 0; first < m; first += kInferRows) {
     const int64_t rows = m - first < kInferRows ? m - first : kInferRows;
-    const int64_t padded = (rows + 63) / 64 * 64;
-    if (padded > rows)
-      SUR_HIP(s, hipMemsetAsync(b.x + rows * kIn, 0, (padded - rows) * kIn * sizeof(float), s->stream));
-    SUR_HIP(s, hipMemcpyAsync(b.x, x + first * kIn, rows * kIn * sizeof(float), kin, s->stream));
-    SUR_HIP(s, forward_batch(s, b, padded));
-    SUR_HIP(s, hipMemcpyAsync(out + first * kOut, b.out, rows * kOut * sizeof(float), kout, s->stream));
+    SUR_HIP(s, hipMemcpyAsync(s->ix, x + first * kIn, rows * kIn * sizeof(float),
+                              hipMemcpyHostToDevice, s->stream));
+    a.n = rows;
+    a.x = s->ix;
+    a.out = s->iout;
+    SUR_HIP(s, fused(s, a, false));
+    SUR_HIP(s, hipMemcpyAsync(out + first * kOut, s->iout, rows * kOut * sizeof(float),
+                              hipMemcpyDeviceToHost, s->stream));
   }
-  if (where == ENS_HOST) SUR_HIP(s, hipStreamSynchronize(s->stream));
+  SUR_HIP(s, hipStreamSynchronize(s->stream));
   return ENS_OK;
 }
 
@@ -1225,23 +1493,27 @@ int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *
   if (n == 0) return ENS_OK;
   DevGuard dg(s->device);
   const double sc0 = 2.0 / (s->in_hi[0] - s->in_lo[0]), sc1 = 2.0 / (s->in_hi[1] - s->in_lo[1]);
-  SUR_HIP(s, ensure_infer(s));
-  const Fwd b = infer_bufs(s);
-  for (int64_t first = 0; first < n; first += kInferRows) {
-    const int64_t rows = n - first < kInferRows ? n - first : kInferRows;
-    const int64_t padded = (rows + 63) / 64 * 64;
-    hipLaunchKernelGGL(k_inputs, dim3(nblk(padded, 256)), dim3(256), 0, s->stream, params, n,
-                       first, padded, s->in_lo[0], sc0, s->in_lo[1], sc1, b.x);
-    SUR_HIP(s, hipGetLastError());
-    SUR_HIP(s, forward_batch(s, b, padded));
-    const bool use_labels = s->nlab && o->label_margin >= 0.0;
-    hipLaunchKernelGGL(k_screen_epi, dim3(nblk(padded, 256)), dim3(256), 0, s->stream, b.out,
-                       b.x, first, padded, n, s->d_mean, s->d_std, (float)o->margin,
-                       (float)o->spread, (float)o->flag_margin,
-                       use_labels ? s->nlab : (const int8_t *)nullptr, s->nlab_G,
-                       (float)o->label_margin, label, resolve, pred_max);
-    SUR_HIP(s, hipGetLastError());
-  }
+  const bool use_labels = s->nlab && o->label_margin >= 0.0;
+  FusedArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.prm = params;
+  a.lo0 = s->in_lo[0];
+  a.sc0 = sc0;
+  a.lo1 = s->in_lo[1];
+  a.sc1 = sc1;
+  a.mean = s->d_mean;
+  a.stdv = s->d_std;
+  a.margin = (float)o->margin;
+  a.spread = (float)o->spread;
+  a.flag_margin = (float)o->flag_margin;
+  a.label_margin = (float)o->label_margin;
+  a.nlab = use_labels ? s->nlab : nullptr;
+  a.GL = s->nlab_G;
+  a.label = label;
+  a.resolve = resolve;
+  a.pmax = pred_max;
+  SUR_HIP(s, fused(s, a, true));
   if (resolve) {
     const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
     if (nb + 1 > s->scan_cap) {

@@ -2,8 +2,10 @@
 oracle evaluated with the same BF16 rounding points.
 
 Tolerances.  Both sides round the same operands to BF16; they differ in the
-accumulation (FP32 on the GPU, FP64 in the oracle) and in the FP32 versus FP64
-sine and GELU, which now and then move an operand across a BF16 rounding
+accumulation (FP32 on the GPU, FP64 in the oracle) and in the sine and GELU
+(on the GPU the hardware sine of an FP32 argument and a rational approximation
+of the normal tail with |error| <= 1.5e-7; in the oracle FP64 library
+functions), which now and then move an operand across a BF16 rounding
 boundary (one BF16 unit, 2^-8 relative, in that one term of a sum).  So:
 per tensor the relative Frobenius error is at most 1e-3; element by element,
 every entry of at least a tenth of the tensor's RMS is within 10% of its own
@@ -71,6 +73,76 @@ def test_forward_matches_oracle():
         out = s.forward(x)
     ref, _ = M.forward(M.unpack(flat), x.astype(np.float64), bf16=True)
     _close(out, ref, "output")
+
+
+@pytest.mark.parametrize("m", [1, 33, 1000])
+def test_forward_ragged_sizes_match_oracle(m):
+    """The fused inference kernel takes 32 points per wave and 4 waves per
+    block: sizes below one wave, one point past a wave, and a ragged tail."""
+    sur = _sur()
+    flat = _f32_params(6)
+    x, _ = _data(m, 3)
+    with sur.Surrogate(max_batch=512) as s:
+        s.set_params(flat)
+        out = s.forward(x)
+    ref, _ = M.forward(M.unpack(flat), x.astype(np.float64), bf16=True)
+    _close(out, ref, f"output m={m}")
+
+
+def test_forward_host_chunks_equal_device_call():
+    """From host memory the inputs pass through the handle's staging buffers
+    65536 rows at a time; from device memory one launch takes all rows.  Both
+    give the same bits, and a seeded sample of rows (both ends of each chunk
+    included) matches the oracle."""
+    import torch
+    sur = _sur()
+    flat = _f32_params(7)
+    m = 65536 + 1000
+    x, _ = _data(m, 4)
+    with sur.Surrogate(max_batch=512) as s:
+        s.set_params(flat)
+        out_h = s.forward(x)
+        out_d = s.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.array_equal(out_h, out_d)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([[0, 65535, 65536, m - 1], rng.integers(0, m, 1000)]))
+    ref, _ = M.forward(M.unpack(flat), x[idx].astype(np.float64), bf16=True)
+    _close(out_h[idx], ref, "output sample")
+
+
+def test_screen_full_grid_sample_matches_oracle():
+    """sur_screen over the whole 4096 x 4096 sweep grid (2^24 points, the
+    screening launch of the screened sweep): the predicted maximum at a seeded
+    sample of points (the grid's corners included) against the oracle's
+    network on the same normalised inputs, and the label wherever the
+    oracle's prediction is not within 1e-2 of the threshold."""
+    import torch
+    sur = _sur()
+    G = 4096
+    P, _ = I.km_grid(G, G)
+    lo = np.array([P[0].min(), np.log(P[1].min())])
+    hi = np.array([P[0].max(), np.log(P[1].max())])
+    mean = np.linspace(0.2, 0.9, 64)
+    std = np.linspace(0.3, 0.6, 64)
+    flat = _f32_params(8)
+    with sur.Surrogate(max_batch=512) as s:
+        s.set_params(flat)
+        s.set_norm(lo, hi, mean, std)
+        label, resolve, pmax, idx = s.screen(torch.from_numpy(P).cuda(), 0.05, 0.5, 0.1)
+        label, resolve, pmax = (v.cpu().numpy() for v in (label, resolve, pmax))
+    rng = np.random.default_rng(9)
+    k = np.unique(np.concatenate([[0, G - 1, G * (G - 1), G * G - 1],
+                                  rng.integers(0, G * G, 4000)]))
+    x = np.stack([(P[0, k] - lo[0]) * (2.0 / (hi[0] - lo[0])) - 1.0,
+                  (np.log(P[1, k]) - lo[1]) * (2.0 / (hi[1] - lo[1])) - 1.0],
+                 axis=1).astype(np.float32)
+    ref, _ = M.forward(M.unpack(flat), x.astype(np.float64), bf16=True)
+    y = ref * std + mean
+    want = y.max(axis=1)
+    _close(pmax[k], want, "predicted max")
+    far = np.abs(want - np.log(2.0)) > 1e-2
+    assert np.array_equal(label[k][far].astype(bool), (want >= np.log(2.0))[far])
+    assert idx.numel() == int(resolve.sum())
 
 
 @pytest.mark.parametrize("m", [64, 128, 4096])
