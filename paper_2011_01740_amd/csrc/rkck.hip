@@ -144,12 +144,12 @@ __device__ __forceinline__ double rfifth(double x) {
 }
 
 // Step-size factor 0.9 E^(-1/5), clamped to [0.2, 5] (E = 0 gives 5).  Outside
-// [1e-4, 4e3] the clamp decides, so the root is only taken where FP32 holds E.
+// [1e-4, 4e3] the clamp decides, so the root is only taken where FP32 holds E
+// (of E limited to that range; the selects leave no branch).
 __device__ __forceinline__ double step_factor(double E) {
-  if (!(E >= 1e-4)) return 5.0;
-  if (E > 4e3) return 0.2;
-  const double f = 0.9 * rfifth(E);
-  return f < 0.2 ? 0.2 : (f > 5.0 ? 5.0 : f);
+  const double f = 0.9 * rfifth(fmin(fmax(E, 1e-4), 4e3));
+  const double fc = f < 0.2 ? 0.2 : (f > 5.0 ? 5.0 : f);
+  return !(E >= 1e-4) ? 5.0 : (E > 4e3 ? 0.2 : fc);
 }
 
 // ------------------------------------------------------------------ models
@@ -892,89 +892,87 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
     return true;
   }
   const double fac = step_factor(E);
+  // The common outcomes (rejection, event retry, plain acceptance) by
+  // selects; only the rare ones branch: an event's secant step, a seat
+  // change or impact, a Poincare point, settling.
+  const bool rej = E > 1.0 && h_try > a.dt_min;
+  const double h_rej = clampd(h_try * fmin(fac, 1.0), a.dt_min, a.dt_max);
+  const double h_next = clampd(h_try * fac, a.dt_min, a.dt_max);
+  const double tol = a.event_tol;
+  // event detection: overshoot -> secant retry from the same point.  The
+  // tests are plain compares; the secant steps (divisions) are formed only
+  // when one of them fired, which few steps do.
+  const double g3o = y[2] - m.delta, g3n = y5[2] - m.delta;  // lift-off
+  const bool free = !m.seated;
+  // y1 crossing below the seat: an impact (y1 > 0 before), or a rebound
+  // swallowed by one step (y1 = 0 before)
+  const bool ev_y1 = free && y[0] >= 0.0 && y5[0] < -tol;
+  const bool ev_max = free && y[1] > 0.0 && y5[1] < -tol;   // local maximum, y2 decreasing
+  const bool ev_lift = !free && g3o < 0.0 && g3n > tol;
+  const bool over = !rej && (ev_y1 || ev_max || ev_lift);
+  double hs = INFINITY;
+  if (over) {
+    if (ev_y1) hs = fmin(hs, y[0] > 0.0 ? h_try * y[0] / (y[0] - y5[0]) : 0.5 * h_try);
+    if (ev_max) hs = fmin(hs, h_try * y[1] / (y[1] - y5[1]));
+    if (ev_lift) hs = fmin(hs, h_try * (-g3o) / (g3n - g3o));
+  }
+  const bool retry = over && L.ev_iter < a.max_event_iter;
+  const bool take = !rej && !retry;   // the step is accepted
+  L.rejected += rej ? 1 : 0;
+  L.evretry += retry ? 1 : 0;
+  L.accepted += take ? 1 : 0;
+  L.status |= (!rej && E > 1.0) ? ENS_SYS_DT_MIN : 0;   // at the step-size floor
+  L.status |= (take && over) ? ENS_SYS_EVENT_ITER : 0;  // secant retries exhausted
+  L.ev_iter = retry ? L.ev_iter + 1 : (take ? 0 : L.ev_iter);
+  L.h = rej ? h_rej : (retry ? hs : h_next);
+  const double y2o = y[1];
+#pragma unroll
+  for (int c = 0; c < D; ++c) y[c] = take ? y5[c] : y[c];
+  if constexpr (SC == kDP) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) fs.k[c] = take ? k7[c] : fs.k[c];
+  }
+  L.t += take ? h_try : 0.0;
+  // an accepted step may lift the body off its seat, or end in a located
+  // impact (Newtonian restitution, Sec. 4.3), or at a located local maximum
+  // of the free flight (the Poincare point)
+  const bool lift = take && !free && y[2] - m.delta >= 0.0;
+  const bool impact = take && free && y[0] <= 0.0 && y[1] < 0.0;
+  const bool pmax = take && free && !impact && y2o > 0.0 && y[1] <= 0.0;
   bool done = false;
-  if (E > 1.0 && h_try > a.dt_min) {
-    L.rejected++;
-    L.h = clampd(h_try * fmin(fac, 1.0), a.dt_min, a.dt_max);
-  } else {
-    if (E > 1.0) L.status |= ENS_SYS_DT_MIN;
-    const double h_next = clampd(h_try * fac, a.dt_min, a.dt_max);
-    const double tol = a.event_tol;
-    // event detection: overshoot -> secant retry from the same point.  The
-    // tests are plain compares; the secant steps (divisions) are formed only
-    // when one of them fired, which few steps do.
-    const double g3o = y[2] - m.delta, g3n = y5[2] - m.delta;  // lift-off
-    const bool free = !m.seated;
-    const bool ev_imp = free && y[0] > 0.0 && y5[0] < -tol;   // impact, y1 decreasing through 0
-    const bool ev_swal = free && y[0] == 0.0 && y5[0] < -tol; // rebound swallowed by one step
-    const bool ev_max = free && y[1] > 0.0 && y5[1] < -tol;   // local maximum, y2 decreasing
-    const bool ev_lift = !free && g3o < 0.0 && g3n > tol;
-    const bool over = ev_imp || ev_swal || ev_max || ev_lift;
-    double hs = INFINITY;
-    if (over) {
-      if (ev_imp) hs = fmin(hs, h_try * y[0] / (y[0] - y5[0]));
-      if (ev_swal) hs = fmin(hs, 0.5 * h_try);
-      if (ev_max) hs = fmin(hs, h_try * y[1] / (y[1] - y5[1]));
-      if (ev_lift) hs = fmin(hs, h_try * (-g3o) / (g3n - g3o));
-    }
-    if (over && L.ev_iter < a.max_event_iter) {
-      L.ev_iter++;
-      L.evretry++;
-      L.h = hs;
+  if (lift || impact) {
+    fs.have = false;
+    if (lift) {
+      m.seated = false;
     } else {
-      if (over) L.status |= ENS_SYS_EVENT_ITER;
-      L.ev_iter = 0;
-      const double y2o = y[1];
-      const bool was_seated = m.seated;
-#pragma unroll
-      for (int c = 0; c < D; ++c) y[c] = y5[c];
-      if constexpr (SC == kDP) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) fs.k[c] = k7[c];
+      const double v_in = y[1];
+      y[0] = 0.0;
+      y[1] = -m.r * v_in;
+      L.impacts++;
+      if (fabs(v_in) < a.v_stick && y[2] < m.delta) {
+        m.seated = true;
+        y[1] = 0.0;
+        L.status |= ENS_SYS_SEATED;
       }
-      L.t += h_try;
-      L.accepted++;
-      L.h = h_next;
-      bool phase_end = false;
-      if (was_seated) {
-        if (y[2] - m.delta >= 0.0) {
-          m.seated = false;
-          fs.have = false;
-        }
-      } else if (y[0] <= 0.0 && y[1] < 0.0) {
-        // located impact: Newtonian restitution (Sec. 4.3)
-        fs.have = false;
-        const double v_in = y[1];
-        y[0] = 0.0;
-        y[1] = -m.r * v_in;
-        L.impacts++;
-        if (fabs(v_in) < a.v_stick && y[2] < m.delta) {
-          m.seated = true;
-          y[1] = 0.0;
-          L.status |= ENS_SYS_SEATED;
-        }
-        if (L.max_impacts > 0 && (int64_t)L.impacts >= L.max_impacts) done = true;
-      } else if (y2o > 0.0 && y[1] <= 0.0) {
-        phase_end = true;  // located local maximum: the Poincare point
-      }
-      L.ymax = y[0] > L.ymax ? y[0] : L.ymax;
-      L.ymin = y[0] < L.ymin ? y[0] : L.ymin;
-      if (phase_end) {
-        fs.have = false;
-        store_record<MPRV>(a, L, y[0], L.ymin);
-        L.phase++;
-        if constexpr (MPRV::kPrio) note_phase_end(L);
-        L.ymax = -INFINITY;
-        L.ymin = INFINITY;
-        L.t_ps = L.t;
-        if (L.phase >= L.n_phases) done = true;
-      } else if (L.t - L.t_ps >= a.t_cap) {
-        store_record<MPRV>(a, L, L.ymax, L.ymin);
-        L.phase++;
-        L.status |= ENS_SYS_SETTLED;
-        done = true;
-      }
+      if (L.max_impacts > 0 && (int64_t)L.impacts >= L.max_impacts) done = true;
     }
+  }
+  L.ymax = (take && y[0] > L.ymax) ? y[0] : L.ymax;
+  L.ymin = (take && y[0] < L.ymin) ? y[0] : L.ymin;
+  if (pmax) {
+    fs.have = false;
+    store_record<MPRV>(a, L, y[0], L.ymin);
+    L.phase++;
+    if constexpr (MPRV::kPrio) note_phase_end(L);
+    L.ymax = -INFINITY;
+    L.ymin = INFINITY;
+    L.t_ps = L.t;
+    if (L.phase >= L.n_phases) done = true;
+  } else if (take && L.t - L.t_ps >= a.t_cap) {
+    store_record<MPRV>(a, L, L.ymax, L.ymin);
+    L.phase++;
+    L.status |= ENS_SYS_SETTLED;
+    done = true;
   }
   if (!done && a.max_steps > 0 && L.attempts >= a.max_steps) {
     L.status |= ENS_SYS_MAX_STEPS;
