@@ -119,15 +119,17 @@ __device__ __forceinline__ double rcp_nr(double d) {
 // residual correction g + (x - g^2) h: within an ulp of the correctly
 // rounded root for normal x, in 8 dependent VALU against 17 for the library
 // sqrt, which also rescales tiny and huge arguments (not needed here: the
-// pressure stays O(1..10)).  x < 0 gives NaN like sqrt; x == 0 gives 0.
+// pressure stays O(1..10)).  The estimate is taken of x + 1e-300, which is
+// x itself for every x above 1e-284 and keeps r finite at x = 0, where
+// g = 0 x r = 0 then gives the root 0 without a select; x < 0 gives NaN like
+// sqrt.
 __device__ __forceinline__ double sqrt_nr(double x) {
-  const double r = __builtin_amdgcn_rsq(x);
+  const double r = __builtin_amdgcn_rsq(x + 1e-300);
   double g = x * r, h = 0.5 * r;
   const double e = fma(-h, g, 0.5);
   g = fma(g, e, g);
   h = fma(h, e, h);
-  g = fma(fma(-g, g, x), h, g);
-  return x == 0.0 ? x : g;
+  return fma(fma(-g, g, x), h, g);
 }
 
 // x^(-1/5) for x in [1e-30, 1e30]: an FP32 estimate r0 from the hardware
@@ -1109,15 +1111,14 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
     // Issue priority follows the wave's longest remaining work, so that the
     // systems that will finish last are not slowed by short ones sharing the
     // SIMD (a wave's own priority; results do not depend on it).
+    // (the wave's largest estimate against each level, by ballots)
     if (M::kPrio && a.prioritize && __ballot(active && L.phase != ph_before) != 0ull) {
-      float r = active ? L.rem : 0.0f;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off));
-      if (r > 1.0e6f)
+      const float r = active ? L.rem : 0.0f;
+      if (__ballot(r > 1.0e6f) != 0ull)
         __builtin_amdgcn_s_setprio(3);
-      else if (r > 2.5e5f)
+      else if (__ballot(r > 2.5e5f) != 0ull)
         __builtin_amdgcn_s_setprio(2);
-      else if (r > 6.0e4f)
+      else if (__ballot(r > 6.0e4f) != 0ull)
         __builtin_amdgcn_s_setprio(1);
       else
         __builtin_amdgcn_s_setprio(0);
