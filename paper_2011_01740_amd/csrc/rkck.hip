@@ -672,7 +672,10 @@ struct Fsal {
 // Estimated work left after a completed phase.
 __device__ __forceinline__ void note_phase_end(Lane &L) {
   const float per = (float)(L.attempts - L.phase_att);
-  L.rem = per * (float)(L.n_phases > (int64_t)L.phase ? L.n_phases - (int64_t)L.phase : 0);
+  // phases left, below 2^32 (the phase count is limited to it)
+  const uint32_t left =
+      L.n_phases > (int64_t)L.phase ? (uint32_t)(L.n_phases - (int64_t)L.phase) : 0u;
+  L.rem = per * (float)left;
   L.phase_att = L.attempts;
 }
 
@@ -685,12 +688,19 @@ __device__ __forceinline__ const RkckCold *cold(const RkckArgs &a) {
   return c;
 }
 
+// Ring slot of the current phase: phase mod R in 32 bits (phases are
+// counted below 2^32; a ring that long never wraps).
+__device__ __forceinline__ int64_t ring_slot(const RkckArgs &a, const Lane &L) {
+  return a.R > (int64_t)UINT32_MAX ? (int64_t)L.phase
+                                   : (int64_t)(L.phase % (uint32_t)a.R);
+}
+
 template <class M>
 __device__ __forceinline__ void store_record(const RkckArgs &a, const Lane &L, double v0,
                                              double v1) {
   if (a.R <= 0) return;
   constexpr int F = M::kF;
-  const int64_t slot = (int64_t)(L.phase % (uint64_t)a.R);
+  const int64_t slot = ring_slot(a, L);
   double *rec = cold(a)->rec;
   rec[(slot * F) * a.n + L.sys] = v0;
   if (F > 1) rec[(slot * F + 1) * a.n + L.sys] = v1;
@@ -700,7 +710,7 @@ __device__ __forceinline__ void store_record(const RkckArgs &a, const Lane &L, d
 template <class M, int K>
 __device__ __forceinline__ void store_growth(const RkckArgs &a, const Lane &L, const double *g) {
   if (a.R <= 0) return;
-  const int64_t slot = (int64_t)(L.phase % (uint64_t)a.R);
+  const int64_t slot = ring_slot(a, L);
   double *rec = cold(a)->rec;
 #pragma unroll
   for (int v = 0; v < K; ++v) rec[(slot * M::kF + 1 + v) * a.n + L.sys] = g[v];
