@@ -172,6 +172,11 @@ typedef struct {
  * [G*G], may be NULL). */
 int sur_fit_label_map(sur_t s, const double *records, int32_t G, int8_t *map_out);
 
+/* Sizes the handle's compaction scratch for screens of up to n_screen
+ * points, so that those sur_screen calls allocate nothing (sur_screen grows
+ * it on demand otherwise).  For callers that time or capture the screen. */
+int sur_reserve(sur_t s, int64_t n_screen);
+
 /* Screens n sweep points params [2][n] (P_A1, f1; double).  Device outputs:
  * label [n] int8 (1: max y1max >= 2), resolve [n] uint8, pred_max [n] float
  * (predicted max_j ln y1max), resolve_idx [n] int64 receiving the indices of

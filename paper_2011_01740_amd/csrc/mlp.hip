@@ -1035,6 +1035,19 @@ hipError_t ensure_infer(sur_ctx *s) {
   return e;
 }
 
+// Compaction scratch (block counts and their scan) for screens of up to n
+// points, grown when a larger screen comes.
+hipError_t reserve_scan(sur_ctx *s, int64_t n) {
+  const int64_t need = (n + kScanBlock - 1) / kScanBlock + 1;
+  if (need <= s->scan_cap) return hipSuccess;
+  (void)hipFree(s->scan);
+  s->scan = nullptr;
+  s->scan_cap = 0;
+  const hipError_t e = hipMalloc((void **)&s->scan, (size_t)need * sizeof(int64_t));
+  if (e == hipSuccess) s->scan_cap = need;
+  return e;
+}
+
 // The fragment-order weight copies of the current parameters, then the fused
 // inference of n points (n > 0).
 hipError_t fused(sur_ctx *s, FusedArgs a, bool screen) {
@@ -1478,6 +1491,14 @@ int sur_forward(sur_t s, const float *x, int64_t m, float *out, int32_t where) {
   return ENS_OK;
 }
 
+int sur_reserve(sur_t s, int64_t n_screen) {
+  if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_reserve: NULL handle");
+  if (n_screen < 0) return sfail(s, ENS_E_INVAL, "sur_reserve: n_screen must be >= 0");
+  DevGuard dg(s->device);
+  SUR_HIP(s, reserve_scan(s, n_screen));
+  return ENS_OK;
+}
+
 int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *o, int8_t *label,
                uint8_t *resolve, float *pred_max, int64_t *resolve_idx, int64_t *n_resolve) {
   if (!s) return sfail(nullptr, ENS_E_INVAL, "sur_screen: NULL handle");
@@ -1516,13 +1537,7 @@ int sur_screen(sur_t s, const double *params, int64_t n, const sur_screen_opts *
   SUR_HIP(s, fused(s, a, true));
   if (resolve) {
     const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-    if (nb + 1 > s->scan_cap) {
-      (void)hipFree(s->scan);
-      s->scan = nullptr;
-      s->scan_cap = 0;
-      SUR_HIP(s, hipMalloc((void **)&s->scan, (size_t)(nb + 1) * sizeof(int64_t)));
-      s->scan_cap = nb + 1;
-    }
+    SUR_HIP(s, reserve_scan(s, n));
     hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(kScanBlock), 0, s->stream, resolve, n,
                        s->scan);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s->stream, s->scan, nb,

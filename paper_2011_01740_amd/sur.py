@@ -41,6 +41,7 @@ def _lib():
         L.sur_train_step.argtypes = [vp, vp, vp, i64, vp, i32]
         L.sur_gradients.argtypes = [vp, vp, vp, i64, vp, vp, i32]
         L.sur_forward.argtypes = [vp, vp, i64, vp, i32]
+        L.sur_reserve.argtypes = [vp, i64]
         L.sur_screen.argtypes = [vp, vp, i64, C.POINTER(sur_screen_opts), vp, vp, vp, vp,
                                  C.POINTER(i64)]
         L.sur_fit_label_map.argtypes = [vp, vp, i32, vp]
@@ -191,16 +192,26 @@ class Surrogate:
                                         C.c_void_p(out.data_ptr())), self.h)
         return out
 
-    def screen(self, params_dev, margin, spread, flag_margin, label_margin=-1.0):
-        """Screen device params [2][n] (float64).  Returns device tensors
-        (label int8, resolve uint8, pred_max float32, resolve_idx int64[:k])."""
+    def reserve(self, n_screen):
+        """Size the compaction scratch for screens of up to n_screen points."""
+        _check(_lib().sur_reserve(self.h, int(n_screen)), self.h)
+
+    @staticmethod
+    def screen_outputs(n, device):
+        """Output tensors for screen(..., out=): label, resolve, pred_max, idx."""
         import torch
+        return (torch.empty(n, dtype=torch.int8, device=device),
+                torch.empty(n, dtype=torch.uint8, device=device),
+                torch.empty(n, dtype=torch.float32, device=device),
+                torch.empty(max(n, 1), dtype=torch.int64, device=device))
+
+    def screen(self, params_dev, margin, spread, flag_margin, label_margin=-1.0, out=None):
+        """Screen device params [2][n] (float64).  Returns device tensors
+        (label int8, resolve uint8, pred_max float32, resolve_idx int64[:k]);
+        `out` (from screen_outputs) receives them instead of new tensors."""
         n = int(params_dev.shape[1])
-        dev = params_dev.device
-        label = torch.empty(n, dtype=torch.int8, device=dev)
-        resolve = torch.empty(n, dtype=torch.uint8, device=dev)
-        pmax = torch.empty(n, dtype=torch.float32, device=dev)
-        idx = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        label, resolve, pmax, idx = out if out is not None else \
+            self.screen_outputs(n, params_dev.device)
         k = C.c_int64()
         o = sur_screen_opts(float(margin), float(spread), float(flag_margin),
                             float(label_margin))

