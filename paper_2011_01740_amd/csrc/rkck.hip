@@ -137,21 +137,63 @@ __device__ __forceinline__ double sqrt_nr(double x) {
 // e = 1 - x r0^5 the series r = r0 (1 - e)^(-1/5) = r0 (1 + e/5 + 3 e^2/25
 // + O(e^3)): the truncation is ~1e-20, below rounding.  ~12 VALU instead of
 // the ~200 of a general pow.
-__device__ __forceinline__ double rfifth(double x) {
+// (c12 = 3/25 and c2 = 1/5 are the series coefficients; rfifth_c takes them as
+// arguments so that a caller can supply them from scalar registers.)
+__device__ __forceinline__ double rfifth_c(double x, double c12, double c2) {
   const double r0 =
       (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf((float)x));
   const double r2 = r0 * r0;
   const double e = fma(-x, r2 * r2 * r0, 1.0);
-  return fma(r0, e * fma(0.12, e, 0.2), r0);
+  return fma(r0, e * fma(c12, e, c2), r0);
 }
+__device__ __forceinline__ double rfifth(double x) { return rfifth_c(x, 0.12, 0.2); }
+
+// The step-size controller's constants as a table in constant memory, read
+// with one scalar load per attempt (scalar_table).  The valve's step takes
+// them from there (its scalar registers are short, and the compiler would
+// rebuild each double from two 32-bit immediates in every attempt); the
+// Keller--Miksis steps keep them as immediates, which its kernel holds.
+struct CtlTab {
+  double e_lo, e_hi, safety, f_lo, f_hi, c12, c2;
+};
+__constant__ CtlTab kCtlTab = {1e-4, 4e3, 0.9, 0.2, 5.0, 0.12, 0.2};
+constexpr CtlTab kCtlImm = {1e-4, 4e3, 0.9, 0.2, 5.0, 0.12, 0.2};
 
 // Step-size factor 0.9 E^(-1/5), clamped to [0.2, 5] (E = 0 gives 5).  Outside
 // [1e-4, 4e3] the clamp decides, so the root is only taken where FP32 holds E
 // (of E limited to that range; the selects leave no branch).
+template <class T>
+__device__ __forceinline__ double step_factor_with(const T &c, double E) {
+  const double f = c.safety * rfifth_c(fmin(fmax(E, c.e_lo), c.e_hi), c.c12, c.c2);
+  const double fc = f < c.f_lo ? c.f_lo : (f > c.f_hi ? c.f_hi : f);
+  return !(E >= c.e_lo) ? c.f_hi : (E > c.e_hi ? c.f_lo : fc);
+}
+template <bool TABLE>
 __device__ __forceinline__ double step_factor(double E) {
-  const double f = 0.9 * rfifth(fmin(fmax(E, 1e-4), 4e3));
-  const double fc = f < 0.2 ? 0.2 : (f > 5.0 ? 5.0 : f);
-  return !(E >= 1e-4) ? 5.0 : (E > 4e3 ? 0.2 : fc);
+  if constexpr (TABLE)
+    return step_factor_with(scalar_table(kCtlTab), E);
+  else
+    return step_factor_with(kCtlImm, E);
+}
+
+// Scaled error of an attempt, E = max_c |err_c| / (rtol max(|y_c|, |y5_c|) +
+// atol), and whether every new component and ratio is finite: 0 v is 0 for a
+// finite v and NaN otherwise, so one compare of the sum of those products
+// decides.
+template <int D>
+__device__ __forceinline__ bool error_ratio(double rtol, double atol, const double *y,
+                                            const double *y5, const double *err, double &E) {
+  E = 0.0;
+  double z = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double sc = fma(rtol, fmax(fabs(y[c]), fabs(y5[c])), atol);
+    const double r = fabs(err[c]) * rcp_nr(sc);
+    z = fma(0.0, y5[c], z);
+    z = fma(0.0, r, z);
+    E = r > E ? r : E;
+  }
+  return z == 0.0;
 }
 
 // ------------------------------------------------------------------ models
@@ -795,20 +837,13 @@ __device__ __forceinline__ bool step_fixed(const RkckArgs &a, M &m, Lane &L, dou
     ck_attempt(m, L.t, y, h_try, y5, err);
   }
   L.attempts++;
-  double E = 0.0;
-  bool finite = true;
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    const double sc = fma(a.rtol, fmax(fabs(y[c]), fabs(y5[c])), a.atol);
-    const double r = fabs(err[c]) * rcp_nr(sc);
-    finite = finite && isfinite(y5[c]) && isfinite(r);
-    E = r > E ? r : E;
-  }
+  double E;
+  const bool finite = error_ratio<D>(a.rtol, a.atol, y, y5, err, E);
   if (!finite) {
     L.status |= ENS_SYS_NONFINITE;
     return true;
   }
-  const double fac = step_factor(E);
+  const double fac = step_factor<false>(E);
   // Accept (E <= 1, or at the step-size floor) or reject, by selects: only
   // the rare phase end and located maximum branch.  After a rejection the
   // step only shrinks.
@@ -890,20 +925,13 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
     ck_attempt(m, L.t, y, h_try, y5, err);
   }
   L.attempts++;
-  double E = 0.0;
-  bool finite = true;
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    const double sc = fma(a.rtol, fmax(fabs(y[c]), fabs(y5[c])), a.atol);
-    const double r = fabs(err[c]) * rcp_nr(sc);
-    finite = finite && isfinite(y5[c]) && isfinite(r);
-    E = r > E ? r : E;
-  }
+  double E;
+  const bool finite = error_ratio<D>(a.rtol, a.atol, y, y5, err, E);
   if (!finite) {
     L.status |= ENS_SYS_NONFINITE;
     return true;
   }
-  const double fac = step_factor(E);
+  const double fac = step_factor<true>(E);
   // The common outcomes (rejection, event retry, plain acceptance) by
   // selects; only the rare ones branch: an event's secant step, a seat
   // change or impact, a Poincare point, settling.
