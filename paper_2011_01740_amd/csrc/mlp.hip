@@ -252,32 +252,43 @@ __global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
 // input, a = sin(x W1^T + b1) (W1: fixed frequencies, b1: phases 0 or pi/2,
 // so a holds sin and cos of each frequency).  The layer is not trained.
 // With rows != NULL, batch row r is dataset row rows[r] of x, and the
-// gathered inputs are also written to xg.  Each thread computes one element
-// in row-major order (z, a) and, when aT is wanted, one in transposed order,
-// so that both stores are coalesced.
-__global__ void k_layer1(const float *__restrict__ x, const int64_t *__restrict__ rows,
-                         float *xg, const float *__restrict__ P, int64_t m, float *z, bf16 *a,
-                         bf16 *aT) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= m * kH) return;
-  {
-    const int64_t r = idx / kH, n = idx % kH;
+// gathered inputs are also written to xg.  A block takes 32 batch rows and
+// thread n the feature n of each: the row-major stores of a (and z) are
+// coalesced across the threads, and each thread writes its 32 transposed
+// values aT[n][r0 .. r0 + 32) as four 16-byte vectors.  m is a multiple of 32.
+__global__ __launch_bounds__(256) void k_layer1(const float *__restrict__ x,
+                                                const int64_t *__restrict__ rows, float *xg,
+                                                const float *__restrict__ P, int64_t m, float *z,
+                                                bf16 *a, bf16 *aT) {
+  __shared__ float xs[32][2];
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int n = threadIdx.x;
+  if (n < 32) {
+    const int64_t r = r0 + n;
     const int64_t src = rows ? rows[r] : r;
     const float x0 = x[2 * src], x1 = x[2 * src + 1];
-    if (rows && n == 0) {
+    xs[n][0] = x0;
+    xs[n][1] = x1;
+    if (rows) {
       xg[2 * r] = x0;
       xg[2 * r + 1] = x1;
     }
-    const float v = fmaf(x1, P[oW1 + 2 * n + 1], fmaf(x0, P[oW1 + 2 * n], P[ob1 + n]));
-    if (z) z[idx] = v;
-    a[idx] = (bf16)feature_sin(v);
+  }
+  __syncthreads();
+  const float w0 = P[oW1 + 2 * n], w1 = P[oW1 + 2 * n + 1], bb = P[ob1 + n];
+  bf16x8 col[4];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const int64_t r = r0 + k;
+    const float v = fmaf(xs[k][1], w1, fmaf(xs[k][0], w0, bb));
+    if (z) z[r * kH + n] = v;
+    const bf16 f = (bf16)feature_sin(v);
+    a[r * kH + n] = f;
+    col[k >> 3][k & 7] = f;
   }
   if (aT) {
-    const int64_t n = idx / m, r = idx % m;
-    const int64_t src = rows ? rows[r] : r;
-    const float v = fmaf(x[2 * src + 1], P[oW1 + 2 * n + 1],
-                         fmaf(x[2 * src], P[oW1 + 2 * n], P[ob1 + n]));
-    aT[idx] = (bf16)feature_sin(v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *(bf16x8 *)(aT + (int64_t)n * m + r0 + 8 * q) = col[q];
   }
 }
 
@@ -406,8 +417,6 @@ __global__ void k_adam(float *__restrict__ P, const float *__restrict__ G, float
                        float *__restrict__ V, const double *__restrict__ hyper, double lr_,
                        double b1_, double b2_, double eps_, double t_base, int step, bf16 *W2,
                        bf16 *W2T, bf16 *W3, bf16 *W3T, bf16 *W4, bf16 *W4T) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kNP || i < oW2) return;   // W1, b1: the fixed feature layer
   if (hyper) {
     lr_ = hyper[0];
     b1_ = hyper[1];
@@ -415,9 +424,17 @@ __global__ void k_adam(float *__restrict__ P, const float *__restrict__ G, float
     eps_ = hyper[3];
     t_base = hyper[4];
   }
-  const double t = t_base + (double)step + 1.0;
-  const float c1 = (float)(1.0 / (1.0 - pow(b1_, t)));
-  const float c2 = (float)(1.0 / (1.0 - pow(b2_, t)));
+  // the bias corrections, once per block (two FP64 powers)
+  __shared__ float corr[2];
+  if (threadIdx.x == 0) {
+    const double t = t_base + (double)step + 1.0;
+    corr[0] = (float)(1.0 / (1.0 - pow(b1_, t)));
+    corr[1] = (float)(1.0 / (1.0 - pow(b2_, t)));
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kNP || i < oW2) return;   // W1, b1: the fixed feature layer
+  const float c1 = corr[0], c2 = corr[1];
   const float lr = (float)lr_, b1 = (float)b1_, b2 = (float)b2_, eps = (float)eps_;
   const float g = G[i];
   const float m = fmaf(b1, Mm[i], (1.0f - b1) * g);
@@ -1076,7 +1093,7 @@ hipError_t fused(sur_ctx *s, FusedArgs a, bool screen) {
 hipError_t forward_batch(sur_ctx *s, const Fwd &b, int64_t m, const int64_t *rows = nullptr,
                          const float *xsrc = nullptr) {
   hipStream_t st = s->stream;
-  hipLaunchKernelGGL(k_layer1, dim3(nblk(m * kH, 256)), dim3(256), 0, st, rows ? xsrc : b.x,
+  hipLaunchKernelGGL(k_layer1, dim3((unsigned)(m / 32)), dim3(256), 0, st, rows ? xsrc : b.x,
                      rows, b.x, s->P, m, b.z1, b.a1, b.a1T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
