@@ -103,15 +103,16 @@ constexpr int min_waves(int base, int sc, bool loc) {
   return (sc == kDP || loc) ? base - 1 : base;
 }
 
-// 1/d from the hardware reciprocal estimate and two Newton steps
-// r <- r + r (1 - d r), each squaring the relative error: within an ulp or
-// two of the correctly rounded quotient for the normal, finite d used here
-// (d = 0 or non-finite gives a non-finite result).
+// 1/d from the hardware reciprocal estimate r (relative error e = 1 - d r
+// below 2^-22) and one third-order correction r (1 + e + e^2), which leaves
+// e^3 < 2^-66 before the final rounding: within an ulp of the correctly
+// rounded quotient for the normal, finite d used here, in three dependent
+// instructions where two Newton steps take four (d = 0 or non-finite gives
+// a non-finite result).
 __device__ __forceinline__ double rcp_nr(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  r = fma(r, fma(-d, r, 1.0), r);
-  r = fma(r, fma(-d, r, 1.0), r);
-  return r;
+  const double r = __builtin_amdgcn_rcp(d);
+  const double e = fma(-d, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
 // sqrt(x) for the valve's chamber pressure: r = v_rsq_f64 (relative error
@@ -159,14 +160,14 @@ struct CtlTab {
 __constant__ CtlTab kCtlTab = {1e-4, 4e3, 0.9, 0.2, 5.0, 0.12, 0.2};
 constexpr CtlTab kCtlImm = {1e-4, 4e3, 0.9, 0.2, 5.0, 0.12, 0.2};
 
-// Step-size factor 0.9 E^(-1/5), clamped to [0.2, 5] (E = 0 gives 5).  Outside
-// [1e-4, 4e3] the clamp decides, so the root is only taken where FP32 holds E
-// (of E limited to that range; the selects leave no branch).
+// Step-size factor 0.9 E^(-1/5), clamped to [0.2, 5] (E = 0 gives 5), for a
+// finite E >= 0.  The root is taken of E limited to [1e-4, 4e3], where FP32
+// holds it: below, 0.9 (1e-4)^(-1/5) = 5.68 clamps to 5, and above,
+// 0.9 (4e3)^(-1/5) = 0.171 clamps to 0.2, the factors of the unlimited E.
 template <class T>
 __device__ __forceinline__ double step_factor_with(const T &c, double E) {
   const double f = c.safety * rfifth_c(fmin(fmax(E, c.e_lo), c.e_hi), c.c12, c.c2);
-  const double fc = f < c.f_lo ? c.f_lo : (f > c.f_hi ? c.f_hi : f);
-  return !(E >= c.e_lo) ? c.f_hi : (E > c.e_hi ? c.f_lo : fc);
+  return fmin(fmax(f, c.f_lo), c.f_hi);
 }
 template <bool TABLE>
 __device__ __forceinline__ double step_factor(double E) {
@@ -191,7 +192,7 @@ __device__ __forceinline__ bool error_ratio(double rtol, double atol, const doub
     const double r = fabs(err[c]) * rcp_nr(sc);
     z = fma(0.0, y5[c], z);
     z = fma(0.0, r, z);
-    E = r > E ? r : E;
+    E = fmax(E, r);
   }
   return z == 0.0;
 }
@@ -353,8 +354,11 @@ struct MKM {
   static constexpr bool kDrive2 = DUAL;
   static constexpr int kF = 1;
   static constexpr bool kTangent = false;
-  double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49, K9d3;  // K9d3 = K9 / 3
-  double s0, c0;  // sin, cos (2 pi t) at the start of the attempted step
+  double K0, K1, K2, K3, K4, K5, K7, K9, K10, K49, K9h;  // K9h = K9 / 2
+  // FAST: K5 and K7 times sin, cos (2 pi t) at the start of the attempted
+  // step, so that each stage forms its forcing terms from its angle offset
+  // directly: K5 sin(a + b) = K5 s0 cos b + K5 c0 sin b, and the same for cos
+  double k5s, k5c, k7s, k7c;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
     const double pa = P[i], f = P[n + i];
     const double rhoL = sh[0], cL = sh[1], pV = sh[2], sig = sh[3], mu = sh[4];
@@ -374,7 +378,7 @@ struct MKM {
     K9 = re * w / (2.0 * M_PI * cL);
     K10 = 3.0 * gam;
     K49 = K4 * K9;
-    K9d3 = K9 / 3.0;   // once per system, not per attempt
+    K9h = 0.5 * K9;    // exact; once per system, not per attempt
     if constexpr (DUAL) {
       const double pa2 = PSYS ? P[2 * n + i] : sh[8];
       const double w2 = 2.0 * M_PI * (PSYS ? P[3 * n + i] : sh[9]);
@@ -404,7 +408,14 @@ struct MKM {
   // stage 4's plus stage 2's, stage 7 the same angle as stage 6.
   double so2, co2, so4, co4, so1, co1;
   __device__ void begin(double t) {
-    if constexpr (FAST) sincospi_quarter(2.0 * t, &s0, &c0);
+    if constexpr (FAST) {
+      double s0, c0;
+      sincospi_quarter(2.0 * t, &s0, &c0);
+      k5s = K5 * s0;
+      k5c = K5 * c0;
+      k7s = K7 * s0;
+      k7c = K7 * c0;
+    }
   }
   // SC: the scheme; S: the stage (1..7); tau: its time; h: the attempted step.
   template <int SC, int S>
@@ -424,11 +435,11 @@ struct MKM {
     const double Dn = fma(y1, fma(-K9, y2, 1.0), K49);
     const double qd = rcp_nr(y1 * Dn);
     const double r1 = Dn * qd;                    // 1 / y1
-    double gas, s, c;                             // (1/y1)^K10; sin, cos (2 pi tau)
+    double gas, s, c;     // (1/y1)^K10; sin, cos (2 pi tau) (not FAST)
+    double so, co;        // FAST: sin, cos of the stage's offset 2 pi c_i h
     if constexpr (FAST) {
       const double r2 = r1 * r1;
       gas = (r2 * r2) * rfifth(y1);
-      double so, co;
       if constexpr (S == 1) {
         so = 0.0;
         co = 1.0;
@@ -477,18 +488,22 @@ struct MKM {
       } else {
         sincos_taylor<9, 10>((2.0 * M_PI * 7.0 / 8.0) * h, &so, &co);     // |x| <= 0.69
       }
-      if constexpr (S == 1) {
-        s = s0;
-        c = c0;
-      } else {
-        s = fma(s0, co, c0 * so);
-        c = fma(c0, co, -(s0 * so));
-      }
     } else {
       gas = exp(-K10 * log(y1));
       sincospi(2.0 * tau, &s, &c);
     }
-    double fs = fma(K5, s, K2), fc = K7 * c;  // forcing terms of N
+    // forcing terms of N: fs = K2 + K5 sin, fc = K7 cos (2 pi tau)
+    double fs, fc;
+    if constexpr (!FAST) {
+      fs = fma(K5, s, K2);
+      fc = K7 * c;
+    } else if constexpr (S == 1) {
+      fs = k5s + K2;
+      fc = k7c;
+    } else {
+      fs = fma(k5s, co, fma(k5c, so, K2));
+      fc = fma(k7c, co, -(k7s * so));
+    }
     if constexpr (DUAL) {
       if (dual) {
         double s2, c2;
@@ -501,7 +516,7 @@ struct MKM {
     double N = fma(K1, y2, K0) * gas;
     N = fma(-fs, u, N);
     N = fma(-fma(K4, y2, K3), r1, N);
-    N = fma(-(fma(-K9d3, y2, 1.0) * 1.5) * y2, y2, N);
+    N = fma(-fma(-K9h, y2, 1.5) * y2, y2, N);
     N = fma(-fc, y1, N);
     f[0] = y2;
     f[1] = N * (y1 * qd);
@@ -1063,7 +1078,11 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
       unsigned long long base = 0;
       if (lane == leader)
         base = atomicAdd(cold(a)->queue + (use_head ? 1 : 0), (unsigned long long)n_idle);
-      base = __shfl(base, leader);
+      // the leader's value to the whole wave as a scalar (so that the queue
+      // flags below are wave-uniform values in scalar registers)
+      base = ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(base >> 32), leader)
+              << 32) |
+             (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, leader);
       const uint64_t first = use_head ? 0 : spread, limit = use_head ? spread : nsys - spread;
       if (base + (unsigned long long)n_idle >= limit) {
         if (use_head)
@@ -1133,33 +1152,41 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
       if (drained) break;
       continue;
     }
-    const uint32_t ph_before = M::kPrio ? L.phase : 0u;
-    if (active) {
-      bool done;
-      if constexpr (M::kEvents)
-        done = step_valve<SC>(a, m, L, y, fs);
-      else
-        done = step_fixed<M, SC, LOC>(a, m, L, y, fs);
-      if (done) {
-        store_lane<M, SC>(a, L, y, seated_of(m));
-        if constexpr (M::kDrive2) cold(a)->phi2[L.sys] = m.phi;
-        active = false;
+    // Attempts until a lane finishes its system: only then can the refill
+    // rule above fire or the wave run out of work, so the refill bookkeeping
+    // is skipped on the other attempts (one ballot each).
+    while (true) {
+      const uint32_t ph_before = M::kPrio ? L.phase : 0u;
+      bool fin = false;
+      if (active) {
+        bool done;
+        if constexpr (M::kEvents)
+          done = step_valve<SC>(a, m, L, y, fs);
+        else
+          done = step_fixed<M, SC, LOC>(a, m, L, y, fs);
+        if (done) {
+          store_lane<M, SC>(a, L, y, seated_of(m));
+          if constexpr (M::kDrive2) cold(a)->phi2[L.sys] = m.phi;
+          active = false;
+          fin = true;
+        }
       }
-    }
-    // Issue priority follows the wave's longest remaining work, so that the
-    // systems that will finish last are not slowed by short ones sharing the
-    // SIMD (a wave's own priority; results do not depend on it).
-    // (the wave's largest estimate against each level, by ballots)
-    if (M::kPrio && a.prioritize && __ballot(active && L.phase != ph_before) != 0ull) {
-      const float r = active ? L.rem : 0.0f;
-      if (__ballot(r > 1.0e6f) != 0ull)
-        __builtin_amdgcn_s_setprio(3);
-      else if (__ballot(r > 2.5e5f) != 0ull)
-        __builtin_amdgcn_s_setprio(2);
-      else if (__ballot(r > 6.0e4f) != 0ull)
-        __builtin_amdgcn_s_setprio(1);
-      else
-        __builtin_amdgcn_s_setprio(0);
+      // Issue priority follows the wave's longest remaining work, so that the
+      // systems that will finish last are not slowed by short ones sharing the
+      // SIMD (a wave's own priority; results do not depend on it).
+      // (the wave's largest estimate against each level, by ballots)
+      if (M::kPrio && a.prioritize && __ballot(active && L.phase != ph_before) != 0ull) {
+        const float r = active ? L.rem : 0.0f;
+        if (__ballot(r > 1.0e6f) != 0ull)
+          __builtin_amdgcn_s_setprio(3);
+        else if (__ballot(r > 2.5e5f) != 0ull)
+          __builtin_amdgcn_s_setprio(2);
+        else if (__ballot(r > 6.0e4f) != 0ull)
+          __builtin_amdgcn_s_setprio(1);
+        else
+          __builtin_amdgcn_s_setprio(0);
+      }
+      if (__ballot(fin) != 0ull) break;
     }
   }
 }
