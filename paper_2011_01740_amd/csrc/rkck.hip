@@ -184,7 +184,6 @@ __device__ __forceinline__ double step_factor(double E) {
 template <int D>
 __device__ __forceinline__ bool error_ratio(double rtol, double atol, const double *y,
                                             const double *y5, const double *err, double &E) {
-  E = 0.0;
   double z = 0.0;
 #pragma unroll
   for (int c = 0; c < D; ++c) {
@@ -192,7 +191,7 @@ __device__ __forceinline__ bool error_ratio(double rtol, double atol, const doub
     const double r = fabs(err[c]) * rcp_nr(sc);
     z = fma(0.0, y5[c], z);
     z = fma(0.0, r, z);
-    E = fmax(E, r);
+    E = c == 0 ? r : fmax(E, r);
   }
   return z == 0.0;
 }
@@ -650,8 +649,10 @@ __device__ __forceinline__ int dp_attempt(M &m, double t, const double *y, doubl
   return have_k1 ? 6 : 7;
 }
 
+// x limited to [lo, hi] for a finite x and lo <= hi (the host checks
+// dt_min <= dt_max), as two min/max instructions.
 __device__ __forceinline__ double clampd(double x, double lo, double hi) {
-  return x < lo ? lo : (x > hi ? hi : x);
+  return fmin(fmax(x, lo), hi);
 }
 
 // Lane-private progress of one system.
@@ -951,8 +952,8 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
   // selects; only the rare ones branch: an event's secant step, a seat
   // change or impact, a Poincare point, settling.
   const bool rej = E > 1.0 && h_try > a.dt_min;
-  const double h_rej = clampd(h_try * fmin(fac, 1.0), a.dt_min, a.dt_max);
-  const double h_next = clampd(h_try * fac, a.dt_min, a.dt_max);
+  // after a rejection the step only shrinks
+  const double h_next = clampd(h_try * (rej ? fmin(fac, 1.0) : fac), a.dt_min, a.dt_max);
   const double tol = a.event_tol;
   // event detection: overshoot -> secant retry from the same point.  The
   // tests are plain compares; the secant steps (divisions) are formed only
@@ -979,7 +980,7 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
   L.status |= (!rej && E > 1.0) ? ENS_SYS_DT_MIN : 0;   // at the step-size floor
   L.status |= (take && over) ? ENS_SYS_EVENT_ITER : 0;  // secant retries exhausted
   L.ev_iter = retry ? L.ev_iter + 1 : (take ? 0 : L.ev_iter);
-  L.h = rej ? h_rej : (retry ? hs : h_next);
+  L.h = retry ? hs : h_next;
   const double y2o = y[1];
 #pragma unroll
   for (int c = 0; c < D; ++c) y[c] = take ? y5[c] : y[c];
@@ -1012,8 +1013,8 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
       if (L.max_impacts > 0 && (int64_t)L.impacts >= L.max_impacts) done = true;
     }
   }
-  L.ymax = (take && y[0] > L.ymax) ? y[0] : L.ymax;
-  L.ymin = (take && y[0] < L.ymin) ? y[0] : L.ymin;
+  L.ymax = take ? fmax(L.ymax, y[0]) : L.ymax;
+  L.ymin = take ? fmin(L.ymin, y[0]) : L.ymin;
   if (pmax) {
     fs.have = false;
     store_record<MPRV>(a, L, y[0], L.ymin);
