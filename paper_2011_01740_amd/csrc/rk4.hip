@@ -31,6 +31,18 @@ struct LorenzCoef {
   double dt, h2, h3, h6, sh, sh2, sh3, sh6, beta;
 };
 
+// Running maximum with one v_max_f64.  The same as a compare-and-select here
+// (a NaN state stays NaN, and both keep the last number).  Written out
+// because the compiler, unable to prove the loop-carried maximum canonical,
+// adds a second v_max (x, x) per iteration to quiet it: one VALU slot in 23
+// of the two-step loop of the one-dimensional models, one in 16 per
+// system of the Lorenz loop.
+__device__ __forceinline__ double vmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 __device__ __forceinline__ void lorenz_step(double &x, double &y, double &w, double &m,
                                             double brho, const LorenzCoef &c) {
   const double x0 = x, y0 = y, w0 = w;
@@ -72,7 +84,7 @@ __device__ __forceinline__ void lorenz_step(double &x, double &y, double &w, dou
   x = fma(c.sh6, d, ax);
   y = fma(c.h6, ky, ay);
   w = fma(c.h6, kw, aw);
-  m = fmax(m, x);
+  m = vmax(m, x);
 }
 
 __global__ void k_fill_u32(unsigned *p, unsigned v, int64_t count) {
@@ -111,15 +123,19 @@ __global__ __launch_bounds__(1024) void k_rk4_lorenz(const double *__restrict__ 
   c.sh3 = sigma * c.h3;
   c.sh6 = sigma * c.h6;
   c.beta = beta;
-  // two steps per iteration: the loop-carried state then needs no copies
-  for (int64_t s = 0; s + 1 < nsteps; s += 2) {
+  // four steps per iteration: the loop-carried state needs no copies and the
+  // loop control is one issue slot in ~600
+  int64_t s = 0;
+  for (; s + 3 < nsteps; s += 4) {
 #pragma unroll
     for (int k = 0; k < SPL; ++k) {
       lorenz_step(x[k], y[k], w[k], m[k], br[k], c);
       lorenz_step(x[k], y[k], w[k], m[k], br[k], c);
+      lorenz_step(x[k], y[k], w[k], m[k], br[k], c);
+      lorenz_step(x[k], y[k], w[k], m[k], br[k], c);
     }
   }
-  if (nsteps & 1) {
+  for (; s < nsteps; ++s) {
 #pragma unroll
     for (int k = 0; k < SPL; ++k) lorenz_step(x[k], y[k], w[k], m[k], br[k], c);
   }
@@ -148,17 +164,6 @@ struct FDiv {
 struct FSin {
   __device__ static double f(double x, double p) { return p * sin(x); }
 };
-
-// Running maximum with one v_max_f64.  The same as a compare-and-select here
-// (a NaN state stays NaN, and both keep the last number).  Written out
-// because the compiler, unable to prove the loop-carried maximum canonical,
-// adds a second v_max (x, x) per iteration to quiet it: one VALU slot in 23
-// of the two-step loop of the one-dimensional models.
-__device__ __forceinline__ double vmax(double a, double b) {
-  double r;
-  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
 
 // One RK4 step of a one-dimensional model in the accumulated stage form; m
 // is the running maximum.
