@@ -3,22 +3,23 @@
 //
 // Every product of the network has the form
 //     C[r][c] = sum_k X[r][k] * Y[c][k]
-// with X and Y row-major BF16 and the reduction index k contiguous, so one
-// wave tile (64 x 64 outputs, 4 x 4 v_mfma_f32_16x16x32_bf16 accumulators)
-// serves the three uses, given the right operands:
+// with X and Y row-major BF16 and the reduction index k contiguous:
 //   forward      Z = A W^T       X = A  [batch][in],   Y = W   [out][in]
 //   data grad    dA = dZ W       X = dZ [batch][out],  Y = W^T [in][out]
 //   weight grad  dW = dZ^T A     X = dZ^T [out][batch], Y = A^T [in][batch]
-// The forward epilogue therefore also writes each activation transposed, the
-// backward epilogue each gradient transposed, and the optimiser refreshes
-// both W and W^T in BF16.  Operands are read as 16-byte vectors straight
-// from global memory (the weights stay in L2), a whole group of K steps at a
-// time.  Weight gradients are split over the batch; bias gradients are column
-// sums that the backward epilogue forms per 32-row tile; one kernel then
-// reduces every partial sum in a fixed order, so every result is
-// deterministic.  The first layer is a fixed random Fourier-feature map of the
-// two inputs (sin of x W1^T + b1, on the vector unit) and is not trained, so
-// no gradient is propagated to it.  A training step is 12 launches.
+// A training step is 3 launches.  The work local to a batch row (the feature
+// layer, the forward products, the loss gradient, the data gradients) runs in
+// one kernel per 16-row tile with the activations in LDS (k_train_fb), which
+// also writes each activation and gradient transposed for the weight
+// gradients.  Those are split over the batch (k_gemm, the three products in
+// one launch, one wave per 32 x 32 output tile, operands read as 16-byte vectors straight from global memory,
+// a whole group of K steps at a time); bias gradients are column sums per
+// 16-row tile; one kernel then reduces every partial sum in a fixed order, so
+// every result is deterministic, and takes each parameter's Adam step on the
+// FP32 master copy at once, refreshing both W and W^T in BF16.  The first layer is a fixed random
+// Fourier-feature map of the two inputs (sin of x W1^T + b1, on the vector
+// unit) and is not trained, so no gradient is propagated to it.  Inference
+// runs the whole network in one kernel (k_fused).
 //
 // MFMA 16x16x32 BF16 operand layout (lane l, 64 lanes): A fragment = row
 // (l mod 16), k = 8 (l / 16) + 0..7; B fragment = column (l mod 16), same k;
@@ -104,54 +105,48 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 }
 
 // ---------------------------------------------------------------- GEMM tile
-enum Epi { EPI_FWD_GELU = 0, EPI_FWD_LINEAR = 1, EPI_BWD_GELU = 2, EPI_PARTIAL = 3 };
-
+// Weight-gradient products: C = sum_k X[r][k] Y[c][k] over one share of the
+// batch (k), written as a partial sum.
 struct GemmArgs {
   const bf16 *X;
   int64_t ldx;
   const bf16 *Y;
   int64_t ldy;
   int64_t R, C, K;       // C[R][C], reduction length K (split over gridDim.z)
-  const float *bias;     // [C]
-  const float *zprev;    // [R][C] pre-activation for the GELU derivative
-  float *out_f32;        // [R][C], or [split][R][C] partial sums
-  bf16 *out_bf16;        // [R][C]
-  bf16 *out_bf16T;       // [C][R]
-  // backward epilogue: column sums of the result over each 32-row tile
-  float *colpart;        // [R/32][C]: sum_r dZ[r][c]              (bias gradient)
+  float *out_f32;        // [split][R][C] partial sums
 };
 
 constexpr int kTile = 32;  // output tile edge per wave
 
-// One wave per 32 x 32 output tile (2 x 2 accumulators); grid (R/32, C/32,
-// split): consecutive blocks share the rows of X, and blocks are spread over
-// the XCDs by block index, so each XCD reads its own share of X.  The K range
-// is taken KG MFMA steps (32 each) at a time: all operand loads of a group are
-// issued before its products, so one memory latency covers KG steps.
-template <int EPI, int KG>
-__global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
-  const int64_t r0 = (int64_t)blockIdx.x * kTile, c0 = (int64_t)blockIdx.y * kTile;
-  const int64_t kchunk = g.K / gridDim.z;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = kb + kchunk;
+// Up to three products in one launch (a training step's weight gradients),
+// each split over its K range in `split` equal parts.
+struct GemmBatch {
+  GemmArgs g[3];
+  int64_t nblk[3];  // blocks of each product: (R/32) (C/32) split
+  int split;
+};
+
+// One wave per 32 x 32 output tile (2 x 2 accumulators).  The blocks of the
+// products follow each other; within one, the tile row runs fastest, then
+// the tile column, then the K part, so consecutive blocks share the rows of
+// X, and blocks are spread over the XCDs by block index, so each XCD reads
+// its own share of X.  The K range is taken KG MFMA steps (32 each) at a
+// time: all operand loads of a group are issued before its products, so one
+// memory latency covers KG steps.
+template <int KG>
+__global__ __launch_bounds__(64) void k_gemm(GemmBatch bt) {
+  int64_t bid = blockIdx.x;
+  const int p = bid < bt.nblk[0] ? 0 : (bid < bt.nblk[0] + bt.nblk[1] ? 1 : 2);
+  bid -= p == 0 ? 0 : (p == 1 ? bt.nblk[0] : bt.nblk[0] + bt.nblk[1]);
+  const GemmArgs g = p == 0 ? bt.g[0] : (p == 1 ? bt.g[1] : bt.g[2]);
+  const int64_t tr = g.R / kTile, tc = g.C / kTile;
+  const int64_t bx = bid % tr, by = (bid / tr) % tc, bz = bid / (tr * tc);
+  const int64_t r0 = bx * kTile, c0 = by * kTile;
+  const int64_t kchunk = g.K / bt.split;
+  const int64_t kb = bz * kchunk, ke = kb + kchunk;
   const int l = threadIdx.x & 63;
   const int64_t lr = l & 15, lk = (l >> 4) * 8;
   const int64_t lc = l & 15, lrow = (l >> 4) * 4;
-  // epilogue operands fetched ahead of the products
-  float zp[2][2][4];
-  if (EPI == EPI_BWD_GELU) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          zp[i][j][q] = g.zprev[(r0 + 16 * i + lrow + q) * g.C + c0 + 16 * j + lc];
-  }
-  float bj[2] = {0.f, 0.f};
-  if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR) {
-    bj[0] = g.bias[c0 + lc];
-    bj[1] = g.bias[c0 + 16 + lc];
-  }
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -178,165 +173,257 @@ __global__ __launch_bounds__(64) void k_gemm(GemmArgs g) {
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][i], b[u][j], acc[i][j], 0, 0, 0);
   }
-
-  float res[2][2][4];  // backward: dZ of the tile, for the column sums
+  float *o = g.out_f32 + bz * g.R * g.C;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int64_t c = c0 + 16 * j + lc;
       const int64_t rb = r0 + 16 * i + lrow;
-      float v[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = acc[i][j][q];
-      if (EPI == EPI_PARTIAL) {
-        float *o = g.out_f32 + (int64_t)blockIdx.z * g.R * g.C;
+      for (int q = 0; q < 4; ++q) o[(rb + q) * g.C + c] = acc[i][j][q];
+    }
+}
+
+// ------------------------------------------------ fused training tile
+// One training step's work that is local to a row of the batch, for a tile
+// of 16 rows per block of 4 waves (a batch of 4096 rows fills every CU): the feature layer, the forward products
+// of layers 2 to 4, the loss gradient of the output layer, and the data
+// gradients back through layers 3 and 2.  The activations and gradients
+// that feed the next product stay in LDS (two BF16 row-major tiles, rows
+// padded to 264 so that the 16 rows of an operand fragment fall on
+// different banks), and each product's weight operands are loaded into
+// registers a layer ahead; each wave computes 64 output features of a 256-wide
+// layer (4 accumulators), so it already holds, in the accumulator
+// layout, the GELU derivatives of exactly the positions whose data gradient
+// it forms on the way back.  What leaves the block is what the
+// weight-gradient products and the reduction need: the activations and
+// gradients transposed ([feature][batch row], BF16), the column sums of each
+// gradient over the tile (bias gradients), and the tile's weighted squared
+// error.  Activations and gradients are rounded to BF16 where they become
+// operands; every product accumulates in FP32, its MFMA steps in increasing
+// k.
+constexpr int kTileLd = kH + 8;
+constexpr int kTR = 16, kNI = kTR / 16;  // rows per tile, 16-row groups
+
+struct TrainArgs {
+  const float *x;          // inputs [*][2]: batch row r is dataset row rows[r] (or r)
+  const int64_t *rows;     // dataset rows of the batch, or NULL
+  const float *tgt;        // targets [*][64], indexed like x
+  const float *P;          // FP32 parameters (W1, b1 .. b4 read here)
+  const bf16 *W2, *W3, *W4;  // BF16 weights [out][in]
+  const bf16 *W3T, *W4T;     // BF16 transposes [in][out]
+  int64_t m;               // batch rows (a multiple of 16)
+  bf16 *a1T, *a2T, *a3T;   // [256][m]
+  bf16 *dz4T;              // [64][m]
+  bf16 *dz3T, *dz2T;       // [256][m]
+  float *cp4, *cp3, *cp2;  // [m/16][64], [m/16][256], [m/16][256]
+  float *lpart;            // [m/16]
+};
+
+// The B operands of a tile product: weight rows c0 + 16 j + (l mod 16),
+// k = 32 s + 8 (l / 16) + 0..7 for every MFMA step s of K, from the row-major
+// weights (ld ldw).  Loaded a whole layer ahead: the weights do not depend on
+// the activations, so a layer's loads are issued before the previous layer's
+// epilogue and barrier, which hides their latency at one wave per SIMD.
+template <int NJ, int K>
+__device__ __forceinline__ void tile_weights(const bf16 *__restrict__ W, int64_t ldw, int c0,
+                                             int l, bf16x8 (&b)[K / 32][NJ]) {
+  const bf16 *wp = W + (int64_t)(c0 + (l & 15)) * ldw + (l >> 4) * 8;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o[(rb + q) * g.C + c] = v[q];
-        continue;
-      }
-      if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR) {
+  for (int s = 0; s < K / 32; ++s)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += bj[j];
-      }
-      if (EPI == EPI_FWD_LINEAR) {
+    for (int j = 0; j < NJ; ++j) b[s][j] = *(const bf16x8 *)(wp + 16 * j * ldw + 32 * s);
+}
+
+// acc[i][j] = the tile's rows 16 i .. 16 i + 15 times the weight rows of
+// b[.][j] over k = 0 .. K, the A operands from the LDS tile, the MFMA steps
+// in increasing k.
+template <int NJ, int K>
+__device__ __forceinline__ void tile_product(const bf16 (*in)[kTileLd],
+                                             const bf16x8 (&b)[K / 32][NJ], int l,
+                                             f32x4 (&acc)[kNI][NJ]) {
+  const int lr = l & 15, lk = (l >> 4) * 8;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) g.out_f32[(rb + q) * g.C + c] = v[q];
-        continue;
-      }
-      float a[4];
-      if (EPI == EPI_FWD_GELU) {
+  for (int i = 0; i < kNI; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) g.out_f32[(rb + q) * g.C + c] = v[q];
+    for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = gelu_f(v[q]);
-      } else {  // EPI_BWD_GELU
+  for (int s = 0; s < K / 32; ++s) {
+    bf16x8 a[kNI];
+#pragma unroll
+    for (int i = 0; i < kNI; ++i) a[i] = *(const bf16x8 *)&in[16 * i + lr][32 * s + lk];
+#pragma unroll
+    for (int i = 0; i < kNI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[s][j], acc[i][j], 0, 0, 0);
+  }
+}
+
+// Column sums over the tile's rows of v (the accumulator layout: lane l
+// holds rows 16 i + 4 (l / 16) + q of column l mod 16): the lane's rows,
+// then the 4 lane groups, in a fixed order; lanes 0 .. 15 hold the sums.
+__device__ __forceinline__ float tile_colsum(const float (&v)[kNI][4]) {
+  float s0 = 0.f;
+#pragma unroll
+  for (int i = 0; i < kNI; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s0 += v[i][q];
+  s0 += __shfl_xor(s0, 16);
+  s0 += __shfl_xor(s0, 32);
+  return s0;
+}
+
+__global__ __launch_bounds__(256) void k_train_fb(TrainArgs g) {
+  __shared__ bf16 act[2][kTR][kTileLd];
+  __shared__ float xs[kTR][2];
+  __shared__ float lw[4];
+  const int64_t m = g.m, r0 = (int64_t)blockIdx.x * kTR;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int lc = l & 15, lrow = (l >> 4) * 4;
+  bf16x8 bw[kH / 32][4];    // the next 256-wide product's weights
+  tile_weights<4, kH>(g.W2, kH, 64 * w, l, bw);
+  // biases and targets of the lane's output positions, loaded ahead
+  float b23[2][4], tq[kNI][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    b23[0][j] = g.P[ob2 + 64 * w + 16 * j + lc];
+    b23[1][j] = g.P[ob3 + 64 * w + 16 * j + lc];
+  }
+  const float b4c = g.P[ob4 + 16 * w + lc];
+#pragma unroll
+  for (int i = 0; i < kNI; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t rr = r0 + 16 * i + lrow + q;
+      tq[i][q] = g.tgt[(g.rows ? g.rows[rr] : rr) * kOut + 16 * w + lc];
+    }
+  if (t < kTR) {
+    const int64_t src = g.rows ? g.rows[r0 + t] : r0 + t;
+    xs[t][0] = g.x[2 * src];
+    xs[t][1] = g.x[2 * src + 1];
+  }
+  __syncthreads();
+  // layer 1: thread t is feature t of the tile's rows
+  {
+    const float w0 = g.P[oW1 + 2 * t], w1 = g.P[oW1 + 2 * t + 1], bb = g.P[ob1 + t];
+    bf16x8 col[kTR / 8];
+#pragma unroll
+    for (int k = 0; k < kTR; ++k) {
+      const bf16 f = (bf16)feature_sin(fmaf(xs[k][1], w1, fmaf(xs[k][0], w0, bb)));
+      act[0][k][t] = f;
+      col[k >> 3][k & 7] = f;
+    }
+#pragma unroll
+    for (int q = 0; q < kTR / 8; ++q) *(bf16x8 *)(g.a1T + (int64_t)t * m + r0 + 8 * q) = col[q];
+  }
+  __syncthreads();
+  // layers 2 and 3: z = a W^T + b, a' = GELU(z); keep GELU'(z) for the way back
+  float gp[2][kNI][4][4];  // [layer 2, 3][i][j][q]
+  f32x4 acc[kNI][4];
+  bf16x8 bw4[kH / 32][1];   // layer 4's weights
+#pragma unroll
+  for (int L = 0; L < 2; ++L) {
+    bf16 *aT = L == 0 ? g.a2T : g.a3T;
+    tile_product<4, kH>(act[L], bw, l, acc);
+    if (L == 0)
+      tile_weights<4, kH>(g.W3, kH, 64 * w, l, bw);
+    else
+      tile_weights<1, kH>(g.W4, kH, 16 * w, l, bw4);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 64 * w + 16 * j + lc;
+      const float bj = b23[L][j];
+#pragma unroll
+      for (int i = 0; i < kNI; ++i) {
+        bf16x4 col;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          a[q] = v[q] * gelu_grad_f(zp[i][j][q]);
-          res[i][j][q] = a[q];
+          const float z = acc[i][j][q] + bj;
+          gp[L][i][j][q] = gelu_grad_f(z);
+          const bf16 a = (bf16)gelu_f(z);
+          act[1 - L][16 * i + lrow + q][c] = a;
+          col[q] = a;
         }
-        if (g.out_f32) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) g.out_f32[(rb + q) * g.C + c] = a[q];
-        }
-      }
-      if (g.out_bf16) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) g.out_bf16[(rb + q) * g.C + c] = (bf16)a[q];
-      }
-      if (g.out_bf16T) {
-        bf16x4 t = {(bf16)a[0], (bf16)a[1], (bf16)a[2], (bf16)a[3]};
-        *(bf16x4 *)(g.out_bf16T + c * g.R + rb) = t;
+        *(bf16x4 *)(aT + (int64_t)c * m + r0 + 16 * i + lrow) = col;
       }
     }
+    __syncthreads();
   }
-  if (EPI == EPI_BWD_GELU && g.colpart) {
-    // per column: the lane's 8 rows, then the 4 lane groups, in a fixed order
+  // layer 4 and the loss gradient 2 w_c (out - t) / (m * 64); wave w takes
+  // the output columns 16 w .. 16 w + 15
+  bf16x8 bwt[kOut / 32][4];  // W4^T for the first product back
+  {
+    f32x4 acc4[kNI][1];
+    tile_product<1, kH>(act[0], bw4, l, acc4);
+    tile_weights<4, kOut>(g.W4T, kOut, 64 * w, l, bwt);
+    const int c = 16 * w + lc;
+    const float bj = b4c;
+    const float wc = out_weight(c);
+    const float scale = 2.0f * wc / (float)(m * kOut);
+    float gv[kNI][4];
+    float sq = 0.f;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      float s0 = 0.f;
+    for (int i = 0; i < kNI; ++i) {
+      bf16x4 col;
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s0 += res[i][j][q];
-      s0 += __shfl_xor(s0, 16);
-      s0 += __shfl_xor(s0, 32);
-      if (l < 16) g.colpart[(int64_t)blockIdx.x * g.C + c0 + 16 * j + lc] = s0;
+      for (int q = 0; q < 4; ++q) {
+        const int rr = 16 * i + lrow + q;
+        const float d = (acc4[i][0][q] + bj) - tq[i][q];
+        sq = fmaf(wc * d, d, sq);
+        gv[i][q] = scale * d;
+        const bf16 gb = (bf16)gv[i][q];
+        act[1][rr][c] = gb;
+        col[q] = gb;
+      }
+      *(bf16x4 *)(g.dz4T + (int64_t)c * m + r0 + 16 * i + lrow) = col;
     }
+    const float cs = tile_colsum(gv);
+    if (l < 16) g.cp4[(int64_t)blockIdx.x * kOut + c] = cs;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+    if (l == 0) lw[w] = sq;
+  }
+  __syncthreads();
+  if (t == 0) g.lpart[blockIdx.x] = ((lw[0] + lw[1]) + lw[2]) + lw[3];
+  // back through layer 3 (dA3 = dZ4 W4, K = 64), then layer 2 (dA2 = dZ3 W3)
+#pragma unroll
+  for (int L = 1; L >= 0; --L) {
+    if (L == 1) {
+      tile_product<4, kOut>(act[1], bwt, l, acc);
+      tile_weights<4, kH>(g.W3T, kH, 64 * w, l, bw);
+    } else {
+      tile_product<4, kH>(act[0], bw, l, acc);
+    }
+    bf16 *dT = L == 1 ? g.dz3T : g.dz2T;
+    float *cp = L == 1 ? g.cp3 : g.cp2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 64 * w + 16 * j + lc;
+      float dz[kNI][4];
+#pragma unroll
+      for (int i = 0; i < kNI; ++i) {
+        bf16x4 col;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          dz[i][q] = acc[i][j][q] * gp[L][i][j][q];
+          const bf16 gb = (bf16)dz[i][q];
+          if (L == 1) act[0][16 * i + lrow + q][c] = gb;
+          col[q] = gb;
+        }
+        *(bf16x4 *)(dT + (int64_t)c * m + r0 + 16 * i + lrow) = col;
+      }
+      const float cs = tile_colsum(dz);
+      if (l < 16) cp[(int64_t)blockIdx.x * kH + c] = cs;
+    }
+    if (L == 1) __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- small kernels
-// Layer 1 (K = 2) on the vector unit: the random Fourier features of the
-// input, a = sin(x W1^T + b1) (W1: fixed frequencies, b1: phases 0 or pi/2,
-// so a holds sin and cos of each frequency).  The layer is not trained.
-// With rows != NULL, batch row r is dataset row rows[r] of x, and the
-// gathered inputs are also written to xg.  A block takes 32 batch rows and
-// thread n the feature n of each: the row-major stores of a (and z) are
-// coalesced across the threads, and each thread writes its 32 transposed
-// values aT[n][r0 .. r0 + 32) as four 16-byte vectors.  m is a multiple of 32.
-__global__ __launch_bounds__(256) void k_layer1(const float *__restrict__ x,
-                                                const int64_t *__restrict__ rows, float *xg,
-                                                const float *__restrict__ P, int64_t m, float *z,
-                                                bf16 *a, bf16 *aT) {
-  __shared__ float xs[32][2];
-  const int64_t r0 = (int64_t)blockIdx.x * 32;
-  const int n = threadIdx.x;
-  if (n < 32) {
-    const int64_t r = r0 + n;
-    const int64_t src = rows ? rows[r] : r;
-    const float x0 = x[2 * src], x1 = x[2 * src + 1];
-    xs[n][0] = x0;
-    xs[n][1] = x1;
-    if (rows) {
-      xg[2 * r] = x0;
-      xg[2 * r + 1] = x1;
-    }
-  }
-  __syncthreads();
-  const float w0 = P[oW1 + 2 * n], w1 = P[oW1 + 2 * n + 1], bb = P[ob1 + n];
-  bf16x8 col[4];
-#pragma unroll
-  for (int k = 0; k < 32; ++k) {
-    const int64_t r = r0 + k;
-    const float v = fmaf(xs[k][1], w1, fmaf(xs[k][0], w0, bb));
-    if (z) z[r * kH + n] = v;
-    const bf16 f = (bf16)feature_sin(v);
-    a[r * kH + n] = f;
-    col[k >> 3][k & 7] = f;
-  }
-  if (aT) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) *(bf16x8 *)(aT + (int64_t)n * m + r0 + 8 * q) = col[q];
-  }
-}
-
-// dZ of the output layer, 2 w_c (out - t) / (m * 64), for a block of 32 rows
-// (256 threads: column t mod 64, rows 8 (t / 64) + 0..7).  Target row r is
-// t[rows[r]] when rows is given.  Per block: column sums of dZ (bias
-// gradient) and the sum of w_c (out - t)^2 (loss), in a fixed order.
-__global__ __launch_bounds__(256) void k_loss_grad(const float *__restrict__ out,
-                                                   const float *__restrict__ t,
-                                                   const int64_t *__restrict__ rows, int64_t m,
-                                                   bf16 *dzb, bf16 *dzbT, float *colpart,
-                                                   float *lpart) {
-  __shared__ float cs[4][kOut];
-  __shared__ float sq4[4][kOut];
-  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * 32 + rg * 8;
-  const float w = out_weight(c);
-  const float scale = 2.0f * w / (float)(m * kOut);
-  float cs_ = 0.f, sq = 0.f;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int64_t r = r0 + k;
-    const int64_t src = rows ? rows[r] : r;
-    const float d = out[r * kOut + c] - t[src * kOut + c];
-    sq = fmaf(w * d, d, sq);
-    const float g = scale * d;
-    cs_ += g;
-    const bf16 gb = (bf16)g;
-    dzb[r * kOut + c] = gb;
-    dzbT[c * m + r] = gb;
-  }
-  cs[rg][c] = cs_;
-  sq4[rg][c] = sq;
-  __syncthreads();
-  if (rg == 0) {
-    colpart[blockIdx.x * kOut + c] = ((cs[0][c] + cs[1][c]) + cs[2][c]) + cs[3][c];
-    sq4[0][c] = ((sq4[0][c] + sq4[1][c]) + sq4[2][c]) + sq4[3][c];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float v = 0.f;
-    for (int k = 0; k < kOut; ++k) v += sq4[0][k];
-    lpart[blockIdx.x] = v;
-  }
-}
-
 // Gradients of all parameters from the partial sums of one batch of m rows
-// (T = m / 32 row tiles, S weight-gradient splits), each summed in a fixed
+// (T = m / 16 row tiles, S weight-gradient splits), each summed in a fixed
 // order, and the batch loss; acc (optional) accumulates the loss.
 struct GradParts {
   const float *w2, *w3;           // [S][256][256]
@@ -348,12 +435,78 @@ struct GradParts {
 constexpr int64_t kNW = 2 * kH * kH + kOut * kH;   // weights of the MFMA layers
 constexpr int kNColSums = 5 * kH + kOut + 1;        // W1 (2 x 256), b1..b4, loss
 constexpr int kReduceWBlocks = (int)((kNW + 255) / 256);
+// Adam on the FP32 master parameters (Kingma and Ba, 2015); the BF16 copies
+// of W2, W3, W4 and their transposes follow the updated values.  The step
+// count is t = t_base + step + 1; with hyper != NULL the learning rate,
+// betas, epsilon and t_base are read from device memory (hyper[0..4]), so a
+// captured epoch replays with new values.
+struct AdamArgs {
+  float *P, *Mm, *V;
+  const double *hyper;
+  double lr, b1, b2, eps, t_base;
+  int step;
+  bf16 *W2, *W2T, *W3, *W3T, *W4, *W4T;
+};
+
+// The block's hyper-parameters and bias corrections (two FP64 powers, in
+// thread 0): h = lr, b1, b2, eps, 1 / (1 - b1^t), 1 / (1 - b2^t).
+__device__ __forceinline__ void adam_setup(const AdamArgs &a, float *h) {
+  if (threadIdx.x == 0) {
+    double lr = a.lr, b1 = a.b1, b2 = a.b2, eps = a.eps, t0 = a.t_base;
+    if (a.hyper) {
+      lr = a.hyper[0];
+      b1 = a.hyper[1];
+      b2 = a.hyper[2];
+      eps = a.hyper[3];
+      t0 = a.hyper[4];
+    }
+    const double t = t0 + (double)a.step + 1.0;
+    h[0] = (float)lr;
+    h[1] = (float)b1;
+    h[2] = (float)b2;
+    h[3] = (float)eps;
+    h[4] = (float)(1.0 / (1.0 - pow(b1, t)));
+    h[5] = (float)(1.0 / (1.0 - pow(b2, t)));
+  }
+  __syncthreads();
+}
+
+// One parameter i (a trained one: W2 onwards) with gradient gr.
+__device__ __forceinline__ void adam_one(const AdamArgs &a, const float *h, int64_t i, float gr) {
+  const float lr = h[0], b1 = h[1], b2 = h[2], eps = h[3], c1 = h[4], c2 = h[5];
+  const float m = fmaf(b1, a.Mm[i], (1.0f - b1) * gr);
+  const float v = fmaf(b2, a.V[i], (1.0f - b2) * gr * gr);
+  a.Mm[i] = m;
+  a.V[i] = v;
+  const float w = a.P[i] - lr * (m * c1) / (sqrtf(v * c2) + eps);
+  a.P[i] = w;
+  const bf16 wb = (bf16)w;
+  if (i >= oW2 && i < ob2) {
+    const int64_t k = i - oW2, o = k / kH, in = k % kH;
+    a.W2[k] = wb;
+    a.W2T[in * kH + o] = wb;
+  } else if (i >= oW3 && i < ob3) {
+    const int64_t k = i - oW3, o = k / kH, in = k % kH;
+    a.W3[k] = wb;
+    a.W3T[in * kH + o] = wb;
+  } else if (i >= oW4 && i < ob4) {
+    const int64_t k = i - oW4, o = k / kH, in = k % kH;
+    a.W4[k] = wb;
+    a.W4T[in * kOut + o] = wb;
+  }
+}
+
 // Blocks [0, kReduceWBlocks): one weight per thread (S partials).  The
 // following blocks: one wave per tile-summed entry (T partials: lane l takes
-// tiles l, l + 64, ..., then a butterfly over the wave).
+// tiles l, l + 64, ..., then a butterfly over the wave).  ADAM: each summed
+// gradient also takes its Adam step at once (the feature layer's entries,
+// whose gradient is 0, and the loss excepted).
+template <bool ADAM>
 __global__ __launch_bounds__(256) void k_reduce_grads(GradParts p, int64_t T, int S,
                                                       float count, float *G, float *loss,
-                                                      float *acc, int first) {
+                                                      float *acc, int first, AdamArgs ad) {
+  __shared__ float h[6];
+  if (ADAM) adam_setup(ad, h);
   if ((int)blockIdx.x < kReduceWBlocks) {
     const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (w >= kNW) return;
@@ -369,6 +522,7 @@ __global__ __launch_bounds__(256) void k_reduce_grads(GradParts p, int64_t T, in
     float g = 0.f;
     for (int k = 0; k < S; ++k) g += src[k * stride];
     G[o] = g;
+    if (ADAM) adam_one(ad, h, o, g);
     return;
   }
   const int e = ((int)blockIdx.x - kReduceWBlocks) * 4 + (threadIdx.x >> 6);
@@ -400,62 +554,12 @@ __global__ __launch_bounds__(256) void k_reduce_grads(GradParts p, int64_t T, in
   if (l == 0) {
     if (dst) {
       *dst = v;
+      if (ADAM && src) adam_one(ad, h, dst - G, v);
     } else {
       const float lv = v / count;
       *loss = lv;
       if (acc) *acc = first ? lv : *acc + lv;
     }
-  }
-}
-
-// Adam on the FP32 master parameters (Kingma and Ba, 2015); the BF16 copies
-// of W2, W3, W4 and their transposes follow the updated values.  The step
-// count is t = t_base + step + 1; with hyper != NULL the learning rate,
-// betas, epsilon and t_base are read from device memory (hyper[0..4]), so a
-// captured epoch replays with new values.
-__global__ void k_adam(float *__restrict__ P, const float *__restrict__ G, float *__restrict__ Mm,
-                       float *__restrict__ V, const double *__restrict__ hyper, double lr_,
-                       double b1_, double b2_, double eps_, double t_base, int step, bf16 *W2,
-                       bf16 *W2T, bf16 *W3, bf16 *W3T, bf16 *W4, bf16 *W4T) {
-  if (hyper) {
-    lr_ = hyper[0];
-    b1_ = hyper[1];
-    b2_ = hyper[2];
-    eps_ = hyper[3];
-    t_base = hyper[4];
-  }
-  // the bias corrections, once per block (two FP64 powers)
-  __shared__ float corr[2];
-  if (threadIdx.x == 0) {
-    const double t = t_base + (double)step + 1.0;
-    corr[0] = (float)(1.0 / (1.0 - pow(b1_, t)));
-    corr[1] = (float)(1.0 / (1.0 - pow(b2_, t)));
-  }
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kNP || i < oW2) return;   // W1, b1: the fixed feature layer
-  const float c1 = corr[0], c2 = corr[1];
-  const float lr = (float)lr_, b1 = (float)b1_, b2 = (float)b2_, eps = (float)eps_;
-  const float g = G[i];
-  const float m = fmaf(b1, Mm[i], (1.0f - b1) * g);
-  const float v = fmaf(b2, V[i], (1.0f - b2) * g * g);
-  Mm[i] = m;
-  V[i] = v;
-  const float w = P[i] - lr * (m * c1) / (sqrtf(v * c2) + eps);
-  P[i] = w;
-  const bf16 wb = (bf16)w;
-  if (i >= oW2 && i < ob2) {
-    const int64_t k = i - oW2, o = k / kH, in = k % kH;
-    W2[k] = wb;
-    W2T[in * kH + o] = wb;
-  } else if (i >= oW3 && i < ob3) {
-    const int64_t k = i - oW3, o = k / kH, in = k % kH;
-    W3[k] = wb;
-    W3T[in * kH + o] = wb;
-  } else if (i >= oW4 && i < ob4) {
-    const int64_t k = i - oW4, o = k / kH, in = k % kH;
-    W4[k] = wb;
-    W4T[in * kOut + o] = wb;
   }
 }
 
@@ -917,12 +1021,12 @@ struct sur_ctx {
        *W4T = nullptr;
   float *d_mean = nullptr, *d_std = nullptr;
   double *d_dmean = nullptr, *d_dstd = nullptr;
-  // activations of one batch
-  float *x = nullptr, *tgt = nullptr, *z2 = nullptr, *z3 = nullptr, *out = nullptr;
-  bf16 *a1 = nullptr, *a1T = nullptr, *a2 = nullptr, *a2T = nullptr, *a3 = nullptr, *a3T = nullptr;
-  bf16 *dz4b = nullptr, *dz4bT = nullptr, *dz3b = nullptr, *dz3bT = nullptr, *dz2b = nullptr,
-       *dz2bT = nullptr;
-  // partial sums of the gradients: split-K weight products, per-32-row-tile
+  // one batch: inputs and targets, the activations and gradients
+  // transposed ([feature][batch row]) for the weight-gradient products
+  float *x = nullptr, *tgt = nullptr;
+  bf16 *a1T = nullptr, *a2T = nullptr, *a3T = nullptr;
+  bf16 *dz4bT = nullptr, *dz3bT = nullptr, *dz2bT = nullptr;
+  // partial sums of the gradients: split-K weight products, per-16-row-tile
   // column sums (biases, layer-1 weights), loss
   float *part2 = nullptr, *part3 = nullptr, *part4 = nullptr;
   float *cp2 = nullptr, *cp3 = nullptr,
@@ -1000,13 +1104,19 @@ hipError_t alloc(T **p, int64_t count) {
 unsigned nblk(int64_t count, int b) { return (unsigned)((count + b - 1) / b); }
 
 // R, C multiples of 32; K / split a multiple of 64.
-template <int EPI>
-hipError_t gemm(hipStream_t st, const GemmArgs &g, int split = 1) {
-  dim3 grid((unsigned)(g.R / kTile), (unsigned)(g.C / kTile), (unsigned)split);
-  if ((g.K / split) % 256 == 0)
-    hipLaunchKernelGGL((k_gemm<EPI, 8>), grid, dim3(64), 0, st, g);
+// The three products of bt.g in one launch (each R, C a multiple of 32, the
+// same K with K / split a multiple of 64).
+hipError_t gemm3(hipStream_t st, GemmBatch bt, int split) {
+  bt.split = split;
+  int64_t total = 0;
+  for (int p = 0; p < 3; ++p) {
+    bt.nblk[p] = (bt.g[p].R / kTile) * (bt.g[p].C / kTile) * split;
+    total += bt.nblk[p];
+  }
+  if ((bt.g[0].K / split) % 256 == 0)
+    hipLaunchKernelGGL((k_gemm<8>), dim3((unsigned)total), dim3(64), 0, st, bt);
   else
-    hipLaunchKernelGGL((k_gemm<EPI, 2>), grid, dim3(64), 0, st, g);
+    hipLaunchKernelGGL((k_gemm<2>), dim3((unsigned)total), dim3(64), 0, st, bt);
   return hipGetLastError();
 }
 
@@ -1022,20 +1132,6 @@ GemmArgs gargs(const bf16 *X, int64_t ldx, const bf16 *Y, int64_t ldy, int64_t R
   g.C = C;
   g.K = K;
   return g;
-}
-
-// Buffers of one training forward pass (z* and a*T are kept for the
-// backward pass).
-struct Fwd {
-  float *x;
-  bf16 *a1, *a2, *a3;
-  float *z1, *z2, *z3;
-  bf16 *a1T, *a2T, *a3T;
-  float *out;
-};
-
-Fwd train_bufs(sur_ctx *s) {
-  return Fwd{s->x, s->a1, s->a2, s->a3, nullptr, s->z2, s->z3, s->a1T, s->a2T, s->a3T, s->out};
 }
 
 constexpr int64_t kInferRows = 65536;
@@ -1087,92 +1183,82 @@ hipError_t fused(sur_ctx *s, FusedArgs a, bool screen) {
   return hipGetLastError();
 }
 
-// Training forward pass of one batch of m rows (m % 64 == 0): inputs from
-// b.x, or with rows != NULL dataset rows rows[0..m) of xsrc (gathered into
-// b.x).
-hipError_t forward_batch(sur_ctx *s, const Fwd &b, int64_t m, const int64_t *rows = nullptr,
-                         const float *xsrc = nullptr) {
-  hipStream_t st = s->stream;
-  hipLaunchKernelGGL(k_layer1, dim3((unsigned)(m / 32)), dim3(256), 0, st, rows ? xsrc : b.x,
-                     rows, b.x, s->P, m, b.z1, b.a1, b.a1T);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  GemmArgs g = gargs(b.a1, kH, s->W2, kH, m, kH, kH);
-  g.bias = s->P + ob2;
-  g.out_f32 = b.z2;
-  g.out_bf16 = b.a2;
-  g.out_bf16T = b.a2T;
-  e = gemm<EPI_FWD_GELU>(st, g);
-  if (e != hipSuccess) return e;
-  g = gargs(b.a2, kH, s->W3, kH, m, kH, kH);
-  g.bias = s->P + ob3;
-  g.out_f32 = b.z3;
-  g.out_bf16 = b.a3;
-  g.out_bf16T = b.a3T;
-  e = gemm<EPI_FWD_GELU>(st, g);
-  if (e != hipSuccess) return e;
-  g = gargs(b.a3, kH, s->W4, kH, m, kOut, kH);
-  g.bias = s->P + ob4;
-  g.out_f32 = b.out;
-  return gemm<EPI_FWD_LINEAR>(st, g);
+// Adam's arguments for the handle's parameters: hyper-parameters from
+// device memory (hyper != NULL, a captured step `step`) or the handle's.
+AdamArgs adam_args(sur_ctx *s, const double *hyper, int step) {
+  AdamArgs a;
+  a.P = s->P;
+  a.Mm = s->Mm;
+  a.V = s->V;
+  a.hyper = hyper;
+  a.lr = s->lr;
+  a.b1 = s->b1;
+  a.b2 = s->b2;
+  a.eps = s->eps;
+  a.t_base = (double)s->t;
+  a.step = step;
+  a.W2 = s->W2;
+  a.W2T = s->W2T;
+  a.W3 = s->W3;
+  a.W3T = s->W3T;
+  a.W4 = s->W4;
+  a.W4T = s->W4T;
+  return a;
 }
 
-// Loss and gradients of all parameters into s->G and s->loss, after
-// forward_batch(train).  Targets: row r of tgt, or row rows[r] with rows;
-// loss_acc (optional) accumulates the loss (first: starts it).
-hipError_t backward_batch(sur_ctx *s, int64_t m, const float *tgt, const int64_t *rows,
-                          float *loss_acc = nullptr, bool first = true) {
+// One batch's loss and gradients of all parameters into s->G and s->loss:
+// the fused tile kernel (forward, loss gradient, data gradients), then the
+// weight gradients (split over the batch) and the fixed-order reduction,
+// which with ad != NULL also takes the Adam step.  Inputs: row r of x and
+// tgt, or row rows[r] with rows; loss_acc (optional) accumulates the loss
+// (first: starts it).
+hipError_t train_batch(sur_ctx *s, int64_t m, const float *x, const float *tgt,
+                       const int64_t *rows, float *loss_acc = nullptr, bool first = true,
+                       const AdamArgs *ad = nullptr) {
   hipStream_t st = s->stream;
   hipError_t e;
   const int split = wgrad_split(m);
-  const int64_t T = m / 32;
-  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)T), dim3(256), 0, st, s->out, tgt, rows, m,
-                     s->dz4b, s->dz4bT, s->cp4, s->lpart);
+  const int64_t T = m / kTR;
+  TrainArgs a;
+  a.x = x;
+  a.rows = rows;
+  a.tgt = tgt;
+  a.P = s->P;
+  a.W2 = s->W2;
+  a.W3 = s->W3;
+  a.W4 = s->W4;
+  a.W3T = s->W3T;
+  a.W4T = s->W4T;
+  a.m = m;
+  a.a1T = s->a1T;
+  a.a2T = s->a2T;
+  a.a3T = s->a3T;
+  a.dz4T = s->dz4bT;
+  a.dz3T = s->dz3bT;
+  a.dz2T = s->dz2bT;
+  a.cp4 = s->cp4;
+  a.cp3 = s->cp3;
+  a.cp2 = s->cp2;
+  a.lpart = s->lpart;
+  hipLaunchKernelGGL(k_train_fb, dim3((unsigned)T), dim3(256), 0, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // output layer
-  GemmArgs g = gargs(s->dz4bT, m, s->a3T, m, kOut, kH, m);
-  g.out_f32 = s->part4;
-  if ((e = gemm<EPI_PARTIAL>(st, g, split)) != hipSuccess) return e;
-  g = gargs(s->dz4b, kOut, s->W4T, kOut, m, kH, kOut);
-  g.zprev = s->z3;
-  g.out_bf16 = s->dz3b;
-  g.out_bf16T = s->dz3bT;
-  g.colpart = s->cp3;
-  if ((e = gemm<EPI_BWD_GELU>(st, g)) != hipSuccess) return e;
-  // layer 3
-  g = gargs(s->dz3bT, m, s->a2T, m, kH, kH, m);
-  g.out_f32 = s->part3;
-  if ((e = gemm<EPI_PARTIAL>(st, g, split)) != hipSuccess) return e;
-  g = gargs(s->dz3b, kH, s->W3T, kH, m, kH, kH);
-  g.zprev = s->z2;
-  g.out_bf16 = s->dz2b;
-  g.out_bf16T = s->dz2bT;
-  g.colpart = s->cp2;
-  if ((e = gemm<EPI_BWD_GELU>(st, g)) != hipSuccess) return e;
-  // layer 2 (its input, the feature layer, is fixed: no gradient flows further)
-  g = gargs(s->dz2bT, m, s->a1T, m, kH, kH, m);
-  g.out_f32 = s->part2;
-  if ((e = gemm<EPI_PARTIAL>(st, g, split)) != hipSuccess) return e;
+  GemmBatch bt;
+  bt.g[0] = gargs(s->dz4bT, m, s->a3T, m, kOut, kH, m);
+  bt.g[0].out_f32 = s->part4;
+  bt.g[1] = gargs(s->dz3bT, m, s->a2T, m, kH, kH, m);
+  bt.g[1].out_f32 = s->part3;
+  bt.g[2] = gargs(s->dz2bT, m, s->a1T, m, kH, kH, m);
+  bt.g[2].out_f32 = s->part2;
+  if ((e = gemm3(st, bt, split)) != hipSuccess) return e;
   GradParts p{s->part2, s->part3, s->cp2, s->cp3, s->part4, s->cp4, s->lpart};
-  hipLaunchKernelGGL(k_reduce_grads, dim3(kReduceWBlocks + (kNColSums + 3) / 4), dim3(256), 0,
-                     st, p, T, split,
-                     (float)(m * kOut), s->G, s->loss, loss_acc, first ? 1 : 0);
-  return hipGetLastError();
-}
-
-hipError_t adam(sur_ctx *s) {
-  hipLaunchKernelGGL(k_adam, dim3(nblk(kNP, 256)), dim3(256), 0, s->stream, s->P, s->G, s->Mm,
-                     s->V, (const double *)nullptr, s->lr, s->b1, s->b2, s->eps,
-                     (double)s->t, 0, s->W2, s->W2T, s->W3, s->W3T, s->W4, s->W4T);
-  s->t += 1;
-  return hipGetLastError();
-}
-
-// Step `step` of a captured epoch: hyper-parameters from s->hyper.
-hipError_t adam_captured(sur_ctx *s, int step) {
-  hipLaunchKernelGGL(k_adam, dim3(nblk(kNP, 256)), dim3(256), 0, s->stream, s->P, s->G, s->Mm,
-                     s->V, (const double *)s->hyper, 0.0, 0.0, 0.0, 0.0, 0.0, step, s->W2,
-                     s->W2T, s->W3, s->W3T, s->W4, s->W4T);
+  const dim3 rg(kReduceWBlocks + (kNColSums + 3) / 4);
+  if (ad)
+    hipLaunchKernelGGL(k_reduce_grads<true>, rg, dim3(256), 0, st, p, T, split,
+                       (float)(m * kOut), s->G, s->loss, loss_acc, first ? 1 : 0, *ad);
+  else
+    hipLaunchKernelGGL(k_reduce_grads<false>, rg, dim3(256), 0, st, p, T, split,
+                       (float)(m * kOut), s->G, s->loss, loss_acc, first ? 1 : 0,
+                       adam_args(s, nullptr, 0));
   return hipGetLastError();
 }
 
@@ -1235,9 +1321,9 @@ int ensure_epoch_graph(sur_ctx *s, const float *x, const float *y, int64_t n, co
   hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
   for (int64_t b = 0; e == hipSuccess && b < nb; ++b) {
     const int64_t *rows = perm + b * batch;
-    e = forward_batch(s, train_bufs(s), batch, rows, x);
-    if (e == hipSuccess) e = backward_batch(s, batch, y, rows, s->loss_acc, b == 0);
-    if (e == hipSuccess) e = adam_captured(s, (int)b);
+    // the step's Adam update from the hyper-parameters in s->hyper
+    const AdamArgs ad = adam_args(s, s->hyper, (int)b);
+    e = train_batch(s, batch, x, y, rows, s->loss_acc, b == 0, &ad);
   }
   hipGraph_t gr = nullptr;
   const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &gr);
@@ -1305,15 +1391,14 @@ int sur_create(int32_t device, void *hip_stream, int64_t max_batch, sur_t *out) 
   A(W4, kOut * kH); A(W4T, kOut * kH); A(W2f, kH * kH); A(W3f, kH * kH);
   A(W4f, kOut * kH);
   A(d_mean, kOut); A(d_std, kOut); A(d_dmean, kOut); A(d_dstd, kOut);
-  A(x, B * kIn); A(tgt, B * kOut); A(z2, B * kH); A(z3, B * kH); A(out, B * kOut);
-  A(a1, B * kH); A(a1T, B * kH); A(a2, B * kH); A(a2T, B * kH); A(a3, B * kH); A(a3T, B * kH);
-  A(dz4b, B * kOut); A(dz4bT, B * kOut); A(dz3b, B * kH); A(dz3bT, B * kH);
-  A(dz2b, B * kH); A(dz2bT, B * kH);
+  A(x, B * kIn); A(tgt, B * kOut);
+  A(a1T, B * kH); A(a2T, B * kH); A(a3T, B * kH);
+  A(dz4bT, B * kOut); A(dz3bT, B * kH); A(dz2bT, B * kH);
   A(part2, (int64_t)kSplit * kH * kH); A(part3, (int64_t)kSplit * kH * kH);
   A(part4, (int64_t)kSplit * kOut * kH);
-  A(cp2, B / 32 * kH);
-  A(cp3, B / 32 * kH); A(cp4, B / 32 * kOut);
-  A(lpart, B / 32); A(loss, 1);
+  A(cp2, B / kTR * kH);
+  A(cp3, B / kTR * kH); A(cp4, B / kTR * kOut);
+  A(lpart, B / kTR); A(loss, 1);
   A(loss_acc, 1);
   A(hyper, 5);
 #undef A
@@ -1338,9 +1423,8 @@ int sur_destroy(sur_t s) {
   DevGuard dg(s->device);
   (void)hipStreamSynchronize(s->stream);
   void *ptrs[] = {s->P, s->G, s->Mm, s->V, s->W2, s->W2T, s->W3, s->W3T, s->W4, s->W4T,
-                  s->d_mean, s->d_std, s->d_dmean, s->d_dstd, s->x, s->tgt, s->z2,
-                  s->z3, s->out, s->a1, s->a1T, s->a2, s->a2T, s->a3, s->a3T, s->dz4b,
-                  s->dz4bT, s->dz3b, s->dz3bT, s->dz2b, s->dz2bT, s->part2, s->part3,
+                  s->d_mean, s->d_std, s->d_dmean, s->d_dstd, s->x, s->tgt, s->a1T,
+                  s->a2T, s->a3T, s->dz4bT, s->dz3bT, s->dz2bT, s->part2, s->part3,
                   s->part4, s->cp2, s->cp3, s->cp4, s->lpart,
                   s->loss, s->loss_acc, s->scan, s->nlab, s->srec, s->ix, s->iout, s->W2f,
                   s->W3f, s->W4f};
@@ -1450,8 +1534,7 @@ int sur_gradients(sur_t s, const float *x, const float *target, int64_t m, float
   if (!x || !target) return sfail(s, ENS_E_INVAL, "sur_gradients: NULL input");
   DevGuard dg(s->device);
   if (int rc = load_batch(s, x, target, m, where)) return rc;
-  SUR_HIP(s, forward_batch(s, train_bufs(s), m));
-  SUR_HIP(s, backward_batch(s, m, s->tgt, nullptr));
+  SUR_HIP(s, train_batch(s, m, s->x, s->tgt, nullptr));
   const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (grads) SUR_HIP(s, hipMemcpyAsync(grads, s->G, kNP * sizeof(float), k, s->stream));
   if (loss) SUR_HIP(s, hipMemcpyAsync(loss, s->loss, sizeof(float), k, s->stream));
@@ -1466,9 +1549,9 @@ int sur_train_step(sur_t s, const float *x, const float *target, int64_t m, floa
   if (!x || !target) return sfail(s, ENS_E_INVAL, "sur_train_step: NULL input");
   DevGuard dg(s->device);
   if (int rc = load_batch(s, x, target, m, where)) return rc;
-  SUR_HIP(s, forward_batch(s, train_bufs(s), m));
-  SUR_HIP(s, backward_batch(s, m, s->tgt, nullptr));
-  SUR_HIP(s, adam(s));
+  const AdamArgs ad = adam_args(s, nullptr, 0);
+  SUR_HIP(s, train_batch(s, m, s->x, s->tgt, nullptr, nullptr, true, &ad));
+  s->t += 1;
   if (loss) {
     const hipMemcpyKind k = where == ENS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     SUR_HIP(s, hipMemcpyAsync(loss, s->loss, sizeof(float), k, s->stream));
