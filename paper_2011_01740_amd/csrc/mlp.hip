@@ -1059,7 +1059,7 @@ struct sur_ctx {
 
 namespace {
 
-constexpr int kSplit = 16;  // largest batch split of the weight-gradient products
+constexpr int kSplit = 8;   // largest batch split of the weight-gradient products
 
 // Batch split of a weight-gradient product: chunks of 256 rows where the
 // batch allows (at most kSplit of them), else chunks of a multiple of 64 rows
