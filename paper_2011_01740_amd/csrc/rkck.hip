@@ -133,6 +133,34 @@ __device__ __forceinline__ double sqrt_nr(double x) {
   return fma(fma(-g, g, x), h, g);
 }
 
+// max / min as one v_max_f64 / v_min_f64.  fmax() and fmin() make the
+// compiler first quiet every operand it cannot prove canonical (a loop-
+// carried state, a kernel argument) with an extra v_max of the value with
+// itself, in case it is a signalling NaN; the operands here are arithmetic
+// results or host-checked step bounds, never signalling NaNs (a quiet NaN
+// in the error norm is caught by its finite test).  The bound of a clamp is
+// a scalar operand (an SGPR pair), as the kernel arguments already are.
+__device__ __forceinline__ double vmax_abs(double a, double b) {   // max(|a|, |b|)
+  double r;
+  asm("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double vmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double vmax_s(double a, double b) {     // b uniform
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(b));
+  return r;
+}
+__device__ __forceinline__ double vmin_s(double a, double b) {     // b uniform
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(b));
+  return r;
+}
+
 // x^(-1/5) for x in [1e-30, 1e30]: an FP32 estimate r0 from the hardware
 // base-2 logarithm and exponential (relative error ~1e-7), then in FP64 with
 // e = 1 - x r0^5 the series r = r0 (1 - e)^(-1/5) = r0 (1 + e/5 + 3 e^2/25
@@ -166,8 +194,8 @@ constexpr CtlTab kCtlImm = {1e-4, 4e3, 0.9, 0.2, 5.0, 0.12, 0.2};
 // 0.9 (4e3)^(-1/5) = 0.171 clamps to 0.2, the factors of the unlimited E.
 template <class T>
 __device__ __forceinline__ double step_factor_with(const T &c, double E) {
-  const double f = c.safety * rfifth_c(fmin(fmax(E, c.e_lo), c.e_hi), c.c12, c.c2);
-  return fmin(fmax(f, c.f_lo), c.f_hi);
+  const double f = c.safety * rfifth_c(vmin_s(vmax_s(E, c.e_lo), c.e_hi), c.c12, c.c2);
+  return vmin_s(vmax_s(f, c.f_lo), c.f_hi);
 }
 template <bool TABLE>
 __device__ __forceinline__ double step_factor(double E) {
@@ -187,11 +215,11 @@ __device__ __forceinline__ bool error_ratio(double rtol, double atol, const doub
   double z = 0.0;
 #pragma unroll
   for (int c = 0; c < D; ++c) {
-    const double sc = fma(rtol, fmax(fabs(y[c]), fabs(y5[c])), atol);
+    const double sc = fma(rtol, vmax_abs(y[c], y5[c]), atol);
     const double r = fabs(err[c]) * rcp_nr(sc);
     z = fma(0.0, y5[c], z);
     z = fma(0.0, r, z);
-    E = c == 0 ? r : fmax(E, r);
+    E = c == 0 ? r : vmax(E, r);
   }
   return z == 0.0;
 }
@@ -268,7 +296,8 @@ struct MLorenz {  // Sec. 4.1
 
 // sin x and cos x from their Taylor series, sin through x^(2 NS - 1) and cos
 // through x^(2 NC - 2), Horner in x^2.  The callers size NS, NC for the
-// largest |x| they pass so that the first omitted term is below 1e-18.
+// largest |x| they pass so that the first omitted term is below 1e-17 of the
+// value (a tenth of its rounding unit).
 constexpr double kInvFact[20] = {
     1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040, 1.0 / 40320,
     1.0 / 362880, 1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600, 1.0 / 6227020800.0,
@@ -448,7 +477,7 @@ struct MKM {
           so = so2;
           co = co2;
         } else if constexpr (S == 3) {
-          sincos_taylor<8, 8>((2.0 * M_PI * 3.0 / 10.0) * h, &so, &co);  // |x| <= 0.24
+          sincos_taylor<6, 7>((2.0 * M_PI * 3.0 / 10.0) * h, &so, &co);  // |x| <= 0.24
         } else if constexpr (S == 4) {
           const double sd = 2.0 * so2 * co2, cd = fma(-2.0 * so2, so2, 1.0);  // 2/5
           so4 = 2.0 * sd * cd;                                                // 4/5
@@ -456,7 +485,7 @@ struct MKM {
           so = so4;
           co = co4;
         } else if constexpr (S == 5) {
-          sincos_taylor<9, 10>((2.0 * M_PI * 8.0 / 9.0) * h, &so, &co);  // |x| <= 0.70
+          sincos_taylor<8, 9>((2.0 * M_PI * 8.0 / 9.0) * h, &so, &co);   // |x| <= 0.70
         } else if constexpr (S == 6) {
           so1 = fma(so4, co2, co4 * so2);                                 // 4/5 + 1/5
           co1 = fma(co4, co2, -(so4 * so2));
@@ -472,7 +501,7 @@ struct MKM {
         co = co2;
       } else if constexpr (S == 3) {
         double so3, co3;
-        sincos_taylor<8, 8>((2.0 * M_PI * 3.0 / 10.0) * h, &so3, &co3);  // |x| <= 0.24
+        sincos_taylor<6, 7>((2.0 * M_PI * 3.0 / 10.0) * h, &so3, &co3);  // |x| <= 0.24
         so4 = 2.0 * so3 * co3;             // doubled angle, for stage 4
         co4 = fma(-2.0 * so3, so3, 1.0);
         so = so3;
@@ -485,7 +514,7 @@ struct MKM {
         so = fma(so4, cd, co4 * sd);
         co = fma(co4, cd, -(so4 * sd));
       } else {
-        sincos_taylor<9, 10>((2.0 * M_PI * 7.0 / 8.0) * h, &so, &co);     // |x| <= 0.69
+        sincos_taylor<8, 9>((2.0 * M_PI * 7.0 / 8.0) * h, &so, &co);      // |x| <= 0.69
       }
     } else {
       gas = exp(-K10 * log(y1));
@@ -652,7 +681,7 @@ __device__ __forceinline__ int dp_attempt(M &m, double t, const double *y, doubl
 // x limited to [lo, hi] for a finite x and lo <= hi (the host checks
 // dt_min <= dt_max), as two min/max instructions.
 __device__ __forceinline__ double clampd(double x, double lo, double hi) {
-  return fmin(fmax(x, lo), hi);
+  return vmin_s(vmax_s(x, lo), hi);
 }
 
 // Lane-private progress of one system.
