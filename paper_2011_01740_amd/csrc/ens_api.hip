@@ -137,6 +137,7 @@ struct ens_ctx {
   int64_t *d_order = nullptr;  // queue order (ens_set_order), valid if use_order
   bool use_order = false;
   double *d_carry = nullptr;   // adaptive: [ENS_NCARRY][n] carried phase accessories
+  double *d_coef = nullptr;    // Keller--Miksis adaptive: [ENS_MAX_COEF][n] coefficients
   // scratch kept for the handle's lifetime (allocated at create or first use)
   char *d_sort = nullptr;      // ens_order_by_work: keys, indices, sort temporaries
   size_t sort_tmp = 0;         // bytes of rocPRIM temporaries inside d_sort
@@ -574,6 +575,8 @@ int ens_create(const ens_desc *d, ens_t *out) {
     if (e == hipSuccess) e = dalloc(h, &h->d_cold, 1);
     if (e == hipSuccess) e = dalloc(h, &h->d_desc, ENS_MAX_ENSEMBLES);
     if (e == hipSuccess && (h->model == ENS_KM || h->model == ENS_KM6)) e = dalloc(h, &h->d_phi, n);
+    if (e == hipSuccess && (h->model == ENS_KM || h->model == ENS_KM6))
+      e = dalloc(h, &h->d_coef, (size_t)ens::ENS_MAX_COEF * n);
     if (e == hipSuccess) e = dalloc(h, &h->d_carry, (size_t)ENS_NCARRY * n);
     if (e == hipSuccess) e = dalloc(h, &h->d_order, n);
     // ens_order_by_work's scratch: sort keys in and out, indices, rocPRIM
@@ -616,6 +619,7 @@ int ens_destroy(ens_t h) {
   dfree(h, h->d_order);
   dfree(h, h->d_desc);
   dfree(h, h->d_carry);
+  dfree(h, h->d_coef);
   dfree(h, h->d_sort);
   dfree(h, h->d_seen);
   dfree(h, h->d_flag);
@@ -824,6 +828,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
   c.queue = h->d_queue;
   c.order = h->use_order ? h->d_order : nullptr;
   c.carry = h->d_carry;
+  c.coef = h->d_coef;
   ENS_HIP(h, ens::launch_set_cold(h->d_cold, c, h->stream));
 
   ens::RkckArgs a;
@@ -855,6 +860,7 @@ static int solve_rkck(ens_t h, const ens_solve_opts *o) {
       e = ens::launch_fill_f64(h->d_rec, std::numeric_limits<double>::quiet_NaN(),
                                (int64_t)rec_count, s);
     if (e == hipSuccess && fill_h) e = ens::launch_fill_f64(h->d_h, o->dt0, h->n, s);
+    if (e == hipSuccess && h->n > 0 && h->d_coef) e = ens::launch_rkck_coef(kmodel, a, s);
     if (e == hipSuccess && h->n > 0) e = ens::launch_rkck(kmodel, h->solver, block, grid, a, s);
     return e;
   };

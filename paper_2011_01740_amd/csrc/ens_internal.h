@@ -44,6 +44,8 @@ struct RkckCold {
   const int64_t *order;     // [n] system taken at each queue position, or null
   double *carry;            // [ENS_NCARRY][n] in/out: the running phase's
                             // y1max, y1min, start time, valve seated (1/0)
+  double *coef;             // [ENS_MAX_COEF][n]: each system's model coefficients,
+                            // filled at the start of a solve (Keller--Miksis), or null
 };
 
 struct RkckArgs {
@@ -91,6 +93,12 @@ void set_thread_error(const char *msg);
 // Fresh phase accessories [ENS_NCARRY][n] from the clock t [n].
 hipError_t launch_fresh_carry(double *carry, const double *t, int64_t n, hipStream_t s);
 hipError_t launch_set_cold(RkckCold *dst, const RkckCold &c, hipStream_t s);
+// Most model coefficients per system that a solve precomputes (Keller--Miksis:
+// the coefficients of its right-hand side, derived from the system's
+// parameters and the shared constants), and the kernel that fills them
+// (nothing to do for a model without such coefficients).
+constexpr int ENS_MAX_COEF = 16;
+hipError_t launch_rkck_coef(int model, const RkckArgs &a, hipStream_t s);
 hipError_t launch_rk4(int model, int block, int spl, const double *p, double *y,
                       double *acc, int64_t n, double dt, int64_t nsteps,
                       const double *shared, hipStream_t s);

@@ -236,6 +236,7 @@ struct MQuad {  // dx/dt = x^2 - p (Sec. 3)
   static constexpr bool kDrive2 = false;
   static constexpr int kF = 1;           // record fields
   static constexpr bool kTangent = false;
+  static constexpr int kNCoef = 0;  // no precomputed coefficients
   double p;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) { p = P[i]; }
   __device__ void begin(double) {}
@@ -263,6 +264,7 @@ struct MLorenz {  // Sec. 4.1
   static constexpr bool kDrive2 = false;
   static constexpr int kF = 1;
   static constexpr bool kTangent = false;
+  static constexpr int kNCoef = 0;  // no precomputed coefficients
   double rho, sigma, beta;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
     rho = P[i];
@@ -416,6 +418,51 @@ struct MKM {
       K8 = re * w2 * pa2 * q2 / (rhoL * cL);
       K11 = w2 / w;                 // omega2 / omega1, correctly rounded
       thpi = th * M_1_PI;           // theta / pi
+    }
+  }
+  // The coefficients init derives, as a solve precomputes them for every
+  // system (k_model_coef: the divisions run once per system, fully
+  // parallel) and a lane loads them when it takes the system up, instead of
+  // deriving them there for the whole wave: [kNCoef][n], the same doubles.
+  static constexpr int kNCoef = DUAL ? 16 : 11;
+  __device__ void store_coef(double *c, int64_t n, int64_t i) const {
+    c[0 * n + i] = K0;
+    c[1 * n + i] = K1;
+    c[2 * n + i] = K2;
+    c[3 * n + i] = K3;
+    c[4 * n + i] = K4;
+    c[5 * n + i] = K5;
+    c[6 * n + i] = K7;
+    c[7 * n + i] = K9;
+    c[8 * n + i] = K10;
+    c[9 * n + i] = K49;
+    c[10 * n + i] = K9h;
+    if constexpr (DUAL) {
+      c[11 * n + i] = K6;
+      c[12 * n + i] = K8;
+      c[13 * n + i] = K11;
+      c[14 * n + i] = thpi;
+      c[15 * n + i] = dual ? 1.0 : 0.0;
+    }
+  }
+  __device__ void load_coef(const double *c, int64_t n, int64_t i) {
+    K0 = c[0 * n + i];
+    K1 = c[1 * n + i];
+    K2 = c[2 * n + i];
+    K3 = c[3 * n + i];
+    K4 = c[4 * n + i];
+    K5 = c[5 * n + i];
+    K7 = c[6 * n + i];
+    K9 = c[7 * n + i];
+    K10 = c[8 * n + i];
+    K49 = c[9 * n + i];
+    K9h = c[10 * n + i];
+    if constexpr (DUAL) {
+      K6 = c[11 * n + i];
+      K8 = c[12 * n + i];
+      K11 = c[13 * n + i];
+      thpi = c[14 * n + i];
+      dual = c[15 * n + i] != 0.0;
     }
   }
   // Second drive: phi = its phase in cycles when the current phase began;
@@ -575,6 +622,7 @@ struct MPRV {
   static constexpr bool kDrive2 = false;
   static constexpr int kF = 2;           // (y1 at the Poincare point, y1min)
   static constexpr bool kTangent = false;
+  static constexpr int kNCoef = 0;  // no precomputed coefficients
   double q, kappa, delta, beta, r;
   bool seated;
   __device__ void init(const double *P, int64_t n, int64_t i, const double *sh) {
@@ -1130,7 +1178,14 @@ __attribute__((amdgpu_waves_per_eu(min_waves(M::kMinWaves, SC, LOC), 8))) void k
           const int64_t i = order ? order[me] : (int64_t)me;
           int e = 0;
           while (e + 1 < a.n_ens && i >= sdesc[e].last) ++e;
-          m.init(cp->p, a.n, i, sdesc[e].shared);
+          if constexpr (M::kNCoef > 0) {
+            if (cp->coef)
+              m.load_coef(cp->coef, a.n, i);
+            else
+              m.init(cp->p, a.n, i, sdesc[e].shared);
+          } else {
+            m.init(cp->p, a.n, i, sdesc[e].shared);
+          }
           if constexpr (M::kDrive2) m.phi = cp->phi2[i];
 #pragma unroll
           for (int c = 0; c < D; ++c) y[c] = cp->y[c * a.n + i];
@@ -1300,6 +1355,22 @@ R visit_model(int model, bool loc, R none, Fn &&fn) {
   return none;
 }
 
+// Each system's model coefficients, from its parameters and its ensemble's
+// shared constants, into the cold pointers' coef array (one system per
+// thread, grid-stride).
+template <class M>
+__global__ __launch_bounds__(256) void k_model_coef(RkckArgs a) {
+  const RkckCold *cp = a.cold;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+    int e = 0;
+    while (e + 1 < a.n_ens && i >= a.desc[e].last) ++e;
+    M m;
+    m.init(cp->p, a.n, i, a.desc[e].shared);
+    m.store_coef(cp->coef, a.n, i);
+  }
+}
+
 template <int SC>
 hipError_t launch_scheme(int model, bool loc, int block, int grid, const RkckArgs &a,
                          hipStream_t s) {
@@ -1329,6 +1400,21 @@ __global__ void k_set_cold(RkckCold *dst, RkckCold c) {
 hipError_t launch_set_cold(RkckCold *dst, const RkckCold &c, hipStream_t s) {
   hipLaunchKernelGGL(k_set_cold, dim3(1), dim3(64), 0, s, dst, c);
   return hipGetLastError();
+}
+
+hipError_t launch_rkck_coef(int model, const RkckArgs &a, hipStream_t s) {
+  return visit_model(model, false, hipSuccess, [&](auto pick) -> hipError_t {
+    using M = typename decltype(pick)::M;
+    if constexpr (M::kNCoef > 0) {
+      static_assert(M::kNCoef <= ENS_MAX_COEF, "coefficient array");
+      const int64_t blocks = (a.n + 255) / 256;
+      hipLaunchKernelGGL(k_model_coef<M>, dim3((unsigned)(blocks < 4096 ? blocks : 4096)),
+                         dim3(256), 0, s, a);
+      return hipGetLastError();
+    } else {
+      return hipSuccess;
+    }
+  });
 }
 
 hipError_t launch_rkck(int model, int solver, int block, int grid, const RkckArgs &a,
