@@ -193,7 +193,9 @@ typedef struct {
 
 /* Creates a handle, allocates every buffer a solve on it needs on `device`
  * (parameters, state, outputs, and for the adaptive solvers the queue, the
- * queue order and the scratch of ens_order_by_work; records are allocated by
+ * queue order and the scratch of ens_order_by_work, and for Keller--Miksis
+ * the coefficients of each system's right-hand side, 16 doubles per system,
+ * which every solve derives first and its kernel then loads; records are allocated by
  * the first solve that keeps more of them than before; ens_set_order,
  * ens_set_params_gather and ens_tune allocate their scratch on first use and
  * keep it)
