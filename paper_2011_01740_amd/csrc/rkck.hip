@@ -1073,39 +1073,48 @@ __device__ __forceinline__ bool step_valve(const RkckArgs &a, MPRV &m, Lane &L, 
   const bool impact = take && free && y[0] <= 0.0 && y[1] < 0.0;
   const bool pmax = take && free && !impact && y2o > 0.0 && y[1] <= 0.0;
   bool done = false;
-  if (lift || impact) {
-    fs.have = false;
-    if (lift) {
-      m.seated = false;
-    } else {
-      const double v_in = y[1];
-      y[0] = 0.0;
-      y[1] = -m.r * v_in;
-      L.impacts++;
-      if (fabs(v_in) < a.v_stick && y[2] < m.delta) {
-        m.seated = true;
-        y[1] = 0.0;
-        L.status |= ENS_SYS_SEATED;
+  // The rare outcomes (a seat change or impact, a Poincare point, settling)
+  // behind one wave-uniform test: most attempts of most waves have none, and
+  // then skip their exec-mask bookkeeping altogether.
+  const bool cap = take && L.t - L.t_ps >= a.t_cap;
+  if (__ballot(lift || impact || pmax || cap) == 0ull) {
+    L.ymax = take ? fmax(L.ymax, y[0]) : L.ymax;
+    L.ymin = take ? fmin(L.ymin, y[0]) : L.ymin;
+  } else {
+    if (lift || impact) {
+      fs.have = false;
+      if (lift) {
+        m.seated = false;
+      } else {
+        const double v_in = y[1];
+        y[0] = 0.0;
+        y[1] = -m.r * v_in;
+        L.impacts++;
+        if (fabs(v_in) < a.v_stick && y[2] < m.delta) {
+          m.seated = true;
+          y[1] = 0.0;
+          L.status |= ENS_SYS_SEATED;
+        }
+        if (L.max_impacts > 0 && (int64_t)L.impacts >= L.max_impacts) done = true;
       }
-      if (L.max_impacts > 0 && (int64_t)L.impacts >= L.max_impacts) done = true;
     }
-  }
-  L.ymax = take ? fmax(L.ymax, y[0]) : L.ymax;
-  L.ymin = take ? fmin(L.ymin, y[0]) : L.ymin;
-  if (pmax) {
-    fs.have = false;
-    store_record<MPRV>(a, L, y[0], L.ymin);
-    L.phase++;
-    if constexpr (MPRV::kPrio) note_phase_end(L);
-    L.ymax = -INFINITY;
-    L.ymin = INFINITY;
-    L.t_ps = L.t;
-    if (L.phase >= L.n_phases) done = true;
-  } else if (take && L.t - L.t_ps >= a.t_cap) {
-    store_record<MPRV>(a, L, L.ymax, L.ymin);
-    L.phase++;
-    L.status |= ENS_SYS_SETTLED;
-    done = true;
+    L.ymax = take ? fmax(L.ymax, y[0]) : L.ymax;
+    L.ymin = take ? fmin(L.ymin, y[0]) : L.ymin;
+    if (pmax) {
+      fs.have = false;
+      store_record<MPRV>(a, L, y[0], L.ymin);
+      L.phase++;
+      if constexpr (MPRV::kPrio) note_phase_end(L);
+      L.ymax = -INFINITY;
+      L.ymin = INFINITY;
+      L.t_ps = L.t;
+      if (L.phase >= L.n_phases) done = true;
+    } else if (take && L.t - L.t_ps >= a.t_cap) {
+      store_record<MPRV>(a, L, L.ymax, L.ymin);
+      L.phase++;
+      L.status |= ENS_SYS_SETTLED;
+      done = true;
+    }
   }
   if (!done && a.max_steps > 0 && L.attempts >= a.max_steps) {
     L.status |= ENS_SYS_MAX_STEPS;
